@@ -1,0 +1,914 @@
+/*
+ * CPU oracle: Monte Carlo radiative transfer with immediate reemission, the
+ * modified random walk and the partial diffusion approximation, after
+ * Min et al. (2009).  Plain, single-threaded FP64.
+ *
+ * TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU-baseline timing).  It
+ * shares no code with the HIP library.
+ *
+ * Where the paper is silent the readings used are stated at each step; the
+ * same readings bind the GPU path, which implements them independently.
+ */
+#include "mcrt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* CODATA 2018, cgs */
+static const double H_PLANCK = 6.62607015e-27;
+static const double K_BOLTZ = 1.380649e-16;
+static const double C_LIGHT = 2.99792458e10;
+static const double SIGMA_SB = 5.670374419e-5;
+static const double PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of two      */
+/* 32x32->64 multiplies with a Weyl-sequence key schedule.                    */
+/* ------------------------------------------------------------------------ */
+void ora_philox4x32_10(uint32_t ctr[4], const uint32_t key_in[2]) {
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)ctr[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)ctr[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ ctr[1] ^ k0;
+    uint32_t n2 = hi0 ^ ctr[3] ^ k1;
+    ctr[0] = n0;
+    ctr[1] = lo1;
+    ctr[2] = n2;
+    ctr[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+/* One packet's stream: draw d uses counter (pid_lo, pid_hi, d/2, 0) and the
+ * 64-bit word (out[2h] << 32 | out[2h+1]) with h = d % 2; the top 53 bits
+ * become a double strictly inside (0, 1). */
+typedef struct {
+  uint32_t key[2];
+  uint64_t pid;
+  uint64_t d;
+  uint32_t buf[4];
+} rng_t;
+
+static double u64_to_unit(uint32_t a, uint32_t b) {
+  uint64_t x = ((uint64_t)a << 32) | (uint64_t)b;
+  return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+static double rng_next(rng_t* r) {
+  uint64_t h = r->d & 1u;
+  if (h == 0) {
+    uint64_t blk = r->d >> 1;
+    r->buf[0] = (uint32_t)r->pid;
+    r->buf[1] = (uint32_t)(r->pid >> 32);
+    r->buf[2] = (uint32_t)blk;
+    r->buf[3] = (uint32_t)(blk >> 32);
+    ora_philox4x32_10(r->buf, r->key);
+  }
+  r->d++;
+  return u64_to_unit(r->buf[2 * h], r->buf[2 * h + 1]);
+}
+
+static void rng_init(rng_t* r, uint64_t seed, uint64_t pid) {
+  r->key[0] = (uint32_t)seed;
+  r->key[1] = (uint32_t)(seed >> 32);
+  r->pid = pid;
+  r->d = 0;
+}
+
+void ora_uniforms(uint64_t seed, uint64_t pid, uint64_t d0, int64_t n, double* out) {
+  rng_t r;
+  rng_init(&r, seed, pid);
+  for (uint64_t i = 0; i < d0; ++i) rng_next(&r);
+  for (int64_t i = 0; i < n; ++i) out[i] = rng_next(&r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Planck bin integrals by composite Simpson in u = ln(nu)                    */
+/* ------------------------------------------------------------------------ */
+static void planck_point(double nu, double T, double* B, double* dB) {
+  double pre = 2.0 * H_PLANCK * nu * nu * nu / (C_LIGHT * C_LIGHT);
+  if (T <= 0.0) {
+    *B = 0.0;
+    *dB = 0.0;
+    return;
+  }
+  double x = H_PLANCK * nu / (K_BOLTZ * T);
+  double ex = exp(-x);
+  double om = -expm1(-x); /* 1 - e^-x */
+  *B = pre * ex / om;
+  *dB = pre * (x / T) * ex / (om * om);
+}
+
+void ora_planck_bins(const double* lambda_edges, int n_lambda, double T, double* Bbar,
+                     double* dBbar) {
+  const int M = 256; /* Simpson sub-intervals per bin */
+  for (int k = 0; k < n_lambda; ++k) {
+    double nu_lo = C_LIGHT / lambda_edges[k + 1];
+    double nu_hi = C_LIGHT / lambda_edges[k];
+    double ua = log(nu_lo), ub = log(nu_hi), hstep = (ub - ua) / M;
+    double sB = 0.0, sdB = 0.0;
+    for (int q = 0; q <= M; ++q) {
+      double u = ua + q * hstep;
+      double nu = exp(u), B, dB;
+      planck_point(nu, T, &B, &dB);
+      double w = (q == 0 || q == M) ? 1.0 : ((q & 1) ? 4.0 : 2.0);
+      sB += w * B * nu; /* dnu = nu du */
+      sdB += w * dB * nu;
+    }
+    Bbar[k] = sB * hstep / 3.0;
+    dBbar[k] = sdB * hstep / 3.0;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tables (Sect. 2.2.3).  Temperature-dependent quantities are tabulated at   */
+/* n_T nodes: node 0 is T = 0, nodes 1..n_T-1 are log-spaced T_lo..T_hi, and  */
+/* values are interpolated linearly in T between nodes (reading).  Frequency  */
+/* integrals are sums over the wavelength bins (reading).                     */
+/* ------------------------------------------------------------------------ */
+int ora_build_tables(const ora_model* m, ora_tables* t) {
+  const int nl = m->n_lambda, nT = t->n_T;
+  if (nT < 3 || nl < 1) return -1;
+  double* Bb = (double*)malloc(sizeof(double) * nl);
+  double* dBb = (double*)malloc(sizeof(double) * nl);
+  double* eta = (double*)malloc(sizeof(double) * nl);
+  double* eta_new = (double*)malloc(sizeof(double) * nl);
+  t->eta_iters_max = 0;
+  double lr = log(t->T_hi / t->T_lo);
+  for (int n = 0; n < nT; ++n) {
+    double T = (n == 0) ? 0.0 : t->T_lo * exp(lr * (double)(n - 1) / (double)(nT - 2));
+    if (n == nT - 1) T = t->T_hi;
+    if (n == 1) T = t->T_lo;
+    t->T[n] = T;
+    ora_planck_bins(m->lambda_edges, nl, T, Bb, dBb);
+    double c = 0.0;
+    for (int k = 0; k < nl; ++k) {
+      c += m->kappa_abs[k] * Bb[k];
+      t->cdf[(size_t)n * nl + k] = c;
+    }
+    if (n == 0) continue;
+    /* eq:eta nu iter: eta_k <- kappa_k dB_k * (sum eta kappa/chi)/(sum eta)
+     *                         + (sigma_k/chi_k) eta_k, from eta = kappa dB */
+    for (int k = 0; k < nl; ++k) eta[k] = m->kappa_abs[k] * dBb[k];
+    int it;
+    for (it = 0; it < 20000; ++it) {
+      double num = 0.0, den = 0.0;
+      for (int k = 0; k < nl; ++k) {
+        double chi = m->kappa_abs[k] + m->kappa_sca[k];
+        num += eta[k] * m->kappa_abs[k] / chi;
+        den += eta[k];
+      }
+      double ratio = num / den, change = 0.0;
+      for (int k = 0; k < nl; ++k) {
+        double chi = m->kappa_abs[k] + m->kappa_sca[k];
+        eta_new[k] = m->kappa_abs[k] * dBb[k] * ratio + (m->kappa_sca[k] / chi) * eta[k];
+        double rel = fabs(eta_new[k] - eta[k]) / (fabs(eta_new[k]) + 1e-300);
+        if (eta_new[k] != 0.0 && rel > change) change = rel;
+      }
+      memcpy(eta, eta_new, sizeof(double) * nl);
+      if (change < 1e-13) break;
+    }
+    if (it + 1 > t->eta_iters_max) t->eta_iters_max = it + 1;
+    /* eq:avd, eq:avd2 (per unit rho), eq:diffusion coeff, kappa-bar */
+    double s_eta = 0.0, s_d = 0.0, s_d2 = 0.0, s_kc = 0.0, s_ic = 0.0;
+    for (int k = 0; k < nl; ++k) {
+      double chi = m->kappa_abs[k] + m->kappa_sca[k];
+      s_eta += eta[k];
+      s_d += eta[k] / chi;
+      s_d2 += eta[k] / (chi * chi);
+      s_kc += eta[k] * m->kappa_abs[k] / chi;
+      s_ic += eta[k] / chi;
+    }
+    double d1 = s_d / s_eta;        /* <d> * rho */
+    double d2 = 2.0 * s_d2 / s_eta; /* <d^2> * rho^2 */
+    t->Drho[n] = d2 / (6.0 * d1);
+    t->kbar[n] = s_kc / s_ic;
+  }
+  /* below T_lo: the T_lo values (the limit T -> 0 is not needed) */
+  t->Drho[0] = t->Drho[1];
+  t->kbar[0] = t->kbar[1];
+  /* star: L = 4 pi R^2 sigma T^4; spectrum restricted to the bins, renormalised */
+  ora_planck_bins(m->lambda_edges, nl, m->T_star, Bb, dBb);
+  double tot = 0.0;
+  for (int k = 0; k < nl; ++k) tot += Bb[k];
+  double c = 0.0;
+  for (int k = 0; k < nl; ++k) {
+    c += Bb[k];
+    t->star_cdf[k] = c / tot;
+  }
+  t->star_cdf[nl - 1] = 1.0;
+  t->L_star = 4.0 * PI * m->R_star * m->R_star * SIGMA_SB * pow(m->T_star, 4.0);
+  free(Bb);
+  free(dBb);
+  free(eta);
+  free(eta_new);
+  return 0;
+}
+
+/* linear-in-T position of T among the nodes: segment n and weight f */
+static void t_segment(const ora_tables* t, double T, int* n, double* f) {
+  int lo = 0, hi = t->n_T - 1; /* invariant T[lo] <= T < T[hi] unless beyond */
+  if (T >= t->T[t->n_T - 1]) {
+    *n = t->n_T - 2;
+  } else {
+    while (hi - lo > 1) {
+      int mid = (lo + hi) / 2;
+      if (t->T[mid] <= T) lo = mid; else hi = mid;
+    }
+    *n = lo;
+  }
+  *f = (T - t->T[*n]) / (t->T[*n + 1] - t->T[*n]);
+}
+
+static double t_interp(const ora_tables* t, const double* tab, double T) {
+  int n;
+  double f;
+  t_segment(t, T, &n, &f);
+  return tab[n] + f * (tab[n + 1] - tab[n]);
+}
+
+/* G(T) = cdf at the last bin; the cell emits 4 pi m G(T) */
+static double G_node(const ora_tables* t, int nl, int n) { return t->cdf[(size_t)n * nl + nl - 1]; }
+
+/* radiative equilibrium: 4 pi m G(T) = E, G piecewise linear in T */
+static double T_of_g(const ora_tables* t, int nl, double g) {
+  if (g <= 0.0) return 0.0;
+  int lo = 0, hi = t->n_T - 1, n;
+  if (g >= G_node(t, nl, hi)) {
+    n = t->n_T - 2;
+  } else {
+    while (hi - lo > 1) {
+      int mid = (lo + hi) / 2;
+      if (G_node(t, nl, mid) <= g) lo = mid; else hi = mid;
+    }
+    n = lo;
+  }
+  double Ga = G_node(t, nl, n), Gb = G_node(t, nl, n + 1);
+  return t->T[n] + (g - Ga) / (Gb - Ga) * (t->T[n + 1] - t->T[n]);
+}
+
+double ora_T_of_E(const ora_model* m, const ora_tables* t, double E, double mass) {
+  if (mass <= 0.0) return 0.0;
+  return T_of_g(t, m->n_lambda, E / (4.0 * PI * mass));
+}
+
+/* Cumulative emission at T of bins 0..k, linear in T between nodes */
+static double cdf_at(const ora_tables* t, int nl, int n, double f, int k) {
+  double a = t->cdf[(size_t)n * nl + k], b = t->cdf[(size_t)(n + 1) * nl + k];
+  return a + f * (b - a);
+}
+
+/* Reemission bin (immediate reemission): from the difference spectrum
+ * kappa_k [Bbar_k(T_new) - Bbar_k(T_old)], or the full spectrum at T_new when
+ * there is no old temperature (T_old < 0) or no difference. */
+static int reemit_bin(const ora_tables* t, int nl, double T_old, double T_new, double xi) {
+  int nn, no = 0;
+  double fn, fo = 0.0;
+  t_segment(t, T_new, &nn, &fn);
+  int use_diff = (T_old >= 0.0 && T_new > T_old);
+  if (use_diff) t_segment(t, T_old, &no, &fo);
+  /* D(k): difference of the cumulative spectra; same-segment case factored */
+  double tot;
+  int same = use_diff && (no == nn);
+  if (same) {
+    tot = (fn - fo) * (t->cdf[(size_t)(nn + 1) * nl + nl - 1] - t->cdf[(size_t)nn * nl + nl - 1]);
+  } else if (use_diff) {
+    tot = cdf_at(t, nl, nn, fn, nl - 1) - cdf_at(t, nl, no, fo, nl - 1);
+  } else {
+    tot = cdf_at(t, nl, nn, fn, nl - 1);
+  }
+  if (!(tot > 0.0)) { /* degenerate difference: full spectrum at T_new */
+    use_diff = 0;
+    same = 0;
+    tot = cdf_at(t, nl, nn, fn, nl - 1);
+  }
+  double target = xi * tot;
+  int lo = 0, hi = nl - 1; /* smallest k with D(k) > target */
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    double Dk;
+    if (same)
+      Dk = (fn - fo) * (t->cdf[(size_t)(nn + 1) * nl + mid] - t->cdf[(size_t)nn * nl + mid]);
+    else if (use_diff)
+      Dk = cdf_at(t, nl, nn, fn, mid) - cdf_at(t, nl, no, fo, mid);
+    else
+      Dk = cdf_at(t, nl, nn, fn, mid);
+    if (Dk > target) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+int ora_reemit_sample(const ora_model* m, const ora_tables* t, double T_old, double T_new,
+                      double xi) {
+  return reemit_bin(t, m->n_lambda, T_old, T_new, xi);
+}
+
+double ora_table_interp(const ora_tables* t, int which, double T) {
+  return t_interp(t, which == 0 ? t->Drho : t->kbar, T);
+}
+
+/* ------------------------------------------------------------------------ */
+/* MRW escape-time law (eq:probability RW).  With s = D c t / R0^2,           */
+/* P(s) = 2 sum_{n>=1} (-1)^{n+1} exp(-n^2 pi^2 s); for small s the           */
+/* equivalent theta-function form 1 - 2 sqrt(pi/x) sum_k exp(-pi^2 (2k+1)^2   */
+/* / (4x)), x = pi^2 s, converges fast.  P decreases from 1 to 0.             */
+/* ------------------------------------------------------------------------ */
+double ora_mrw_survival(double s) {
+  if (s <= 0.0) return 1.0;
+  double x = PI * PI * s;
+  if (s >= 0.1) {
+    double sum = 0.0;
+    for (int n = 1; n < 200; ++n) {
+      double term = exp(-(double)n * n * x);
+      sum += (n & 1) ? term : -term;
+      if (term < 1e-300 || term < 1e-18 * fabs(sum)) break;
+    }
+    return 2.0 * sum;
+  }
+  double sum = 0.0;
+  for (int k = 0; k < 200; ++k) {
+    double a = (double)(2 * k + 1);
+    double term = exp(-PI * PI * a * a / (4.0 * x));
+    sum += term;
+    if (term < 1e-300 || term < 1e-18 * sum) break;
+  }
+  return 1.0 - 2.0 * sqrt(PI / x) * sum;
+}
+
+/* P(s) = P0 by bisection on log s (P is strictly decreasing) */
+double ora_mrw_escape_s(double P0) {
+  double lo = 1e-6, hi = 10.0;
+  while (ora_mrw_survival(lo) < P0) lo *= 0.5;
+  while (ora_mrw_survival(hi) > P0) hi *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = sqrt(lo * hi);
+    if (ora_mrw_survival(mid) > P0) lo = mid; else hi = mid;
+    if (hi - lo <= 1e-16 * hi) break;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: folded spherical grid.  Cell (i, j) is r_i <= r < r_{i+1} and    */
+/* mu_j <= |z|/r < mu_{j+1}; both mirror halves belong to the cell.  Faces:   */
+/* spheres r_i, r_{i+1}; cones mu_j (j >= 1) and mu_{j+1} (j+1 < n_mu).  The   */
+/* midplane and the pole are not faces.                                       */
+/* ------------------------------------------------------------------------ */
+int64_t ora_locate(const ora_model* m, double x, double y, double z) {
+  double r2 = (x * x + y * y) + z * z;
+  double z2 = z * z;
+  if (!(r2 >= m->r_edges[0] * m->r_edges[0])) return -1;
+  if (!(r2 < m->r_edges[m->n_r] * m->r_edges[m->n_r])) return -1;
+  int i = 0;
+  for (int e = 1; e < m->n_r; ++e)
+    if (m->r_edges[e] * m->r_edges[e] <= r2) i = e;
+  int j = 0;
+  for (int e = 1; e < m->n_mu; ++e)
+    if ((m->mu_edges[e] * m->mu_edges[e]) * r2 <= z2) j = e;
+  return (int64_t)i * m->n_mu + j;
+}
+
+/* path length to a sphere of squared radius R2, leaving it from inside */
+static int sphere_out(double pd, double c, double* s) {
+  double disc = pd * pd - c;
+  if (c >= 0.0 && (pd > 0.0 || disc < 0.0)) { *s = 0.0; return 1; }
+  if (disc < 0.0) disc = 0.0;
+  double sq = sqrt(disc);
+  *s = (pd > 0.0) ? -c / (pd + sq) : -pd + sq;
+  return 1;
+}
+
+/* path length to a sphere of squared radius R2, reached from outside */
+static int sphere_in(double pd, double c, double* s) {
+  if (c <= 0.0 && pd < 0.0) { *s = 0.0; return 1; }
+  if (pd >= 0.0) return 0;
+  double disc = pd * pd - c;
+  if (disc < 0.0) return 0;
+  *s = c / (-pd + sqrt(disc));
+  return 1;
+}
+
+/* path length to leave the cone pair |z| = mu r.  f(s) = A s^2 + 2 B s + C
+ * with f < 0 inside the midplane-side wedge.  upper = 1: the cell lies on the
+ * wedge side (f < 0) and leaves when f turns positive; upper = 0: the cell
+ * lies on the pole side and leaves when f turns negative. */
+static int cone_exit(double A, double B, double C, int upper, double* s) {
+  if (upper) {
+    if (C >= 0.0 && B > 0.0) { *s = 0.0; return 1; }
+  } else {
+    if (C <= 0.0 && B < 0.0) { *s = 0.0; return 1; }
+  }
+  double disc = B * B - A * C;
+  if (disc < 0.0) return 0;
+  double sq = sqrt(disc);
+  double v;
+  if (upper)
+    v = (B > 0.0) ? C / (-B - sq) : (-B + sq) / A;
+  else
+    v = (B < 0.0) ? C / (-B + sq) : (-B - sq) / A;
+  if (!(v > 0.0) || isinf(v)) return 0;
+  *s = v;
+  return 1;
+}
+
+/* face ids: 0 inner sphere, 1 outer sphere, 2 lower cone, 3 upper cone */
+static double face_distance(const ora_model* m, int i, int j, const double p[3],
+                            const double d[3], int* face) {
+  double pd = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
+  double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  double best = INFINITY, s;
+  *face = -1;
+  double ro = m->r_edges[i + 1];
+  if (sphere_out(pd, rr - ro * ro, &s) && s < best) { best = s; *face = 1; }
+  double ri = m->r_edges[i];
+  if (sphere_in(pd, rr - ri * ri, &s) && s < best) { best = s; *face = 0; }
+  if (j >= 1) {
+    double mu = m->mu_edges[j], m2 = mu * mu;
+    double A = d[2] * d[2] - m2 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double B = p[2] * d[2] - m2 * pd;
+    double C = p[2] * p[2] - m2 * rr;
+    if (cone_exit(A, B, C, 0, &s) && s < best) { best = s; *face = 2; }
+  }
+  if (j + 1 < m->n_mu) {
+    double mu = m->mu_edges[j + 1], m2 = mu * mu;
+    double A = d[2] * d[2] - m2 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double B = p[2] * d[2] - m2 * pd;
+    double C = p[2] * p[2] - m2 * rr;
+    if (cone_exit(A, B, C, 1, &s) && s < best) { best = s; *face = 3; }
+  }
+  return best;
+}
+
+/* distance from p to the nearest of the cell's bounding surfaces (spheres
+ * and full cones; a lower bound of the distance to the cell boundary) */
+static double min_face_distance(const ora_model* m, int i, int j, const double p[3]) {
+  double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  double d = r - m->r_edges[i];
+  double d2 = m->r_edges[i + 1] - r;
+  if (d2 < d) d = d2;
+  double mu = fabs(p[2]) / r;
+  double smu = sqrt(fmax(0.0, 1.0 - mu * mu));
+  if (j >= 1) { /* r sin(theta_j - theta) */
+    double me = m->mu_edges[j];
+    double v = r * (sqrt(1.0 - me * me) * mu - me * smu);
+    if (v < d) d = v;
+  }
+  if (j + 1 < m->n_mu) { /* r sin(theta - theta_{j+1}) */
+    double me = m->mu_edges[j + 1];
+    double v = r * (me * smu - sqrt(1.0 - me * me) * mu);
+    if (v < d) d = v;
+  }
+  return d > 0.0 ? d : 0.0;
+}
+
+static void iso_dir(rng_t* r, double d[3]) {
+  double w = 2.0 * rng_next(r) - 1.0;
+  double ph = 2.0 * PI * rng_next(r);
+  double st = sqrt(fmax(0.0, 1.0 - w * w));
+  d[0] = st * cos(ph);
+  d[1] = st * sin(ph);
+  d[2] = w;
+}
+
+void ora_cell_volumes(const ora_model* m, double* V) {
+  for (int i = 0; i < m->n_r; ++i) {
+    double a = m->r_edges[i], b = m->r_edges[i + 1];
+    double dr3 = b * b * b - a * a * a;
+    for (int j = 0; j < m->n_mu; ++j)
+      V[(size_t)i * m->n_mu + j] = 4.0 * PI / 3.0 * dr3 * (m->mu_edges[j + 1] - m->mu_edges[j]);
+  }
+}
+
+void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {
+  int nc = m->n_r * m->n_mu;
+  double* V = (double*)malloc(sizeof(double) * nc);
+  ora_cell_volumes(m, V);
+  for (int c = 0; c < nc; ++c) T[c] = ora_T_of_E(m, t, E_abs[c], m->rho[c] * V[c]);
+  free(V);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transport of packets [offset, offset + n) of a run of n_total packets.     */
+/* Each packet carries eps = L_star / n_total.                                */
+/* ------------------------------------------------------------------------ */
+int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t n_packets,
+            uint64_t n_total, uint64_t seed, uint64_t offset, double* E_abs, uint32_t* visits,
+            uint32_t* n_abs, uint32_t* n_mrw_cell, double* sed, double* E_star,
+            long long* counters, ora_packet_rec* recs, int64_t n_recs) {
+  const int nl = m->n_lambda, nmu = m->n_mu, nr = m->n_r;
+  const int nc = nr * nmu;
+  const double eps = t->L_star / (double)n_total;
+  double* V = (double*)malloc(sizeof(double) * nc);
+  double* inv4pim = (double*)malloc(sizeof(double) * nc);
+  ora_cell_volumes(m, V);
+  for (int c = 0; c < nc; ++c) {
+    double mass = m->rho[c] * V[c];
+    inv4pim[c] = mass > 0.0 ? 1.0 / (4.0 * PI * mass) : 0.0;
+  }
+  const double r_in = m->r_edges[0];
+
+  for (uint64_t q = 0; q < n_packets; ++q) {
+    uint64_t pid = offset + q;
+    rng_t rng;
+    rng_init(&rng, seed, pid);
+    long long n_cross = 0, n_scat = 0, n_ab = 0, n_mrw = 0, events = 0;
+    int fate = 0;
+    /* launch: uniform point on the stellar sphere (azimuth 0 by symmetry),
+     * Lambertian outward direction, bin from the stellar spectrum */
+    double p[3], d[3];
+    double ws = 2.0 * rng_next(&rng) - 1.0;
+    double st = sqrt(fmax(0.0, 1.0 - ws * ws));
+    p[0] = m->R_star * st;
+    p[1] = 0.0;
+    p[2] = m->R_star * ws;
+    double mup = sqrt(rng_next(&rng));
+    double php = 2.0 * PI * rng_next(&rng);
+    double sp = sqrt(fmax(0.0, 1.0 - mup * mup));
+    double ct = cos(php), sn = sin(php);
+    /* n = (st, 0, ws); e_theta = (ws, 0, -st); e_phi = (0, 1, 0) */
+    d[0] = mup * st + sp * ct * ws;
+    d[1] = sp * sn;
+    d[2] = mup * ws - sp * ct * st;
+    double xs = rng_next(&rng);
+    int k = 0;
+    while (k < nl - 1 && !(t->star_cdf[k] > xs)) ++k;
+    double tau = -log(rng_next(&rng));
+    counters[ORA_C_LAUNCH]++;
+    int i = -1, j = 0, n_int = 0;
+
+    for (;;) {
+      if (++events > o->max_events) { fate = 3; break; }
+      if (i < 0) {
+        /* inner hole: free flight to the star or back to r_in */
+        double pd = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
+        double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+        double s;
+        if (sphere_in(pd, rr - m->R_star * m->R_star, &s)) {
+          for (int a = 0; a < 3; ++a) p[a] += s * d[a];
+          fate = 2;
+          break;
+        }
+        sphere_out(pd, rr - r_in * r_in, &s);
+        for (int a = 0; a < 3; ++a) p[a] += s * d[a];
+        i = 0;
+        double r2 = (p[0] * p[0] + p[1] * p[1]) + p[2] * p[2], z2 = p[2] * p[2];
+        j = 0;
+        for (int e = 1; e < nmu; ++e)
+          if ((m->mu_edges[e] * m->mu_edges[e]) * r2 <= z2) j = e;
+        visits[(size_t)i * nmu + j]++;
+        n_int = 0;
+        ++n_cross;
+        continue;
+      }
+      int c = i * nmu + j;
+      double chi = m->kappa_abs[k] + m->kappa_sca[k];
+      double alpha = m->rho[c] * chi;
+      int face;
+      double sb = face_distance(m, i, j, p, d, &face);
+      double tau_b = alpha * sb;
+      if (tau_b <= tau) {
+        /* reach the face: move, spend optical depth, step the index */
+        for (int a = 0; a < 3; ++a) p[a] += sb * d[a];
+        tau -= tau_b;
+        ++n_cross;
+        if (face == 1) {
+          if (i + 1 == nr) { /* escape: SED bin by |cos i| of the direction */
+            int mi = (int)(fabs(d[2]) * o->n_inc);
+            if (mi >= o->n_inc) mi = o->n_inc - 1;
+            sed[(size_t)k * o->n_inc + mi] += eps;
+            fate = 1;
+            break;
+          }
+          ++i;
+        } else if (face == 0) {
+          --i;
+          if (i < 0) { n_int = 0; continue; }
+        } else if (face == 2) {
+          --j;
+        } else {
+          ++j;
+        }
+        visits[(size_t)i * nmu + j]++;
+        n_int = 0;
+        continue;
+      }
+      /* interaction inside the cell */
+      double sint = tau / alpha;
+      for (int a = 0; a < 3; ++a) p[a] += sint * d[a];
+      double omega = m->kappa_sca[k] / chi;
+      if (rng_next(&rng) < omega) {
+        ++n_scat;
+      } else {
+        ++n_ab;
+        n_abs[c]++;
+        double E_old = E_abs[c];
+        E_abs[c] = E_old + eps;
+        double xb = rng_next(&rng);
+        if (o->frozen_T) {
+          k = reemit_bin(t, nl, -1.0, o->frozen_T[c], xb);
+        } else {
+          double T_old = T_of_g(t, nl, E_old * inv4pim[c]);
+          double T_new = T_of_g(t, nl, E_abs[c] * inv4pim[c]);
+          k = reemit_bin(t, nl, T_old, T_new, xb);
+        }
+      }
+      iso_dir(&rng, d);
+      ++n_int;
+      /* modified random walk (eqs. modified RW .. criterion) */
+      if (o->mrw) {
+        for (;;) {
+          if (n_int < o->n_int_min) break;
+          double Tc = o->frozen_T ? o->frozen_T[c] : T_of_g(t, nl, E_abs[c] * inv4pim[c]);
+          double Drho = t_interp(t, t->Drho, Tc);
+          double lam_R = 3.0 * Drho / m->rho[c]; /* 1/(rho chi_R) */
+          double dmin = min_face_distance(m, i, j, p);
+          if (!(dmin > o->gamma * lam_R)) break;
+          if (++events > o->max_events) break;
+          double R0 = dmin * (1.0 - 1e-6);
+          double s = ora_mrw_escape_s(rng_next(&rng));
+          double D = Drho / m->rho[c];
+          double ell = s * R0 * R0 / D; /* c t */
+          double dE = eps * m->rho[c] * t_interp(t, t->kbar, Tc) * ell;
+          double nrm[3];
+          iso_dir(&rng, nrm);
+          for (int a = 0; a < 3; ++a) p[a] += R0 * nrm[a];
+          double E_old = E_abs[c];
+          E_abs[c] = E_old + dE;
+          double xb = rng_next(&rng);
+          if (o->frozen_T) {
+            k = reemit_bin(t, nl, -1.0, o->frozen_T[c], xb);
+          } else {
+            double T_old = T_of_g(t, nl, E_old * inv4pim[c]);
+            double T_new = T_of_g(t, nl, E_abs[c] * inv4pim[c]);
+            k = reemit_bin(t, nl, T_old, T_new, xb);
+          }
+          iso_dir(&rng, d);
+          ++n_mrw;
+          n_mrw_cell[c]++;
+        }
+      }
+      tau = -log(rng_next(&rng));
+    }
+    if (fate == 1) counters[ORA_C_ESCAPED]++;
+    else if (fate == 2) { counters[ORA_C_STAR]++; *E_star += eps; }
+    else counters[ORA_C_CAPPED]++;
+    counters[ORA_C_CROSS] += n_cross;
+    counters[ORA_C_SCAT] += n_scat;
+    counters[ORA_C_ABS] += n_ab;
+    counters[ORA_C_MRW] += n_mrw;
+    if ((int64_t)q < n_recs) {
+      ora_packet_rec* R = &recs[q];
+      R->fate = fate;
+      R->k = k;
+      R->n_cross = n_cross;
+      R->n_scat = n_scat;
+      R->n_abs = n_ab;
+      R->n_mrw = n_mrw;
+      R->n_draws = (int64_t)rng.d;
+      R->x = p[0]; R->y = p[1]; R->z = p[2];
+      R->u = d[0]; R->v = d[1]; R->w = d[2];
+    }
+  }
+  free(V);
+  free(inv4pim);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PDA (Sect. 2.2.1, eq:T diffusion): div(D grad T^4) = 0 on the region,     */
+/* Dirichlet T from the Monte Carlo run on the neighbouring cells.  Finite    */
+/* volumes on the (r, mu) cells: flux A_f D_f (u_b - u_a) / dist_f with the   */
+/* harmonic mean of the two cells' D; zero flux at the grid edges, the pole,  */
+/* the (folded) midplane and towards dust-free cells.                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int nr, nmu;
+  double *rc, *thc;        /* cell centres */
+  double *Ar, *Amu;        /* face areas: Ar[i*nmu+j] face r_{i+1}; Amu[i*nmu+j] face mu_{j+1} */
+} pda_geom;
+
+static void pda_geom_init(const ora_model* m, pda_geom* g) {
+  int nr = m->n_r, nmu = m->n_mu;
+  g->nr = nr;
+  g->nmu = nmu;
+  g->rc = (double*)malloc(sizeof(double) * nr);
+  g->thc = (double*)malloc(sizeof(double) * nmu);
+  g->Ar = (double*)malloc(sizeof(double) * nr * nmu);
+  g->Amu = (double*)malloc(sizeof(double) * nr * nmu);
+  for (int i = 0; i < nr; ++i) g->rc[i] = 0.5 * (m->r_edges[i] + m->r_edges[i + 1]);
+  for (int j = 0; j < nmu; ++j)
+    g->thc[j] = 0.5 * (acos(m->mu_edges[j]) + acos(m->mu_edges[j + 1]));
+  for (int i = 0; i < nr; ++i)
+    for (int j = 0; j < nmu; ++j) {
+      double rf = m->r_edges[i + 1];
+      g->Ar[i * nmu + j] = 2.0 * PI * rf * rf * 2.0 * (m->mu_edges[j + 1] - m->mu_edges[j]);
+      double mf = m->mu_edges[j + 1];
+      double a = m->r_edges[i], b = m->r_edges[i + 1];
+      g->Amu[i * nmu + j] = PI * (b * b - a * a) * 2.0 * sqrt(fmax(0.0, 1.0 - mf * mf));
+    }
+}
+
+static void pda_geom_free(pda_geom* g) {
+  free(g->rc); free(g->thc); free(g->Ar); free(g->Amu);
+}
+
+/* conductance of the face between cells a and b (b = a's neighbour) */
+static double face_cond(const pda_geom* g, int ia, int ja, int ib, int jb, double Da, double Db) {
+  double A, dist;
+  if (ib != ia) {
+    int ilo = ia < ib ? ia : ib;
+    A = g->Ar[ilo * g->nmu + ja];
+    dist = fabs(g->rc[ib] - g->rc[ia]);
+  } else {
+    int jlo = ja < jb ? ja : jb;
+    A = g->Amu[ia * g->nmu + jlo];
+    dist = g->rc[ia] * fabs(g->thc[jb] - g->thc[ja]);
+  }
+  double Df = 2.0 * Da * Db / (Da + Db);
+  return A * Df / dist;
+}
+
+/* banded Cholesky, half-bandwidth bw, full-grid ordering; LL^T in place.
+ * band[c][q] holds A[c][c-bw+q], q = 0..bw */
+static int band_cholesky_solve(int n, int bw, double* band, double* x) {
+  for (int c = 0; c < n; ++c) {
+    int q0 = c - bw < 0 ? bw - c : 0;
+    for (int q = q0; q <= bw; ++q) {
+      int r = c - bw + q; /* column index, r <= c */
+      double s = band[(size_t)c * (bw + 1) + q];
+      int kk0 = (c - bw > r - bw ? c - bw : r - bw);
+      if (kk0 < 0) kk0 = 0;
+      for (int kk = kk0; kk < r; ++kk)
+        s -= band[(size_t)c * (bw + 1) + (kk - c + bw)] * band[(size_t)r * (bw + 1) + (kk - r + bw)];
+      if (r == c) {
+        if (!(s > 0.0)) return -1;
+        band[(size_t)c * (bw + 1) + bw] = sqrt(s);
+      } else {
+        band[(size_t)c * (bw + 1) + q] = s / band[(size_t)r * (bw + 1) + bw];
+      }
+    }
+  }
+  for (int c = 0; c < n; ++c) { /* L y = b */
+    double s = x[c];
+    int kk0 = c - bw < 0 ? 0 : c - bw;
+    for (int kk = kk0; kk < c; ++kk) s -= band[(size_t)c * (bw + 1) + (kk - c + bw)] * x[kk];
+    x[c] = s / band[(size_t)c * (bw + 1) + bw];
+  }
+  for (int c = n - 1; c >= 0; --c) { /* L^T x = y */
+    double s = x[c];
+    int kk1 = c + bw >= n ? n - 1 : c + bw;
+    for (int kk = c + 1; kk <= kk1; ++kk) s -= band[(size_t)kk * (bw + 1) + (c - kk + bw)] * x[kk];
+    x[c] = s / band[(size_t)c * (bw + 1) + bw];
+  }
+  return 0;
+}
+
+/* assemble and solve once: D from T_D (region) and T_D (Dirichlet cells), u
+ * Dirichlet = T_bc^4.  kscale scales chi per cell (NULL = 1). */
+static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geom* g,
+                          const uint8_t* reg, const double* T_D, const double* T_bc,
+                          const double* kscale, double* u) {
+  int nr = m->n_r, nmu = m->n_mu, n = nr * nmu, bw = nmu;
+  double* band = (double*)calloc((size_t)n * (bw + 1), sizeof(double));
+  double* D = (double*)malloc(sizeof(double) * n);
+  for (int c = 0; c < n; ++c) {
+    double ks = kscale ? kscale[c] : 1.0;
+    D[c] = m->rho[c] > 0.0 ? t_interp(t, t->Drho, T_D[c]) / (m->rho[c] * ks) : 0.0;
+  }
+  for (int c = 0; c < n; ++c) {
+    if (reg[c] != 1) {
+      band[(size_t)c * (bw + 1) + bw] = 1.0;
+      u[c] = pow(T_bc[c], 4.0);
+      continue;
+    }
+    u[c] = 0.0;
+  }
+  for (int c = 0; c < n; ++c) {
+    if (reg[c] != 1) continue;
+    int i = c / nmu, j = c % nmu;
+    int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    double diag = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      int ib = nb[q][0], jb = nb[q][1];
+      if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+      int cb = ib * nmu + jb;
+      if (!(m->rho[cb] > 0.0)) continue;
+      double a = face_cond(g, i, j, ib, jb, D[c], D[cb]);
+      diag += a;
+      if (reg[cb] == 1) {
+        if (cb < c) band[(size_t)c * (bw + 1) + (cb - c + bw)] = -a;
+      } else {
+        u[c] += a * pow(T_bc[cb], 4.0);
+      }
+    }
+    band[(size_t)c * (bw + 1) + bw] = diag;
+  }
+  int rc = band_cholesky_solve(n, bw, band, u);
+  free(band);
+  free(D);
+  return rc;
+}
+
+/* cells of `reg` (value 1) whose connected component touches no usable
+ * Dirichlet neighbour are set to 2 */
+static void pda_components(const ora_model* m, uint8_t* reg) {
+  int nr = m->n_r, nmu = m->n_mu, n = nr * nmu;
+  int* comp = (int*)malloc(sizeof(int) * n);
+  int* stack = (int*)malloc(sizeof(int) * n);
+  for (int c = 0; c < n; ++c) comp[c] = -1;
+  for (int c0 = 0; c0 < n; ++c0) {
+    if (reg[c0] != 1 || comp[c0] >= 0) continue;
+    int top = 0, touches = 0, cnt = 0;
+    stack[top++] = c0;
+    comp[c0] = c0;
+    int* members = (int*)malloc(sizeof(int) * n);
+    while (top > 0) {
+      int c = stack[--top];
+      members[cnt++] = c;
+      int i = c / nmu, j = c % nmu;
+      int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+      for (int q = 0; q < 4; ++q) {
+        int ib = nb[q][0], jb = nb[q][1];
+        if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+        int cb = ib * nmu + jb;
+        if (!(m->rho[cb] > 0.0)) continue;
+        if (reg[cb] == 1) {
+          if (comp[cb] < 0) { comp[cb] = c0; stack[top++] = cb; }
+        } else {
+          touches = 1;
+        }
+      }
+    }
+    if (!touches)
+      for (int q = 0; q < cnt; ++q) reg[members[q]] = 2;
+    free(members);
+  }
+  free(comp);
+  free(stack);
+}
+
+int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc, const uint8_t* region_in,
+            double* T_out, uint8_t* region_out, int max_sweeps, double tol, int* n_sweeps,
+            double* last_change) {
+  int nr = m->n_r, nmu = m->n_mu, n = nr * nmu;
+  for (int c = 0; c < n; ++c) region_out[c] = (region_in[c] && m->rho[c] > 0.0) ? 1 : 0;
+  pda_components(m, region_out);
+  /* floor for the initial guess: the smallest Dirichlet temperature */
+  double Tfloor = INFINITY;
+  for (int c = 0; c < n; ++c) {
+    if (region_out[c] != 1) continue;
+    int i = c / nmu, j = c % nmu;
+    int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    for (int q = 0; q < 4; ++q) {
+      int ib = nb[q][0], jb = nb[q][1];
+      if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+      int cb = ib * nmu + jb;
+      if (m->rho[cb] > 0.0 && region_out[cb] != 1 && T_mc[cb] < Tfloor) Tfloor = T_mc[cb];
+    }
+  }
+  if (!isfinite(Tfloor)) Tfloor = 0.0;
+  for (int c = 0; c < n; ++c)
+    T_out[c] = (region_out[c] == 1) ? fmax(T_mc[c], Tfloor) : T_mc[c];
+  pda_geom g;
+  pda_geom_init(m, &g);
+  double* u = (double*)malloc(sizeof(double) * n);
+  int sweeps = 0, rc = 0;
+  double change = 0.0;
+  for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
+    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, u);
+    if (rc) break;
+    change = 0.0;
+    for (int c = 0; c < n; ++c) {
+      if (region_out[c] != 1) continue;
+      double Tn = pow(fmax(u[c], 0.0), 0.25);
+      double ch = fabs(Tn - T_out[c]) / fmax(Tn, 1e-300);
+      if (ch > change) change = ch;
+      T_out[c] = Tn;
+    }
+    if (change < tol) break;
+  }
+  if (sweeps > max_sweeps) sweeps = max_sweeps;
+  *n_sweeps = sweeps;
+  *last_change = change;
+  free(u);
+  pda_geom_free(&g);
+  return rc;
+}
+
+int ora_pda_linear(const ora_model* m, const ora_tables* t, const double* T_D, const double* T_bc,
+                   const double* kscale, const uint8_t* region, double* T_out) {
+  int n = m->n_r * m->n_mu;
+  pda_geom g;
+  pda_geom_init(m, &g);
+  double* u = (double*)malloc(sizeof(double) * n);
+  int rc = pda_solve_once(m, t, &g, region, T_D, T_bc, kscale, u);
+  for (int c = 0; c < n; ++c) T_out[c] = region[c] == 1 ? pow(fmax(u[c], 0.0), 0.25) : T_bc[c];
+  free(u);
+  pda_geom_free(&g);
+  return rc;
+}

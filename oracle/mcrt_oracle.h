@@ -1,0 +1,116 @@
+/*
+ * CPU oracle for Monte Carlo radiative transfer in an axisymmetric dust disk
+ * with immediate reemission, the modified random walk (MRW) and the partial
+ * diffusion approximation (PDA), after Min et al. (2009).
+ *
+ * TEST INFRASTRUCTURE.  Plain, single-threaded, FP64 and deliberately slow.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * call it.  It shares no source with the HIP library; the two meet only in the
+ * input arrays a test builds from the seeded workload generator.
+ *
+ * Units: cgs.  Cell id = i_r * n_mu + j_mu; j_mu = 0 is the midplane row of the
+ * folded polar coordinate mu = |cos theta|.
+ */
+#ifndef MCRT_ORACLE_H
+#define MCRT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int n_r, n_mu, n_lambda;
+  const double* r_edges;       /* [n_r+1] */
+  const double* mu_edges;      /* [n_mu+1], 0 = midplane ... 1 = pole */
+  const double* rho;           /* [n_r*n_mu] dust density */
+  const double* lambda_edges;  /* [n_lambda+1] cm */
+  const double* kappa_abs;     /* [n_lambda] mixture absorption opacity, cm^2/g */
+  const double* kappa_sca;     /* [n_lambda] mixture scattering opacity */
+  double T_star, R_star;
+} ora_model;
+
+typedef struct {
+  int n_T;                     /* nodes; node 0 is T = 0 */
+  double T_lo, T_hi;           /* first non-zero node, last node */
+  double* T;                   /* [n_T] */
+  double* cdf;                 /* [n_T][n_lambda]  sum_{k'<=k} kappa_k' Bbar_k'(T_n) */
+  double* Drho;                /* [n_T]  D * rho of the diffusion coefficient */
+  double* kbar;                /* [n_T]  mean absorption opacity of an MRW step */
+  double* star_cdf;            /* [n_lambda] cumulative star spectrum, last = 1 */
+  double L_star;
+  int eta_iters_max;           /* largest eta fixed-point iteration count */
+} ora_tables;
+
+typedef struct {
+  int mrw;                     /* 0/1 */
+  double gamma;                /* MRW criterion */
+  int n_int_min;               /* interactions in the cell before MRW */
+  int n_inc;                   /* SED inclination bins */
+  long long max_events;        /* per-packet cap */
+  const double* frozen_T;      /* NULL: running (immediate reemission) mode */
+} ora_opts;
+
+typedef struct {
+  int32_t fate;                /* 1 escaped, 2 hit the star, 3 capped */
+  int32_t k;                   /* final wavelength bin */
+  int64_t n_cross, n_scat, n_abs, n_mrw, n_draws;
+  double x, y, z, u, v, w;     /* final position and direction */
+} ora_packet_rec;
+
+enum { ORA_C_ESCAPED = 0, ORA_C_STAR, ORA_C_CAPPED, ORA_C_CROSS, ORA_C_SCAT, ORA_C_ABS,
+       ORA_C_MRW, ORA_C_LAUNCH, ORA_N_COUNTERS };
+
+/* Philox4x32-10 (Salmon et al. 2011): in-place on ctr with the given key. */
+void ora_philox4x32_10(uint32_t ctr[4], const uint32_t key[2]);
+/* uniform doubles of packet `pid`, draws [d0, d0+n) of its stream */
+void ora_uniforms(uint64_t seed, uint64_t pid, uint64_t d0, int64_t n, double* out);
+
+/* Planck bin integrals at one temperature: Bbar[k] = int_bin B_nu dnu and
+ * dBbar[k] = int_bin dB_nu/dT dnu. */
+void ora_planck_bins(const double* lambda_edges, int n_lambda, double T, double* Bbar,
+                     double* dBbar);
+
+int ora_build_tables(const ora_model* m, ora_tables* t);   /* arrays preallocated */
+
+int64_t ora_locate(const ora_model* m, double x, double y, double z);
+
+/* T from absorbed power E of a cell of mass `mass` */
+double ora_T_of_E(const ora_model* m, const ora_tables* t, double E, double mass);
+
+/* reemission bin for an absorption that raised the cell from T_old to T_new
+ * (T_old < 0: full spectrum at T_new), xi in (0,1) */
+int ora_reemit_sample(const ora_model* m, const ora_tables* t, double T_old, double T_new,
+                      double xi);
+/* linear-in-T table value: which = 0 D*rho, 1 kappa-bar */
+double ora_table_interp(const ora_tables* t, int which, double T);
+
+/* MRW: solve P(s) = P0 for s = D c t / R0^2 */
+double ora_mrw_escape_s(double P0);
+double ora_mrw_survival(double s);
+
+int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o,
+            uint64_t n_packets, uint64_t n_total, uint64_t seed, uint64_t offset,
+            double* E_abs, uint32_t* visits, uint32_t* n_abs, uint32_t* n_mrw_cell,
+            double* sed, double* E_star, long long* counters, ora_packet_rec* recs,
+            int64_t n_recs);
+
+void ora_cell_volumes(const ora_model* m, double* V);
+void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T);
+
+/* PDA: region_in[c] = 1 marks candidate cells.  region_out: 1 solved, 2 left at
+ * the MC value (no Dirichlet neighbour), 0 outside. */
+int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc,
+            const uint8_t* region_in, double* T_out, uint8_t* region_out,
+            int max_sweeps, double tol, int* n_sweeps, double* last_change);
+
+/* One linear PDA solve with the diffusion coefficient frozen at T_D (the
+ * differentiation workload): u = T^4 on the region, Dirichlet T_bc outside. */
+int ora_pda_linear(const ora_model* m, const ora_tables* t, const double* T_D,
+                   const double* T_bc, const double* kscale, const uint8_t* region,
+                   double* T_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,298 @@
+"""Pins of the CPU oracle against facts fixed by the paper and the mathematics
+(closed forms, invariants, limits, brute force) -- not against itself.
+
+Each test names the passage of Min et al. (2009) it follows.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+from paper_0902_3092_amd import workloads as W
+
+SIGMA_SB = 5.670374419e-5
+H, KB, CL = 6.62607015e-27, 1.380649e-16, 2.99792458e10
+
+
+# ---------------------------------------------------------------- Planck bins
+@pytest.mark.parametrize("T", [10.0, 300.0, 3000.0])
+def test_planck_bins_stefan_boltzmann(oracle_mod, T):
+    """Sum of bin integrals over a range that holds the whole spectrum equals
+    sigma T^4 / pi, and of dB/dT equals 4 sigma T^3 / pi (closed forms)."""
+    lam = np.exp(np.linspace(math.log(1e-8), math.log(1e3), 801))  # 1e-4 um .. 10 m
+    B, dB = oracle_mod.planck_bins(lam, T)
+    assert B.sum() == pytest.approx(SIGMA_SB * T ** 4 / math.pi, rel=1e-9)
+    assert dB.sum() == pytest.approx(4 * SIGMA_SB * T ** 3 / math.pi, rel=1e-9)
+
+
+def test_planck_bins_limits(oracle_mod):
+    """Rayleigh-Jeans and Wien limits of one bin (closed forms)."""
+    T = 1000.0
+    lam = np.array([10.0, 20.0])  # cm: x ~ 1e-5, Rayleigh-Jeans
+    B, dB = oracle_mod.planck_bins(lam, T)
+    nu_a, nu_b = CL / 20.0, CL / 10.0
+    rj = 2 * KB * T / CL ** 2 * (nu_b ** 3 - nu_a ** 3) / 3
+    assert B[0] == pytest.approx(rj, rel=1e-4)
+    assert dB[0] == pytest.approx(rj / T, rel=1e-4)
+    lam = np.array([1e-6, 2e-6])  # 0.01-0.02 um at 1000 K: x ~ 700-1400, Wien
+    T = 30000.0
+    B, _ = oracle_mod.planck_bins(lam, T)
+    f = lambda nu: 2 * H * nu ** 3 / CL ** 2 * math.exp(-H * nu / (KB * T))
+    wien = integrate.quad(f, CL / 2e-6, CL / 1e-6, epsrel=1e-12)[0]
+    assert B[0] == pytest.approx(wien, rel=1e-6)
+
+
+# ------------------------------------------------------- diffusion tables
+def _random_albedo_disk(seed, n_lambda=60):
+    d = W.small_disk(n_lambda=n_lambda)
+    rng = np.random.default_rng(seed)
+    alb = rng.uniform(0.1, 0.8, n_lambda)
+    d.kappa_sca = d.kappa_abs * alb / (1 - alb)
+    return d
+
+
+@pytest.mark.parametrize("scattering", [True, False])
+def test_eta_fixed_point_closed_form(oracle_mod, scattering):
+    """Sect. 2.2.3: the eta iteration's fixed point is eta = A chi dB/dT, so
+    D = <d^2>/(6<d>) = 1/(3 rho chi_R) with the Rosseland mean of the total
+    extinction, and kappa-bar = int kappa dB/dT / int dB/dT.  Without
+    scattering D reduces to the Rosseland coefficient (eq:RossDiff)."""
+    d = _random_albedo_disk(7)
+    if not scattering:
+        d.kappa_sca = np.zeros_like(d.kappa_sca)
+    ora = oracle_mod.Oracle(d, n_T=40)
+    ka, ks = d.kappa_abs[0], d.kappa_sca[0]
+    chi = ka + ks
+    for n in range(1, 40, 3):
+        T = ora.T_nodes[n]
+        _, dB = oracle_mod.planck_bins(d.lambda_edges, T)
+        inv_chiR = (dB / chi).sum() / dB.sum()
+        kbar = (ka * dB).sum() / dB.sum()
+        assert ora.Drho[n] == pytest.approx(inv_chiR / 3.0, rel=1e-10)
+        assert ora.kbar[n] == pytest.approx(kbar, rel=1e-10)
+    if scattering:
+        assert ora.tables.eta_iters_max > 5   # the iteration really iterated
+
+
+# -------------------------------------------------- temperature inversion
+def test_T_inversion_vs_direct_planck(oracle_mod):
+    """Radiative equilibrium 4 pi m sum_k kappa_k Bbar_k(T) = E solved directly
+    (untabulated) agrees with the tabulated inversion to the table's
+    interpolation error, which shrinks ~ (dT/T)^2 with more nodes."""
+    d = W.small_disk(n_lambda=50)
+    ka = d.kappa_abs[0]
+    mass = 1.0e25
+    errs = {}
+    for nT in (64, 256):
+        ora = oracle_mod.Oracle(d, n_T=nT)
+        worst = 0.0
+        for T_true in (15.0, 73.3, 250.0, 999.0, 2222.0):
+            B, _ = oracle_mod.planck_bins(d.lambda_edges, T_true)
+            E = 4 * math.pi * mass * (ka * B).sum()
+            T = ora.T_of_E(E, mass)
+            worst = max(worst, abs(T / T_true - 1))
+        errs[nT] = worst
+    assert errs[256] < 2e-3
+    assert errs[256] < errs[64] / 8
+
+
+def test_T_inversion_exact_at_nodes(oracle_mod):
+    d = W.small_disk(n_lambda=30)
+    ora = oracle_mod.Oracle(d, n_T=64)
+    ka = d.kappa_abs[0]
+    mass = 3.0e24
+    for n in (1, 10, 33, 63):
+        T = ora.T_nodes[n]
+        B, _ = oracle_mod.planck_bins(d.lambda_edges, T)
+        E = 4 * math.pi * mass * (ka * B).sum()
+        assert ora.T_of_E(E, mass) == pytest.approx(T, rel=1e-12)
+    assert ora.T_of_E(0.0, mass) == 0.0
+
+
+def test_reemission_difference_spectrum(oracle_mod):
+    """Immediate reemission (Sect. 2.1, BW01): on an absorption raising the
+    cell from T_old to T_new the packet is re-emitted with probability
+    proportional to kappa_k [Bbar_k(T_new) - Bbar_k(T_old)].  Stratified draws
+    reproduce that distribution (computed directly from the Planck bins)."""
+    d = W.small_disk(n_lambda=40)
+    ora = oracle_mod.Oracle(d, n_T=64)
+    ka = d.kappa_abs[0]
+    N = 20000
+    xi = (np.arange(N) + 0.5) / N
+    for (n_old, n_new) in [(0, 30), (20, 21), (25, 40)]:
+        T_old, T_new = ora.T_nodes[n_old], ora.T_nodes[n_new]
+        Bo, _ = oracle_mod.planck_bins(d.lambda_edges, T_old)
+        Bn, _ = oracle_mod.planck_bins(d.lambda_edges, T_new)
+        p = ka * (Bn - Bo)
+        p /= p.sum()
+        ks = np.array([ora.reemit_sample(T_old, T_new, x) for x in xi])
+        hist = np.bincount(ks, minlength=len(ka)) / N
+        assert np.abs(hist - p).max() < 2.0 / N + 1e-9
+    # telescoping: a chain T_0=0 -> T_1 -> ... -> T_m of equal energy steps
+    # re-emits in total the full spectrum kappa_k Bbar_k(T_m)
+    Tn = ora.T_nodes
+    chain = [0.0] + [Tn[n] for n in (12, 18, 24, 30)]
+    Bm, _ = oracle_mod.planck_bins(d.lambda_edges, chain[-1])
+    full = ka * Bm
+    tot = np.zeros(len(ka))
+    for a, b in zip(chain[:-1], chain[1:]):
+        Ba, _ = oracle_mod.planck_bins(d.lambda_edges, a) if a > 0 else (np.zeros(len(ka)), 0)
+        Bb, _ = oracle_mod.planck_bins(d.lambda_edges, b)
+        w = (ka * (Bb - Ba)).sum()
+        ks = np.array([ora.reemit_sample(a, b, x) for x in xi[::4]])
+        tot += w * np.bincount(ks, minlength=len(ka)) / len(ks)
+    assert np.allclose(tot / full.sum(), full / full.sum(), atol=4 * 4.0 / N)
+
+
+# ------------------------------------------------------------- MRW law
+def test_escape_law_forms_and_moments(oracle_mod):
+    """eq:probability RW: P(s) = 2 sum (-1)^{n+1} exp(-n^2 pi^2 s) with
+    s = D c t / R0^2 decreases from 1 to 0; its theta-function form for small
+    s joins continuously; E[s] = 1/6 and Var[s] = 1/90 (integrating P)."""
+    P = oracle_mod.mrw_survival
+    assert P(1e-4) == pytest.approx(1.0, abs=1e-12)
+    s = np.linspace(0.002, 2.0, 400)
+    v = np.array([P(x) for x in s])
+    assert np.all(np.diff(v) < 0)
+    # direct alternating series with many terms, independent of the switch
+    direct = lambda x: 2 * sum((-1) ** (n + 1) * math.exp(-n * n * math.pi ** 2 * x)
+                               for n in range(1, 400))
+    for x in (0.05, 0.1 - 1e-9, 0.1, 0.1 + 1e-9, 0.3, 1.0):
+        assert P(x) == pytest.approx(direct(x), abs=1e-13)
+    m1 = integrate.quad(P, 0, 5, limit=200, epsabs=1e-14)[0]
+    m2 = integrate.quad(lambda x: 2 * x * P(x), 0, 5, limit=200, epsabs=1e-14)[0]
+    assert m1 == pytest.approx(1 / 6, abs=1e-11)
+    assert m2 - m1 ** 2 == pytest.approx(1 / 90, abs=1e-11)
+    for P0 in (1e-9, 0.01, 0.5, 0.9, 0.999999):
+        assert P(oracle_mod.mrw_escape_s(P0)) == pytest.approx(P0, rel=1e-10)
+
+
+def test_escape_law_vs_brownian_brute_force(oracle_mod):
+    """Fleck & Canfield's absorbing-sphere law, checked against explicit 3-D
+    Brownian motion from the centre of a unit sphere with D c = 1 (so s = t):
+    the empirical survival matches P(s) (Kolmogorov distance)."""
+    rng = np.random.default_rng(11)
+    n, dt = 20000, 2e-5
+    x = np.zeros((n, 3))
+    t_exit = np.full(n, np.nan)
+    alive = np.ones(n, bool)
+    t = 0.0
+    while alive.any() and t < 3.0:
+        idx = np.nonzero(alive)[0]
+        x[idx] += rng.normal(0.0, math.sqrt(2 * dt), (len(idx), 3))
+        t += dt
+        out = idx[(x[idx] ** 2).sum(1) >= 1.0]
+        t_exit[out] = t
+        alive[out] = False
+    ts = np.sort(t_exit[~np.isnan(t_exit)])
+    emp = np.arange(1, len(ts) + 1) / n
+    model = np.array([1 - oracle_mod.mrw_survival(s) for s in ts])
+    assert np.abs(emp - model).max() < 0.02
+    assert ts.mean() == pytest.approx(1 / 6, rel=0.03)
+
+
+@pytest.mark.parametrize("tau0", [10.0, 30.0])
+def test_mrw_mean_path_vs_photon_random_walk(oracle_mod, tau0):
+    """The MRW mean path to leave a sphere of radius R0 is R0^2/(6D) = tau0^2
+    lambda/2 for D = lambda/3 (eq:diffusion coeff with <d>=lambda,
+    <d^2>=2 lambda^2).  An explicit photon random walk (exponential flights,
+    isotropic) takes slightly longer, by O(1/tau0): the underestimate the paper
+    reports for small spheres (Sect. 3.2)."""
+    rng = np.random.default_rng(int(tau0))
+    n = 6000
+    pos = np.zeros((n, 3))
+    path = np.zeros(n)
+    alive = np.ones(n, bool)
+    while alive.any():
+        idx = np.nonzero(alive)[0]
+        m = len(idx)
+        w = rng.uniform(-1, 1, m)
+        ph = rng.uniform(0, 2 * math.pi, m)
+        st = np.sqrt(1 - w * w)
+        d = np.stack([st * np.cos(ph), st * np.sin(ph), w], 1)
+        L = rng.exponential(1.0, m)
+        p = pos[idx]
+        b = (p * d).sum(1)
+        c = (p * p).sum(1) - tau0 ** 2
+        s_exit = -b + np.sqrt(b * b - c)
+        leave = L >= s_exit
+        path[idx] += np.where(leave, s_exit, L)
+        pos[idx] = p + np.where(leave, s_exit, L)[:, None] * d
+        alive[idx[leave]] = False
+    s_mrw = np.array([oracle_mod.mrw_escape_s(P0) for P0 in (np.arange(4000) + 0.5) / 4000])
+    mean_mrw = s_mrw.mean() * tau0 ** 2 / (1.0 / 3.0)     # s R0^2 / D, lambda = 1
+    assert mean_mrw == pytest.approx(tau0 ** 2 / 2, rel=2e-3)
+    excess = path.mean() / mean_mrw - 1
+    assert 0.0 < excess < 3.0 / tau0
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_stream_statistics(oracle_mod):
+    """Counter-based streams: uniform in (0,1), uncorrelated between packets
+    and between consecutive draws."""
+    u = np.concatenate([oracle_mod.uniforms(123, pid, 0, 2000) for pid in range(200)])
+    assert u.min() > 0 and u.max() < 1
+    assert u.mean() == pytest.approx(0.5, abs=4 * math.sqrt(1 / 12 / len(u)))
+    assert u.var() == pytest.approx(1 / 12, rel=0.01)
+    h = np.bincount((u * 100).astype(int), minlength=100)
+    chi2 = ((h - len(u) / 100) ** 2 / (len(u) / 100)).sum()
+    assert chi2 < 99 + 5 * math.sqrt(2 * 99)
+    c1 = np.corrcoef(u[:-1], u[1:])[0, 1]
+    assert abs(c1) < 5 / math.sqrt(len(u))
+    a = oracle_mod.uniforms(123, 7, 0, 50000)
+    b = oracle_mod.uniforms(123, 8, 0, 50000)
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / math.sqrt(50000)
+    c = oracle_mod.uniforms(124, 7, 0, 50000)
+    assert abs(np.corrcoef(a, c)[0, 1]) < 5 / math.sqrt(50000)
+    # offsets continue the same stream
+    assert np.array_equal(oracle_mod.uniforms(5, 9, 3, 10), oracle_mod.uniforms(5, 9, 0, 13)[3:])
+
+
+def test_philox_round_is_a_bijection_sample(oracle_mod):
+    """Philox with a fixed key is a permutation of 128-bit counters: distinct
+    counters give distinct outputs; flipping one counter bit changes about
+    half of the output bits (avalanche)."""
+    key = np.array([0x12345678, 0x9abcdef0], np.uint32)
+    outs = set()
+    flips = []
+    for i in range(3000):
+        ctr = np.array([i, 0, 0, 0], np.uint32)
+        o = oracle_mod.philox4x32_10(ctr, key)
+        outs.add(tuple(int(v) for v in o))
+        ctr2 = ctr.copy()
+        ctr2[2] ^= np.uint32(1 << (i % 32))
+        o2 = oracle_mod.philox4x32_10(ctr2, key)
+        flips.append(sum(bin(int(x) ^ int(y)).count("1") for x, y in zip(o, o2)))
+    assert len(outs) == 3000
+    assert np.mean(flips) == pytest.approx(64, abs=1.5)
+
+
+# ---------------------------------------------------------------- locate
+def test_locate_vs_brute_force(oracle_mod):
+    d = W.small_disk(n_r=9, n_mu=7)
+    ora = oracle_mod.Oracle(d)
+    rng = np.random.default_rng(3)
+    n = 4000
+    r = np.exp(rng.uniform(np.log(d.r_edges[0] * 0.5), np.log(d.r_edges[-1] * 1.5), n))
+    mu = rng.uniform(-1, 1, n)
+    ph = rng.uniform(0, 2 * np.pi, n)
+    st = np.sqrt(1 - mu ** 2)
+    xyz = np.stack([r * st * np.cos(ph), r * st * np.sin(ph), r * mu], 1)
+    got = ora.locate(xyz)
+    rr = np.sqrt((xyz ** 2).sum(1))
+    am = np.abs(xyz[:, 2]) / rr
+    i = np.searchsorted(d.r_edges, rr, side="right") - 1
+    j = np.searchsorted(d.mu_edges, am, side="right") - 1
+    j = np.minimum(j, d.n_mu - 1)
+    want = np.where((rr >= d.r_edges[0]) & (rr < d.r_edges[-1]), i * d.n_mu + j, -1)
+    # away from faces the two must agree exactly
+    far = (np.min(np.abs(rr[:, None] / d.r_edges[None, :] - 1), 1) > 1e-9) & \
+          (np.min(np.abs(am[:, None] - d.mu_edges[None, :]), 1) > 1e-9)
+    assert far.sum() > 3900
+    assert np.array_equal(got[far], want[far])
+    # exactly on a sphere: the cell outside it (half-open); on the outer edge: outside
+    for e in range(d.n_r):
+        assert ora.locate([[d.r_edges[e], 0, 0]])[0] == e * d.n_mu + 0
+    assert ora.locate([[d.r_edges[-1], 0, 0]])[0] == -1
+    assert ora.locate([[0, 0, d.r_edges[2] * 1.01]])[0] == 2 * d.n_mu + d.n_mu - 1
