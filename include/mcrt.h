@@ -1,0 +1,199 @@
+/*
+ * mcrt -- Monte Carlo radiative transfer in axisymmetric dust disks on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is that of Min, Dullemond, Dominik, de Koter & Hovenier (2009),
+ * "Radiative transfer in very optically thick circumstellar disks":
+ * photon packets from the star are traced through an (r, theta) dust grid
+ * with immediate reemission (Sect. 2.1, after Bjorkman & Wood 2001), the
+ * modified random walk accelerates packets caught in optically thick cells
+ * (Sect. 2.2.2, eqs. RW .. criterion, with the diffusion coefficient of
+ * Sect. 2.2.3), and the partial diffusion approximation (Sect. 2.2.1,
+ * eq. T diffusion) replaces the temperature of cells with few photons.
+ *
+ * Conventions for every entry point
+ *  - Units are cgs.  Cell id = i_r * n_mu + j_mu; j_mu = 0 is the midplane row
+ *    of the folded polar coordinate mu = |cos theta| (both hemispheres belong
+ *    to one cell).
+ *  - Descriptor structs and the host arrays they point to are read during the
+ *    call only and may be freed afterwards (the library copies them).
+ *  - Pointers named *_dev are device memory owned by the caller; the library
+ *    never frees them.  Calls are asynchronous on the given stream unless
+ *    stated; results are valid after the stream has been synchronised.
+ *  - The context owns its device state (tallies, tables, solver scratch); it
+ *    is released by mcrt_destroy.  A context may be used from one host thread
+ *    at a time; calls on one context must be issued on one stream (or be
+ *    ordered by the caller).
+ *  - Return value: MCRT_OK (0) or a negative MCRT_E_* code; nothing aborts.
+ *    mcrt_strerror() describes a code; mcrt_last_error() gives the text of
+ *    the last failure on the calling thread.
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCRT_OK 0
+#define MCRT_E_ARG (-1)             /* invalid argument or descriptor */
+#define MCRT_E_OOM (-2)             /* device allocation failed */
+#define MCRT_E_HIP (-3)             /* a HIP runtime call failed */
+#define MCRT_E_NOT_CONVERGED (-4)   /* PDA solver hit its iteration cap */
+#define MCRT_E_STUCK (-5)           /* packets hit the per-packet event cap */
+#define MCRT_E_SINGULAR_REGION (-6) /* a PDA region part has no Dirichlet neighbour (solved
+                                       without it: informational) */
+
+#define MCRT_FP64 0                 /* tracking, tallies and inversion in FP64 */
+#define MCRT_FP32 1                 /* packet geometry in FP32 cell-relative coordinates;
+                                       tallies, inversion and PDA in FP64 */
+
+typedef struct mcrt_ctx mcrt_ctx;
+
+/* Folded spherical grid.  r_edges[n_r+1] strictly increasing (the inner
+ * radius r_edges[0] bounds an empty hole around the star);
+ * mu_edges[n_mu+1] strictly increasing from 0 (midplane) to 1 (pole). */
+typedef struct {
+  int32_t n_r, n_mu;
+  const double* r_edges;
+  const double* mu_edges;
+} mcrt_grid;
+
+/* The star: a uniform-brightness sphere radiating as a blackbody
+ * (L = 4 pi R^2 sigma T^4), centred at the origin, R_star < r_edges[0]. */
+typedef struct {
+  double T_star, R_star;
+} mcrt_star;
+
+/* Dust: n_species grain types in fixed mass fractions (the same mixture in
+ * every cell).  Opacities are constant within each wavelength bin;
+ * lambda_edges[n_lambda+1] in cm, strictly increasing.  kappa_abs and
+ * kappa_sca are [n_species][n_lambda] mass absorption / isotropic scattering
+ * coefficients in cm^2/g. */
+typedef struct {
+  int32_t n_lambda, n_species;
+  const double* lambda_edges;
+  const double* kappa_abs;
+  const double* kappa_sca;
+  const double* mass_frac;
+} mcrt_dust;
+
+/* Run options (mcrt_default_options fills the defaults noted). */
+typedef struct {
+  int32_t precision;     /* MCRT_FP64 (default) or MCRT_FP32 */
+  int32_t mrw;           /* 1: modified random walk on (default 0) */
+  double gamma;          /* MRW start: d_min > gamma / (rho chi_R)  (default 3) */
+  int32_t n_int_min;     /* interactions since entering the cell before MRW (20) */
+  int32_t n_T;           /* temperature-table nodes, node 0 = 0 K (256) */
+  double T_lo, T_hi;     /* first non-zero and last node, K (1, 1e4) */
+  int32_t n_inc;         /* SED bins in |cos i| (10) */
+  int64_t max_events;    /* per-packet event cap (2^30) */
+  int32_t pda_visits;    /* PDA region: cells with fewer packet entries (100) */
+  int32_t pda_max_sweeps;/* Picard sweeps on D(T) (50) */
+  double pda_tol;        /* Picard stop: max |dT/T| (1e-8) */
+  int32_t cg_max_iter;   /* per solve (20000) */
+  double cg_tol;         /* preconditioned relative residual (1e-12) */
+  int32_t mrw_coef_T;    /* 0: MRW uses the running cell T; 1: the T of the
+                            previous pass (set by mcrt_update_T) (0) */
+  int32_t block_size;    /* trace workgroup size, 0 = library choice */
+  int32_t blocks_per_cu; /* trace workgroups per compute unit, 0 = library choice */
+} mcrt_options;
+
+void mcrt_default_options(mcrt_options* opt);
+
+/* Create a context on the current HIP device: copies the grid, star, dust and
+ * the per-cell dust density rho[n_r*n_mu] (host, g/cm^3), and builds the FP64
+ * tables of Sect. 2.2.3 (Planck bin integrals, emission CDF, diffusion
+ * coefficient and mean absorption opacity of the MRW).  Synchronous. */
+int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
+               const mcrt_dust* dust, const double* rho, const mcrt_options* opt);
+void mcrt_destroy(mcrt_ctx* ctx);
+
+/* Zero the absorbed-energy, visit, absorption, MRW, SED and event tallies. */
+int mcrt_reset(mcrt_ctx* ctx, hipStream_t stream);
+
+/* Trace packets [offset, offset + n_packets) of a run of n_total packets,
+ * each carrying L_star / n_total (Sect. 2.1).  Packet p draws its random
+ * numbers from Philox4x32-10 keyed by seed, counter (p, draw index).
+ * Absorptions re-emit immediately from the difference of the cell's emission
+ * spectrum before and after the absorption; with mrw=1 packets in optically
+ * thick cells take modified-random-walk steps (Sect. 2.2.2).  Tallies add to
+ * the context's.  frozen_T_dev (nullable, [n_cells] K): re-emit from the
+ * full spectrum at these fixed temperatures instead (no coupling between
+ * packets; a test mode).  rec_dev (nullable): mcrt_packet_rec for packets
+ * [offset, offset + n_recs).  Returns MCRT_E_STUCK after the stream has
+ * drained if any packet hit max_events (synchronous in that case only when
+ * check_stuck != 0). */
+typedef struct {
+  int32_t fate;                    /* 1 escaped, 2 hit the star, 3 capped */
+  int32_t k;                       /* final wavelength bin */
+  int64_t n_cross, n_scat, n_abs, n_mrw, n_draws;
+  double x, y, z, u, v, w;         /* final position and direction */
+} mcrt_packet_rec;
+
+int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
+               uint64_t offset, const double* frozen_T_dev, mcrt_packet_rec* rec_dev,
+               int64_t n_recs, hipStream_t stream);
+
+/* Radiative equilibrium per cell: 4 pi m_i G(T_i) = E_i with G the emission
+ * per unit mass and steradian, linear in T between table nodes.  Updates the
+ * context's T and, if T_dev != NULL, copies it there ([n_cells] double). */
+int mcrt_update_T(mcrt_ctx* ctx, double* T_dev, hipStream_t stream);
+
+/* Partial diffusion approximation (Sect. 2.2.1): solve div(D grad T^4) = 0
+ * on the region (mask_dev[c] = 1; NULL: cells with fewer than pda_visits
+ * entries), Dirichlet T from the Monte Carlo temperature of the neighbouring
+ * cells, D = 1/(3 rho chi_R) with chi_R the Rosseland mean of the total
+ * extinction (the diffusion coefficient of Sect. 2.2.3 with isotropic
+ * scattering), Picard iteration on D(T), Jacobi-preconditioned CG.  Updates
+ * the context's T.  stats (host, nullable) receives sweeps, CG iterations and
+ * residuals; waits for the stream. */
+typedef struct {
+  int32_t sweeps, cg_iters_total, cg_iters_last, n_region, n_isolated;
+  double last_change, last_residual;
+} mcrt_pda_stats;
+
+int mcrt_pda_solve(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats,
+                   hipStream_t stream);
+
+/* Escaped luminosity per wavelength bin and |cos i| bin: sed_dev
+ * [n_lambda][n_inc] double, erg/s (not divided by the solid angle). */
+int mcrt_sed(mcrt_ctx* ctx, double* sed_dev, hipStream_t stream);
+
+/* Cell of each point: xyz_dev [n][3] double, cell_dev [n] int32 (-1 outside
+ * the grid).  r^2 = (x*x + y*y) + z*z and z*z against mu_e^2 r^2, no fused
+ * multiply-add, half-open cells [r_e, r_e+1) x [mu_e, mu_e+1). */
+int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_dev,
+                hipStream_t stream);
+
+#define MCRT_GET_E_ABS 0    /* double [n_cells], erg/s absorbed */
+#define MCRT_GET_VISITS 1   /* uint32 [n_cells], packet entries */
+#define MCRT_GET_N_ABS 2    /* uint32 [n_cells], absorption events */
+#define MCRT_GET_N_MRW 3    /* uint32 [n_cells], MRW steps */
+#define MCRT_GET_T 4        /* double [n_cells], K */
+#define MCRT_GET_REGION 5   /* uint8 [n_cells]: 1 PDA-solved, 2 isolated, 0 outside */
+#define MCRT_GET_COUNTERS 6 /* uint64 [8]: escaped, star, capped, crossings,
+                               scatterings, absorptions, MRW steps, launches */
+#define MCRT_GET_E_STAR 7   /* double [1], erg/s absorbed by the star */
+#define MCRT_GET_TABLES 8   /* double: T nodes [n_T], cdf [n_T][n_lambda], D*rho [n_T],
+                               kappa-bar [n_T], star cdf [n_lambda], L_star [1] */
+
+/* Copy a context array into caller device memory (async, device to device). */
+int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream);
+/* Size in bytes of what mcrt_get(what) writes. */
+int64_t mcrt_get_size(mcrt_ctx* ctx, int what);
+
+/* Overwrite the context's temperature (e.g. with a PDA result or a test
+ * field): T_dev [n_cells] double. */
+int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
+
+const char* mcrt_strerror(int code);
+const char* mcrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -45,8 +45,8 @@ void ora_philox4x32_10(uint32_t ctr[4], const uint32_t key_in[2]) {
 }
 
 /* One packet's stream: draw d uses counter (pid_lo, pid_hi, d/2, 0) and the
- * 64-bit word (out[2h] << 32 | out[2h+1]) with h = d % 2; the top 53 bits
- * become a double strictly inside (0, 1). */
+ * 64-bit word (out[2h] << 32 | out[2h+1]) with h = d % 2; its top 52 bits x
+ * give (x + 1/2) / 2^52, a double strictly inside (0, 1). */
 typedef struct {
   uint32_t key[2];
   uint64_t pid;
@@ -56,7 +56,7 @@ typedef struct {
 
 static double u64_to_unit(uint32_t a, uint32_t b) {
   uint64_t x = ((uint64_t)a << 32) | (uint64_t)b;
-  return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  return ((double)(x >> 12) + 0.5) * (1.0 / 4503599627370496.0);
 }
 
 static double rng_next(rng_t* r) {

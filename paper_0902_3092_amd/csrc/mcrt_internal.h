@@ -1,0 +1,106 @@
+// Internal declarations of the mcrt library: the context, the device-side
+// parameter blocks and the kernel launchers.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "mcrt.h"
+
+namespace mcrt {
+
+// Counters, in the order of MCRT_GET_COUNTERS.
+enum { C_ESCAPED = 0, C_STAR, C_CAPPED, C_CROSS, C_SCAT, C_ABS, C_MRW, C_LAUNCH, N_COUNTERS };
+
+// Nodes of the MRW escape-time table: s as a function of v = ln(-ln P0).
+constexpr int MRW_TAB_N = 512;
+constexpr double MRW_TAB_V0 = -38.0;
+constexpr double MRW_TAB_V1 = 4.0;
+
+// Read-only model data on the device (FP64).
+struct DevModel {
+  int n_r, n_mu, n_lambda, n_T, n_inc;
+  const double* r_edges;   // [n_r+1]
+  const double* r2;        // [n_r+1] r_e * r_e
+  const double* mu_edges;  // [n_mu+1]
+  const double* mu2;       // [n_mu+1] mu_e * mu_e
+  const double* smu;       // [n_mu+1] sqrt(1 - mu_e^2)
+  const double* rho;       // [n_cells]
+  const double* inv4pim;   // [n_cells] 1 / (4 pi m), 0 for empty cells
+  const double* Tn;        // [n_T] table nodes
+  const double* cdf;       // [n_T][n_lambda] cumulative kappa_k Bbar_k(T_n)
+  const double* G;         // [n_T] cdf[n][n_lambda-1]
+  const double* Drho;      // [n_T] D * rho
+  const double* kbar;      // [n_T] mean absorption opacity of an MRW step
+  const double* star_cdf;  // [n_lambda]
+  const double* chi;       // [n_lambda] extinction per mass
+  const double* omega;     // [n_lambda] albedo
+  const double* mrw_tab;   // [MRW_TAB_N] s at nodes of v
+  const float* cdf32;      // [n_T][n_lambda] FP32 copy
+  const float* star_cdf32; // [n_lambda]
+  const float* chi32;      // [n_lambda]
+  const float* omega32;    // [n_lambda]
+  double R_star, L_star;
+};
+
+// Mutable per-run tallies.
+struct DevTally {
+  double* E_abs;               // [n_cells]
+  uint32_t* visits;            // [n_cells]
+  uint32_t* n_abs;             // [n_cells]
+  uint32_t* n_mrw;             // [n_cells]
+  double* sed;                 // [n_lambda][n_inc]
+  double* E_star;              // [1]
+  unsigned long long* counters;// [N_COUNTERS]
+};
+
+struct TraceArgs {
+  DevModel m;
+  DevTally t;
+  double eps;                  // L_star / n_total
+  uint32_t key0, key1;
+  uint64_t offset, n_packets;
+  unsigned long long* next;    // work counter, zeroed before the launch
+  int mrw, n_int_min;
+  double gamma;
+  long long max_events;
+  const double* frozen_T;      // nullable
+  const double* T_coef;        // nullable: fixed T for the MRW coefficients
+  mcrt_packet_rec* recs;       // nullable
+  int64_t n_recs;
+};
+
+}  // namespace mcrt
+
+struct mcrt_ctx {
+  int device = 0;
+  int n_cu = 0;
+  mcrt_options opt;
+  int n_r = 0, n_mu = 0, n_lambda = 0, n_cells = 0;
+  double L_star = 0.0;
+  mcrt::DevModel m{};
+  mcrt::DevTally t{};
+  // owned device allocations
+  double* d_T = nullptr;        // current temperature
+  double* d_T_prev = nullptr;   // temperature of the previous pass (MRW coefficients)
+  uint8_t* d_region = nullptr;
+  unsigned long long* d_next = nullptr;
+  void* d_blob = nullptr;       // model + tables
+  void* d_tally_blob = nullptr;
+  void* d_pda_blob = nullptr;   // PDA solver scratch
+  size_t pda_bytes = 0;
+  bool have_T_prev = false;
+  // host copies
+  std::string err;
+};
+
+namespace mcrt {
+int launch_trace(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
+int launch_locate(mcrt_ctx* ctx, const double* xyz, int64_t n, int32_t* cell, hipStream_t s);
+int launch_update_T(mcrt_ctx* ctx, hipStream_t s);
+int launch_zero(void* p, size_t bytes, hipStream_t s);
+int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s);
+void set_error(mcrt_ctx* ctx, const std::string& msg);
+}  // namespace mcrt

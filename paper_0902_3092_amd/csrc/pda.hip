@@ -1,0 +1,600 @@
+// Temperature update and the partial diffusion approximation on gfx950.
+//
+// update_T: one thread per cell inverts 4 pi m G(T) = E (G linear in T
+// between table nodes), FP64.
+//
+// PDA (Sect. 2.2.1, eq. T diffusion): div(D grad u) = 0, u = T^4, on the
+// low-photon region with Dirichlet u from the Monte Carlo T of neighbouring
+// cells.  Finite volumes on the (r, mu) cells: the conductance of a face is
+// A_f D_f / dist_f with the harmonic mean D_f of the two cells' D = D*rho(T)/rho
+// (the diffusion coefficient of Sect. 2.2.3); faces toward the grid edges,
+// the pole, the folded midplane and dust-free cells carry no flux.  The
+// symmetric 5-point operator is stored as diag + east (i+1) + north (j+1)
+// conductances over the whole grid (zero outside the region).  Jacobi-
+// preconditioned CG runs two fused streaming kernels per iteration with all
+// scalars on the device:
+//   K1: p <- z + beta p (z = r/diag, recomputed at the neighbours as well),
+//       q = A p, partial p.q
+//   K2: alpha = rz/pq, x += alpha p, r -= alpha q, partial r.z; the last
+//       workgroup forms beta and the convergence flag.
+// Algorithmic traffic per unknown and iteration: K1 reads diag, east, north,
+// r, p (neighbour values come from cache) and writes p, q; K2 reads diag,
+// x, p, q, r and writes x, r: 15 doubles = 120 bytes.
+// Picard sweeps on D(T) wrap the solve.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mcrt_internal.h"
+
+namespace mcrt {
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int BS = 256;
+
+__device__ inline int seg_of_g(const double* x, int n, double v) {
+  if (v >= x[n - 1]) return n - 2;
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (x[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline double T_from_g(const double* G, const double* Tn, int n_T, double g) {
+  if (g <= 0.0) return 0.0;
+  int n = seg_of_g(G, n_T, g);
+  return Tn[n] + (g - G[n]) / (G[n + 1] - G[n]) * (Tn[n + 1] - Tn[n]);
+}
+
+__device__ inline double table_at(const double* Tn, int n_T, const double* tab, double T) {
+  int n = seg_of_g(Tn, n_T, T);
+  double f = (T - Tn[n]) / (Tn[n + 1] - Tn[n]);
+  return tab[n] + f * (tab[n + 1] - tab[n]);
+}
+
+__global__ void update_T_kernel(DevModel M, const double* E, double* T, int nc) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  T[c] = T_from_g(M.G, M.Tn, M.n_T, E[c] * M.inv4pim[c]);
+}
+
+__global__ void fill_kernel(uint32_t* p, size_t n_words) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; t < n_words; t += stride) p[t] = 0u;
+}
+
+// ------------------------------------------------------------------ PDA
+struct PdaScalars {
+  double rz, rz_new, pq, rz_ref;
+  double beta;
+  unsigned int ticket;
+  int done;
+  int iter;
+  int pad;
+  unsigned long long floor_bits;   // min Dirichlet T (bits of a non-negative double)
+  unsigned long long change_bits;  // max |dT/T| of a Picard sweep
+  int n_region, n_isolated;
+  int changed;                     // component propagation
+  int pad2;
+};
+
+struct PdaArrays {
+  uint8_t* region;
+  uint8_t* touch;
+  double *Tw, *Tbc, *diag, *aE, *aN, *b, *x, *r, *p0, *p1, *q;
+  PdaScalars* sc;
+};
+
+__device__ inline bool in_grid(int i, int j, int n_r, int n_mu) {
+  return i >= 0 && i < n_r && j >= 0 && j < n_mu;
+}
+
+__global__ void pda_region_kernel(DevModel M, const uint8_t* mask, const uint32_t* visits,
+                                  int thr, PdaArrays P) {
+  int nc = M.n_r * M.n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  bool in = M.rho[c] > 0.0 && (mask ? mask[c] != 0 : visits[c] < (uint32_t)thr);
+  P.region[c] = in ? 1 : 0;
+}
+
+// touch = region cell with a dust-bearing non-region neighbour
+__global__ void pda_touch_kernel(DevModel M, PdaArrays P) {
+  int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  uint8_t t = 0;
+  if (P.region[c] == 1) {
+    int i = c / n_mu, j = c - i * n_mu;
+    const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    for (int q = 0; q < 4; ++q) {
+      int ib = i + di[q], jb = j + dj[q];
+      if (!in_grid(ib, jb, n_r, n_mu)) continue;
+      int cb = ib * n_mu + jb;
+      if (M.rho[cb] > 0.0 && P.region[cb] != 1) t = 1;
+    }
+    atomicAdd(&P.sc->n_region, 1);
+  }
+  P.touch[c] = t;
+}
+
+// Spread "touches Dirichlet" through connected region cells by alternating
+// row and column scans (each thread one line, forward and backward), in one
+// workgroup, until nothing changes; unreached region cells become 2.
+__global__ void pda_components_kernel(DevModel M, PdaArrays P) {
+  const int n_r = M.n_r, n_mu = M.n_mu;
+  __shared__ int changed;
+  for (int round = 0; round < 100000; ++round) {
+    if (threadIdx.x == 0) changed = 0;
+    __syncthreads();
+    int local = 0;
+    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {  // rows: fixed i, along j
+      uint8_t carry = 0;
+      for (int j = 0; j < n_mu; ++j) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+      carry = 0;
+      for (int j = n_mu - 1; j >= 0; --j) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n_mu; j += blockDim.x) {  // columns: fixed j, along i
+      uint8_t carry = 0;
+      for (int i = 0; i < n_r; ++i) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+      carry = 0;
+      for (int i = n_r - 1; i >= 0; --i) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+    }
+    if (local) atomicOr(&changed, 1);
+    __syncthreads();
+    int ch = changed;
+    __syncthreads();
+    if (!ch) break;
+  }
+  int n_iso = 0;
+  for (int c = threadIdx.x; c < n_r * n_mu; c += blockDim.x) {
+    if (P.region[c] == 1 && !P.touch[c]) {
+      P.region[c] = 2;
+      ++n_iso;
+    }
+  }
+  if (n_iso) atomicAdd(&P.sc->n_isolated, n_iso);
+}
+
+__global__ void pda_floor_kernel(DevModel M, const double* T_mc, PdaArrays P) {
+  int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc || P.region[c] != 1) return;
+  int i = c / n_mu, j = c - i * n_mu;
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  double m = INFINITY;
+  for (int q = 0; q < 4; ++q) {
+    int ib = i + di[q], jb = j + dj[q];
+    if (!in_grid(ib, jb, n_r, n_mu)) continue;
+    int cb = ib * n_mu + jb;
+    if (M.rho[cb] > 0.0 && P.region[cb] != 1) m = fmin(m, T_mc[cb]);
+  }
+  if (m < INFINITY) atomicMin(&P.sc->floor_bits, (unsigned long long)__double_as_longlong(m));
+}
+
+// full = 1: everything (region counts, floor = +inf); 0: the CG and Picard scalars only
+__global__ void pda_reset_scalars_kernel(PdaScalars* S, int full) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  S->rz = S->rz_new = S->pq = S->rz_ref = S->beta = 0.0;
+  S->ticket = 0;
+  S->done = 0;
+  S->iter = 0;
+  S->change_bits = 0ull;
+  if (full) {
+    S->floor_bits = 0x7FF0000000000000ull;
+    S->n_region = S->n_isolated = 0;
+    S->changed = 0;
+  }
+}
+
+__global__ void pda_init_T_kernel(DevModel M, const double* T_mc, PdaArrays P) {
+  int nc = M.n_r * M.n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double fl = __longlong_as_double((long long)P.sc->floor_bits);
+  if (!(fl < INFINITY)) fl = 0.0;
+  double t = T_mc[c];
+  P.Tbc[c] = t;
+  P.Tw[c] = (P.region[c] == 1) ? fmax(t, fl) : t;
+}
+
+// face conductance A_f D_f / dist_f between cell a=(i,j) and its neighbour b
+struct PdaGeom {
+  const double* rc;   // [n_r] (r_i + r_i+1)/2
+  const double* thc;  // [n_mu] (acos mu_j + acos mu_j+1)/2
+  const double* Ar;   // [n_r][n_mu] area of sphere r_{i+1} over the cell's mu range
+  const double* Amu;  // [n_r][n_mu] area of cone mu_{j+1} over the cell's r range
+  const double* kscale;  // nullable per-cell extinction scale
+};
+
+__device__ inline double Dcell(const DevModel& M, const PdaGeom& g, const double* Tw, int c) {
+  double ks = g.kscale ? g.kscale[c] : 1.0;
+  return table_at(M.Tn, M.n_T, M.Drho, Tw[c]) / (M.rho[c] * ks);
+}
+
+__global__ void pda_assemble_kernel(DevModel M, PdaGeom g, PdaArrays P) {
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  if (P.region[c] != 1) {
+    P.diag[c] = 1.0;
+    P.aE[c] = 0.0;
+    P.aN[c] = 0.0;
+    P.b[c] = 0.0;
+    return;
+  }
+  const int i = c / n_mu, j = c - i * n_mu;
+  const double Da = Dcell(M, g, P.Tw, c);
+  double diag = 0.0, rhs = 0.0, aE = 0.0, aN = 0.0;
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  for (int q = 0; q < 4; ++q) {
+    int ib = i + di[q], jb = j + dj[q];
+    if (!in_grid(ib, jb, n_r, n_mu)) continue;
+    int cb = ib * n_mu + jb;
+    if (!(M.rho[cb] > 0.0)) continue;
+    double Db = Dcell(M, g, P.Tw, cb);
+    double A, dist;
+    if (q < 2) {
+      int ilo = i < ib ? i : ib;
+      A = g.Ar[ilo * n_mu + j];
+      dist = fabs(g.rc[ib] - g.rc[i]);
+    } else {
+      int jlo = j < jb ? j : jb;
+      A = g.Amu[i * n_mu + jlo];
+      dist = g.rc[i] * fabs(g.thc[jb] - g.thc[j]);
+    }
+    double a = A * (2.0 * Da * Db / (Da + Db)) / dist;
+    diag += a;
+    if (P.region[cb] == 1) {
+      if (q == 1) aE = a;
+      if (q == 3) aN = a;
+    } else {
+      double t = P.Tbc[cb];
+      double t2 = t * t;
+      rhs += a * (t2 * t2);
+    }
+  }
+  P.diag[c] = diag;
+  P.aE[c] = aE;
+  P.aN[c] = aN;
+  P.b[c] = rhs;
+}
+
+__device__ inline double block_sum(double v) {
+  __shared__ double red[BS / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+  return s;  // valid in thread 0
+}
+
+// (A v)_c for region cells (v zero outside the region)
+__device__ inline double apply_A(const PdaArrays& P, const double* v, int c, int i, int j, int n_r,
+                                 int n_mu) {
+  double y = P.diag[c] * v[c];
+  if (i + 1 < n_r) y -= P.aE[c] * v[c + n_mu];
+  if (i > 0) y -= P.aE[c - n_mu] * v[c - n_mu];
+  if (j + 1 < n_mu) y -= P.aN[c] * v[c + 1];
+  if (j > 0) y -= P.aN[c - 1] * v[c - 1];
+  return y;
+}
+
+// r = b - A x, z = r / diag, p = z; partial r.z and b.(b/diag)
+__global__ void pcg_start_kernel(int n_r, int n_mu, PdaArrays P) {
+  int nc = n_r * n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double rz = 0.0, bb = 0.0;
+  if (c < nc) {
+    if (P.region[c] == 1) {
+      int i = c / n_mu, j = c - i * n_mu;
+      double r = P.b[c] - apply_A(P, P.x, c, i, j, n_r, n_mu);
+      P.r[c] = r;
+      rz = r * r / P.diag[c];
+      bb = P.b[c] * P.b[c] / P.diag[c];
+    } else {
+      P.r[c] = 0.0;
+    }
+    P.p0[c] = 0.0;
+    P.p1[c] = 0.0;
+  }
+  double s1 = block_sum(rz);
+  __syncthreads();
+  double s2 = block_sum(bb);
+  if (threadIdx.x == 0) {
+    unsafeAtomicAdd(&P.sc->rz, s1);
+    unsafeAtomicAdd(&P.sc->rz_ref, s2);
+  }
+}
+
+__device__ inline double p_new_at(const PdaArrays& P, const double* pold, double beta, int c) {
+  return P.region[c] == 1 ? P.r[c] / P.diag[c] + beta * pold[c] : 0.0;
+}
+
+__global__ void pcg_k1(int n_r, int n_mu, PdaArrays P, const double* pold, double* pnew) {
+  if (P.sc->done) return;
+  const int nc = n_r * n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = P.sc->iter == 0 ? 0.0 : P.sc->beta;
+  double pq = 0.0;
+  if (c < nc) {
+    if (P.region[c] == 1) {
+      int i = c / n_mu, j = c - i * n_mu;
+      double pc = p_new_at(P, pold, beta, c);
+      double y = P.diag[c] * pc;
+      if (i + 1 < n_r) y -= P.aE[c] * p_new_at(P, pold, beta, c + n_mu);
+      if (i > 0) y -= P.aE[c - n_mu] * p_new_at(P, pold, beta, c - n_mu);
+      if (j + 1 < n_mu) y -= P.aN[c] * p_new_at(P, pold, beta, c + 1);
+      if (j > 0) y -= P.aN[c - 1] * p_new_at(P, pold, beta, c - 1);
+      pnew[c] = pc;
+      P.q[c] = y;
+      pq = pc * y;
+    } else {
+      pnew[c] = 0.0;
+      P.q[c] = 0.0;
+    }
+  }
+  double s = block_sum(pq);
+  if (threadIdx.x == 0) unsafeAtomicAdd(&P.sc->pq, s);
+}
+
+__global__ void pcg_k2(int n_r, int n_mu, PdaArrays P, const double* p, double tol2,
+                       int max_iter) {
+  if (P.sc->done) return;
+  const int nc = n_r * n_mu;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const double pq = P.sc->pq;
+  const double alpha = pq != 0.0 ? P.sc->rz / pq : 0.0;
+  double rz = 0.0;
+  if (c < nc && P.region[c] == 1) {
+    P.x[c] += alpha * p[c];
+    double r = P.r[c] - alpha * P.q[c];
+    P.r[c] = r;
+    rz = r * r / P.diag[c];
+  }
+  double s = block_sum(rz);
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    unsafeAtomicAdd(&P.sc->rz_new, s);
+    __threadfence();
+    unsigned t = atomicAdd(&P.sc->ticket, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    PdaScalars* S = P.sc;
+    double rzn = __hip_atomic_load(&S->rz_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double rzo = S->rz;
+    S->beta = rzo != 0.0 ? rzn / rzo : 0.0;
+    S->rz = rzn;
+    S->rz_new = 0.0;
+    S->pq = 0.0;
+    S->ticket = 0;
+    S->iter += 1;
+    if (!(rzn > tol2 * S->rz_ref) || S->iter >= max_iter) S->done = 1;
+  }
+}
+
+// T <- u^(1/4) on the region, max |dT/T|
+__global__ void pda_update_kernel(int nc, PdaArrays P) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc || P.region[c] != 1) return;
+  double u = P.x[c] > 0.0 ? P.x[c] : 0.0;
+  double Tn = sqrt(sqrt(u));
+  double ch = fabs(Tn - P.Tw[c]) / fmax(Tn, 1e-300);
+  P.Tw[c] = Tn;
+  atomicMax(&P.sc->change_bits, (unsigned long long)__double_as_longlong(ch));
+}
+
+__global__ void pda_x_from_T_kernel(int nc, PdaArrays P) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double t = P.Tw[c];
+  double t2 = t * t;
+  P.x[c] = P.region[c] == 1 ? t2 * t2 : 0.0;
+}
+
+__global__ void pda_writeback_kernel(int nc, PdaArrays P, double* T_out, uint8_t* reg_out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  if (P.region[c] == 1) T_out[c] = P.Tw[c];
+  reg_out[c] = P.region[c];
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int launch_update_T(mcrt_ctx* ctx, hipStream_t s) {
+  int nc = ctx->n_cells;
+  hipLaunchKernelGGL(update_T_kernel, dim3((nc + BS - 1) / BS), dim3(BS), 0, s, ctx->m,
+                     ctx->t.E_abs, ctx->d_T, nc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(ctx, std::string("update_T launch: ") + hipGetErrorString(e));
+    return MCRT_E_HIP;
+  }
+  return MCRT_OK;
+}
+
+int launch_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t words = bytes / 4;
+  if (!words) return MCRT_OK;
+  unsigned nb = (unsigned)((words + 255) / 256);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
+
+// Geometry arrays of the PDA live at the start of the PDA scratch blob.
+static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
+  const int nc = ctx->n_cells, n_r = ctx->n_r, n_mu = ctx->n_mu;
+  size_t nd = (size_t)nc * sizeof(double);
+  size_t bytes = align256(sizeof(PdaScalars)) + 2 * align256(nc) + 11 * align256(nd) +
+                 align256(n_r * sizeof(double)) + align256(n_mu * sizeof(double)) +
+                 2 * align256(nd);
+  if (ctx->d_pda_blob == nullptr) {
+    if (hipMalloc(&ctx->d_pda_blob, bytes) != hipSuccess) {
+      set_error(ctx, "PDA scratch allocation failed");
+      return MCRT_E_OOM;
+    }
+    ctx->pda_bytes = bytes;
+    // geometry (host FP64, uploaded once)
+    std::vector<double> rc(n_r), thc(n_mu), Ar(nc), Amu(nc);
+    std::vector<double> re(n_r + 1), me(n_mu + 1);
+    hipMemcpy(re.data(), ctx->m.r_edges, (n_r + 1) * sizeof(double), hipMemcpyDeviceToHost);
+    hipMemcpy(me.data(), ctx->m.mu_edges, (n_mu + 1) * sizeof(double), hipMemcpyDeviceToHost);
+    for (int i = 0; i < n_r; ++i) rc[i] = 0.5 * (re[i] + re[i + 1]);
+    for (int j = 0; j < n_mu; ++j) thc[j] = 0.5 * (std::acos(me[j]) + std::acos(me[j + 1]));
+    for (int i = 0; i < n_r; ++i)
+      for (int j = 0; j < n_mu; ++j) {
+        double rf = re[i + 1];
+        Ar[i * n_mu + j] = 2.0 * PI * rf * rf * 2.0 * (me[j + 1] - me[j]);
+        double mf = me[j + 1];
+        double a = re[i], b = re[i + 1];
+        Amu[i * n_mu + j] = PI * (b * b - a * a) * 2.0 * std::sqrt(std::fmax(0.0, 1.0 - mf * mf));
+      }
+    char* q = (char*)ctx->d_pda_blob;
+    q += align256(sizeof(PdaScalars)) + 2 * align256(nc) + 11 * align256(nd);
+    hipMemcpy(q, rc.data(), n_r * sizeof(double), hipMemcpyHostToDevice);
+    q += align256(n_r * sizeof(double));
+    hipMemcpy(q, thc.data(), n_mu * sizeof(double), hipMemcpyHostToDevice);
+    q += align256(n_mu * sizeof(double));
+    hipMemcpy(q, Ar.data(), nd, hipMemcpyHostToDevice);
+    q += align256(nd);
+    hipMemcpy(q, Amu.data(), nd, hipMemcpyHostToDevice);
+  }
+  char* q = (char*)ctx->d_pda_blob;
+  P.sc = (PdaScalars*)q;
+  q += align256(sizeof(PdaScalars));
+  P.region = (uint8_t*)q;
+  q += align256(nc);
+  P.touch = (uint8_t*)q;
+  q += align256(nc);
+  double** arr[11] = {&P.Tw, &P.Tbc, &P.diag, &P.aE, &P.aN, &P.b, &P.x, &P.r, &P.p0, &P.p1, &P.q};
+  for (auto a : arr) {
+    *a = (double*)q;
+    q += align256(nd);
+  }
+  g.rc = (const double*)q;
+  q += align256(n_r * sizeof(double));
+  g.thc = (const double*)q;
+  q += align256(n_mu * sizeof(double));
+  g.Ar = (const double*)q;
+  q += align256(nd);
+  g.Amu = (const double*)q;
+  g.kscale = nullptr;
+  return MCRT_OK;
+}
+
+int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s) {
+  PdaArrays P;
+  PdaGeom g;
+  int rc = pda_alloc(ctx, P, g);
+  if (rc) return rc;
+  const int nc = ctx->n_cells, n_r = ctx->n_r, n_mu = ctx->n_mu;
+  const dim3 grid((nc + BS - 1) / BS), blk(BS);
+  const DevModel& M = ctx->m;
+  hipLaunchKernelGGL(pda_reset_scalars_kernel, dim3(1), dim3(64), 0, s, P.sc, 1);
+  hipLaunchKernelGGL(pda_region_kernel, grid, blk, 0, s, M, mask, ctx->t.visits,
+                     ctx->opt.pda_visits, P);
+  hipLaunchKernelGGL(pda_touch_kernel, grid, blk, 0, s, M, P);
+  hipLaunchKernelGGL(pda_components_kernel, dim3(1), dim3(256), 0, s, M, P);
+  hipLaunchKernelGGL(pda_floor_kernel, grid, blk, 0, s, M, ctx->d_T, P);
+  hipLaunchKernelGGL(pda_init_T_kernel, grid, blk, 0, s, M, ctx->d_T, P);
+  PdaScalars h{};
+  hipMemcpyAsync(&h, P.sc, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    set_error(ctx, "PDA setup failed");
+    return MCRT_E_HIP;
+  }
+  mcrt_pda_stats out{};
+  out.n_region = h.n_region - h.n_isolated;
+  out.n_isolated = h.n_isolated;
+  int status = MCRT_OK;
+  if (out.n_region > 0) {
+    const double tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+    const int chunk = 16;
+    int sweep;
+    for (sweep = 1; sweep <= ctx->opt.pda_max_sweeps; ++sweep) {
+      hipLaunchKernelGGL(pda_assemble_kernel, grid, blk, 0, s, M, g, P);
+      hipLaunchKernelGGL(pda_x_from_T_kernel, grid, blk, 0, s, nc, P);
+      hipLaunchKernelGGL(pda_reset_scalars_kernel, dim3(1), dim3(64), 0, s, P.sc, 0);
+      hipLaunchKernelGGL(pcg_start_kernel, grid, blk, 0, s, n_r, n_mu, P);
+      int it = 0;
+      for (;;) {
+        for (int q = 0; q < chunk; ++q, ++it) {
+          const double* pold = (it & 1) ? P.p1 : P.p0;
+          double* pnew = (it & 1) ? P.p0 : P.p1;
+          hipLaunchKernelGGL(pcg_k1, grid, blk, 0, s, n_r, n_mu, P, pold, pnew);
+          hipLaunchKernelGGL(pcg_k2, grid, blk, 0, s, n_r, n_mu, P, (const double*)pnew, tol2,
+                             ctx->opt.cg_max_iter);
+        }
+        hipMemcpyAsync(&h, P.sc, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+          set_error(ctx, "PDA CG failed");
+          return MCRT_E_HIP;
+        }
+        if (h.done) break;
+      }
+      out.cg_iters_total += h.iter;
+      out.cg_iters_last = h.iter;
+      out.last_residual = h.rz_ref > 0.0 ? std::sqrt(h.rz / h.rz_ref) : 0.0;
+      if (h.iter >= ctx->opt.cg_max_iter) status = MCRT_E_NOT_CONVERGED;
+      hipLaunchKernelGGL(pda_update_kernel, grid, blk, 0, s, nc, P);
+      hipMemcpyAsync(&h, P.sc, sizeof(h), hipMemcpyDeviceToHost, s);
+      if (hipStreamSynchronize(s) != hipSuccess) {
+        set_error(ctx, "PDA update failed");
+        return MCRT_E_HIP;
+      }
+      double change;
+      unsigned long long bits = h.change_bits;
+      std::memcpy(&change, &bits, sizeof(change));
+      out.last_change = change;
+      out.sweeps = sweep;
+      if (change < ctx->opt.pda_tol) break;
+    }
+    if (sweep > ctx->opt.pda_max_sweeps && status == MCRT_OK) status = MCRT_E_NOT_CONVERGED;
+  }
+  hipLaunchKernelGGL(pda_writeback_kernel, grid, blk, 0, s, nc, P, ctx->d_T, ctx->d_region);
+  if (hipGetLastError() != hipSuccess) {
+    set_error(ctx, "PDA launch failed");
+    return MCRT_E_HIP;
+  }
+  if (st) *st = out;
+  if (status == MCRT_OK && out.n_isolated > 0) status = MCRT_E_SINGULAR_REGION;
+  return status;
+}
+
+}  // namespace mcrt

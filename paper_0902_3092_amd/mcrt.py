@@ -1,0 +1,257 @@
+"""Python binding of the mcrt C-ABI (include/mcrt.h): argument marshalling only.
+
+Every step of the method runs in the HIP library ``libmcrt.so``; this module
+passes device pointers of torch tensors and the current HIP stream through
+ctypes, with the same names as the C entry points.  If the library is missing
+it raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcrt.so")
+_lib = None
+
+OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
+    GET_TABLES = range(9)
+COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch"]
+
+EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
+           "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
+           "mcrt_get_size", "mcrt_set_T", "mcrt_strerror", "mcrt_last_error"]
+
+
+class McrtError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        L = lib()
+        msg = "%s: %s (%s)" % (where, L.mcrt_strerror(code).decode(), L.mcrt_last_error().decode())
+        super().__init__(msg)
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_mu", C.c_int32), ("r_edges", C.c_void_p),
+                ("mu_edges", C.c_void_p)]
+
+
+class Star(C.Structure):
+    _fields_ = [("T_star", C.c_double), ("R_star", C.c_double)]
+
+
+class Dust(C.Structure):
+    _fields_ = [("n_lambda", C.c_int32), ("n_species", C.c_int32), ("lambda_edges", C.c_void_p),
+                ("kappa_abs", C.c_void_p), ("kappa_sca", C.c_void_p), ("mass_frac", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("mrw", C.c_int32), ("gamma", C.c_double),
+                ("n_int_min", C.c_int32), ("n_T", C.c_int32), ("T_lo", C.c_double),
+                ("T_hi", C.c_double), ("n_inc", C.c_int32), ("max_events", C.c_int64),
+                ("pda_visits", C.c_int32), ("pda_max_sweeps", C.c_int32),
+                ("pda_tol", C.c_double), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
+                ("mrw_coef_T", C.c_int32), ("block_size", C.c_int32),
+                ("blocks_per_cu", C.c_int32)]
+
+
+class PdaStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("cg_iters_total", C.c_int32),
+                ("cg_iters_last", C.c_int32), ("n_region", C.c_int32),
+                ("n_isolated", C.c_int32), ("last_change", C.c_double),
+                ("last_residual", C.c_double)]
+
+
+REC_DTYPE = np.dtype([("fate", np.int32), ("k", np.int32), ("n_cross", np.int64),
+                      ("n_scat", np.int64), ("n_abs", np.int64), ("n_mrw", np.int64),
+                      ("n_draws", np.int64), ("x", np.float64), ("y", np.float64),
+                      ("z", np.float64), ("u", np.float64), ("v", np.float64),
+                      ("w", np.float64)])
+
+
+def lib():
+    """Load libmcrt.so (built by build.py).  Raises if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmcrt.so is not built (run paper_0902_3092_amd/build.py or "
+                               "__graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        L.mcrt_default_options.argtypes = [vp]
+        L.mcrt_default_options.restype = None
+        L.mcrt_setup.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mcrt_destroy.argtypes = [vp]
+        L.mcrt_destroy.restype = None
+        L.mcrt_reset.argtypes = [vp, vp]
+        L.mcrt_trace.argtypes = [vp, u64, u64, u64, u64, vp, vp, i64, vp]
+        L.mcrt_update_T.argtypes = [vp, vp, vp]
+        L.mcrt_pda_solve.argtypes = [vp, vp, vp, vp]
+        L.mcrt_sed.argtypes = [vp, vp, vp]
+        L.mcrt_locate.argtypes = [vp, vp, i64, vp, vp]
+        L.mcrt_get.argtypes = [vp, C.c_int, vp, vp]
+        L.mcrt_get_size.argtypes = [vp, C.c_int]
+        L.mcrt_get_size.restype = i64
+        L.mcrt_set_T.argtypes = [vp, vp, vp]
+        L.mcrt_strerror.argtypes = [C.c_int]
+        L.mcrt_strerror.restype = C.c_char_p
+        L.mcrt_last_error.argtypes = []
+        L.mcrt_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().mcrt_default_options(C.byref(o))
+    return o
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(rc, where, allow=()):
+    if rc != OK and rc not in allow:
+        raise McrtError(rc, where)
+    return rc
+
+
+class Context:
+    """mcrt_setup on one disk model (any object with the workload Disk fields)."""
+
+    def __init__(self, disk, *, precision: str = "fp64", mrw: bool = False, gamma: float = 3.0,
+                 n_int_min: int = 20, n_T: int = 256, T_lo: float = 1.0, T_hi: float = 1.0e4,
+                 n_inc: int = 10, max_events: int = 1 << 30, pda_visits: int = 100,
+                 pda_max_sweeps: int = 50, pda_tol: float = 1e-8, cg_max_iter: int = 20000,
+                 cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
+                 blocks_per_cu: int = 0, rho=None):
+        import torch  # noqa: F401  (the device context)
+        L = lib()
+        o = default_options()
+        o.precision = FP32 if precision == "fp32" else FP64
+        o.mrw = int(mrw)
+        o.gamma, o.n_int_min, o.n_T, o.T_lo, o.T_hi = gamma, n_int_min, n_T, T_lo, T_hi
+        o.n_inc, o.max_events, o.pda_visits = n_inc, max_events, pda_visits
+        o.pda_max_sweeps, o.pda_tol, o.cg_max_iter, o.cg_tol = pda_max_sweeps, pda_tol, \
+            cg_max_iter, cg_tol
+        o.mrw_coef_T, o.block_size, o.blocks_per_cu = mrw_coef_T, block_size, blocks_per_cu
+        self.options = o
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
+                      f64(disk.kappa_abs), f64(disk.kappa_sca), f64(disk.mass_frac),
+                      f64(disk.rho if rho is None else rho)]
+        re, me, le, ka, ks, mf, rh = self._keep
+        g = Grid(len(re) - 1, len(me) - 1, re.ctypes.data, me.ctypes.data)
+        s = Star(float(disk.T_star), float(disk.R_star))
+        d = Dust(len(le) - 1, ka.shape[0], le.ctypes.data, ka.ctypes.data, ks.ctypes.data,
+                 mf.ctypes.data)
+        h = C.c_void_p()
+        _check(L.mcrt_setup(C.byref(h), C.byref(g), C.byref(s), C.byref(d), rh.ctypes.data,
+                            C.byref(o)), "mcrt_setup")
+        self.handle = h
+        self.n_r, self.n_mu, self.n_lambda = g.n_r, g.n_mu, d.n_lambda
+        self.n_cells = self.n_r * self.n_mu
+        self.n_inc = n_inc
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mcrt_destroy(h)
+            self.handle = None
+
+    # -- entry points -------------------------------------------------------
+    def reset(self, stream=None):
+        _check(lib().mcrt_reset(self.handle, _stream(stream)), "mcrt_reset")
+
+    def trace(self, n_packets: int, seed: int, *, n_total: Optional[int] = None, offset: int = 0,
+              frozen_T=None, n_recs: int = 0, stream=None):
+        """mcrt_trace; returns the packet records (torch uint8 buffer viewed as REC_DTYPE by
+        records_numpy) when n_recs > 0."""
+        import torch
+        n_total = n_packets if n_total is None else n_total
+        recs = None
+        if n_recs > 0:
+            recs = torch.zeros(n_recs * REC_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        if frozen_T is not None:
+            assert frozen_T.dtype == torch.float64 and frozen_T.is_cuda
+            assert frozen_T.numel() == self.n_cells
+        rc = lib().mcrt_trace(self.handle, n_packets, n_total, seed, offset, _ptr(frozen_T),
+                              _ptr(recs), n_recs, _stream(stream))
+        _check(rc, "mcrt_trace", allow=(E_STUCK,))
+        return recs
+
+    @staticmethod
+    def records_numpy(recs):
+        return np.frombuffer(recs.cpu().numpy().tobytes(), dtype=REC_DTYPE)
+
+    def update_T(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_update_T(self.handle, _ptr(out), _stream(stream)), "mcrt_update_T")
+        return out
+
+    def pda_solve(self, mask=None, stream=None) -> dict:
+        st = PdaStats()
+        rc = lib().mcrt_pda_solve(self.handle, _ptr(mask), C.byref(st), _stream(stream))
+        _check(rc, "mcrt_pda_solve", allow=(E_SINGULAR_REGION,))
+        out = {f: getattr(st, f) for f, _ in PdaStats._fields_}
+        out["rc"] = rc
+        return out
+
+    def sed(self, stream=None):
+        import torch
+        out = torch.empty((self.n_lambda, self.n_inc), dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_sed(self.handle, _ptr(out), _stream(stream)), "mcrt_sed")
+        return out
+
+    def locate(self, xyz, stream=None):
+        import torch
+        assert xyz.dtype == torch.float64 and xyz.is_cuda and xyz.is_contiguous()
+        n = xyz.numel() // 3
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().mcrt_locate(self.handle, _ptr(xyz), n, _ptr(out), _stream(stream)),
+               "mcrt_locate")
+        return out
+
+    def get(self, what: int, stream=None):
+        import torch
+        nbytes = lib().mcrt_get_size(self.handle, what)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _check(lib().mcrt_get(self.handle, what, _ptr(buf), _stream(stream)), "mcrt_get")
+        dt = {GET_E_ABS: torch.float64, GET_VISITS: torch.int32, GET_N_ABS: torch.int32,
+              GET_N_MRW: torch.int32, GET_T: torch.float64, GET_REGION: torch.uint8,
+              GET_COUNTERS: torch.int64, GET_E_STAR: torch.float64,
+              GET_TABLES: torch.float64}[what]
+        return buf.view(dt)
+
+    def counters(self) -> dict:
+        v = self.get(GET_COUNTERS).cpu().numpy()
+        return dict(zip(COUNTER_NAMES, (int(x) for x in v)))
+
+    def tables(self) -> dict:
+        v = self.get(GET_TABLES).cpu().numpy()
+        nT, nl = self.options.n_T, self.n_lambda
+        out, q = {}, 0
+        for name, n in (("T", nT), ("cdf", nT * nl), ("Drho", nT), ("kbar", nT),
+                        ("star_cdf", nl), ("L_star", 1)):
+            out[name] = v[q:q + n]
+            q += n
+        out["cdf"] = out["cdf"].reshape(nT, nl)
+        out["L_star"] = float(out["L_star"][0])
+        return out
+
+    def set_T(self, T, stream=None):
+        _check(lib().mcrt_set_T(self.handle, _ptr(T), _stream(stream)), "mcrt_set_T")
