@@ -21,9 +21,14 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, 
          "-Wno-unused-result", "-Wno-unused-value"]
 
 
+# The FP32 tracking kernel uses the hardware reciprocal and square root
+# (about 1 ulp) instead of the correctly rounded FP32 sequences.
+EXTRA = {"trace_fp32.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))

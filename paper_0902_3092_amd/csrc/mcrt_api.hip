@@ -314,6 +314,23 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
     double v = mcrt::MRW_TAB_V0 + (mcrt::MRW_TAB_V1 - mcrt::MRW_TAB_V0) * q / (mcrt::MRW_TAB_N - 1);
     mrw_tab[q] = mrw_solve_v(v);
   }
+  // guide over u = ln g: bin b starts at exp(lnG0 + b / inv_du)
+  const double lnG0 = std::log(G[1]);
+  const double inv_du = (mcrt::N_GUIDE - 1) / (std::log(G[nT - 1]) - lnG0);
+  std::vector<int> guide(mcrt::N_GUIDE);
+  {
+    int n = 1;
+    for (int b = 0; b < mcrt::N_GUIDE; ++b) {
+      double g = std::exp(lnG0 + b / inv_du);
+      while (n < nT - 2 && G[n + 1] <= g) ++n;
+      guide[b] = n;
+    }
+  }
+  std::vector<double> inv_dT(nT, 0.0), g_slope(nT, 0.0);
+  for (int n = 0; n + 1 < nT; ++n) {
+    inv_dT[n] = 1.0 / (Tn[n + 1] - Tn[n]);
+    g_slope[n] = (Tn[n + 1] - Tn[n]) / (G[n + 1] - G[n]);
+  }
   std::vector<double> r2(n_r + 1), mu2(n_mu + 1), smu(n_mu + 1), inv4pim(nc);
   for (int e = 0; e <= n_r; ++e) r2[e] = grid->r_edges[e] * grid->r_edges[e];
   for (int e = 0; e <= n_mu; ++e) {
@@ -344,6 +361,10 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   M.n_lambda = nl;
   M.n_T = nT;
   M.n_inc = opt->n_inc;
+  M.lnT_lo = std::log(opt->T_lo);
+  M.inv_dlnT = (double)(nT - 2) / std::log(opt->T_hi / opt->T_lo);
+  M.lnG0 = lnG0;
+  M.inv_du = inv_du;
   M.R_star = star->R_star;
   M.L_star = ctx->L_star;
   std::vector<Part> parts = {
@@ -367,6 +388,9 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       {star32.data(), nl * sizeof(float), (void**)&M.star_cdf32},
       {chi32.data(), nl * sizeof(float), (void**)&M.chi32},
       {om32.data(), nl * sizeof(float), (void**)&M.omega32},
+      {guide.data(), guide.size() * sizeof(int), (void**)&M.g_guide},
+      {inv_dT.data(), nT * sizeof(double), (void**)&M.inv_dT},
+      {g_slope.data(), nT * sizeof(double), (void**)&M.g_slope},
   };
   size_t total = 0;
   for (auto& p : parts) total += al(p.bytes);

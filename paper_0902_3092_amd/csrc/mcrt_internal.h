@@ -42,8 +42,15 @@ struct DevModel {
   const float* star_cdf32; // [n_lambda]
   const float* chi32;      // [n_lambda]
   const float* omega32;    // [n_lambda]
+  const int* g_guide;      // [N_GUIDE] largest n with G[n] <= exp(lnG0 + b / inv_du)
+  const double* inv_dT;    // [n_T] 1 / (T[n+1] - T[n])  (last entry unused)
+  const double* g_slope;   // [n_T] (T[n+1] - T[n]) / (G[n+1] - G[n])
+  double lnT_lo, inv_dlnT; // T nodes 1..n_T-1 = T_lo exp((n-1) dlnT)
+  double lnG0, inv_du;     // guide bins over ln g
   double R_star, L_star;
 };
+
+constexpr int N_GUIDE = 1024;
 
 // Mutable per-run tallies.
 struct DevTally {
