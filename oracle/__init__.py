@@ -93,6 +93,7 @@ def lib():
         L.ora_update_T.argtypes = [vp, vp, vp, vp]
         L.ora_pda.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, dbl, vp, vp]
         L.ora_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.ora_pda_grad_direct.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
         _lib = L
     return _lib
 
@@ -244,3 +245,25 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("oracle PDA: matrix not positive definite")
         return T_out
+
+
+def _pda_grad_direct(self, T_D, T_bc, region, dJdT, cells, kscale=None):
+    """dJ/dlog rho and dJ/ds of the linear PDA (D frozen at T_D) for the
+    listed cells, by the direct method (one solve per parameter)."""
+    T_D = np.ascontiguousarray(T_D, dtype=np.float64)
+    T_bc = np.ascontiguousarray(T_bc, dtype=np.float64)
+    reg = np.ascontiguousarray(region, dtype=np.uint8)
+    g = np.ascontiguousarray(dJdT, dtype=np.float64)
+    cl = np.ascontiguousarray(cells, dtype=np.int32)
+    ks = None if kscale is None else np.ascontiguousarray(kscale, dtype=np.float64)
+    gr = np.empty(len(cl))
+    gs = np.empty(len(cl))
+    rc = lib().ora_pda_grad_direct(C.byref(self.model), C.byref(self.tables), _p(T_D), _p(T_bc),
+                                   _p(ks) if ks is not None else None, _p(reg), _p(g), _p(cl),
+                                   len(cl), _p(gr), _p(gs))
+    if rc != 0:
+        raise RuntimeError("oracle PDA: matrix not positive definite")
+    return gr, gs
+
+
+Oracle.pda_grad_direct = _pda_grad_direct

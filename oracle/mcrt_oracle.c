@@ -683,7 +683,9 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
 /* PDA (Sect. 2.2.1, eq:T diffusion): div(D grad T^4) = 0 on the region,     */
 /* Dirichlet T from the Monte Carlo run on the neighbouring cells.  Finite    */
 /* volumes on the (r, mu) cells: flux A_f D_f (u_b - u_a) / dist_f with the   */
-/* harmonic mean of the two cells' D; zero flux at the grid edges, the pole,  */
+/* harmonic mean of the two cells' D, taken as 2 / (1/D_a + 1/D_b) on the   */
+/* cells' resistances R = 1/D = rho s / (D rho)(T) (finite even where D      */
+/* overflows); zero flux at the grid edges, the pole,                        */
 /* the (folded) midplane and towards dust-free cells.                         */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -717,8 +719,9 @@ static void pda_geom_free(pda_geom* g) {
   free(g->rc); free(g->thc); free(g->Ar); free(g->Amu);
 }
 
-/* conductance of the face between cells a and b (b = a's neighbour) */
-static double face_cond(const pda_geom* g, int ia, int ja, int ib, int jb, double Da, double Db) {
+/* conductance of the face between cells a and b (b = a's neighbour), from
+ * the cells' resistances R = 1/D */
+static double face_cond(const pda_geom* g, int ia, int ja, int ib, int jb, double Ra, double Rb) {
   double A, dist;
   if (ib != ia) {
     int ilo = ia < ib ? ia : ib;
@@ -729,8 +732,26 @@ static double face_cond(const pda_geom* g, int ia, int ja, int ib, int jb, doubl
     A = g->Amu[ia * g->nmu + jlo];
     dist = g->rc[ia] * fabs(g->thc[jb] - g->thc[ja]);
   }
-  double Df = 2.0 * Da * Db / (Da + Db);
+  double Df = 2.0 / (Ra + Rb);
   return A * Df / dist;
+}
+
+static int band_cholesky_solve(int n, int bw, double* band, double* x);
+
+/* solve with an already factored band (L in band) */
+static void band_solve_factored(int n, int bw, const double* band, double* x) {
+  for (int c = 0; c < n; ++c) {
+    double s = x[c];
+    int kk0 = c - bw < 0 ? 0 : c - bw;
+    for (int kk = kk0; kk < c; ++kk) s -= band[(size_t)c * (bw + 1) + (kk - c + bw)] * x[kk];
+    x[c] = s / band[(size_t)c * (bw + 1) + bw];
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double s = x[c];
+    int kk1 = c + bw >= n ? n - 1 : c + bw;
+    for (int kk = c + 1; kk <= kk1; ++kk) s -= band[(size_t)kk * (bw + 1) + (c - kk + bw)] * x[kk];
+    x[c] = s / band[(size_t)c * (bw + 1) + bw];
+  }
 }
 
 /* banded Cholesky, half-bandwidth bw, full-grid ordering; LL^T in place.
@@ -775,10 +796,10 @@ static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geo
                           const double* kscale, double* u) {
   int nr = m->n_r, nmu = m->n_mu, n = nr * nmu, bw = nmu;
   double* band = (double*)calloc((size_t)n * (bw + 1), sizeof(double));
-  double* D = (double*)malloc(sizeof(double) * n);
+  double* R = (double*)malloc(sizeof(double) * n);
   for (int c = 0; c < n; ++c) {
     double ks = kscale ? kscale[c] : 1.0;
-    D[c] = m->rho[c] > 0.0 ? t_interp(t, t->Drho, T_D[c]) / (m->rho[c] * ks) : 0.0;
+    R[c] = m->rho[c] > 0.0 ? m->rho[c] * ks / t_interp(t, t->Drho, T_D[c]) : 0.0;
   }
   for (int c = 0; c < n; ++c) {
     if (reg[c] != 1) {
@@ -798,7 +819,7 @@ static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geo
       if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
       int cb = ib * nmu + jb;
       if (!(m->rho[cb] > 0.0)) continue;
-      double a = face_cond(g, i, j, ib, jb, D[c], D[cb]);
+      double a = face_cond(g, i, j, ib, jb, R[c], R[cb]);
       diag += a;
       if (reg[cb] == 1) {
         if (cb < c) band[(size_t)c * (bw + 1) + (cb - c + bw)] = -a;
@@ -810,7 +831,7 @@ static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geo
   }
   int rc = band_cholesky_solve(n, bw, band, u);
   free(band);
-  free(D);
+  free(R);
   return rc;
 }
 
@@ -906,9 +927,116 @@ int ora_pda_linear(const ora_model* m, const ora_tables* t, const double* T_D, c
   pda_geom g;
   pda_geom_init(m, &g);
   double* u = (double*)malloc(sizeof(double) * n);
-  int rc = pda_solve_once(m, t, &g, region, T_D, T_bc, kscale, u);
-  for (int c = 0; c < n; ++c) T_out[c] = region[c] == 1 ? pow(fmax(u[c], 0.0), 0.25) : T_bc[c];
+  uint8_t* reg = (uint8_t*)malloc(n);
+  for (int c = 0; c < n; ++c) reg[c] = (region[c] && m->rho[c] > 0.0) ? 1 : 0;
+  pda_components(m, reg);
+  int rc = pda_solve_once(m, t, &g, reg, T_D, T_bc, kscale, u);
+  for (int c = 0; c < n; ++c) T_out[c] = reg[c] == 1 ? pow(fmax(u[c], 0.0), 0.25) : T_bc[c];
   free(u);
+  free(reg);
+  pda_geom_free(&g);
+  return rc;
+}
+
+/* Gradient of an objective J(T) of the linear PDA solve (D frozen at T_D)
+ * with respect to log rho_c and s_c of the cells listed, by the direct
+ * (tangent-linear) method: A du/dp = -dr/dp for each parameter p, with the
+ * residual r(u, p) = A(D(p)) u - b(D(p)) and D_c = (D rho)(T_D,c)/(rho_c s_c),
+ * then dJ/dp = sum_i dJ/dT_i dT_i/du_i du_i/dp.  One factorisation, one
+ * solve per parameter. */
+int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T_D,
+                        const double* T_bc, const double* kscale, const uint8_t* region_in,
+                        const double* dJdT, const int* cells, int n_req, double* g_logrho,
+                        double* g_kscale) {
+  int nr = m->n_r, nmu = m->n_mu, n = nr * nmu, bw = nmu;
+  pda_geom g;
+  pda_geom_init(m, &g);
+  uint8_t* reg = (uint8_t*)malloc(n);
+  for (int c = 0; c < n; ++c) reg[c] = (region_in[c] && m->rho[c] > 0.0) ? 1 : 0;
+  pda_components(m, reg);
+  double* R = (double*)malloc(sizeof(double) * n);
+  double* ks = (double*)malloc(sizeof(double) * n);
+  double* ubc = (double*)malloc(sizeof(double) * n);
+  for (int c = 0; c < n; ++c) {
+    ks[c] = kscale ? kscale[c] : 1.0;
+    R[c] = m->rho[c] > 0.0 ? m->rho[c] * ks[c] / t_interp(t, t->Drho, T_D[c]) : 0.0;
+    ubc[c] = pow(T_bc[c], 4.0);
+  }
+  /* assemble (same operator as the forward) and factor */
+  double* band = (double*)calloc((size_t)n * (bw + 1), sizeof(double));
+  double* u = (double*)malloc(sizeof(double) * n);
+  for (int c = 0; c < n; ++c) {
+    if (reg[c] != 1) {
+      band[(size_t)c * (bw + 1) + bw] = 1.0;
+      u[c] = ubc[c];
+      continue;
+    }
+    u[c] = 0.0;
+  }
+  for (int c = 0; c < n; ++c) {
+    if (reg[c] != 1) continue;
+    int i = c / nmu, j = c % nmu;
+    int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    double diag = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      int ib = nb[q][0], jb = nb[q][1];
+      if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+      int cb = ib * nmu + jb;
+      if (!(m->rho[cb] > 0.0)) continue;
+      double a = face_cond(&g, i, j, ib, jb, R[c], R[cb]);
+      diag += a;
+      if (reg[cb] == 1) {
+        if (cb < c) band[(size_t)c * (bw + 1) + (cb - c + bw)] = -a;
+      } else {
+        u[c] += a * ubc[cb];
+      }
+    }
+    band[(size_t)c * (bw + 1) + bw] = diag;
+  }
+  int rc = band_cholesky_solve(n, bw, band, u); /* factors band in place, u = solution */
+  double* dTdu = (double*)malloc(sizeof(double) * n);
+  for (int c = 0; c < n; ++c)
+    dTdu[c] = (reg[c] == 1 && u[c] > 0.0) ? 0.25 * pow(u[c], -0.75) : 0.0;
+  double* w = (double*)malloc(sizeof(double) * n);
+  for (int r = 0; rc == 0 && r < n_req; ++r) {
+    int c = cells[r];
+    g_logrho[r] = 0.0;
+    if (g_kscale) g_kscale[r] = 0.0;
+    if (!(m->rho[c] > 0.0)) continue;
+    for (int k = 0; k < n; ++k) w[k] = 0.0;
+    int i = c / nmu, j = c % nmu;
+    int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    int any = 0;
+    for (int q = 0; q < 4; ++q) {
+      int ib = nb[q][0], jb = nb[q][1];
+      if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+      int cb = ib * nmu + jb;
+      if (!(m->rho[cb] > 0.0)) continue;
+      if (reg[c] != 1 && reg[cb] != 1) continue;
+      /* a_f = (A_f/dist_f) 2 / (R_c + R_b) and dR_c / dlog rho_c = R_c */
+      double a1 = face_cond(&g, i, j, ib, jb, 1.0, 1.0);  /* A_f / dist_f */
+      double sden = R[c] + R[cb];
+      double da = -a1 * 2.0 * R[c] / (sden * sden); /* per unit log rho_c */
+      if (reg[c] == 1) w[c] -= da * (u[c] - u[cb]);
+      if (reg[cb] == 1) w[cb] -= da * (u[cb] - u[c]);
+      any = 1;
+    }
+    if (!any) continue;
+    band_solve_factored(n, bw, band, w);
+    double s = 0.0;
+    for (int k = 0; k < n; ++k)
+      if (reg[k] == 1) s += dJdT[k] * dTdu[k] * w[k];
+    g_logrho[r] = s;
+    if (g_kscale) g_kscale[r] = s / ks[c]; /* dR/ds = R/s: the same with 1/s */
+  }
+  free(w);
+  free(dTdu);
+  free(band);
+  free(u);
+  free(ubc);
+  free(ks);
+  free(R);
+  free(reg);
   pda_geom_free(&g);
   return rc;
 }

@@ -110,6 +110,14 @@ int ora_pda_linear(const ora_model* m, const ora_tables* t, const double* T_D,
                    const double* T_bc, const double* kscale, const uint8_t* region,
                    double* T_out);
 
+/* Gradient of J(T) of the linear solve above w.r.t. log rho and the
+ * extinction scale s of the listed cells (direct method; dJdT [n_cells];
+ * outputs [n_req]). */
+int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T_D,
+                        const double* T_bc, const double* kscale, const uint8_t* region,
+                        const double* dJdT, const int* cells, int n_req, double* g_logrho,
+                        double* g_kscale);
+
 #ifdef __cplusplus
 }
 #endif
