@@ -42,7 +42,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    p.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    p.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison step")
     p.add_argument("--packets", type=int, default=1000000)
     p.add_argument("--cpu-packets", type=int, default=300000)
     p.add_argument("--no-cpu", action="store_true")
@@ -139,6 +140,19 @@ def main():
         "events_per_step": c,
         "pda": {k: pda[k] for k in ("sweeps", "cg_iters_total", "n_region")},
     }
+    if not a.no_plain and a.precision != "fp64":
+        # the plain FP64 path on the same step, for comparison (one timed step)
+        ctx64 = mcrt.Context(disk, precision="fp64", mrw=True, gamma=o.gamma,
+                             n_int_min=o.n_int_min, pda_visits=o.pda_visits, n_T=o.n_T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx64.reset()
+        ctx64.trace(N, o.seed + 777)
+        ctx64.update_T()
+        ctx64.pda_solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["plain_fp64"] = {"value": N / dt, "ms_per_step": dt * 1e3, "steps": 1}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(disk, o, a.cpu_packets)
     print(json.dumps(out))

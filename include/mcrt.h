@@ -100,6 +100,7 @@ typedef struct {
                             previous pass (set by mcrt_update_T) (0) */
   int32_t block_size;    /* trace workgroup size, 0 = library choice */
   int32_t blocks_per_cu; /* trace workgroups per compute unit, 0 = library choice */
+  int32_t pda_solver;    /* 0 auto, 1 grid-wide CG kernels, 2 one workgroup per disk (0) */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
@@ -159,6 +160,28 @@ typedef struct {
 int mcrt_pda_solve(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats,
                    hipStream_t stream);
 
+/* Linear PDA for differentiation: eq. T diffusion on the cells with
+ * mask_dev[c] = 1 (parts without a Dirichlet neighbour are left out and
+ * flagged 2 in MCRT_GET_REGION) with the diffusion coefficient frozen at a
+ * given temperature field, D_c = (D rho)(T_D,c) / (rho_c s_c): one linear
+ * solve of the finite-volume system for u = T^4 (Jacobi-PCG), Dirichlet T_bc
+ * on the other cells.  rho_dev (nullable: the context's density) and
+ * kscale_dev (nullable: s = 1) are [n_cells] doubles; s scales the mass
+ * extinction of a cell.  T_out_dev [n_cells] receives T (T_bc outside the
+ * region).  The solution is kept for mcrt_pda_adjoint.  Waits for the stream. */
+int mcrt_pda_linear(mcrt_ctx* ctx, const uint8_t* mask_dev, const double* rho_dev,
+                    const double* kscale_dev, const double* T_D_dev, const double* T_bc_dev,
+                    double* T_out_dev, mcrt_pda_stats* stats, hipStream_t stream);
+
+/* Adjoint of the last mcrt_pda_linear: given dJ/dT [n_cells] for any
+ * objective J of its output T, writes dJ/d(log rho_c) to g_logrho_dev and
+ * (nullable) dJ/ds_c to g_kscale_dev, both [n_cells], through the
+ * dependence of the diffusion coefficient (the explicit dependence of J on
+ * rho, e.g. through cell masses, is the caller's).  One more symmetric solve.
+ * Waits for the stream. */
+int mcrt_pda_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev,
+                     double* g_kscale_dev, hipStream_t stream);
+
 /* Escaped luminosity per wavelength bin and |cos i| bin: sed_dev
  * [n_lambda][n_inc] double, erg/s (not divided by the solid angle). */
 int mcrt_sed(mcrt_ctx* ctx, double* sed_dev, hipStream_t stream);
@@ -189,6 +212,23 @@ int64_t mcrt_get_size(mcrt_ctx* ctx, int what);
 /* Overwrite the context's temperature (e.g. with a PDA result or a test
  * field): T_dev [n_cells] double. */
 int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
+
+/* Batched passes over many disks: for each of n_iter passes, clear the
+ * tallies of every context, trace n_packets[d] packets of context d (seed
+ * seeds[d] + (pass << 32); each packet carries L_star / n_packets[d]) with
+ * ALL disks in one persistent launch (workgroups shared out by packet
+ * count), invert the temperatures, and solve each disk's PDA on its
+ * low-visit cells with one workgroup per disk.  Contexts whose mrw_coef_T is
+ * 1 take the MRW coefficients of pass k from the temperature after pass k-1.
+ * use_graph != 0 captures all passes in one HIP graph and submits it once.
+ * Every context must use MCRT_FP32 and live on the current device.  stats
+ * (host, nullable) receives each disk's PDA statistics of the last pass.
+ * Synchronous: returns after the stream has drained.  The n-iteration
+ * outer loop of the method (Sect. 2.5: radiative transfer repeated on an
+ * updated structure) run for a batch of models. */
+int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
+                   const uint64_t* seeds, int n_iter, int use_graph, mcrt_pda_stats* stats,
+                   hipStream_t stream);
 
 const char* mcrt_strerror(int code);
 const char* mcrt_last_error(void);

@@ -1,0 +1,35 @@
+"""torch.autograd front end of the differentiable PDA solve.
+
+``pda_temperature(ctx, log_rho, kscale, mask, T_D, T_bc)`` returns the PDA
+temperature field (one linear solve with the diffusion coefficient frozen at
+T_D, eq. T diffusion of Sect. 2.2.1) and is differentiable with respect to the
+per-cell log density and extinction scale: the backward pass calls the HIP
+adjoint solve (mcrt_pda_adjoint).  Both directions run in the library.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import mcrt
+
+
+class PDAFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, log_rho, kscale, ctx, mask, T_D, T_bc):
+        rho = torch.exp(log_rho.detach()).contiguous()
+        ks = kscale.detach().contiguous()
+        T, _ = ctx.pda_linear(mask, T_D.contiguous(), T_bc.contiguous(), rho=rho, kscale=ks)
+        fctx.mcrt_ctx = ctx
+        fctx.keep = (rho, ks)   # the saved solve refers to these buffers
+        return T
+
+    @staticmethod
+    def backward(fctx, grad_T):
+        g_logrho, g_ks = fctx.mcrt_ctx.pda_adjoint(grad_T.contiguous())
+        return g_logrho, g_ks, None, None, None, None
+
+
+def pda_temperature(ctx: "mcrt.Context", log_rho, kscale, mask, T_D, T_bc):
+    """Differentiable PDA temperature (see module doc).  All tensors float64 on
+    the device of the context, [n_cells]; mask uint8."""
+    return PDAFunction.apply(log_rho, kscale, ctx, mask, T_D, T_bc)

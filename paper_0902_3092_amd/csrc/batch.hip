@@ -1,0 +1,163 @@
+// Many disks, several passes: {trace -> temperature -> PDA} x n_iter over a
+// batch of contexts, each pass one persistent trace launch for all disks and
+// one workgroup-per-disk PDA launch, optionally captured in a HIP graph and
+// replayed as one submission.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mcrt_internal.h"
+
+namespace {
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int fail_batch(int code, const std::string& msg) {
+  mcrt::set_error(nullptr, msg);
+  return code;
+}
+}  // namespace
+
+extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
+                              const uint64_t* seeds, int n_iter, int use_graph,
+                              mcrt_pda_stats* stats, hipStream_t s) {
+  if (!ctxs || n_disks < 1 || !n_packets || !seeds || n_iter < 1)
+    return fail_batch(MCRT_E_ARG, "bad batch arguments");
+  for (int d = 0; d < n_disks; ++d) {
+    if (!ctxs[d] || n_packets[d] == 0) return fail_batch(MCRT_E_ARG, "bad context or packet count");
+    if (ctxs[d]->opt.precision != MCRT_FP32)
+      return fail_batch(MCRT_E_ARG, "batched runs use FP32 tracking (precision = MCRT_FP32)");
+    if (ctxs[d]->device != ctxs[0]->device) return fail_batch(MCRT_E_ARG, "contexts on one device");
+  }
+  mcrt_ctx* c0 = ctxs[0];
+  // launch shape: LDS for the largest disk, workgroups shared by packets
+  size_t lds = 0;
+  for (int d = 0; d < n_disks; ++d) lds = std::max(lds, mcrt::trace_fp32_lds(ctxs[d]->m, true));
+  const bool cdf_lds = lds <= mcrt::trace_fp32_lds_cap();
+  if (!cdf_lds) {  // every disk reads its emission CDF from L2 instead
+    lds = 0;
+    for (int d = 0; d < n_disks; ++d) lds = std::max(lds, mcrt::trace_fp32_lds(ctxs[d]->m, false));
+  }
+  const int per_cu = mcrt::trace_fp32_blocks_per_cu(lds, cdf_lds);
+  const long long total_blocks = std::max<long long>((long long)c0->n_cu * per_cu, n_disks);
+  double sumN = 0.0;
+  for (int d = 0; d < n_disks; ++d) sumN += (double)n_packets[d];
+  std::vector<int> nb(n_disks);
+  long long used = 0;
+  for (int d = 0; d < n_disks; ++d) {
+    long long want = (long long)std::floor((double)total_blocks * (double)n_packets[d] / sumN);
+    long long need = ((long long)n_packets[d] + 511) / 512;
+    nb[d] = (int)std::max<long long>(1, std::min(want, need));
+    used += nb[d];
+  }
+  std::vector<int> block_disk;
+  block_disk.reserve(used);
+  for (int d = 0; d < n_disks; ++d)
+    for (int b = 0; b < nb[d]; ++b) block_disk.push_back(d);
+  // arguments for every pass, uploaded before any work is queued
+  const size_t targs = sizeof(mcrt::TraceArgs);
+  std::vector<mcrt::TraceArgs> ta((size_t)n_iter * n_disks);
+  for (int it = 0; it < n_iter; ++it)
+    for (int d = 0; d < n_disks; ++d) {
+      mcrt_ctx* c = ctxs[d];
+      mcrt::TraceArgs a = mcrt::make_trace_args(c, n_packets[d], n_packets[d],
+                                                seeds[d] + ((uint64_t)it << 32), 0, nullptr,
+                                                nullptr, 0);
+      // passes after the first may take the MRW coefficients from the
+      // previous pass's (PDA-corrected) temperature
+      a.T_coef = (c->opt.mrw_coef_T == 1 && it > 0) ? c->d_T_prev : nullptr;
+      ta[(size_t)it * n_disks + d] = a;
+    }
+  const size_t pda_bytes = mcrt::pda_wg_args_size() * n_disks;
+  std::vector<char> pda_host(pda_bytes);
+  int rc = mcrt::pda_batch_fill(ctxs, n_disks, pda_host.data());
+  if (rc) return rc;
+  size_t bytes = al(ta.size() * targs) + al(block_disk.size() * sizeof(int)) + al(pda_bytes);
+  void* blob = nullptr;
+  if (hipMalloc(&blob, bytes) != hipSuccess) return fail_batch(MCRT_E_OOM, "batch arguments");
+  char* q = (char*)blob;
+  mcrt::TraceArgs* d_ta = (mcrt::TraceArgs*)q;
+  q += al(ta.size() * targs);
+  int* d_bd = (int*)q;
+  q += al(block_disk.size() * sizeof(int));
+  void* d_pda = q;
+  hipError_t e = hipMemcpy(d_ta, ta.data(), ta.size() * targs, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(d_bd, block_disk.data(), block_disk.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_pda, pda_host.data(), pda_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(blob);
+    return fail_batch(MCRT_E_HIP, "batch argument upload");
+  }
+  mcrt::prepare_trace_fp32_batch(lds, cdf_lds);
+  // the passes
+  auto enqueue = [&](hipStream_t s) -> int {
+    for (int it = 0; it < n_iter; ++it) {
+      for (int d = 0; d < n_disks; ++d) {
+        mcrt_ctx* c = ctxs[d];
+        size_t tally = (size_t)((char*)c->d_next - (char*)c->t.E_abs) + 8;  // tallies + counter
+        int r = mcrt::launch_zero(c->t.E_abs, tally, s);
+        if (r) return r;
+        if (it > 0 && c->opt.mrw_coef_T == 1) {
+          r = mcrt::launch_copy(c->d_T_prev, c->d_T, (size_t)c->n_cells, s);
+          if (r) return r;
+        }
+      }
+      int r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd,
+                                            (int)block_disk.size(), lds, cdf_lds, s);
+      if (r) return r;
+      for (int d = 0; d < n_disks; ++d) {
+        r = mcrt::launch_update_T(ctxs[d], s);
+        if (r) return r;
+      }
+      r = mcrt::pda_batch_launch(d_pda, n_disks, s);
+      if (r) return r;
+    }
+    return MCRT_OK;
+  };
+  int status = MCRT_OK;
+  if (use_graph) {
+    // capture on a stream of our own (the caller's may be the null stream,
+    // which cannot be captured), then submit the graph on the caller's stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      status = enqueue(cs);
+      hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      if (status == MCRT_OK && e2 == hipSuccess)
+        e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (status == MCRT_OK && e2 == hipSuccess) e2 = hipGraphLaunch(exec, s);
+      if (status == MCRT_OK && e2 != hipSuccess) {
+        mcrt::set_error(nullptr, std::string("graph: ") + hipGetErrorString(e2));
+        status = MCRT_E_HIP;
+      }
+    } else {
+      mcrt::set_error(nullptr, std::string("stream capture: ") + hipGetErrorString(e));
+      status = MCRT_E_HIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && status == MCRT_OK) status = MCRT_E_HIP;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+  } else {
+    status = enqueue(s);
+    if (hipStreamSynchronize(s) != hipSuccess && status == MCRT_OK) status = MCRT_E_HIP;
+  }
+  if (status == MCRT_OK && stats) {
+    for (int d = 0; d < n_disks; ++d)
+      if (hipMemcpy(&stats[d], mcrt::pda_stats_slot(ctxs[d]), sizeof(mcrt_pda_stats),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        status = MCRT_E_HIP;
+  }
+  if (status == MCRT_OK)
+    for (int d = 0; d < n_disks; ++d)
+      if (ctxs[d]->opt.mrw_coef_T == 1) ctxs[d]->have_T_prev = true;
+  (void)hipFree(blob);
+  return status;
+}

@@ -161,6 +161,29 @@ void set_error(mcrt_ctx* ctx, const std::string& msg) {
 int launch_trace_fp64(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
 int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
 
+TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
+                          uint64_t offset, const double* frozen_T, mcrt_packet_rec* recs,
+                          int64_t n_recs) {
+  TraceArgs a{};
+  a.m = ctx->m;
+  a.t = ctx->t;
+  a.eps = ctx->L_star / (double)n_total;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.offset = offset;
+  a.n_packets = n_packets;
+  a.next = ctx->d_next;
+  a.mrw = ctx->opt.mrw;
+  a.n_int_min = ctx->opt.n_int_min;
+  a.gamma = ctx->opt.gamma;
+  a.max_events = ctx->opt.max_events;
+  a.frozen_T = frozen_T;
+  a.T_coef = (ctx->opt.mrw_coef_T == 1 && ctx->have_T_prev) ? ctx->d_T_prev : nullptr;
+  a.recs = recs;
+  a.n_recs = n_recs;
+  return a;
+}
+
 int launch_trace(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
   if (ctx->opt.precision == MCRT_FP32) return launch_trace_fp32(ctx, a, s);
   return launch_trace_fp64(ctx, a, s);
@@ -188,6 +211,7 @@ void mcrt_default_options(mcrt_options* o) {
   o->mrw_coef_T = 0;
   o->block_size = 0;
   o->blocks_per_cu = 0;
+  o->pda_solver = 0;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -213,7 +237,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
     return fail(nullptr, MCRT_E_ARG, "star must be hot and inside the inner hole");
   if (opt->n_T < 3 || !(opt->T_lo > 0.0) || !(opt->T_hi > opt->T_lo) || opt->n_inc < 1 ||
       opt->max_events < 1 || opt->n_int_min < 0 || !(opt->gamma >= 0.0) ||
-      (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32))
+      (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
+      opt->pda_solver > 2)
     return fail(nullptr, MCRT_E_ARG, "bad options");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)
@@ -444,6 +469,7 @@ void mcrt_destroy(mcrt_ctx* ctx) {
   if (ctx->d_blob) hipFree(ctx->d_blob);
   if (ctx->d_tally_blob) hipFree(ctx->d_tally_blob);
   if (ctx->d_pda_blob) hipFree(ctx->d_pda_blob);
+  if (ctx->d_lin_args) hipFree(ctx->d_lin_args);
   delete ctx;
 }
 
@@ -462,23 +488,8 @@ int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t see
     return fail(ctx, MCRT_E_ARG, "packets [offset, offset+n) must lie in [0, n_total)");
   if (n_recs < 0 || (n_recs > 0 && !rec_dev)) return fail(ctx, MCRT_E_ARG, "bad record buffer");
   if (n_packets == 0) return MCRT_OK;
-  mcrt::TraceArgs a{};
-  a.m = ctx->m;
-  a.t = ctx->t;
-  a.eps = ctx->L_star / (double)n_total;
-  a.key0 = (uint32_t)seed;
-  a.key1 = (uint32_t)(seed >> 32);
-  a.offset = offset;
-  a.n_packets = n_packets;
-  a.next = ctx->d_next;
-  a.mrw = ctx->opt.mrw;
-  a.n_int_min = ctx->opt.n_int_min;
-  a.gamma = ctx->opt.gamma;
-  a.max_events = ctx->opt.max_events;
-  a.frozen_T = frozen_T_dev;
-  a.T_coef = (ctx->opt.mrw_coef_T == 1 && ctx->have_T_prev) ? ctx->d_T_prev : nullptr;
-  a.recs = rec_dev;
-  a.n_recs = n_recs;
+  mcrt::TraceArgs a = mcrt::make_trace_args(ctx, n_packets, n_total, seed, offset, frozen_T_dev,
+                                            rec_dev, n_recs);
   int rc = mcrt::launch_zero(ctx->d_next, 8, stream);
   if (rc) return fail(ctx, rc, "clearing the work counter failed");
   return mcrt::launch_trace(ctx, a, stream);
@@ -505,6 +516,21 @@ int mcrt_pda_solve(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats
   if (!mask_dev && ctx->opt.pda_visits <= 0)
     return fail(ctx, MCRT_E_ARG, "no PDA mask and pda_visits <= 0");
   return mcrt::pda_solve(ctx, mask_dev, stats, stream);
+}
+
+int mcrt_pda_linear(mcrt_ctx* ctx, const uint8_t* mask_dev, const double* rho_dev,
+                    const double* kscale_dev, const double* T_D_dev, const double* T_bc_dev,
+                    double* T_out_dev, mcrt_pda_stats* stats, hipStream_t stream) {
+  if (!ctx || !mask_dev || !T_D_dev || !T_bc_dev || !T_out_dev)
+    return fail(ctx, MCRT_E_ARG, "mcrt_pda_linear: null argument");
+  return mcrt::pda_linear(ctx, mask_dev, rho_dev, kscale_dev, T_D_dev, T_bc_dev, T_out_dev, stats,
+                          stream);
+}
+
+int mcrt_pda_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev,
+                     double* g_kscale_dev, hipStream_t stream) {
+  if (!ctx || !dJdT_dev || !g_logrho_dev) return fail(ctx, MCRT_E_ARG, "mcrt_pda_adjoint: null argument");
+  return mcrt::pda_adjoint(ctx, dJdT_dev, g_logrho_dev, g_kscale_dev, nullptr, stream);
 }
 
 int mcrt_sed(mcrt_ctx* ctx, double* sed_dev, hipStream_t stream) {

@@ -99,6 +99,9 @@ struct mcrt_ctx {
   void* d_pda_blob = nullptr;   // PDA solver scratch
   size_t pda_bytes = 0;
   bool have_T_prev = false;
+  void* d_lin_args = nullptr;        // argument slot of the linear PDA / adjoint
+  const double* lin_rho = nullptr;   // density of the last linear forward
+  bool lin_ready = false;
   // host copies
   std::string err;
 };
@@ -110,4 +113,24 @@ int launch_update_T(mcrt_ctx* ctx, hipStream_t s);
 int launch_zero(void* p, size_t bytes, hipStream_t s);
 int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s);
 void set_error(mcrt_ctx* ctx, const std::string& msg);
+int pda_linear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const double* kscale,
+               const double* T_D, const double* T_bc, double* T_out, mcrt_pda_stats* st,
+               hipStream_t s);
+int pda_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_kscale,
+                mcrt_pda_stats* st, hipStream_t s);
+// batches
+size_t pda_wg_args_size();
+int pda_batch_fill(mcrt_ctx** ctxs, int n, void* host);
+int pda_batch_launch(const void* d_args, int n, hipStream_t s);
+mcrt_pda_stats* pda_stats_slot(mcrt_ctx* ctx);
+int launch_copy(double* dst, const double* src, size_t n, hipStream_t s);
+size_t trace_fp32_lds(const DevModel& M, bool with_cdf);
+size_t trace_fp32_lds_cap();
+int trace_fp32_blocks_per_cu(size_t lds, bool cdf_lds);
+int prepare_trace_fp32_batch(size_t lds, bool cdf_lds);
+int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk, int n_blocks,
+                            size_t lds, bool cdf_lds, hipStream_t s);
+TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
+                          uint64_t offset, const double* frozen_T, mcrt_packet_rec* recs,
+                          int64_t n_recs);
 }  // namespace mcrt

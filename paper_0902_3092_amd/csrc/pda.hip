@@ -234,9 +234,12 @@ struct PdaGeom {
   const double* kscale;  // nullable per-cell extinction scale
 };
 
-__device__ inline double Dcell(const DevModel& M, const PdaGeom& g, const double* Tw, int c) {
+// resistance R = 1/D = rho s / (D rho)(T) of a dusty cell: the face mean
+// 2 / (R_a + R_b) is the harmonic mean of D and stays finite where D itself
+// would overflow (densities in the subnormal range)
+__device__ inline double Rcell(const DevModel& M, const PdaGeom& g, const double* Tw, int c) {
   double ks = g.kscale ? g.kscale[c] : 1.0;
-  return table_at(M.Tn, M.n_T, M.Drho, Tw[c]) / (M.rho[c] * ks);
+  return M.rho[c] * ks / table_at(M.Tn, M.n_T, M.Drho, Tw[c]);
 }
 
 __global__ void pda_assemble_kernel(DevModel M, PdaGeom g, PdaArrays P) {
@@ -251,7 +254,7 @@ __global__ void pda_assemble_kernel(DevModel M, PdaGeom g, PdaArrays P) {
     return;
   }
   const int i = c / n_mu, j = c - i * n_mu;
-  const double Da = Dcell(M, g, P.Tw, c);
+  const double Ra = Rcell(M, g, P.Tw, c);
   double diag = 0.0, rhs = 0.0, aE = 0.0, aN = 0.0;
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
   for (int q = 0; q < 4; ++q) {
@@ -259,7 +262,7 @@ __global__ void pda_assemble_kernel(DevModel M, PdaGeom g, PdaArrays P) {
     if (!in_grid(ib, jb, n_r, n_mu)) continue;
     int cb = ib * n_mu + jb;
     if (!(M.rho[cb] > 0.0)) continue;
-    double Db = Dcell(M, g, P.Tw, cb);
+    double Rb = Rcell(M, g, P.Tw, cb);
     double A, dist;
     if (q < 2) {
       int ilo = i < ib ? i : ib;
@@ -270,7 +273,7 @@ __global__ void pda_assemble_kernel(DevModel M, PdaGeom g, PdaArrays P) {
       A = g.Amu[i * n_mu + jlo];
       dist = g.rc[i] * fabs(g.thc[jb] - g.thc[j]);
     }
-    double a = A * (2.0 * Da * Db / (Da + Db)) / dist;
+    double a = A * (2.0 / (Ra + Rb)) / dist;
     diag += a;
     if (P.region[cb] == 1) {
       if (q == 1) aE = a;
@@ -434,6 +437,276 @@ __global__ void pda_writeback_kernel(int nc, PdaArrays P, double* T_out, uint8_t
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ------------------------------------------------------------------------
+// The whole PDA of one disk in one workgroup: region, components, floor,
+// Picard sweeps with assembly and Jacobi-PCG, write-back.  No host round
+// trips, so it can be captured in a graph; in a batch each workgroup solves
+// one disk.  Reductions use wavefront shuffles and LDS.
+// ------------------------------------------------------------------------
+constexpr int WG = 1024;
+
+struct PdaWgArgs {
+  DevModel M;
+  PdaArrays P;
+  PdaGeom g;
+  const uint8_t* mask;      // nullable: visits rule
+  const uint32_t* visits;
+  int thr;
+  const double* T_mc;       // Monte Carlo temperature (Dirichlet data, initial guess)
+  double* T_out;            // region cells overwritten
+  uint8_t* reg_out;
+  int max_sweeps;
+  double tol;
+  int cg_max_iter;
+  double cg_tol2;
+  mcrt_pda_stats* stats;    // device, nullable
+};
+
+template <bool MAX>
+__device__ double wg_reduce(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(v, off);
+    v = MAX ? fmax(v, o) : v + o;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = MAX ? fmax(r, red[q]) : r + red[q];
+  return r;
+}
+
+__device__ double apply_A_at(const PdaArrays& P, const double* v, int c, int n_r, int n_mu) {
+  int i = c / n_mu, j = c - i * n_mu;
+  return apply_A(P, v, c, i, j, n_r, n_mu);
+}
+
+__device__ void components_wg(const DevModel& M, const PdaArrays& P, int* changed) {
+  const int n_r = M.n_r, n_mu = M.n_mu;
+  for (int round = 0; round < 100000; ++round) {
+    if (threadIdx.x == 0) *changed = 0;
+    __syncthreads();
+    int local = 0;
+    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+      uint8_t carry = 0;
+      for (int j = 0; j < n_mu; ++j) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+      carry = 0;
+      for (int j = n_mu - 1; j >= 0; --j) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n_mu; j += blockDim.x) {
+      uint8_t carry = 0;
+      for (int i = 0; i < n_r; ++i) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+      carry = 0;
+      for (int i = n_r - 1; i >= 0; --i) {
+        int c = i * n_mu + j;
+        if (P.region[c] != 1) { carry = 0; continue; }
+        if (carry && !P.touch[c]) { P.touch[c] = 1; local = 1; }
+        carry = P.touch[c];
+      }
+    }
+    if (local) atomicOr(changed, 1);
+    __syncthreads();
+    int ch = *changed;
+    __syncthreads();
+    if (!ch) break;
+  }
+}
+
+__global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
+  const PdaWgArgs& a = args[blockIdx.x];
+  const DevModel& M = a.M;
+  const PdaArrays& P = a.P;
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  __shared__ double red[WG / 64];
+  __shared__ int changed;
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  // region and Dirichlet contact
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    bool in = M.rho[c] > 0.0 && (a.mask ? a.mask[c] != 0 : a.visits[c] < (uint32_t)a.thr);
+    P.region[c] = in ? 1 : 0;
+  }
+  __syncthreads();
+  double n_reg = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    uint8_t t = 0;
+    if (P.region[c] == 1) {
+      int i = c / n_mu, j = c - i * n_mu;
+      for (int q = 0; q < 4; ++q) {
+        int ib = i + di[q], jb = j + dj[q];
+        if (!in_grid(ib, jb, n_r, n_mu)) continue;
+        int cb = ib * n_mu + jb;
+        if (M.rho[cb] > 0.0 && P.region[cb] != 1) t = 1;
+      }
+      n_reg += 1.0;
+    }
+    P.touch[c] = t;
+  }
+  n_reg = wg_reduce<false>(n_reg, red);
+  components_wg(M, P, &changed);
+  double n_iso = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x)
+    if (P.region[c] == 1 && !P.touch[c]) {
+      P.region[c] = 2;
+      n_iso += 1.0;
+    }
+  n_iso = wg_reduce<false>(n_iso, red);
+  // floor: smallest Dirichlet temperature next to the region
+  double mflo = -INFINITY;  // max of -T
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    if (P.region[c] != 1) continue;
+    int i = c / n_mu, j = c - i * n_mu;
+    for (int q = 0; q < 4; ++q) {
+      int ib = i + di[q], jb = j + dj[q];
+      if (!in_grid(ib, jb, n_r, n_mu)) continue;
+      int cb = ib * n_mu + jb;
+      if (M.rho[cb] > 0.0 && P.region[cb] != 1) mflo = fmax(mflo, -a.T_mc[cb]);
+    }
+  }
+  double fl = -wg_reduce<true>(mflo, red);
+  if (!(fl < INFINITY)) fl = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double t = a.T_mc[c];
+    P.Tbc[c] = t;
+    P.Tw[c] = (P.region[c] == 1) ? fmax(t, fl) : t;
+  }
+  __syncthreads();
+  const int n_solve = (int)(n_reg - n_iso + 0.5);
+  int sweeps = 0, iters_total = 0, iters_last = 0;
+  double change = 0.0, resid = 0.0;
+  if (n_solve > 0) {
+    for (sweeps = 1; sweeps <= a.max_sweeps; ++sweeps) {
+      // assemble with D from the current temperature
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        if (P.region[c] != 1) {
+          P.diag[c] = 1.0; P.aE[c] = 0.0; P.aN[c] = 0.0; P.b[c] = 0.0;
+          P.x[c] = 0.0; P.r[c] = 0.0; P.p0[c] = 0.0; P.q[c] = 0.0;
+          continue;
+        }
+        const int i = c / n_mu, j = c - i * n_mu;
+        const double Ra = Rcell(M, a.g, P.Tw, c);
+        double diag = 0.0, rhs = 0.0, aE = 0.0, aN = 0.0;
+        for (int q = 0; q < 4; ++q) {
+          int ib = i + di[q], jb = j + dj[q];
+          if (!in_grid(ib, jb, n_r, n_mu)) continue;
+          int cb = ib * n_mu + jb;
+          if (!(M.rho[cb] > 0.0)) continue;
+          double Rb = Rcell(M, a.g, P.Tw, cb);
+          double A, dist;
+          if (q < 2) {
+            int ilo = i < ib ? i : ib;
+            A = a.g.Ar[ilo * n_mu + j];
+            dist = fabs(a.g.rc[ib] - a.g.rc[i]);
+          } else {
+            int jlo = j < jb ? j : jb;
+            A = a.g.Amu[i * n_mu + jlo];
+            dist = a.g.rc[i] * fabs(a.g.thc[jb] - a.g.thc[j]);
+          }
+          double cond = A * (2.0 / (Ra + Rb)) / dist;
+          diag += cond;
+          if (P.region[cb] == 1) {
+            if (q == 1) aE = cond;
+            if (q == 3) aN = cond;
+          } else {
+            double t = P.Tbc[cb], t2 = t * t;
+            rhs += cond * (t2 * t2);
+          }
+        }
+        P.diag[c] = diag; P.aE[c] = aE; P.aN[c] = aN; P.b[c] = rhs;
+        double t = P.Tw[c], t2 = t * t;
+        P.x[c] = t2 * t2;
+      }
+      __syncthreads();
+      // Jacobi-PCG from the current T^4
+      double rz = 0.0, bb = 0.0;
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        if (P.region[c] != 1) continue;
+        double r = P.b[c] - apply_A_at(P, P.x, c, n_r, n_mu);
+        P.r[c] = r;
+        double z = r / P.diag[c];
+        P.p0[c] = z;
+        rz += r * z;
+        bb += P.b[c] * P.b[c] / P.diag[c];
+      }
+      rz = wg_reduce<false>(rz, red);
+      const double rz_ref = wg_reduce<false>(bb, red);
+      int it = 0;
+      while (rz > a.cg_tol2 * rz_ref && it < a.cg_max_iter) {
+        double pq = 0.0;
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+          if (P.region[c] != 1) continue;
+          double y = apply_A_at(P, P.p0, c, n_r, n_mu);
+          P.q[c] = y;
+          pq += P.p0[c] * y;
+        }
+        pq = wg_reduce<false>(pq, red);
+        const double alpha = pq != 0.0 ? rz / pq : 0.0;
+        double rzn = 0.0;
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+          if (P.region[c] != 1) continue;
+          P.x[c] += alpha * P.p0[c];
+          double r = P.r[c] - alpha * P.q[c];
+          P.r[c] = r;
+          rzn += r * r / P.diag[c];
+        }
+        rzn = wg_reduce<false>(rzn, red);
+        const double beta = rz != 0.0 ? rzn / rz : 0.0;
+        rz = rzn;
+        ++it;
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+          if (P.region[c] != 1) continue;
+          P.p0[c] = P.r[c] / P.diag[c] + beta * P.p0[c];
+        }
+        __syncthreads();
+      }
+      iters_total += it;
+      iters_last = it;
+      resid = rz_ref > 0.0 ? sqrt(rz / rz_ref) : 0.0;
+      double ch = 0.0;
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        if (P.region[c] != 1) continue;
+        double u = P.x[c] > 0.0 ? P.x[c] : 0.0;
+        double Tn = sqrt(sqrt(u));
+        ch = fmax(ch, fabs(Tn - P.Tw[c]) / fmax(Tn, 1e-300));
+        P.Tw[c] = Tn;
+      }
+      change = wg_reduce<true>(ch, red);
+      if (change < a.tol) break;
+    }
+    if (sweeps > a.max_sweeps) sweeps = a.max_sweeps;
+  }
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    if (P.region[c] == 1) a.T_out[c] = P.Tw[c];
+    a.reg_out[c] = P.region[c];
+  }
+  if (threadIdx.x == 0 && a.stats) {
+    mcrt_pda_stats s;
+    s.sweeps = sweeps;
+    s.cg_iters_total = iters_total;
+    s.cg_iters_last = iters_last;
+    s.n_region = n_solve;
+    s.n_isolated = (int)(n_iso + 0.5);
+    s.last_change = change;
+    s.last_residual = resid;
+    *a.stats = s;
+  }
+}
+
 }  // namespace
 
 int launch_update_T(mcrt_ctx* ctx, hipStream_t s) {
@@ -463,7 +736,7 @@ static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
   size_t nd = (size_t)nc * sizeof(double);
   size_t bytes = align256(sizeof(PdaScalars)) + 2 * align256(nc) + 11 * align256(nd) +
                  align256(n_r * sizeof(double)) + align256(n_mu * sizeof(double)) +
-                 2 * align256(nd);
+                 2 * align256(nd) + align256(sizeof(PdaWgArgs)) + align256(sizeof(mcrt_pda_stats));
   if (ctx->d_pda_blob == nullptr) {
     if (hipMalloc(&ctx->d_pda_blob, bytes) != hipSuccess) {
       set_error(ctx, "PDA scratch allocation failed");
@@ -518,12 +791,70 @@ static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
   return MCRT_OK;
 }
 
+// device slots for one single-workgroup solve: arguments and statistics
+static void pda_wg_slots(mcrt_ctx* ctx, PdaWgArgs** args, mcrt_pda_stats** stats) {
+  const int nc = ctx->n_cells;
+  size_t nd = (size_t)nc * sizeof(double);
+  char* q = (char*)ctx->d_pda_blob + ctx->pda_bytes - align256(sizeof(PdaWgArgs)) -
+            align256(sizeof(mcrt_pda_stats));
+  (void)nd;
+  *args = (PdaWgArgs*)q;
+  *stats = (mcrt_pda_stats*)(q + align256(sizeof(PdaWgArgs)));
+}
+
+static int pda_solve_wg(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s,
+                        const PdaArrays& P, const PdaGeom& g) {
+  PdaWgArgs h;
+  h.M = ctx->m;
+  h.P = P;
+  h.g = g;
+  h.mask = mask;
+  h.visits = ctx->t.visits;
+  h.thr = ctx->opt.pda_visits;
+  h.T_mc = ctx->d_T;
+  h.T_out = ctx->d_T;
+  h.reg_out = ctx->d_region;
+  h.max_sweeps = ctx->opt.pda_max_sweeps;
+  h.tol = ctx->opt.pda_tol;
+  h.cg_max_iter = ctx->opt.cg_max_iter;
+  h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  PdaWgArgs* d_args;
+  mcrt_pda_stats* d_stats;
+  pda_wg_slots(ctx, &d_args, &d_stats);
+  h.stats = d_stats;
+  // the previous solve on this context may still read the argument slot
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(d_args, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error(ctx, "PDA argument upload failed");
+    return MCRT_E_HIP;
+  }
+  hipLaunchKernelGGL(pda_wg_kernel, dim3(1), dim3(WG), 0, s, (const PdaWgArgs*)d_args);
+  if (hipGetLastError() != hipSuccess) {
+    set_error(ctx, "PDA launch failed");
+    return MCRT_E_HIP;
+  }
+  mcrt_pda_stats out{};
+  if (hipMemcpyAsync(&out, d_stats, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error(ctx, "PDA failed");
+    return MCRT_E_HIP;
+  }
+  if (st) *st = out;
+  if (out.cg_iters_last >= ctx->opt.cg_max_iter ||
+      (out.n_region > 0 && !(out.last_change < ctx->opt.pda_tol)))
+    return MCRT_E_NOT_CONVERGED;
+  return out.n_isolated > 0 ? MCRT_E_SINGULAR_REGION : MCRT_OK;
+}
+
 int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s) {
   PdaArrays P;
   PdaGeom g;
+  ctx->lin_ready = false;  // the scratch of a linear solve is overwritten
   int rc = pda_alloc(ctx, P, g);
   if (rc) return rc;
   const int nc = ctx->n_cells, n_r = ctx->n_r, n_mu = ctx->n_mu;
+  if (ctx->opt.pda_solver == 2 || (ctx->opt.pda_solver == 0 && nc <= 65536))
+    return pda_solve_wg(ctx, mask, st, s, P, g);
   const dim3 grid((nc + BS - 1) / BS), blk(BS);
   const DevModel& M = ctx->m;
   hipLaunchKernelGGL(pda_reset_scalars_kernel, dim3(1), dim3(64), 0, s, P.sc, 1);
@@ -595,6 +926,410 @@ int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_
   if (st) *st = out;
   if (status == MCRT_OK && out.n_isolated > 0) status = MCRT_E_SINGULAR_REGION;
   return status;
+}
+
+// ------------------------------------------------------------------------
+// Differentiation of the PDA with respect to the density and an extinction
+// scale per cell.  The forward is one linear solve with the diffusion
+// coefficient frozen at a given temperature field T_D:
+//   D_c = (D rho)(T_D,c) / (rho_c s_c),  A(D) u = b(D),  T = u^(1/4) on the region,
+// Dirichlet T_bc elsewhere.  For an objective J(T) the adjoint solves
+// A lambda = dJ/du (A is symmetric) and, with the residual r = A u - b,
+//   dJ/dp = - lambda . dr/dp,   dr/dp = sum_faces (dr/da_f)(da_f/dD_c)(dD_c/dp),
+// a_f = A_f 2 D_a D_b / ((D_a + D_b) dist_f), dD_c/dlog rho_c = -D_c,
+// dD_c/ds_c = -D_c / s_c.  The face term lambda . dr/da_f is
+// (lambda_a - lambda_b)(u_a - u_b) between two region cells and
+// lambda_a (u_a - u_b) between a region cell a and a Dirichlet cell b.
+// ------------------------------------------------------------------------
+namespace {
+
+struct PdaLinArgs {
+  DevModel M;
+  PdaArrays P;
+  PdaGeom g;
+  const uint8_t* mask;
+  const double* rho;       // per-cell density (defaults to the model's)
+  const double* kscale;    // nullable
+  const double* T_D;
+  const double* T_bc;
+  double* T_out;
+  uint8_t* reg_out;
+  int cg_max_iter;
+  double cg_tol2;
+  mcrt_pda_stats* stats;
+  // adjoint
+  const double* dJdT;
+  double* g_logrho;
+  double* g_kscale;
+};
+
+// face conductance from the two resistances, and its derivative by R_a
+__device__ inline double lin_cond(const PdaLinArgs& a, int i, int j, int ib, int jb, double Ra,
+                                  double Rb, double* dA_dRa) {
+  double A, dist;
+  const int n_mu = a.M.n_mu;
+  if (ib != i) {
+    int ilo = i < ib ? i : ib;
+    A = a.g.Ar[ilo * n_mu + j];
+    dist = fabs(a.g.rc[ib] - a.g.rc[i]);
+  } else {
+    int jlo = j < jb ? j : jb;
+    A = a.g.Amu[i * n_mu + jlo];
+    dist = a.g.rc[i] * fabs(a.g.thc[jb] - a.g.thc[j]);
+  }
+  double s = Ra + Rb;
+  if (dA_dRa) *dA_dRa = -A / dist * 2.0 / (s * s);
+  return A * (2.0 / s) / dist;
+}
+
+// Jacobi-PCG on the assembled operator: solves A x = b over region == 1
+__device__ int wg_cg(const PdaArrays& P, int n_r, int n_mu, const double* b, double* x,
+                     int max_iter, double tol2, double* red, double* resid) {
+  const int nc = n_r * n_mu;
+  double rz = 0.0, bb = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    if (P.region[c] != 1) continue;
+    double r = b[c] - apply_A_at(P, x, c, n_r, n_mu);
+    P.r[c] = r;
+    double z = r / P.diag[c];
+    P.p0[c] = z;
+    rz += r * z;
+    bb += b[c] * b[c] / P.diag[c];
+  }
+  rz = wg_reduce<false>(rz, red);
+  const double ref = wg_reduce<false>(bb, red);
+  int it = 0;
+  while (rz > tol2 * ref && it < max_iter) {
+    double pq = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      double y = apply_A_at(P, P.p0, c, n_r, n_mu);
+      P.q[c] = y;
+      pq += P.p0[c] * y;
+    }
+    pq = wg_reduce<false>(pq, red);
+    const double alpha = pq != 0.0 ? rz / pq : 0.0;
+    double rzn = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      x[c] += alpha * P.p0[c];
+      double r = P.r[c] - alpha * P.q[c];
+      P.r[c] = r;
+      rzn += r * r / P.diag[c];
+    }
+    rzn = wg_reduce<false>(rzn, red);
+    const double beta = rz != 0.0 ? rzn / rz : 0.0;
+    rz = rzn;
+    ++it;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      P.p0[c] = P.r[c] / P.diag[c] + beta * P.p0[c];
+    }
+    __syncthreads();
+  }
+  *resid = ref > 0.0 ? sqrt(rz / ref) : 0.0;
+  return it;
+}
+
+// Forward: region from the mask (components without Dirichlet contact -> 2),
+// R = 1/D from T_D, one linear solve.  Keeps u (x), R (p1), s (b), T_bc (Tbc)
+// and the operator for the adjoint.
+__global__ void __launch_bounds__(WG) pda_linear_kernel(const PdaLinArgs* args) {
+  const PdaLinArgs& a = *args;
+  const DevModel& M = a.M;
+  const PdaArrays& P = a.P;
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  __shared__ double red[WG / 64];
+  __shared__ int changed;
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    P.region[c] = (a.rho[c] > 0.0 && a.mask[c] != 0) ? 1 : 0;
+    double s = a.kscale ? a.kscale[c] : 1.0;
+    P.p1[c] = a.rho[c] > 0.0 ? a.rho[c] * s / table_at(M.Tn, M.n_T, M.Drho, a.T_D[c]) : 0.0;
+    P.Tbc[c] = a.T_bc[c];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    uint8_t t = 0;
+    if (P.region[c] == 1) {
+      int i = c / n_mu, j = c - i * n_mu;
+      for (int q = 0; q < 4; ++q) {
+        int ib = i + di[q], jb = j + dj[q];
+        if (!in_grid(ib, jb, n_r, n_mu)) continue;
+        int cb = ib * n_mu + jb;
+        if (a.rho[cb] > 0.0 && P.region[cb] != 1) t = 1;
+      }
+    }
+    P.touch[c] = t;
+  }
+  __syncthreads();
+  components_wg(M, P, &changed);
+  for (int c = threadIdx.x; c < nc; c += blockDim.x)
+    if (P.region[c] == 1 && !P.touch[c]) P.region[c] = 2;
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    P.x[c] = 0.0; P.r[c] = 0.0; P.p0[c] = 0.0; P.q[c] = 0.0;
+    if (P.region[c] != 1) {
+      P.diag[c] = 1.0; P.aE[c] = 0.0; P.aN[c] = 0.0; P.Tw[c] = 0.0;
+      continue;
+    }
+    const int i = c / n_mu, j = c - i * n_mu;
+    double diag = 0.0, rhs = 0.0, aE = 0.0, aN = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      int ib = i + di[q], jb = j + dj[q];
+      if (!in_grid(ib, jb, n_r, n_mu)) continue;
+      int cb = ib * n_mu + jb;
+      if (!(a.rho[cb] > 0.0)) continue;
+      double cond = lin_cond(a, i, j, ib, jb, P.p1[c], P.p1[cb], nullptr);
+      diag += cond;
+      if (P.region[cb] == 1) {
+        if (q == 1) aE = cond;
+        if (q == 3) aN = cond;
+      } else {
+        double t = P.Tbc[cb], t2 = t * t;
+        rhs += cond * (t2 * t2);
+      }
+    }
+    P.diag[c] = diag; P.aE[c] = aE; P.aN[c] = aN;
+    P.Tw[c] = rhs;  // right-hand side
+    double t = a.T_D[c], t2 = t * t;
+    P.x[c] = t2 * t2;
+  }
+  __syncthreads();
+  double resid;
+  int it = wg_cg(P, n_r, n_mu, P.Tw, P.x, a.cg_max_iter, a.cg_tol2, red, &resid);
+  double n1 = 0.0, n2 = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    n1 += P.region[c] == 1 ? 1.0 : 0.0;
+    n2 += P.region[c] == 2 ? 1.0 : 0.0;
+    P.b[c] = a.kscale ? a.kscale[c] : 1.0;
+    double u = P.x[c] > 0.0 ? P.x[c] : 0.0;
+    a.T_out[c] = P.region[c] == 1 ? sqrt(sqrt(u)) : P.Tbc[c];
+    a.reg_out[c] = P.region[c];
+  }
+  n1 = wg_reduce<false>(n1, red);
+  n2 = wg_reduce<false>(n2, red);
+  if (threadIdx.x == 0 && a.stats) {
+    mcrt_pda_stats s{};
+    s.sweeps = 1;
+    s.cg_iters_total = it;
+    s.cg_iters_last = it;
+    s.n_region = (int)n1;
+    s.n_isolated = (int)n2;
+    s.last_residual = resid;
+    *a.stats = s;
+  }
+}
+
+// Adjoint of the linear solve above (same workgroup arrays).
+__global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args) {
+  const PdaLinArgs& a = *args;
+  const DevModel& M = a.M;
+  const PdaArrays& P = a.P;
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  __shared__ double red[WG / 64];
+  // right-hand side dJ/du = dJ/dT * T / (4 u) on the region, staged in the
+  // g_logrho output (overwritten by the gradient at the end); lambda in Tw
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double g = 0.0;
+    if (P.region[c] == 1) {
+      double u = P.x[c];
+      g = u > 0.0 ? a.dJdT[c] * sqrt(sqrt(u)) / (4.0 * u) : 0.0;
+    }
+    P.Tw[c] = 0.0;
+    a.g_logrho[c] = g;
+  }
+  __syncthreads();
+  double resid;
+  int it = wg_cg(P, n_r, n_mu, a.g_logrho, P.Tw, a.cg_max_iter, a.cg_tol2, red, &resid);
+  __syncthreads();
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double dJdR = 0.0;
+    if (a.rho[c] > 0.0) {
+      const int i = c / n_mu, j = c - i * n_mu;
+      const bool rc_ = P.region[c] == 1;
+      double uc = rc_ ? P.x[c] : P.Tbc[c] * P.Tbc[c] * P.Tbc[c] * P.Tbc[c];
+      for (int q = 0; q < 4; ++q) {
+        int ib = i + di[q], jb = j + dj[q];
+        if (!in_grid(ib, jb, n_r, n_mu)) continue;
+        int cb = ib * n_mu + jb;
+        if (!(a.rho[cb] > 0.0)) continue;
+        const bool rb = P.region[cb] == 1;
+        if (!rc_ && !rb) continue;
+        double ub = rb ? P.x[cb] : P.Tbc[cb] * P.Tbc[cb] * P.Tbc[cb] * P.Tbc[cb];
+        double lam_dr;  // lambda . dr/da_f
+        if (rc_ && rb) lam_dr = (P.Tw[c] - P.Tw[cb]) * (uc - ub);
+        else if (rc_) lam_dr = P.Tw[c] * (uc - ub);
+        else lam_dr = P.Tw[cb] * (ub - uc);
+        double dA;
+        (void)lin_cond(a, i, j, ib, jb, P.p1[c], P.p1[cb], &dA);
+        dJdR -= lam_dr * dA;
+      }
+    }
+    // dR/dlog rho = R, dR/ds = R/s
+    const double R = P.p1[c];
+    a.g_logrho[c] = R * dJdR;
+    if (a.g_kscale) a.g_kscale[c] = R / P.b[c] * dJdR;
+  }
+  if (threadIdx.x == 0 && a.stats) {
+    mcrt_pda_stats s{};
+    s.sweeps = 1;
+    s.cg_iters_total = it;
+    s.cg_iters_last = it;
+    s.last_residual = resid;
+    *a.stats = s;
+  }
+}
+
+}  // namespace
+
+// The argument slot of the single-workgroup solve doubles as the slot of the
+// linear/adjoint pair (both are synchronous).
+static int pda_lin_call(mcrt_ctx* ctx, const PdaLinArgs& h, bool adjoint, mcrt_pda_stats* st,
+                        hipStream_t s) {
+  static_assert(sizeof(PdaLinArgs) <= 4096, "argument slot");
+  PdaWgArgs* d_args;
+  mcrt_pda_stats* d_stats;
+  pda_wg_slots(ctx, &d_args, &d_stats);
+  PdaLinArgs hh = h;
+  hh.stats = d_stats;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(ctx->d_lin_args, &hh, sizeof(hh), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error(ctx, "PDA argument upload failed");
+    return MCRT_E_HIP;
+  }
+  if (adjoint)
+    hipLaunchKernelGGL(pda_adjoint_kernel, dim3(1), dim3(WG), 0, s,
+                       (const PdaLinArgs*)ctx->d_lin_args);
+  else
+    hipLaunchKernelGGL(pda_linear_kernel, dim3(1), dim3(WG), 0, s,
+                       (const PdaLinArgs*)ctx->d_lin_args);
+  mcrt_pda_stats out{};
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&out, d_stats, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error(ctx, "PDA linear/adjoint launch failed");
+    return MCRT_E_HIP;
+  }
+  if (st) *st = out;
+  return out.cg_iters_last >= ctx->opt.cg_max_iter ? MCRT_E_NOT_CONVERGED : MCRT_OK;
+}
+
+int pda_linear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const double* kscale,
+               const double* T_D, const double* T_bc, double* T_out, mcrt_pda_stats* st,
+               hipStream_t s) {
+  PdaArrays P;
+  PdaGeom g;
+  int rc = pda_alloc(ctx, P, g);
+  if (rc) return rc;
+  if (!ctx->d_lin_args && hipMalloc(&ctx->d_lin_args, sizeof(PdaLinArgs)) != hipSuccess) {
+    set_error(ctx, "PDA argument slot");
+    return MCRT_E_OOM;
+  }
+  PdaLinArgs h{};
+  h.M = ctx->m;
+  h.P = P;
+  h.g = g;
+  h.mask = mask;
+  h.rho = rho ? rho : ctx->m.rho;
+  h.kscale = kscale;
+  h.T_D = T_D;
+  h.T_bc = T_bc;
+  h.T_out = T_out;
+  h.reg_out = ctx->d_region;
+  h.cg_max_iter = ctx->opt.cg_max_iter;
+  h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  ctx->lin_rho = h.rho;
+  ctx->lin_ready = true;
+  return pda_lin_call(ctx, h, false, st, s);
+}
+
+int pda_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_kscale,
+                mcrt_pda_stats* st, hipStream_t s) {
+  if (!ctx->lin_ready) {
+    set_error(ctx, "mcrt_pda_adjoint needs a preceding mcrt_pda_linear");
+    return MCRT_E_ARG;
+  }
+  PdaArrays P;
+  PdaGeom g;
+  int rc = pda_alloc(ctx, P, g);
+  if (rc) return rc;
+  PdaLinArgs h{};
+  h.M = ctx->m;
+  h.P = P;
+  h.g = g;
+  h.rho = ctx->lin_rho;
+  h.dJdT = dJdT;
+  h.g_logrho = g_logrho;
+  h.g_kscale = g_kscale;
+  h.cg_max_iter = ctx->opt.cg_max_iter;
+  h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  return pda_lin_call(ctx, h, true, st, s);
+}
+
+// ---------------------------------------------------------------- batches
+size_t pda_wg_args_size() { return sizeof(PdaWgArgs); }
+
+// Host-side arguments of the single-workgroup PDA of each context (visits
+// rule, in place on the context's T and region), statistics into each
+// context's slot.
+int pda_batch_fill(mcrt_ctx** ctxs, int n, void* host) {
+  PdaWgArgs* out = (PdaWgArgs*)host;
+  for (int d = 0; d < n; ++d) {
+    mcrt_ctx* ctx = ctxs[d];
+    PdaArrays P;
+    PdaGeom g;
+    int rc = pda_alloc(ctx, P, g);
+    if (rc) return rc;
+    PdaWgArgs& h = out[d];
+    h.M = ctx->m;
+    h.P = P;
+    h.g = g;
+    h.mask = nullptr;
+    h.visits = ctx->t.visits;
+    h.thr = ctx->opt.pda_visits;
+    h.T_mc = ctx->d_T;
+    h.T_out = ctx->d_T;
+    h.reg_out = ctx->d_region;
+    h.max_sweeps = ctx->opt.pda_max_sweeps;
+    h.tol = ctx->opt.pda_tol;
+    h.cg_max_iter = ctx->opt.cg_max_iter;
+    h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+    PdaWgArgs* da;
+    mcrt_pda_stats* ds;
+    pda_wg_slots(ctx, &da, &ds);
+    h.stats = ds;
+  }
+  return MCRT_OK;
+}
+
+int pda_batch_launch(const void* d_args, int n, hipStream_t s) {
+  hipLaunchKernelGGL(pda_wg_kernel, dim3(n), dim3(WG), 0, s, (const PdaWgArgs*)d_args);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
+
+mcrt_pda_stats* pda_stats_slot(mcrt_ctx* ctx) {
+  PdaWgArgs* da;
+  mcrt_pda_stats* ds;
+  pda_wg_slots(ctx, &da, &ds);
+  return ds;
+}
+
+namespace {
+__global__ void copy_kernel(double* dst, const double* src, size_t n) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; t < n; t += stride) dst[t] = src[t];
+}
+}  // namespace
+
+int launch_copy(double* dst, const double* src, size_t n, hipStream_t s) {
+  if (!n) return MCRT_OK;
+  unsigned nb = (unsigned)((n + 255) / 256);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(copy_kernel, dim3(nb), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
 }
 
 }  // namespace mcrt

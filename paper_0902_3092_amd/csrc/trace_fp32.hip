@@ -139,7 +139,7 @@ __device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
 }
 
 template <bool CDF_LDS>
-__global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
+__device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   extern __shared__ double smem[];
   const DevModel& M = A.m;
   const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda, n_T = M.n_T;
@@ -200,6 +200,7 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
   double Tc = -1.0;
   double mrw_T = -2.0, mrw_Drho = 0.0, mrw_kbar = 0.0;  // MRW coefficients at mrw_T
   float mrw_lim = 0.0f;
+  float d_safe = 0.0f;  // lower bound of the distance to every face of the cell
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   for (;;) {
@@ -282,16 +283,24 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
         rho = M.rho[j];
         Tc = -1.0;
         mrw_T = -2.0;
+        d_safe = 0.0f;
         n_int = 0;
         ++pc_cross;
       }
     } else {
       const int c = i * n_mu + j;
       const float alpha = (float)rho * L.chi[k];
-      int face;
-      float sb = boundary32(an, L, n_mu, i, j, q, d, face);
-      float tau_b = alpha * sb;
-      if (tau_b <= tau) {
+      int face = 1;
+      float sb = 0.0f, tau_b = 0.0f;
+      // a flight shorter than the guaranteed distance to every face stays in
+      // the cell: the face distances are not needed for it
+      const bool inside = tau < alpha * d_safe;
+      if (!inside) {
+        sb = boundary32(an, L, n_mu, i, j, q, d, face);
+        tau_b = alpha * sb;
+      }
+      if (!inside && tau_b <= tau) {
+        d_safe = 0.0f;
         q[0] += sb * d[0]; q[1] += sb * d[1]; q[2] += sb * d[2];
         tau -= tau_b;
         if (tau < 0.0f) tau = 0.0f;
@@ -331,6 +340,7 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
       } else {
         float sint = tau / alpha;
         q[0] += sint * d[0]; q[1] += sint * d[1]; q[2] += sint * d[2];
+        d_safe -= sint;
         const double* fz = A.frozen_T;
         if (rng.next() < L.omega[k]) {
           ++pc_scat;
@@ -372,7 +382,11 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
             }
             const double Drho = mrw_Drho;
             const float lim = mrw_lim;
-            if (!(min_boundary32(an, L, n_mu, i, j, q) > lim)) break;
+            {
+              float dm = min_boundary32(an, L, n_mu, i, j, q);
+              d_safe = 0.999f * dm;
+              if (!(dm > lim)) break;
+            }
             // re-anchor so the sphere radius is exact to FP32 precision of itself
             reanchor(an, q, L, n_mu, i, j);
             float dmin = min_boundary32(an, L, n_mu, i, j, q);
@@ -400,6 +414,7 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
             Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
             k = reemit_search<float>(R, nl, xb);
             iso32(rng, d);
+            d_safe = 0.0f;
             ++pc_mrw;
             atomicAdd(&A.t.n_mrw[c], 1u);
           }
@@ -444,6 +459,20 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
 }
 
 template <bool CDF_LDS>
+__global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
+  trace_fp32_body<CDF_LDS>(A);
+}
+
+// Many disks in one launch: workgroup b works on disk block_disk[b] for the
+// whole launch (its tables stay in LDS), taking packets from that disk's
+// counter; workgroups are shared out in proportion to the disks' packets.
+template <bool CDF_LDS>
+__global__ void __launch_bounds__(BS32) trace_fp32_batch_kernel(const TraceArgs* __restrict__ As,
+                                                                const int* __restrict__ block_disk) {
+  trace_fp32_body<CDF_LDS>(As[block_disk[blockIdx.x]]);
+}
+
+template <bool CDF_LDS>
 int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   auto kern = trace_fp32_kernel<CDF_LDS>;
   if (lds > 64 * 1024)
@@ -473,6 +502,49 @@ int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
   size_t with = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, true);
   if (with <= cap) return launch32<true>(ctx, a, with, s);
   return launch32<false>(ctx, a, lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, false), s);
+}
+
+size_t trace_fp32_lds(const DevModel& M, bool with_cdf) {
+  return lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, with_cdf);
+}
+
+size_t trace_fp32_lds_cap() { return 155 * 1024; }
+
+int trace_fp32_blocks_per_cu(size_t lds, bool cdf_lds) {
+  int occ = 0;
+  hipError_t e = cdf_lds ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &occ, trace_fp32_batch_kernel<true>, BS32, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &occ, trace_fp32_batch_kernel<false>, BS32, lds);
+  return (e != hipSuccess || occ < 1) ? 1 : occ;
+}
+
+// Kernel attributes are set here, outside any stream capture.
+int prepare_trace_fp32_batch(size_t lds, bool cdf_lds) {
+  if (lds <= 64 * 1024) return MCRT_OK;
+  hipError_t e = cdf_lds ? hipFuncSetAttribute((const void*)trace_fp32_batch_kernel<true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                         : hipFuncSetAttribute((const void*)trace_fp32_batch_kernel<false>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)e;  // not needed on every runtime; a real limit shows at launch
+  (void)hipGetLastError();
+  return MCRT_OK;
+}
+
+int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk, int n_blocks,
+                            size_t lds, bool cdf_lds, hipStream_t s) {
+  if (cdf_lds)
+    hipLaunchKernelGGL(trace_fp32_batch_kernel<true>, dim3(n_blocks), dim3(BS32), lds, s, d_args,
+                       d_block_disk);
+  else
+    hipLaunchKernelGGL(trace_fp32_batch_kernel<false>, dim3(n_blocks), dim3(BS32), lds, s, d_args,
+                       d_block_disk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(nullptr, std::string("batched trace launch: ") + hipGetErrorString(e));
+    return MCRT_E_HIP;
+  }
+  return MCRT_OK;
 }
 
 }  // namespace mcrt

@@ -25,7 +25,8 @@ COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "la
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
-           "mcrt_get_size", "mcrt_set_T", "mcrt_strerror", "mcrt_last_error"]
+           "mcrt_get_size", "mcrt_set_T", "mcrt_strerror", "mcrt_last_error",
+           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint"]
 
 
 class McrtError(RuntimeError):
@@ -57,7 +58,7 @@ class Options(C.Structure):
                 ("pda_visits", C.c_int32), ("pda_max_sweeps", C.c_int32),
                 ("pda_tol", C.c_double), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
                 ("mrw_coef_T", C.c_int32), ("block_size", C.c_int32),
-                ("blocks_per_cu", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("pda_solver", C.c_int32)]
 
 
 class PdaStats(C.Structure):
@@ -102,6 +103,9 @@ def lib():
         L.mcrt_strerror.restype = C.c_char_p
         L.mcrt_last_error.argtypes = []
         L.mcrt_last_error.restype = C.c_char_p
+        L.mcrt_batch_run.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp, vp]
+        L.mcrt_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mcrt_pda_adjoint.argtypes = [vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -136,7 +140,7 @@ class Context:
                  n_inc: int = 10, max_events: int = 1 << 30, pda_visits: int = 100,
                  pda_max_sweeps: int = 50, pda_tol: float = 1e-8, cg_max_iter: int = 20000,
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
-                 blocks_per_cu: int = 0, rho=None):
+                 blocks_per_cu: int = 0, pda_solver: int = 0, rho=None):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()
@@ -147,6 +151,7 @@ class Context:
         o.pda_max_sweeps, o.pda_tol, o.cg_max_iter, o.cg_tol = pda_max_sweeps, pda_tol, \
             cg_max_iter, cg_tol
         o.mrw_coef_T, o.block_size, o.blocks_per_cu = mrw_coef_T, block_size, blocks_per_cu
+        o.pda_solver = pda_solver
         self.options = o
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
@@ -255,3 +260,38 @@ class Context:
 
     def set_T(self, T, stream=None):
         _check(lib().mcrt_set_T(self.handle, _ptr(T), _stream(stream)), "mcrt_set_T")
+
+    def pda_linear(self, mask, T_D, T_bc, rho=None, kscale=None, stream=None):
+        """mcrt_pda_linear: one PDA solve with D frozen at T_D; returns (T, stats)."""
+        import torch
+        T_out = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        st = PdaStats()
+        rc = lib().mcrt_pda_linear(self.handle, _ptr(mask), _ptr(rho), _ptr(kscale), _ptr(T_D),
+                                   _ptr(T_bc), _ptr(T_out), C.byref(st), _stream(stream))
+        _check(rc, "mcrt_pda_linear")
+        return T_out, {f: getattr(st, f) for f, _ in PdaStats._fields_}
+
+    def pda_adjoint(self, dJdT, stream=None):
+        """mcrt_pda_adjoint of the last pda_linear: (dJ/dlog rho, dJ/ds)."""
+        import torch
+        g_r = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        g_s = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        rc = lib().mcrt_pda_adjoint(self.handle, _ptr(dJdT.contiguous()), _ptr(g_r), _ptr(g_s),
+                                    _stream(stream))
+        _check(rc, "mcrt_pda_adjoint")
+        return g_r, g_s
+
+
+def batch_run(contexts, n_packets, seeds, n_iter: int = 5, use_graph: bool = True,
+              stream=None):
+    """mcrt_batch_run over Context objects; returns the per-disk PDA statistics
+    of the last pass."""
+    n = len(contexts)
+    handles = (C.c_void_p * n)(*[c.handle.value for c in contexts])
+    npk = (C.c_uint64 * n)(*[int(x) for x in n_packets])
+    sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    stats = (PdaStats * n)()
+    rc = lib().mcrt_batch_run(handles, n, npk, sd, n_iter, int(use_graph), stats,
+                              _stream(stream))
+    _check(rc, "mcrt_batch_run")
+    return [{f: getattr(s, f) for f, _ in PdaStats._fields_} for s in stats]

@@ -210,6 +210,32 @@ def config(name: str):
     raise KeyError(name)
 
 
+def pda_grad_inputs(disk: Disk, chi_R, tau_min: float = 10.0):
+    """Inputs of the differentiation workload on ``disk``.
+
+    T_D = T_bc = T_star (R_star / 2r)^(1/2) at the cell-centre radius (the
+    optically thin gray temperature, a smooth field); region = cells whose
+    vertical Rosseland optical depth from the pole to the cell centre exceeds
+    ``tau_min``, the depth summed along theta at fixed r with
+    ``chi_R(T)`` (cm^2/g, a callable the caller takes from a temperature
+    table) evaluated at T_D; extinction scales 1; objective weights
+    w_c = m_c / sum m over the midplane row (mass-weighted midplane T).
+    Returns (T_D, T_bc, mask uint8, kscale, w), all [n_cells]."""
+    rc = 0.5 * (disk.r_edges[:-1] + disk.r_edges[1:])
+    T_D = np.repeat(disk.T_star * np.sqrt(disk.R_star / (2.0 * rc)), disk.n_mu)
+    th = np.arccos(np.clip(disk.mu_edges, -1.0, 1.0))       # decreasing with mu
+    dth = th[:-1] - th[1:]                                    # [n_mu] > 0
+    dtau = (disk.rho * np.asarray(chi_R(T_D))).reshape(disk.n_r, disk.n_mu) \
+        * rc[:, None] * dth[None, :]
+    above = np.cumsum(dtau[:, ::-1], axis=1)[:, ::-1] - dtau  # cells nearer the pole
+    tau_c = above + 0.5 * dtau
+    mask = (tau_c > tau_min).astype(np.uint8).reshape(-1)
+    m = (disk.rho * cell_volumes(disk)).reshape(disk.n_r, disk.n_mu)
+    w = np.zeros((disk.n_r, disk.n_mu))
+    w[:, 0] = m[:, 0] / m[:, 0].sum()
+    return T_D, T_D.copy(), mask, np.ones(disk.n_cells), w.reshape(-1)
+
+
 def batch_draws(n_disks: int = 64, seed: int = 3) -> List[dict]:
     """Draw the batched workload: per disk, in this order, log10 M ~ U(-5,-1),
     H/r0 ~ U(0.02, 0.05), n_r ~ U{50..200}, packets ~ logU(1e6, 1e7)."""

@@ -202,7 +202,8 @@ def test_plain_run_statistical_parity(mcrt, oracle_mod, torch_cuda, precision):
     assert Sg.sum(axis=(1, 2)).mean() == pytest.approx(So.sum(axis=(1, 2)).mean(), rel=2e-3)
 
 
-def test_pda_matches_oracle_cholesky(mcrt, oracle_mod, torch_cuda):
+@pytest.mark.parametrize("solver", [1, 2])
+def test_pda_matches_oracle_cholesky(mcrt, oracle_mod, torch_cuda, solver):
     """Same region and Dirichlet temperatures: the GPU Jacobi-PCG with Picard
     sweeps reproduces the oracle's banded-Cholesky Picard solution."""
     torch = torch_cuda
@@ -213,7 +214,7 @@ def test_pda_matches_oracle_cholesky(mcrt, oracle_mod, torch_cuda):
     mask = np.zeros((d.n_r, d.n_mu), np.uint8)
     mask[5:35, 0:12] = 1
     mask[20:24, 12:16] = 1
-    ctx = mcrt.Context(d)
+    ctx = mcrt.Context(d, pda_solver=solver)
     ctx.set_T(torch.from_numpy(T_mc).cuda())
     st = ctx.pda_solve(torch.from_numpy(mask.reshape(-1)).cuda())
     T_g = ctx.get(mcrt.GET_T).cpu().numpy()
