@@ -9,9 +9,13 @@ cells, 100 wavelength bins, kappa ~ 1/lambda beyond 1 micron, albedo 0.5,
 midplane radial optical depth 1e5 (inputs synthetic and seeded).
 
 Printed: one JSON line with packets/s of the whole step, the roofline of the
-trace kernel (events x FP operations per event, from the HIP-event duration
-of the kernel), and the CPU oracle timed on a bounded sample of the same
-workload on this host.
+trace kernel (events x FP operations per event over the HIP-event duration of
+the kernel), the midplane-temperature error of the timed run against a
+reference run (FP64, no random walk, 10x the packets), the plain FP64 path on
+the same step, the batched form over the 64-disk workload at reduced packet
+counts, the PDA and its adjoint on the 200 x 120 differentiation workload,
+and the CPU oracle timed on a bounded sample of the same step on this host.
+Stage lines go to stderr.
 """
 from __future__ import annotations
 
@@ -35,6 +39,15 @@ if ROOT not in sys.path:
 # and a reemission; a launch places the packet on the star.
 FLOPS_PER_EVENT = {"cross": 62, "scat": 25, "abs": 90, "mrw": 270, "launch": 40}
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
+HBM_PEAK = 8.0e12
+# Jacobi-PCG bytes per unknown and iteration (FP64): the operator product
+# reads diag, two couplings and p and writes q (40 B); the update reads x, r,
+# p, q and diag and writes x, r and p (64 B).
+PCG_BYTES_PER_UNKNOWN = 104
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -43,10 +56,20 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
-    p.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison step")
     p.add_argument("--packets", type=int, default=1000000)
-    p.add_argument("--cpu-packets", type=int, default=300000)
+    p.add_argument("--ref-factor", type=int, default=10,
+                   help="packets of the reference run (FP64, no MRW) as a multiple of --packets")
+    p.add_argument("--batch-scale", type=float, default=0.01,
+                   help="packets of the 64-disk batched workload as a fraction of its draws")
+    p.add_argument("--cpu-packets", type=int, default=1000000)
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-ref", action="store_true")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-pda", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="only copy this many MiB device to device once (a plain copy kernel of "
+                        "known size, to scale the HBM byte counters) and exit")
     return p.parse_args()
 
 
@@ -67,6 +90,80 @@ def cpu_baseline(disk, opts, n_packets):
                       % (n_packets, dt)}
 
 
+def midplane_error(disk, T, T_ref, visits, region):
+    """Mass-weighted mean and max |T/T_ref - 1| over the midplane row, cells
+    with >= 100 packet entries or in the PDA region; fraction within 1 %."""
+    import numpy as np
+    from paper_0902_3092_amd import workloads as W
+    n_mu = disk.n_mu
+    m = (disk.rho * W.cell_volumes(disk))[0::n_mu]
+    T, T_ref = T[0::n_mu], T_ref[0::n_mu]
+    ok = ((visits[0::n_mu] >= 100) | (region[0::n_mu] == 1)) & (T_ref > 0) & (m > 0)
+    if not ok.any():
+        return None
+    e = np.abs(T[ok] / T_ref[ok] - 1.0)
+    return {"mean_mass_weighted": float((e * m[ok]).sum() / m[ok].sum()), "max": float(e.max()),
+            "frac_within_1pct": float((e <= 0.01).mean()), "cells": int(ok.sum())}
+
+
+def run_once(ctx, n, seed):
+    ctx.reset()
+    ctx.trace(n, seed)
+    ctx.update_T()
+    return ctx.pda_solve()
+
+
+def fields(ctx, mcrt):
+    return (ctx.get(mcrt.GET_T).cpu().numpy(), ctx.get(mcrt.GET_VISITS).cpu().numpy(),
+            ctx.get(mcrt.GET_REGION).cpu().numpy())
+
+
+def batched(mcrt, W, scale, torch):
+    draws = W.batch_draws()
+    ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
+                         pda_visits=100) for b in draws]
+    npk = [max(1000, int(round(b["n_packets"] * scale))) for b in draws]
+    seeds = [b["seed"] for b in draws]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mcrt.batch_run(ctxs, npk, seeds, n_iter=1, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": sum(npk) / dt, "unit": "photon packets/s", "ms": dt * 1e3,
+            "disks": len(ctxs), "packets": sum(npk), "packet_scale": scale, "iterations": 1,
+            "graph": True, "cells": int(sum(c.n_cells for c in ctxs)),
+            "pda_region_cells": int(sum(s["n_region"] for s in st)),
+            "pda_cg_iters_max": int(max(s["cg_iters_total"] for s in st))}
+
+
+def pda_grad(mcrt, W, torch):
+    import numpy as np
+    d, _ = W.config("pda_grad")
+    ctx = mcrt.Context(d)
+    tb = ctx.tables()
+    chi = lambda T: np.interp(T, tb["T"], 1.0 / (3.0 * tb["Drho"]))
+    T_D, T_bc, mask, ks, w = W.pda_grad_inputs(d, chi)
+    dev = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+    m_t, TD_t, Tbc_t, ks_t, w_t = dev(mask, np.uint8), dev(T_D), dev(T_bc), dev(ks), dev(w)
+    ctx.pda_linear(m_t, TD_t, Tbc_t, kscale=ks_t)          # warm-up
+    ctx.pda_adjoint(w_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ctx.pda_linear(m_t, TD_t, Tbc_t, kscale=ks_t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.pda_adjoint(w_t)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    nbytes = st["cg_iters_total"] * st["n_region"] * PCG_BYTES_PER_UNKNOWN
+    gbs = nbytes / (t1 - t0)
+    return {"workload": "200 r x 120 theta, 1e-1 Msun, region tau_R > 10",
+            "n_region": st["n_region"], "cg_iters": st["cg_iters_total"],
+            "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
+            "pcg_bytes_per_unknown_iter": PCG_BYTES_PER_UNKNOWN,
+            "achieved_GBps": gbs / 1e9, "frac_hbm_peak": gbs / HBM_PEAK}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -75,6 +172,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if a.copy_mib > 0:
+        n = a.copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+        return
 
     from paper_0902_3092_amd import mcrt
     from paper_0902_3092_amd import workloads as W
@@ -95,6 +202,7 @@ def main():
         ctx.update_T()
         return ctx.pda_solve()
 
+    log("warmup %d step(s)" % a.warmup)
     for i in range(a.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -102,6 +210,7 @@ def main():
            for _ in range(a.steps)]
     counters = []
     pda = None
+    log("timing %d step(s)" % a.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
@@ -111,6 +220,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / a.steps
     trace_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    T_meas, vis_meas, reg_meas = fields(ctx, mcrt)
     c = counters[-1]
     flops = sum(FLOPS_PER_EVENT[k] * c[k] for k in FLOPS_PER_EVENT)
     t_trace = float(np.mean(trace_ms)) * 1e-3
@@ -140,22 +250,54 @@ def main():
         "events_per_step": c,
         "pda": {k: pda[k] for k in ("sweeps", "cg_iters_total", "n_region")},
     }
+    T64 = None
     if not a.no_plain and a.precision != "fp64":
-        # the plain FP64 path on the same step, for comparison (one timed step)
+        log("plain FP64 step")
         ctx64 = mcrt.Context(disk, precision="fp64", mrw=True, gamma=o.gamma,
                              n_int_min=o.n_int_min, pda_visits=o.pda_visits, n_T=o.n_T)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx64.reset()
-        ctx64.trace(N, o.seed + 777)
-        ctx64.update_T()
-        ctx64.pda_solve()
+        run_once(ctx64, N, o.seed + 777)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        T64, vis64, reg64 = fields(ctx64, mcrt)
         out["plain_fp64"] = {"value": N / dt, "ms_per_step": dt * 1e3, "steps": 1}
+        del ctx64
+    if not a.no_ref:
+        nref = a.ref_factor * N
+        log("reference run: FP64, no MRW, %d packets" % nref)
+        ref = mcrt.Context(disk, precision="fp64", mrw=False, pda_visits=o.pda_visits, n_T=o.n_T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # one run of nref packets, traced in chunks of N (same tallies)
+        ref.reset()
+        for k in range(a.ref_factor):
+            ref.trace(N, o.seed + 4242, n_total=nref, offset=k * N)
+            torch.cuda.synchronize()
+            log("reference chunk %d/%d done (%.1f s)" % (k + 1, a.ref_factor,
+                                                          time.perf_counter() - t0))
+        ref.update_T()
+        ref.pda_solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        T_ref = ref.get(mcrt.GET_T).cpu().numpy()
+        out["midplane_T_error"] = {
+            "reference": "FP64, no MRW, %d packets, same PDA rule (%.1f s)" % (nref, dt),
+            "timed_run": midplane_error(disk, T_meas, T_ref, vis_meas, reg_meas)}
+        if T64 is not None:
+            out["midplane_T_error"]["plain_fp64"] = midplane_error(disk, T64, T_ref, vis64, reg64)
+        del ref
+    if not a.no_batch:
+        log("batched: 64 disks x %.3g of the drawn packets, one graph-captured pass"
+            % a.batch_scale)
+        out["batched"] = batched(mcrt, W, a.batch_scale, torch)
+    if not a.no_pda:
+        log("PDA and adjoint on the differentiation workload")
+        out["pda_grad"] = pda_grad(mcrt, W, torch)
     if not a.no_cpu:
+        log("CPU oracle, %d packets" % a.cpu_packets)
         out["cpu_baseline"] = cpu_baseline(disk, o, a.cpu_packets)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
