@@ -40,10 +40,13 @@ if ROOT not in sys.path:
 FLOPS_PER_EVENT = {"cross": 62, "scat": 25, "abs": 90, "mrw": 270, "launch": 40}
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
 HBM_PEAK = 8.0e12
-# Jacobi-PCG bytes per unknown and iteration (FP64): the operator product
+# PCG bytes per unknown and iteration (FP64).  Jacobi: the operator product
 # reads diag, two couplings and p and writes q (40 B); the update reads x, r,
-# p, q and diag and writes x, r and p (64 B).
-PCG_BYTES_PER_UNKNOWN = 104
+# p, q and diag and writes x, r and p (64 B).  Theta-line preconditioner: the
+# update no longer reads diag (-8 B); the forward sweep reads r, the pivot and
+# a coupling and writes y, the backward sweep reads y, the pivot and a
+# coupling and writes z (+64 B).
+PCG_BYTES_PER_UNKNOWN = {0: 104, 1: 160}
 
 
 def log(msg):
@@ -57,10 +60,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     p.add_argument("--packets", type=int, default=1000000)
-    p.add_argument("--ref-factor", type=int, default=10,
+    p.add_argument("--ref-factor", type=int, default=4,
                    help="packets of the reference run (FP64, no MRW) as a multiple of --packets")
     p.add_argument("--batch-scale", type=float, default=0.01,
                    help="packets of the 64-disk batched workload as a fraction of its draws")
+    p.add_argument("--ensemble", type=int, default=16,
+                   help="independent passes of the same step in one batched launch")
     p.add_argument("--cpu-packets", type=int, default=1000000)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-ref", action="store_true")
@@ -90,20 +95,26 @@ def cpu_baseline(disk, opts, n_packets):
                       % (n_packets, dt)}
 
 
-def midplane_error(disk, T, T_ref, visits, region):
+def midplane_error(disk, T, T_ref, visits, region, n_abs):
     """Mass-weighted mean and max |T/T_ref - 1| over the midplane row, cells
-    with >= 100 packet entries or in the PDA region; fraction within 1 %."""
+    with >= 100 packet entries or in the PDA region; fraction within 1 %; and
+    the photon noise 1/(4 sqrt(N_abs)) of the run's Monte Carlo cells among
+    them, mass-weighted (the PDA cells' error is not photon noise)."""
     import numpy as np
     from paper_0902_3092_amd import workloads as W
     n_mu = disk.n_mu
     m = (disk.rho * W.cell_volumes(disk))[0::n_mu]
     T, T_ref = T[0::n_mu], T_ref[0::n_mu]
-    ok = ((visits[0::n_mu] >= 100) | (region[0::n_mu] == 1)) & (T_ref > 0) & (m > 0)
+    reg, na = region[0::n_mu], n_abs[0::n_mu].astype(np.float64)
+    ok = ((visits[0::n_mu] >= 100) | (reg == 1)) & (T_ref > 0) & (m > 0)
     if not ok.any():
         return None
     e = np.abs(T[ok] / T_ref[ok] - 1.0)
+    mc = ok & (reg != 1) & (na > 0)
+    noise = (float((m[mc] / (4.0 * np.sqrt(na[mc]))).sum() / m[mc].sum()) if mc.any() else None)
     return {"mean_mass_weighted": float((e * m[ok]).sum() / m[ok].sum()), "max": float(e.max()),
-            "frac_within_1pct": float((e <= 0.01).mean()), "cells": int(ok.sum())}
+            "frac_within_1pct": float((e <= 0.01).mean()), "cells": int(ok.sum()),
+            "pda_cells": int((ok & (reg == 1)).sum()), "photon_noise_mass_weighted": noise}
 
 
 def run_once(ctx, n, seed):
@@ -115,7 +126,7 @@ def run_once(ctx, n, seed):
 
 def fields(ctx, mcrt):
     return (ctx.get(mcrt.GET_T).cpu().numpy(), ctx.get(mcrt.GET_VISITS).cpu().numpy(),
-            ctx.get(mcrt.GET_REGION).cpu().numpy())
+            ctx.get(mcrt.GET_REGION).cpu().numpy(), ctx.get(mcrt.GET_N_ABS).cpu().numpy())
 
 
 def batched(mcrt, W, scale, torch):
@@ -134,6 +145,23 @@ def batched(mcrt, W, scale, torch):
             "graph": True, "cells": int(sum(c.n_cells for c in ctxs)),
             "pda_region_cells": int(sum(s["n_region"] for s in st)),
             "pda_cg_iters_max": int(max(s["cg_iters_total"] for s in st))}
+
+
+def ensemble(mcrt, disk, o, n_packets, K, torch):
+    """K independent passes of the timed step (seeds differ) as one batched
+    launch: the passes' longest random walks overlap instead of queueing."""
+    ctxs = [mcrt.Context(disk, precision="fp32", mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                         pda_visits=o.pda_visits, n_T=o.n_T) for _ in range(K)]
+    seeds = [o.seed + 5000 + q for q in range(K)]
+    mcrt.batch_run(ctxs, [n_packets] * K, seeds, n_iter=1, use_graph=True)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mcrt.batch_run(ctxs, [n_packets] * K, seeds, n_iter=1, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": K * n_packets / dt, "unit": "photon packets/s", "passes": K,
+            "packets_per_pass": n_packets, "ms": dt * 1e3, "graph": True,
+            "pda_region_cells_max": int(max(x["n_region"] for x in st))}
 
 
 def pda_grad(mcrt, W, torch):
@@ -155,12 +183,14 @@ def pda_grad(mcrt, W, torch):
     ctx.pda_adjoint(w_t)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    nbytes = st["cg_iters_total"] * st["n_region"] * PCG_BYTES_PER_UNKNOWN
+    bpu = PCG_BYTES_PER_UNKNOWN[ctx.options.pda_precond]
+    nbytes = st["cg_iters_total"] * st["n_region"] * bpu
     gbs = nbytes / (t1 - t0)
     return {"workload": "200 r x 120 theta, 1e-1 Msun, region tau_R > 10",
+            "preconditioner": "theta lines" if ctx.options.pda_precond else "Jacobi",
             "n_region": st["n_region"], "cg_iters": st["cg_iters_total"],
             "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
-            "pcg_bytes_per_unknown_iter": PCG_BYTES_PER_UNKNOWN,
+            "pcg_bytes_per_unknown_iter": bpu,
             "achieved_GBps": gbs / 1e9, "frac_hbm_peak": gbs / HBM_PEAK}
 
 
@@ -220,7 +250,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / a.steps
     trace_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
-    T_meas, vis_meas, reg_meas = fields(ctx, mcrt)
+    T_meas, vis_meas, reg_meas, nabs_meas = fields(ctx, mcrt)
     c = counters[-1]
     flops = sum(FLOPS_PER_EVENT[k] * c[k] for k in FLOPS_PER_EVENT)
     t_trace = float(np.mean(trace_ms)) * 1e-3
@@ -260,7 +290,7 @@ def main():
         run_once(ctx64, N, o.seed + 777)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        T64, vis64, reg64 = fields(ctx64, mcrt)
+        T64, vis64, reg64, nabs64 = fields(ctx64, mcrt)
         out["plain_fp64"] = {"value": N / dt, "ms_per_step": dt * 1e3, "steps": 1}
         del ctx64
     if not a.no_ref:
@@ -283,11 +313,14 @@ def main():
         T_ref = ref.get(mcrt.GET_T).cpu().numpy()
         out["midplane_T_error"] = {
             "reference": "FP64, no MRW, %d packets, same PDA rule (%.1f s)" % (nref, dt),
-            "timed_run": midplane_error(disk, T_meas, T_ref, vis_meas, reg_meas)}
+            "timed_run": midplane_error(disk, T_meas, T_ref, vis_meas, reg_meas, nabs_meas)}
         if T64 is not None:
-            out["midplane_T_error"]["plain_fp64"] = midplane_error(disk, T64, T_ref, vis64, reg64)
+            out["midplane_T_error"]["plain_fp64"] = midplane_error(disk, T64, T_ref, vis64, reg64,
+                                                                   nabs64)
         del ref
     if not a.no_batch:
+        log("batched: %d passes of the step in one launch" % a.ensemble)
+        out["batched_same_disk"] = ensemble(mcrt, disk, o, N, a.ensemble, torch)
         log("batched: 64 disks x %.3g of the drawn packets, one graph-captured pass"
             % a.batch_scale)
         out["batched"] = batched(mcrt, W, a.batch_scale, torch)

@@ -101,6 +101,10 @@ typedef struct {
   int32_t block_size;    /* trace workgroup size, 0 = library choice */
   int32_t blocks_per_cu; /* trace workgroups per compute unit, 0 = library choice */
   int32_t pda_solver;    /* 0 auto, 1 grid-wide CG kernels, 2 one workgroup per disk (0) */
+  int32_t pda_precond;   /* CG preconditioner of the one-workgroup solver: 0 Jacobi (the
+                            diagonal), 1 block Jacobi on the theta lines of each radius
+                            (tridiagonal blocks, solved exactly) (1); the grid-wide solver
+                            uses the diagonal */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);

@@ -41,6 +41,11 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
     lds = 0;
     for (int d = 0; d < n_disks; ++d) lds = std::max(lds, mcrt::trace_fp32_lds(ctxs[d]->m, false));
   }
+  // room for the visit histograms of the disks whose tables and histogram fit
+  for (int d = 0; d < n_disks; ++d) {
+    size_t want = mcrt::trace_fp32_lds(ctxs[d]->m, cdf_lds) + (size_t)4 * ctxs[d]->n_cells;
+    if (want <= mcrt::trace_fp32_lds_cap()) lds = std::max(lds, want);
+  }
   const int per_cu = mcrt::trace_fp32_blocks_per_cu(lds, cdf_lds);
   const long long total_blocks = std::max<long long>((long long)c0->n_cu * per_cu, n_disks);
   double sumN = 0.0;
@@ -69,6 +74,7 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
       // passes after the first may take the MRW coefficients from the
       // previous pass's (PDA-corrected) temperature
       a.T_coef = (c->opt.mrw_coef_T == 1 && it > 0) ? c->d_T_prev : nullptr;
+      a.vis_lds = mcrt::trace_fp32_lds(c->m, cdf_lds) + (size_t)4 * c->n_cells <= lds;
       ta[(size_t)it * n_disks + d] = a;
     }
   const size_t pda_bytes = mcrt::pda_wg_args_size() * n_disks;

@@ -212,6 +212,7 @@ void mcrt_default_options(mcrt_options* o) {
   o->block_size = 0;
   o->blocks_per_cu = 0;
   o->pda_solver = 0;
+  o->pda_precond = 1;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -238,7 +239,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   if (opt->n_T < 3 || !(opt->T_lo > 0.0) || !(opt->T_hi > opt->T_lo) || opt->n_inc < 1 ||
       opt->max_events < 1 || opt->n_int_min < 0 || !(opt->gamma >= 0.0) ||
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
-      opt->pda_solver > 2)
+      opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1)
     return fail(nullptr, MCRT_E_ARG, "bad options");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)

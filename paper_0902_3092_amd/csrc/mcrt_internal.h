@@ -77,6 +77,7 @@ struct TraceArgs {
   const double* T_coef;        // nullable: fixed T for the MRW coefficients
   mcrt_packet_rec* recs;       // nullable
   int64_t n_recs;
+  int vis_lds;                 // FP32 path: visit counts in a per-workgroup LDS histogram
 };
 
 }  // namespace mcrt

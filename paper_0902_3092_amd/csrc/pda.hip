@@ -88,6 +88,7 @@ struct PdaArrays {
   uint8_t* region;
   uint8_t* touch;
   double *Tw, *Tbc, *diag, *aE, *aN, *b, *x, *r, *p0, *p1, *q;
+  double *z, *lm;  // preconditioned residual; pivots of the theta-line factorisation
   PdaScalars* sc;
 };
 
@@ -459,6 +460,7 @@ struct PdaWgArgs {
   double tol;
   int cg_max_iter;
   double cg_tol2;
+  int precond;              // 0 diagonal, 1 theta lines
   mcrt_pda_stats* stats;    // device, nullable
 };
 
@@ -526,6 +528,117 @@ __device__ void components_wg(const DevModel& M, const PdaArrays& P, int* change
     __syncthreads();
     if (!ch) break;
   }
+}
+
+// Preconditioner of the workgroup CG.  Diagonal (Jacobi), or block Jacobi
+// with one block per radius: the region cells of the theta line i couple to
+// their theta neighbours through aN, a tridiagonal system solved exactly
+// (Thomas algorithm, one thread per line).  The blocks are diagonally
+// dominant (diag sums every face), so the pivots lm stay positive.  lm = 0
+// outside the region.
+__device__ void line_factor(const PdaArrays& P, int n_r, int n_mu) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+    const int c0 = i * n_mu;
+    double mprev = 0.0;
+    for (int j = 0; j < n_mu; ++j) {
+      const int c = c0 + j;
+      double m = 0.0;
+      if (P.region[c] == 1) {
+        const double a = j > 0 ? P.aN[c - 1] : 0.0;
+        m = 1.0 / (P.diag[c] - a * a * mprev);
+      }
+      P.lm[c] = m;
+      mprev = m;
+    }
+  }
+  __syncthreads();
+}
+
+// z = M^-1 v on the region (z = 0 elsewhere).  Ends with a barrier.
+__device__ void wg_precond(const PdaArrays& P, int n_r, int n_mu, int precond, const double* v,
+                           double* z) {
+  const int nc = n_r * n_mu;
+  if (!precond) {
+    for (int c = threadIdx.x; c < nc; c += blockDim.x)
+      z[c] = P.region[c] == 1 ? v[c] / P.diag[c] : 0.0;
+    __syncthreads();
+    return;
+  }
+  __syncthreads();  // v written by other threads
+  for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+    const int c0 = i * n_mu;
+    double y = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < n_mu; ++j) {
+      const int c = c0 + j;
+      const double m = P.lm[c];
+      const double a = j > 0 ? P.aN[c - 1] : 0.0;
+      y = m != 0.0 ? (v[c] + a * y) * m : 0.0;
+      z[c] = y;
+    }
+    double zn = 0.0;
+#pragma unroll 4
+    for (int j = n_mu - 1; j >= 0; --j) {
+      const int c = c0 + j;
+      zn = z[c] + P.aN[c] * P.lm[c] * zn;
+      z[c] = zn;
+    }
+  }
+  __syncthreads();
+}
+
+// Preconditioned CG on the assembled operator: solves A x = b over region ==
+// 1 from the given x; stops when r.z <= tol2 * b.(M^-1 b).
+__device__ int wg_cg(const PdaArrays& P, int n_r, int n_mu, int precond, const double* b,
+                     double* x, int max_iter, double tol2, double* red, double* resid) {
+  const int nc = n_r * n_mu;
+  if (precond) line_factor(P, n_r, n_mu);
+  wg_precond(P, n_r, n_mu, precond, b, P.z);
+  double bb = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x)
+    if (P.region[c] == 1) bb += b[c] * P.z[c];
+  const double ref = wg_reduce<false>(bb, red);
+  for (int c = threadIdx.x; c < nc; c += blockDim.x)
+    if (P.region[c] == 1) P.r[c] = b[c] - apply_A_at(P, x, c, n_r, n_mu);
+  wg_precond(P, n_r, n_mu, precond, P.r, P.z);
+  double rz = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    if (P.region[c] != 1) continue;
+    P.p0[c] = P.z[c];
+    rz += P.r[c] * P.z[c];
+  }
+  rz = wg_reduce<false>(rz, red);
+  int it = 0;
+  while (rz > tol2 * ref && it < max_iter) {
+    double pq = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      double y = apply_A_at(P, P.p0, c, n_r, n_mu);
+      P.q[c] = y;
+      pq += P.p0[c] * y;
+    }
+    pq = wg_reduce<false>(pq, red);
+    const double alpha = pq != 0.0 ? rz / pq : 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      x[c] += alpha * P.p0[c];
+      P.r[c] -= alpha * P.q[c];
+    }
+    wg_precond(P, n_r, n_mu, precond, P.r, P.z);
+    double rzn = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x)
+      if (P.region[c] == 1) rzn += P.r[c] * P.z[c];
+    rzn = wg_reduce<false>(rzn, red);
+    const double beta = rz != 0.0 ? rzn / rz : 0.0;
+    rz = rzn;
+    ++it;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x)
+      if (P.region[c] == 1) P.p0[c] = P.z[c] + beta * P.p0[c];
+    __syncthreads();
+  }
+  *resid = ref > 0.0 ? sqrt(rz / ref) : 0.0;
+  return it;
 }
 
 __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
@@ -632,51 +745,10 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
         P.x[c] = t2 * t2;
       }
       __syncthreads();
-      // Jacobi-PCG from the current T^4
-      double rz = 0.0, bb = 0.0;
-      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        if (P.region[c] != 1) continue;
-        double r = P.b[c] - apply_A_at(P, P.x, c, n_r, n_mu);
-        P.r[c] = r;
-        double z = r / P.diag[c];
-        P.p0[c] = z;
-        rz += r * z;
-        bb += P.b[c] * P.b[c] / P.diag[c];
-      }
-      rz = wg_reduce<false>(rz, red);
-      const double rz_ref = wg_reduce<false>(bb, red);
-      int it = 0;
-      while (rz > a.cg_tol2 * rz_ref && it < a.cg_max_iter) {
-        double pq = 0.0;
-        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-          if (P.region[c] != 1) continue;
-          double y = apply_A_at(P, P.p0, c, n_r, n_mu);
-          P.q[c] = y;
-          pq += P.p0[c] * y;
-        }
-        pq = wg_reduce<false>(pq, red);
-        const double alpha = pq != 0.0 ? rz / pq : 0.0;
-        double rzn = 0.0;
-        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-          if (P.region[c] != 1) continue;
-          P.x[c] += alpha * P.p0[c];
-          double r = P.r[c] - alpha * P.q[c];
-          P.r[c] = r;
-          rzn += r * r / P.diag[c];
-        }
-        rzn = wg_reduce<false>(rzn, red);
-        const double beta = rz != 0.0 ? rzn / rz : 0.0;
-        rz = rzn;
-        ++it;
-        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-          if (P.region[c] != 1) continue;
-          P.p0[c] = P.r[c] / P.diag[c] + beta * P.p0[c];
-        }
-        __syncthreads();
-      }
+      // PCG from the current T^4
+      int it = wg_cg(P, n_r, n_mu, a.precond, P.b, P.x, a.cg_max_iter, a.cg_tol2, red, &resid);
       iters_total += it;
       iters_last = it;
-      resid = rz_ref > 0.0 ? sqrt(rz / rz_ref) : 0.0;
       double ch = 0.0;
       for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         if (P.region[c] != 1) continue;
@@ -734,7 +806,7 @@ int launch_zero(void* p, size_t bytes, hipStream_t s) {
 static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
   const int nc = ctx->n_cells, n_r = ctx->n_r, n_mu = ctx->n_mu;
   size_t nd = (size_t)nc * sizeof(double);
-  size_t bytes = align256(sizeof(PdaScalars)) + 2 * align256(nc) + 11 * align256(nd) +
+  size_t bytes = align256(sizeof(PdaScalars)) + 2 * align256(nc) + 13 * align256(nd) +
                  align256(n_r * sizeof(double)) + align256(n_mu * sizeof(double)) +
                  2 * align256(nd) + align256(sizeof(PdaWgArgs)) + align256(sizeof(mcrt_pda_stats));
   if (ctx->d_pda_blob == nullptr) {
@@ -759,7 +831,7 @@ static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
         Amu[i * n_mu + j] = PI * (b * b - a * a) * 2.0 * std::sqrt(std::fmax(0.0, 1.0 - mf * mf));
       }
     char* q = (char*)ctx->d_pda_blob;
-    q += align256(sizeof(PdaScalars)) + 2 * align256(nc) + 11 * align256(nd);
+    q += align256(sizeof(PdaScalars)) + 2 * align256(nc) + 13 * align256(nd);
     hipMemcpy(q, rc.data(), n_r * sizeof(double), hipMemcpyHostToDevice);
     q += align256(n_r * sizeof(double));
     hipMemcpy(q, thc.data(), n_mu * sizeof(double), hipMemcpyHostToDevice);
@@ -775,7 +847,8 @@ static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
   q += align256(nc);
   P.touch = (uint8_t*)q;
   q += align256(nc);
-  double** arr[11] = {&P.Tw, &P.Tbc, &P.diag, &P.aE, &P.aN, &P.b, &P.x, &P.r, &P.p0, &P.p1, &P.q};
+  double** arr[13] = {&P.Tw, &P.Tbc, &P.diag, &P.aE, &P.aN, &P.b, &P.x, &P.r, &P.p0, &P.p1, &P.q,
+                      &P.z, &P.lm};
   for (auto a : arr) {
     *a = (double*)q;
     q += align256(nd);
@@ -818,6 +891,7 @@ static int pda_solve_wg(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, 
   h.tol = ctx->opt.pda_tol;
   h.cg_max_iter = ctx->opt.cg_max_iter;
   h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  h.precond = ctx->opt.pda_precond;
   PdaWgArgs* d_args;
   mcrt_pda_stats* d_stats;
   pda_wg_slots(ctx, &d_args, &d_stats);
@@ -956,6 +1030,7 @@ struct PdaLinArgs {
   uint8_t* reg_out;
   int cg_max_iter;
   double cg_tol2;
+  int precond;
   mcrt_pda_stats* stats;
   // adjoint
   const double* dJdT;
@@ -980,55 +1055,6 @@ __device__ inline double lin_cond(const PdaLinArgs& a, int i, int j, int ib, int
   double s = Ra + Rb;
   if (dA_dRa) *dA_dRa = -A / dist * 2.0 / (s * s);
   return A * (2.0 / s) / dist;
-}
-
-// Jacobi-PCG on the assembled operator: solves A x = b over region == 1
-__device__ int wg_cg(const PdaArrays& P, int n_r, int n_mu, const double* b, double* x,
-                     int max_iter, double tol2, double* red, double* resid) {
-  const int nc = n_r * n_mu;
-  double rz = 0.0, bb = 0.0;
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    if (P.region[c] != 1) continue;
-    double r = b[c] - apply_A_at(P, x, c, n_r, n_mu);
-    P.r[c] = r;
-    double z = r / P.diag[c];
-    P.p0[c] = z;
-    rz += r * z;
-    bb += b[c] * b[c] / P.diag[c];
-  }
-  rz = wg_reduce<false>(rz, red);
-  const double ref = wg_reduce<false>(bb, red);
-  int it = 0;
-  while (rz > tol2 * ref && it < max_iter) {
-    double pq = 0.0;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      if (P.region[c] != 1) continue;
-      double y = apply_A_at(P, P.p0, c, n_r, n_mu);
-      P.q[c] = y;
-      pq += P.p0[c] * y;
-    }
-    pq = wg_reduce<false>(pq, red);
-    const double alpha = pq != 0.0 ? rz / pq : 0.0;
-    double rzn = 0.0;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      if (P.region[c] != 1) continue;
-      x[c] += alpha * P.p0[c];
-      double r = P.r[c] - alpha * P.q[c];
-      P.r[c] = r;
-      rzn += r * r / P.diag[c];
-    }
-    rzn = wg_reduce<false>(rzn, red);
-    const double beta = rz != 0.0 ? rzn / rz : 0.0;
-    rz = rzn;
-    ++it;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      if (P.region[c] != 1) continue;
-      P.p0[c] = P.r[c] / P.diag[c] + beta * P.p0[c];
-    }
-    __syncthreads();
-  }
-  *resid = ref > 0.0 ? sqrt(rz / ref) : 0.0;
-  return it;
 }
 
 // Forward: region from the mask (components without Dirichlet contact -> 2),
@@ -1097,7 +1123,7 @@ __global__ void __launch_bounds__(WG) pda_linear_kernel(const PdaLinArgs* args) 
   }
   __syncthreads();
   double resid;
-  int it = wg_cg(P, n_r, n_mu, P.Tw, P.x, a.cg_max_iter, a.cg_tol2, red, &resid);
+  int it = wg_cg(P, n_r, n_mu, a.precond, P.Tw, P.x, a.cg_max_iter, a.cg_tol2, red, &resid);
   double n1 = 0.0, n2 = 0.0;
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     n1 += P.region[c] == 1 ? 1.0 : 0.0;
@@ -1141,7 +1167,7 @@ __global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args)
   }
   __syncthreads();
   double resid;
-  int it = wg_cg(P, n_r, n_mu, a.g_logrho, P.Tw, a.cg_max_iter, a.cg_tol2, red, &resid);
+  int it = wg_cg(P, n_r, n_mu, a.precond, a.g_logrho, P.Tw, a.cg_max_iter, a.cg_tol2, red, &resid);
   __syncthreads();
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -1240,6 +1266,7 @@ int pda_linear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const doub
   h.reg_out = ctx->d_region;
   h.cg_max_iter = ctx->opt.cg_max_iter;
   h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  h.precond = ctx->opt.pda_precond;
   ctx->lin_rho = h.rho;
   ctx->lin_ready = true;
   return pda_lin_call(ctx, h, false, st, s);
@@ -1265,6 +1292,7 @@ int pda_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_k
   h.g_kscale = g_kscale;
   h.cg_max_iter = ctx->opt.cg_max_iter;
   h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  h.precond = ctx->opt.pda_precond;
   return pda_lin_call(ctx, h, true, st, s);
 }
 
@@ -1296,6 +1324,7 @@ int pda_batch_fill(mcrt_ctx** ctxs, int n, void* host) {
     h.tol = ctx->opt.pda_tol;
     h.cg_max_iter = ctx->opt.cg_max_iter;
     h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+    h.precond = ctx->opt.pda_precond;
     PdaWgArgs* da;
     mcrt_pda_stats* ds;
     pda_wg_slots(ctx, &da, &ds);

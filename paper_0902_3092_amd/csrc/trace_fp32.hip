@@ -33,9 +33,11 @@ struct Lds32 {
   float *mu32, *smu32, *star_cdf, *chi, *omega;
   TabView tv;
   const float* cdf;
+  uint32_t* vis;  // per-workgroup visit histogram [n_cells], or null
 };
 
-size_t lds32_bytes(int n_r, int n_mu, int n_T, int nl, bool with_cdf) {
+// Bytes of the tables; a visit histogram, when used, follows at this offset.
+__host__ __device__ inline size_t lds32_bytes(int n_r, int n_mu, int n_T, int nl, bool with_cdf) {
   size_t dbl = (size_t)(n_r + 1) + (n_mu + 1) + MRW_TAB_N + 6 * (size_t)n_T;
   size_t flt = (size_t)2 * (n_mu + 1) + (size_t)3 * nl + (with_cdf ? (size_t)n_T * nl : 0);
   return dbl * 8 + N_GUIDE * 4 + ((flt * 4 + 7) & ~(size_t)7);
@@ -184,6 +186,11 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
     }
     L.tv = TabView{n_T, nl, M.lnT_lo, M.inv_dlnT, M.lnG0, M.inv_du, N_GUIDE, Tn, G, Drho, kbar,
                    gq, invdT, gslope};
+    L.vis = nullptr;
+    if (A.vis_lds) {
+      L.vis = (uint32_t*)((char*)smem + lds32_bytes(n_r, n_mu, n_T, nl, CDF_LDS));
+      for (int a = threadIdx.x; a < n_r * n_mu; a += blockDim.x) L.vis[a] = 0u;
+    }
   }
   __syncthreads();
 
@@ -197,11 +204,22 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   uint64_t pid = 0;
   uint32_t pc_cross = 0, pc_scat = 0, pc_abs = 0, pc_mrw = 0;
   double rho = 0.0;
-  double Tc = -1.0;
+  double Tc = -1.0;     // running temperature of the cell (lazily from its tally)
+  double im = 0.0;      // 1 / (4 pi m) of the cell
+  double Tfix = 0.0;    // the cell's fixed temperature (frozen field or MRW coefficient field)
+  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
   double mrw_T = -2.0, mrw_Drho = 0.0, mrw_kbar = 0.0;  // MRW coefficients at mrw_T
   float mrw_lim = 0.0f;
   float d_safe = 0.0f;  // lower bound of the distance to every face of the cell
+  // upper bound of that distance (the last computed one plus the path flown
+  // since): while it is within the MRW limit the criterion cannot hold
+  float dm_up = INFINITY;
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // absorptions and MRW steps in the current cell, added to the tallies when
+  // the packet leaves it; the cell's tally after this lane's last deposit and
+  // its temperature (reused when no other packet deposited in between)
+  uint32_t cell_abs = 0, cell_mrw = 0;
+  double E_seen = -1.0, T_seen = 0.0;
 
   for (;;) {
     unsigned long long idle = __ballot(!alive);
@@ -279,11 +297,14 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
         double r2 = (an.A[0] * an.A[0] + an.A[1] * an.A[1]) + an.A[2] * an.A[2];
         j = mu_row(L.mu2, n_mu, r2, an.A[2] * an.A[2]);
         set_anchor(an, L, n_mu, i, j);
-        atomicAdd(&A.t.visits[j], 1u);
         rho = M.rho[j];
+        im = M.inv4pim[j];
+        if (fixT) Tfix = fixT[j];
+        if (L.vis) atomicAdd(&L.vis[j], 1u); else atomicAdd(&A.t.visits[j], 1u);
         Tc = -1.0;
         mrw_T = -2.0;
         d_safe = 0.0f;
+        dm_up = INFINITY;
         n_int = 0;
         ++pc_cross;
       }
@@ -301,6 +322,10 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
       }
       if (!inside && tau_b <= tau) {
         d_safe = 0.0f;
+        dm_up = INFINITY;
+        if (cell_abs) { atomicAdd(&A.t.n_abs[c], cell_abs); cell_abs = 0; }
+        if (cell_mrw) { atomicAdd(&A.t.n_mrw[c], cell_mrw); cell_mrw = 0; }
+        E_seen = -1.0;
         q[0] += sb * d[0]; q[1] += sb * d[1]; q[2] += sb * d[2];
         tau -= tau_b;
         if (tau < 0.0f) tau = 0.0f;
@@ -325,10 +350,12 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
           ++j;
         }
         if (entered) {
-          reanchor(an, q, L, n_mu, i, j);
           int cn = i * n_mu + j;
-          atomicAdd(&A.t.visits[cn], 1u);
           rho = M.rho[cn];
+          im = M.inv4pim[cn];
+          if (fixT) Tfix = fixT[cn];
+          reanchor(an, q, L, n_mu, i, j);
+          if (L.vis) atomicAdd(&L.vis[cn], 1u); else atomicAdd(&A.t.visits[cn], 1u);
         } else if (fate == 0) {
           // into the hole: keep the FP64 position in the anchor
           an.A[0] += (double)q[0]; an.A[1] += (double)q[1]; an.A[2] += (double)q[2];
@@ -341,37 +368,41 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
         float sint = tau / alpha;
         q[0] += sint * d[0]; q[1] += sint * d[1]; q[2] += sint * d[2];
         d_safe -= sint;
+        dm_up += 1.00001f * sint;
         const double* fz = A.frozen_T;
         if (rng.next() < L.omega[k]) {
           ++pc_scat;
+          iso32(rng, d);
         } else {
           ++pc_abs;
-          atomicAdd(&A.t.n_abs[c], 1u);
+          ++cell_abs;
+          // the tally update is in flight while the next draws are made
           double E_old = unsafeAtomicAdd(&A.t.E_abs[c], A.eps);
           float xb = rng.next();
+          iso32(rng, d);
           double T_old = -1.0, T_new;
           if (fz) {
-            T_new = fz[c];
+            T_new = Tfix;
           } else {
-            double im = M.inv4pim[c];
-            T_old = T_of_g(L.tv, E_old * im);
-            T_new = T_of_g(L.tv, (E_old + A.eps) * im);
+            const double E_new = E_old + A.eps;
+            T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
+            T_new = T_of_g(L.tv, E_new * im);
+            E_seen = E_new;
+            T_seen = T_new;
             Tc = T_new;
           }
           Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
           k = reemit_search<float>(R, nl, xb);
         }
-        iso32(rng, d);
         ++n_int;
         if (A.mrw) {
           while (n_int >= A.n_int_min) {
             double T_here;
-            if (fz) T_here = fz[c];
-            else if (A.T_coef) T_here = A.T_coef[c];
+            if (fixT) T_here = Tfix;
             else {
               if (Tc < 0.0)
                 Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT) * M.inv4pim[c]);
+                                                    __HIP_MEMORY_SCOPE_AGENT) * im);
               T_here = Tc;
             }
             if (T_here != mrw_T) {  // MRW coefficients of this cell at this T
@@ -382,9 +413,11 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
             }
             const double Drho = mrw_Drho;
             const float lim = mrw_lim;
+            if (dm_up <= lim) break;
             {
               float dm = min_boundary32(an, L, n_mu, i, j, q);
               d_safe = 0.999f * dm;
+              dm_up = 1.00001f * dm;
               if (!(dm > lim)) break;
             }
             // re-anchor so the sphere radius is exact to FP32 precision of itself
@@ -397,32 +430,42 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
             double s = mrw_escape_s(L.mrw_tab, P0);
             double ell = s * R0 * R0 * rho / Drho;
             double dE = A.eps * rho * mrw_kbar * ell;
+            double E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
             float nv[3];
             iso32(rng, nv);
             q[0] = (float)R0 * nv[0]; q[1] = (float)R0 * nv[1]; q[2] = (float)R0 * nv[2];
-            double E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
             float xb = rng.next();
+            iso32(rng, d);
             double T_old = -1.0, T_new;
             if (fz) {
-              T_new = fz[c];
+              T_new = Tfix;
             } else {
-              double im = M.inv4pim[c];
-              T_old = T_of_g(L.tv, E_old * im);
-              T_new = T_of_g(L.tv, (E_old + dE) * im);
+              const double E_new = E_old + dE;
+              T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
+              T_new = T_of_g(L.tv, E_new * im);
+              E_seen = E_new;
+              T_seen = T_new;
               Tc = T_new;
             }
             Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
             k = reemit_search<float>(R, nl, xb);
-            iso32(rng, d);
             d_safe = 0.0f;
+            dm_up = INFINITY;
             ++pc_mrw;
-            atomicAdd(&A.t.n_mrw[c], 1u);
+            ++cell_mrw;
           }
         }
         tau = -__logf(rng.next());
       }
     }
     if (fate != 0) {
+      if (cell_abs | cell_mrw) {  // the packet ended in a cell (capped)
+        const int c = i * n_mu + j;
+        if (i >= 0 && cell_abs) atomicAdd(&A.t.n_abs[c], cell_abs);
+        if (i >= 0 && cell_mrw) atomicAdd(&A.t.n_mrw[c], cell_mrw);
+        cell_abs = cell_mrw = 0;
+      }
+      E_seen = -1.0;
       if (fate == 1) tot[C_ESCAPED]++;
       else if (fate == 2) { tot[C_STAR]++; unsafeAtomicAdd(A.t.E_star, A.eps); }
       else tot[C_CAPPED]++;
@@ -456,6 +499,13 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
     }
   }
   flush_counters(A.t.counters, tot, N_COUNTERS);
+  if (L.vis) {
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_r * n_mu; a += blockDim.x) {
+      uint32_t v = L.vis[a];
+      if (v) atomicAdd(&A.t.visits[a], v);
+    }
+  }
 }
 
 template <bool CDF_LDS>
@@ -496,12 +546,21 @@ int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
 
 }  // namespace
 
+// LDS: the tables (with the emission CDF when it fits), then the visit
+// histogram when that fits too.
 int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
   const DevModel& M = ctx->m;
   const size_t cap = 155 * 1024;
+  const size_t vis = (size_t)4 * M.n_r * M.n_mu;
+  TraceArgs b = a;
   size_t with = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, true);
-  if (with <= cap) return launch32<true>(ctx, a, with, s);
-  return launch32<false>(ctx, a, lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, false), s);
+  if (with <= cap) {
+    b.vis_lds = with + vis <= cap;
+    return launch32<true>(ctx, b, b.vis_lds ? with + vis : with, s);
+  }
+  size_t without = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, false);
+  b.vis_lds = without + vis <= cap;
+  return launch32<false>(ctx, b, b.vis_lds ? without + vis : without, s);
 }
 
 size_t trace_fp32_lds(const DevModel& M, bool with_cdf) {

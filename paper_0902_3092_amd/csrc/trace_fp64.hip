@@ -38,9 +38,10 @@ struct Lds64 {
   TabView tv;
   const double* cdf64;   // LDS or global
   const float* cdf32;    // LDS guess table (nullptr: search cdf64 directly)
+  uint32_t* vis;         // per-workgroup visit histogram [n_cells], or null
 };
 
-size_t lds_small_bytes(int n_r, int n_mu, int n_T, int nl) {
+__host__ __device__ inline size_t lds_small_bytes(int n_r, int n_mu, int n_T, int nl) {
   return sizeof(double) * ((size_t)2 * (n_r + 1) + (size_t)3 * (n_mu + 1) + (size_t)6 * n_T +
                            (size_t)3 * nl + MRW_TAB_N) +
          sizeof(int) * N_GUIDE;
@@ -161,6 +162,13 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
       for (int a = threadIdx.x; a < n_T * nl; a += blockDim.x) c[a] = M.cdf32[a];
       L.cdf32 = c;
     }
+    L.vis = nullptr;
+    if (A.vis_lds) {
+      size_t off = lds_small_bytes(n_r, n_mu, n_T, nl) +
+                   (CDF_MODE == 2 ? (size_t)n_T * nl * 8 : CDF_MODE == 1 ? (size_t)n_T * nl * 4 : 0);
+      L.vis = (uint32_t*)((char*)smem + off);
+      for (int a = threadIdx.x; a < n_r * n_mu; a += blockDim.x) L.vis[a] = 0u;
+    }
   }
   __syncthreads();
 
@@ -173,8 +181,21 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
   uint64_t pid = 0;
   uint32_t pc_cross = 0, pc_scat = 0, pc_abs = 0, pc_mrw = 0;
   double rho = 0.0;    // density of the current cell
+  double im = 0.0;     // 1 / (4 pi m) of the current cell
   double Tc = -1.0;    // running temperature of the current cell (< 0: not known)
+  double Tfix = 0.0;   // the cell's fixed temperature (frozen field or MRW coefficient field)
+  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
   double mrw_T = -2.0, mrw_Drho = 0.0, mrw_kbar = 0.0, mrw_lim = 0.0;  // MRW coefficients
+  // bounds of the distance to the cell boundary: d_safe below (a flight
+  // shorter than it stays in the cell, so the face distances are not needed),
+  // dm_up above (the last computed distance plus the path flown since: while
+  // it is within the MRW limit the criterion cannot hold)
+  double d_safe = 0.0, dm_up = INFINITY;
+  // absorptions and MRW steps in the current cell, added to the tallies when
+  // the packet leaves it; the cell's tally after this lane's last deposit and
+  // its temperature (reused when no other packet deposited in between)
+  uint32_t cell_abs = 0, cell_mrw = 0;
+  double E_seen = -1.0, T_seen = 0.0;
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   for (;;) {
@@ -248,20 +269,33 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
         i = 0;
         double r2 = (p[0] * p[0] + p[1] * p[1]) + p[2] * p[2];
         j = mu_row(L.mu2, n_mu, r2, p[2] * p[2]);
-        atomicAdd(&A.t.visits[j], 1u);
         rho = M.rho[j];
+        im = M.inv4pim[j];
+        if (fixT) Tfix = fixT[j];
+        if (L.vis) atomicAdd(&L.vis[j], 1u); else atomicAdd(&A.t.visits[j], 1u);
         Tc = -1.0;
         mrw_T = -2.0;
+        d_safe = 0.0;
+        dm_up = INFINITY;
         n_int = 0;
         ++pc_cross;
       }
     } else {
       const int c = i * n_mu + j;
       const double alpha = rho * L.chi[k];
-      int face;
-      double sb = boundary64(L, n_mu, i, j, p, d, face);
-      double tau_b = alpha * sb;
-      if (tau_b <= tau) {
+      int face = 1;
+      double sb = 0.0, tau_b = 0.0;
+      const bool inside = tau < alpha * d_safe;
+      if (!inside) {
+        sb = boundary64(L, n_mu, i, j, p, d, face);
+        tau_b = alpha * sb;
+      }
+      if (!inside && tau_b <= tau) {
+        if (cell_abs) { atomicAdd(&A.t.n_abs[c], cell_abs); cell_abs = 0; }
+        if (cell_mrw) { atomicAdd(&A.t.n_mrw[c], cell_mrw); cell_mrw = 0; }
+        E_seen = -1.0;
+        d_safe = 0.0;
+        dm_up = INFINITY;
         p[0] += sb * d[0]; p[1] += sb * d[1]; p[2] += sb * d[2];
         tau -= tau_b;
         ++pc_cross;
@@ -286,8 +320,10 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
         }
         if (entered) {
           int cn = i * n_mu + j;
-          atomicAdd(&A.t.visits[cn], 1u);
           rho = M.rho[cn];
+          im = M.inv4pim[cn];
+          if (fixT) Tfix = fixT[cn];
+          if (L.vis) atomicAdd(&L.vis[cn], 1u); else atomicAdd(&A.t.visits[cn], 1u);
         }
         Tc = -1.0;
         mrw_T = -2.0;
@@ -296,36 +332,41 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
         // interaction in the cell
         double sint = tau / alpha;
         p[0] += sint * d[0]; p[1] += sint * d[1]; p[2] += sint * d[2];
+        d_safe -= sint;
+        dm_up += 1.000001 * sint;
         const double* fz = A.frozen_T;
         if (rng.next() < L.omega[k]) {
           ++pc_scat;
+          iso64(rng, d);
         } else {
           ++pc_abs;
-          atomicAdd(&A.t.n_abs[c], 1u);
+          ++cell_abs;
+          // the tally update is in flight while the next draws are made
           double E_old = unsafeAtomicAdd(&A.t.E_abs[c], A.eps);
           double xb = rng.next();
+          iso64(rng, d);
           if (fz) {
-            k = reemit64(L, -1.0, fz[c], xb);
+            k = reemit64(L, -1.0, Tfix, xb);
           } else {
-            double im = M.inv4pim[c];
-            double T_old = T_of_g(L.tv, E_old * im);
-            double T_new = T_of_g(L.tv, (E_old + A.eps) * im);
+            const double E_new = E_old + A.eps;
+            double T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
+            double T_new = T_of_g(L.tv, E_new * im);
+            E_seen = E_new;
+            T_seen = T_new;
             Tc = T_new;
             k = reemit64(L, T_old, T_new, xb);
           }
         }
-        iso64(rng, d);
         ++n_int;
         if (A.mrw) {
           // modified random walk while the start criterion holds
           while (n_int >= A.n_int_min) {
             double T_here;
-            if (fz) T_here = fz[c];
-            else if (A.T_coef) T_here = A.T_coef[c];
+            if (fixT) T_here = Tfix;
             else {
               if (Tc < 0.0)
                 Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT) * M.inv4pim[c]);
+                                                    __HIP_MEMORY_SCOPE_AGENT) * im);
               T_here = Tc;
             }
             if (T_here != mrw_T) {  // MRW coefficients of this cell at this T
@@ -336,36 +377,50 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
               mrw_lim = A.gamma * lam_R;
             }
             const double Drho = mrw_Drho;
+            if (dm_up <= mrw_lim) break;
             double dmin = min_boundary64(L, n_mu, i, j, p);
+            d_safe = 0.999 * dmin;
+            dm_up = 1.000001 * dmin;
             if (!(dmin > mrw_lim)) break;
             if (++events > A.max_events) break;
             double R0 = dmin * (1.0 - 1e-6);
             double s = mrw_escape_s(L.mrw_tab, rng.next());
             double ell = s * R0 * R0 * rho / Drho;  // c t = s R0^2 / D
             double dE = A.eps * rho * mrw_kbar * ell;
+            double E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
             double nrm[3];
             iso64(rng, nrm);
             p[0] += R0 * nrm[0]; p[1] += R0 * nrm[1]; p[2] += R0 * nrm[2];
-            double E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
             double xb = rng.next();
+            iso64(rng, d);
             if (fz) {
-              k = reemit64(L, -1.0, fz[c], xb);
+              k = reemit64(L, -1.0, Tfix, xb);
             } else {
-              double im = M.inv4pim[c];
-              double T_old = T_of_g(L.tv, E_old * im);
-              double T_new = T_of_g(L.tv, (E_old + dE) * im);
+              const double E_new = E_old + dE;
+              double T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
+              double T_new = T_of_g(L.tv, E_new * im);
+              E_seen = E_new;
+              T_seen = T_new;
               Tc = T_new;
               k = reemit64(L, T_old, T_new, xb);
             }
-            iso64(rng, d);
+            d_safe = 0.0;
+            dm_up = INFINITY;
             ++pc_mrw;
-            atomicAdd(&A.t.n_mrw[c], 1u);
+            ++cell_mrw;
           }
         }
         tau = -log(rng.next());
       }
     }
     if (fate != 0) {
+      if (cell_abs | cell_mrw) {  // the packet ended in a cell (capped)
+        const int c = i * n_mu + j;
+        if (i >= 0 && cell_abs) atomicAdd(&A.t.n_abs[c], cell_abs);
+        if (i >= 0 && cell_mrw) atomicAdd(&A.t.n_mrw[c], cell_mrw);
+        cell_abs = cell_mrw = 0;
+      }
+      E_seen = -1.0;
       if (fate == 1) tot[C_ESCAPED]++;
       else if (fate == 2) { tot[C_STAR]++; unsafeAtomicAdd(A.t.E_star, A.eps); }
       else tot[C_CAPPED]++;
@@ -400,6 +455,13 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
     }
   }
   flush_counters(A.t.counters, tot, N_COUNTERS);
+  if (L.vis) {
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_r * n_mu; a += blockDim.x) {
+      uint32_t v = L.vis[a];
+      if (v) atomicAdd(&A.t.visits[a], v);
+    }
+  }
 }
 
 __global__ void locate_kernel(const double* r2e, const double* mu2e, int n_r, int n_mu,
@@ -464,15 +526,26 @@ int launch_locate(mcrt_ctx* ctx, const double* xyz, int64_t n, int32_t* cell, hi
   return MCRT_OK;
 }
 
+// LDS: the small tables, the emission CDF in FP64, else its FP32 guide copy,
+// else neither; then the visit histogram when that fits too.
 int launch_trace_fp64(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
   const DevModel& M = ctx->m;
-  const size_t cap = 150 * 1024;
+  const size_t cap = 155 * 1024;
   size_t small = lds_small_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda);
   size_t c64 = (size_t)M.n_T * M.n_lambda * sizeof(double);
   size_t c32 = c64 / 2;
-  if (small + c64 <= cap) return launch_mode<2>(ctx, a, small + c64, s);
-  if (small + c32 <= cap) return launch_mode<1>(ctx, a, small + c32, s);
-  return launch_mode<0>(ctx, a, small, s);
+  const size_t vis = (size_t)4 * M.n_r * M.n_mu;
+  TraceArgs b = a;
+  if (small + c64 <= cap) {
+    b.vis_lds = small + c64 + vis <= cap;
+    return launch_mode<2>(ctx, b, small + c64 + (b.vis_lds ? vis : 0), s);
+  }
+  if (small + c32 <= cap) {
+    b.vis_lds = small + c32 + vis <= cap;
+    return launch_mode<1>(ctx, b, small + c32 + (b.vis_lds ? vis : 0), s);
+  }
+  b.vis_lds = small + vis <= cap;
+  return launch_mode<0>(ctx, b, small + (b.vis_lds ? vis : 0), s);
 }
 
 }  // namespace mcrt
