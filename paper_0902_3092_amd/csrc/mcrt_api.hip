@@ -181,6 +181,7 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
   a.T_coef = (ctx->opt.mrw_coef_T == 1 && ctx->have_T_prev) ? ctx->d_T_prev : nullptr;
   a.recs = recs;
   a.n_recs = n_recs;
+  a.wave_events = ctx->opt.wave_events;
   return a;
 }
 
@@ -213,6 +214,7 @@ void mcrt_default_options(mcrt_options* o) {
   o->blocks_per_cu = 0;
   o->pda_solver = 0;
   o->pda_precond = 1;
+  o->wave_events = 32;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -239,7 +241,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   if (opt->n_T < 3 || !(opt->T_lo > 0.0) || !(opt->T_hi > opt->T_lo) || opt->n_inc < 1 ||
       opt->max_events < 1 || opt->n_int_min < 0 || !(opt->gamma >= 0.0) ||
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
-      opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1)
+      opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0)
     return fail(nullptr, MCRT_E_ARG, "bad options");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)

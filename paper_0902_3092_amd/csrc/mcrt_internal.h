@@ -78,6 +78,7 @@ struct TraceArgs {
   mcrt_packet_rec* recs;       // nullable
   int64_t n_recs;
   int vis_lds;                 // FP32 path: visit counts in a per-workgroup LDS histogram
+  long long wave_events;       // FP32 path: whole-wavefront mode for a lone last packet (0: off)
 };
 
 }  // namespace mcrt

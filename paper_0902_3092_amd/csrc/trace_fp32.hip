@@ -129,7 +129,8 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   return dmin > 0.0f ? dmin : 0.0f;
 }
 
-__device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
+template <class RNG>
+__device__ __forceinline__ void iso32(RNG& r, float d[3]) {
   float w = 2.0f * r.next() - 1.0f;
   float ph = 2.0f * (float)KPI * r.next();
   float st = sqrtf(fmaxf(0.0f, 1.0f - w * w));
@@ -138,6 +139,416 @@ __device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
   d[0] = st * cs;
   d[1] = st * sn;
   d[2] = w;
+}
+
+// ------------------------------------------------------------------ packets
+// Transport state of one packet.
+struct Pk {
+  Anchor an;
+  float q[3], d[3], tau;
+  int k, i, j, n_int;
+  long long events;
+  uint32_t pc_cross, pc_scat, pc_abs, pc_mrw;
+  double rho;                        // density of the cell
+  double im;                         // 1 / (4 pi m) of the cell
+  double Tc;                         // running temperature of the cell (< 0: from its tally)
+  double Tfix;                       // the cell's fixed temperature (frozen or MRW field)
+  double mrw_T, mrw_Drho, mrw_kbar;  // MRW coefficients at mrw_T
+  float mrw_lim;
+  float d_safe;   // lower bound of the distance to every face of the cell
+  float dm_up;    // upper bound of it: the last computed one plus the path flown since
+                  // (while it is within the MRW limit the criterion cannot hold)
+  // absorptions and MRW steps in this stay in the cell, added to the tallies
+  // when the packet leaves it; the cell's tally after this packet's last
+  // deposit and its temperature (reused when nobody deposited in between)
+  uint32_t cell_abs, cell_mrw;
+  double E_seen, T_seen;
+};
+
+// ------------------------------------------------------ whole-wave mode
+// Once every packet of the launch has been handed out, a wavefront whose
+// last live packet is still going runs that packet with all 64 lanes: the
+// control flow is uniform, lane l generates Philox block blk0 + l so one
+// pass of the generator yields 256 draws, and the reemission bin is found by
+// a 64-wide ballot.  A lone lane issues about one instruction per ten
+// cycles, so these cuts in instruction count are what shortens the longest
+// random walks, which set the length of a launch.
+__device__ __forceinline__ int bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ float bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ long long bcast(long long v, int l) {
+  const uint32_t lo = bcast((uint32_t)v, l), hi = bcast((uint32_t)((unsigned long long)v >> 32), l);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ uint64_t bcast(uint64_t v, int l) {
+  return (uint64_t)bcast((long long)v, l);
+}
+__device__ __forceinline__ double bcast(double v, int l) {
+  return __longlong_as_double(bcast((long long)__double_as_longlong(v), l));
+}
+
+__device__ __forceinline__ Pk bcast(const Pk& P, int l) {
+  Pk S;
+  for (int a = 0; a < 3; ++a) {
+    S.an.A[a] = bcast(P.an.A[a], l);
+    S.an.Af[a] = bcast(P.an.Af[a], l);
+    S.q[a] = bcast(P.q[a], l);
+    S.d[a] = bcast(P.d[a], l);
+  }
+  S.an.K_in = bcast(P.an.K_in, l);
+  S.an.K_out = bcast(P.an.K_out, l);
+  S.an.L_lo = bcast(P.an.L_lo, l);
+  S.an.L_hi = bcast(P.an.L_hi, l);
+  S.tau = bcast(P.tau, l);
+  S.k = bcast(P.k, l);
+  S.i = bcast(P.i, l);
+  S.j = bcast(P.j, l);
+  S.n_int = bcast(P.n_int, l);
+  S.events = bcast(P.events, l);
+  S.pc_cross = bcast(P.pc_cross, l);
+  S.pc_scat = bcast(P.pc_scat, l);
+  S.pc_abs = bcast(P.pc_abs, l);
+  S.pc_mrw = bcast(P.pc_mrw, l);
+  S.rho = bcast(P.rho, l);
+  S.im = bcast(P.im, l);
+  S.Tc = bcast(P.Tc, l);
+  S.Tfix = bcast(P.Tfix, l);
+  S.mrw_T = bcast(P.mrw_T, l);
+  S.mrw_Drho = bcast(P.mrw_Drho, l);
+  S.mrw_kbar = bcast(P.mrw_kbar, l);
+  S.mrw_lim = bcast(P.mrw_lim, l);
+  S.d_safe = bcast(P.d_safe, l);
+  S.dm_up = bcast(P.dm_up, l);
+  S.cell_abs = bcast(P.cell_abs, l);
+  S.cell_mrw = bcast(P.cell_mrw, l);
+  S.E_seen = bcast(P.E_seen, l);
+  S.T_seen = bcast(P.T_seen, l);
+  return S;
+}
+
+// The stream of one packet (the same draws as Rng32) served to a wavefront.
+struct WaveRng {
+  uint64_t pid;
+  uint32_t k0, k1;
+  uint32_t p0, p1, p2;  // words left from the block the lane stream had open
+  int npend;
+  uint32_t blk0;        // next block to generate
+  int pos;              // next word of the buffer (256: empty)
+  uint32_t w0, w1, w2, w3;  // this lane's block of the buffer
+  uint64_t nd;          // draws so far
+
+  __device__ __forceinline__ void init(const Rng32& r, int l) {
+    pid = bcast(r.pid, l);
+    k0 = bcast(r.k0, l);
+    k1 = bcast(r.k1, l);
+    p0 = bcast(r.o1, l);
+    p1 = bcast(r.o2, l);
+    p2 = bcast(r.o3, l);
+    npend = (int)bcast(r.have, l);
+    blk0 = bcast(r.blk, l);
+    pos = 256;
+    w0 = w1 = w2 = w3 = 0u;
+    nd = bcast((uint64_t)r.draws(), l);
+  }
+  __device__ __forceinline__ float next() {
+    ++nd;
+    if (npend > 0) {
+      const uint32_t w = p0;
+      p0 = p1;
+      p1 = p2;
+      --npend;
+      return Rng32::unit(w);
+    }
+    if (pos == 256) {
+      uint32_t c0 = (uint32_t)pid, c1 = (uint32_t)(pid >> 32), c2 = blk0 + (uint32_t)__lane_id(),
+               c3 = 0;
+      philox4x32_10(c0, c1, c2, c3, k0, k1);
+      w0 = c0;
+      w1 = c1;
+      w2 = c2;
+      w3 = c3;
+      blk0 += 64u;
+      pos = 0;
+    }
+    const int comp = pos & 3;
+    const uint32_t x = comp == 0 ? w0 : comp == 1 ? w1 : comp == 2 ? w2 : w3;
+    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)x, pos >> 2);
+    ++pos;
+    return Rng32::unit(w);
+  }
+  __device__ __forceinline__ uint64_t draws() const { return nd; }
+};
+
+// Smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane.
+template <typename C>
+__device__ __forceinline__ int reemit_search_wave(const Reemit<C>& R, int nl, C xi) {
+  const C target = xi * R.D(nl - 1);
+  const int lane = __lane_id();
+  for (int base = 0; base < nl; base += 64) {
+    const int kk = base + lane < nl ? base + lane : nl - 1;
+    const unsigned long long m = __ballot(base + lane < nl && R.D(kk) > target);
+    if (m) return base + __ffsll((long long)m) - 1;
+  }
+  return nl - 1;
+}
+
+__device__ __forceinline__ double wave_bcast0(double v) { return bcast(v, 0); }
+
+// One event of packet P: a flight through the central hole, a face
+// crossing, or an interaction (scattering, or absorption with immediate
+// reemission, Sect. 2.1) followed by MRW steps while the criterion holds
+// (Sect. 2.2.2).  Returns the fate (0 going on, 1 escaped, 2 star, 3 capped).
+// WAVE: the whole wavefront works on P (all lanes hold the same state) and
+// lane 0 issues the memory updates.
+template <bool WAVE, class RNG>
+__device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, const Lds32& L,
+                                       const double* fixT, int lane) {
+  const DevModel& M = A.m;
+  const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda;
+  const bool issuer = !WAVE || lane == 0;
+  auto visit = [&](int cn) {
+    if (issuer) {
+      if (L.vis) atomicAdd(&L.vis[cn], 1u); else atomicAdd(&A.t.visits[cn], 1u);
+    }
+  };
+  auto deposit = [&](int c, double dE) -> double {  // returns the tally before
+    double E_old = 0.0;
+    if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    if (WAVE) E_old = wave_bcast0(E_old);
+    return E_old;
+  };
+  auto search = [&](const Reemit<float>& R, float xb) -> int {
+    if (WAVE) return reemit_search_wave<float>(R, nl, xb);
+    return reemit_search<float>(R, nl, xb);
+  };
+  int fate = 0;
+  if (++P.events > A.max_events) {
+    fate = 3;
+  } else if (P.i < 0) {
+    // central hole, FP64: the star or the inner grid sphere
+    double Q[3] = {P.an.A[0] + (double)P.q[0], P.an.A[1] + (double)P.q[1],
+                   P.an.A[2] + (double)P.q[2]};
+    double D[3] = {(double)P.d[0], (double)P.d[1], (double)P.d[2]};
+    double pd = Q[0] * D[0] + Q[1] * D[1] + Q[2] * D[2];
+    double rr = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+    double s = enter_sphere<double>(pd, rr - M.R_star * M.R_star);
+    P.q[0] = P.q[1] = P.q[2] = 0.0f;
+    if (s >= 0.0) {
+      P.an.A[0] = Q[0] + s * D[0]; P.an.A[1] = Q[1] + s * D[1]; P.an.A[2] = Q[2] + s * D[2];
+      fate = 2;
+    } else {
+      s = exit_sphere<double>(pd, rr - L.r2[0]);
+      P.an.A[0] = Q[0] + s * D[0]; P.an.A[1] = Q[1] + s * D[1]; P.an.A[2] = Q[2] + s * D[2];
+      P.i = 0;
+      double r2 = (P.an.A[0] * P.an.A[0] + P.an.A[1] * P.an.A[1]) + P.an.A[2] * P.an.A[2];
+      P.j = mu_row(L.mu2, n_mu, r2, P.an.A[2] * P.an.A[2]);
+      set_anchor(P.an, L, n_mu, P.i, P.j);
+      P.rho = M.rho[P.j];
+      P.im = M.inv4pim[P.j];
+      if (fixT) P.Tfix = fixT[P.j];
+      visit(P.j);
+      P.Tc = -1.0;
+      P.mrw_T = -2.0;
+      P.d_safe = 0.0f;
+      P.dm_up = INFINITY;
+      P.n_int = 0;
+      ++P.pc_cross;
+    }
+  } else {
+    const int c = P.i * n_mu + P.j;
+    const float alpha = (float)P.rho * L.chi[P.k];
+    int face = 1;
+    float sb = 0.0f, tau_b = 0.0f;
+    // a flight shorter than the guaranteed distance to every face stays in
+    // the cell: the face distances are not needed for it
+    const bool inside = P.tau < alpha * P.d_safe;
+    if (!inside) {
+      sb = boundary32(P.an, L, n_mu, P.i, P.j, P.q, P.d, face);
+      tau_b = alpha * sb;
+    }
+    if (!inside && tau_b <= P.tau) {
+      P.d_safe = 0.0f;
+      P.dm_up = INFINITY;
+      if (issuer && P.cell_abs) atomicAdd(&A.t.n_abs[c], P.cell_abs);
+      if (issuer && P.cell_mrw) atomicAdd(&A.t.n_mrw[c], P.cell_mrw);
+      P.cell_abs = P.cell_mrw = 0;
+      P.E_seen = -1.0;
+      P.q[0] += sb * P.d[0]; P.q[1] += sb * P.d[1]; P.q[2] += sb * P.d[2];
+      P.tau -= tau_b;
+      if (P.tau < 0.0f) P.tau = 0.0f;
+      ++P.pc_cross;
+      bool entered = true;
+      if (face == 1) {
+        if (P.i + 1 == n_r) {
+          int m = (int)(fabsf(P.d[2]) * M.n_inc);
+          m = m < M.n_inc ? m : M.n_inc - 1;
+          if (issuer) unsafeAtomicAdd(&A.t.sed[P.k * M.n_inc + m], A.eps);
+          fate = 1;
+          entered = false;
+        } else {
+          ++P.i;
+        }
+      } else if (face == 0) {
+        --P.i;
+        if (P.i < 0) entered = false;
+      } else if (face == 2) {
+        --P.j;
+      } else {
+        ++P.j;
+      }
+      if (entered) {
+        int cn = P.i * n_mu + P.j;
+        P.rho = M.rho[cn];
+        P.im = M.inv4pim[cn];
+        if (fixT) P.Tfix = fixT[cn];
+        reanchor(P.an, P.q, L, n_mu, P.i, P.j);
+        visit(cn);
+      } else if (fate == 0) {
+        // into the hole: keep the FP64 position in the anchor
+        P.an.A[0] += (double)P.q[0]; P.an.A[1] += (double)P.q[1]; P.an.A[2] += (double)P.q[2];
+        P.q[0] = P.q[1] = P.q[2] = 0.0f;
+      }
+      P.Tc = -1.0;
+      P.mrw_T = -2.0;
+      P.n_int = 0;
+    } else {
+      float sint = P.tau / alpha;
+      P.q[0] += sint * P.d[0]; P.q[1] += sint * P.d[1]; P.q[2] += sint * P.d[2];
+      P.d_safe -= sint;
+      P.dm_up += 1.00001f * sint;
+      const double* fz = A.frozen_T;
+      if (rng.next() < L.omega[P.k]) {
+        ++P.pc_scat;
+        iso32(rng, P.d);
+      } else {
+        ++P.pc_abs;
+        ++P.cell_abs;
+        // the tally update is in flight while the next draws are made
+        double E_old = deposit(c, A.eps);
+        float xb = rng.next();
+        iso32(rng, P.d);
+        double T_old = -1.0, T_new;
+        if (fz) {
+          T_new = P.Tfix;
+        } else {
+          const double E_new = E_old + A.eps;
+          T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
+          T_new = T_of_g(L.tv, E_new * P.im);
+          P.E_seen = E_new;
+          P.T_seen = T_new;
+          P.Tc = T_new;
+        }
+        Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
+        P.k = search(R, xb);
+      }
+      ++P.n_int;
+      if (A.mrw) {
+        while (P.n_int >= A.n_int_min) {
+          double T_here;
+          if (fixT) T_here = P.Tfix;
+          else {
+            if (P.Tc < 0.0)
+              P.Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT) * P.im);
+            T_here = P.Tc;
+          }
+          if (T_here != P.mrw_T) {  // MRW coefficients of this cell at this T
+            P.mrw_T = T_here;
+            P.mrw_Drho = interp_T(L.tv, L.tv.Drho, T_here);
+            P.mrw_kbar = interp_T(L.tv, L.tv.kbar, T_here);
+            P.mrw_lim = (float)(A.gamma * 3.0 * P.mrw_Drho / P.rho);
+          }
+          const double Drho = P.mrw_Drho;
+          const float lim = P.mrw_lim;
+          if (P.dm_up <= lim) break;
+          {
+            float dm = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
+            P.d_safe = 0.999f * dm;
+            P.dm_up = 1.00001f * dm;
+            if (!(dm > lim)) break;
+          }
+          // re-anchor so the sphere radius is exact to FP32 precision of itself
+          reanchor(P.an, P.q, L, n_mu, P.i, P.j);
+          float dmin = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
+          if (!(dmin > lim)) break;
+          if (++P.events > A.max_events) break;
+          double R0 = (double)dmin * (1.0 - 1e-5);
+          double P0 = (double)rng.next();
+          double s = mrw_escape_s(L.mrw_tab, P0);
+          double ell = s * R0 * R0 * P.rho / Drho;
+          double dE = A.eps * P.rho * P.mrw_kbar * ell;
+          double E_old = deposit(c, dE);
+          float nv[3];
+          iso32(rng, nv);
+          P.q[0] = (float)R0 * nv[0]; P.q[1] = (float)R0 * nv[1]; P.q[2] = (float)R0 * nv[2];
+          float xb = rng.next();
+          iso32(rng, P.d);
+          double T_old = -1.0, T_new;
+          if (fz) {
+            T_new = P.Tfix;
+          } else {
+            const double E_new = E_old + dE;
+            T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
+            T_new = T_of_g(L.tv, E_new * P.im);
+            P.E_seen = E_new;
+            P.T_seen = T_new;
+            P.Tc = T_new;
+          }
+          Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
+          P.k = search(R, xb);
+          P.d_safe = 0.0f;
+          P.dm_up = INFINITY;
+          ++P.pc_mrw;
+          ++P.cell_mrw;
+        }
+      }
+      P.tau = -__logf(rng.next());
+    }
+  }
+  return fate;
+}
+
+// End of a packet: remaining per-cell counts, counters, the star's tally and
+// the optional record.
+template <bool WAVE, class RNG>
+__device__ __forceinline__ void finish32(Pk& P, const RNG& rng, int fate, uint64_t pid,
+                                         const TraceArgs& A, uint32_t* tot, int lane) {
+  const int n_mu = A.m.n_mu;
+  if (!WAVE || lane == 0) {
+    if (P.i >= 0 && (P.cell_abs | P.cell_mrw)) {  // the packet ended in a cell (capped)
+      const int c = P.i * n_mu + P.j;
+      if (P.cell_abs) atomicAdd(&A.t.n_abs[c], P.cell_abs);
+      if (P.cell_mrw) atomicAdd(&A.t.n_mrw[c], P.cell_mrw);
+    }
+    if (fate == 1) tot[C_ESCAPED]++;
+    else if (fate == 2) { tot[C_STAR]++; unsafeAtomicAdd(A.t.E_star, A.eps); }
+    else tot[C_CAPPED]++;
+    tot[C_CROSS] += P.pc_cross;
+    tot[C_SCAT] += P.pc_scat;
+    tot[C_ABS] += P.pc_abs;
+    tot[C_MRW] += P.pc_mrw;
+    if (A.recs) {
+      int64_t r = (int64_t)(pid - A.offset);
+      if (r >= 0 && r < A.n_recs) {
+        mcrt_packet_rec& Rr = A.recs[r];
+        Rr.fate = fate;
+        Rr.k = P.k;
+        Rr.n_cross = P.pc_cross;
+        Rr.n_scat = P.pc_scat;
+        Rr.n_abs = P.pc_abs;
+        Rr.n_mrw = P.pc_mrw;
+        Rr.n_draws = (int64_t)rng.draws();
+        Rr.x = P.an.A[0] + P.q[0]; Rr.y = P.an.A[1] + P.q[1]; Rr.z = P.an.A[2] + P.q[2];
+        Rr.u = P.d[0]; Rr.v = P.d[1]; Rr.w = P.d[2];
+      }
+    }
+  }
+  P.cell_abs = P.cell_mrw = 0;
+  P.E_seen = -1.0;
 }
 
 template <bool CDF_LDS>
@@ -195,31 +606,14 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   __syncthreads();
 
   const int lane = __lane_id();
+  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
   bool alive = false, exhausted = false;
   Rng32 rng;
-  Anchor an;
-  float q[3] = {0, 0, 0}, d[3] = {0, 0, 1}, tau = 0.0f;
-  int k = 0, i = -1, j = 0, n_int = 0;
-  long long events = 0;
+  Pk P;
+  P.i = -1;
+  P.events = 0;
   uint64_t pid = 0;
-  uint32_t pc_cross = 0, pc_scat = 0, pc_abs = 0, pc_mrw = 0;
-  double rho = 0.0;
-  double Tc = -1.0;     // running temperature of the cell (lazily from its tally)
-  double im = 0.0;      // 1 / (4 pi m) of the cell
-  double Tfix = 0.0;    // the cell's fixed temperature (frozen field or MRW coefficient field)
-  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
-  double mrw_T = -2.0, mrw_Drho = 0.0, mrw_kbar = 0.0;  // MRW coefficients at mrw_T
-  float mrw_lim = 0.0f;
-  float d_safe = 0.0f;  // lower bound of the distance to every face of the cell
-  // upper bound of that distance (the last computed one plus the path flown
-  // since): while it is within the MRW limit the criterion cannot hold
-  float dm_up = INFINITY;
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
-  // absorptions and MRW steps in the current cell, added to the tallies when
-  // the packet leaves it; the cell's tally after this lane's last deposit and
-  // its temperature (reused when no other packet deposited in between)
-  uint32_t cell_abs = 0, cell_mrw = 0;
-  double E_seen = -1.0, T_seen = 0.0;
 
   for (;;) {
     unsigned long long idle = __ballot(!alive);
@@ -238,256 +632,75 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
           // launch on the star (FP64 position), Lambertian outward direction
           float ws = 2.0f * rng.next() - 1.0f;
           float st = sqrtf(fmaxf(0.0f, 1.0f - ws * ws));
-          an.A[0] = M.R_star * (double)st;
-          an.A[1] = 0.0;
-          an.A[2] = M.R_star * (double)ws;
+          P.an.A[0] = M.R_star * (double)st;
+          P.an.A[1] = 0.0;
+          P.an.A[2] = M.R_star * (double)ws;
           float mup = sqrtf(rng.next());
           float php = 2.0f * (float)KPI * rng.next();
           float sp = sqrtf(fmaxf(0.0f, 1.0f - mup * mup));
           float sn, cs;
           __sincosf(php, &sn, &cs);
-          d[0] = mup * st + sp * cs * ws;
-          d[1] = sp * sn;
-          d[2] = mup * ws - sp * cs * st;
-          float nrm = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-          d[0] *= nrm; d[1] *= nrm; d[2] *= nrm;
+          P.d[0] = mup * st + sp * cs * ws;
+          P.d[1] = sp * sn;
+          P.d[2] = mup * ws - sp * cs * st;
+          float nrm = rsqrtf(P.d[0] * P.d[0] + P.d[1] * P.d[1] + P.d[2] * P.d[2]);
+          P.d[0] *= nrm; P.d[1] *= nrm; P.d[2] *= nrm;
           float xs = rng.next();
           int lo = 0, hi = nl - 1;
           while (lo < hi) {
             int mid = (lo + hi) >> 1;
             if (L.star_cdf[mid] > xs) hi = mid; else lo = mid + 1;
           }
-          k = lo;
-          tau = -__logf(rng.next());
-          q[0] = q[1] = q[2] = 0.0f;
-          i = -1;
-          j = 0;
-          n_int = 0;
-          events = 0;
-          pc_cross = pc_scat = pc_abs = pc_mrw = 0;
+          P.k = lo;
+          P.tau = -__logf(rng.next());
+          P.q[0] = P.q[1] = P.q[2] = 0.0f;
+          P.i = -1;
+          P.j = 0;
+          P.n_int = 0;
+          P.events = 0;
+          P.pc_cross = P.pc_scat = P.pc_abs = P.pc_mrw = 0;
+          P.rho = P.im = P.Tfix = 0.0;
+          P.Tc = -1.0;
+          P.mrw_T = -2.0;
+          P.mrw_Drho = P.mrw_kbar = 0.0;
+          P.mrw_lim = 0.0f;
+          P.d_safe = 0.0f;
+          P.dm_up = INFINITY;
+          P.cell_abs = P.cell_mrw = 0;
+          P.E_seen = -1.0;
+          P.T_seen = 0.0;
           tot[C_LAUNCH]++;
           alive = true;
         }
       }
     }
-    if (__ballot(alive) == 0ull) {
+    const unsigned long long live = __ballot(alive);
+    if (live == 0ull) {
       if (exhausted) break;
       continue;
     }
-    if (!alive) continue;
-
-    int fate = 0;
-    if (++events > A.max_events) {
-      fate = 3;
-    } else if (i < 0) {
-      // central hole, FP64: the star or the inner grid sphere
-      double P[3] = {an.A[0] + (double)q[0], an.A[1] + (double)q[1], an.A[2] + (double)q[2]};
-      double D[3] = {(double)d[0], (double)d[1], (double)d[2]};
-      double pd = P[0] * D[0] + P[1] * D[1] + P[2] * D[2];
-      double rr = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
-      double s = enter_sphere<double>(pd, rr - M.R_star * M.R_star);
-      q[0] = q[1] = q[2] = 0.0f;
-      if (s >= 0.0) {
-        an.A[0] = P[0] + s * D[0]; an.A[1] = P[1] + s * D[1]; an.A[2] = P[2] + s * D[2];
-        fate = 2;
-      } else {
-        s = exit_sphere<double>(pd, rr - L.r2[0]);
-        an.A[0] = P[0] + s * D[0]; an.A[1] = P[1] + s * D[1]; an.A[2] = P[2] + s * D[2];
-        i = 0;
-        double r2 = (an.A[0] * an.A[0] + an.A[1] * an.A[1]) + an.A[2] * an.A[2];
-        j = mu_row(L.mu2, n_mu, r2, an.A[2] * an.A[2]);
-        set_anchor(an, L, n_mu, i, j);
-        rho = M.rho[j];
-        im = M.inv4pim[j];
-        if (fixT) Tfix = fixT[j];
-        if (L.vis) atomicAdd(&L.vis[j], 1u); else atomicAdd(&A.t.visits[j], 1u);
-        Tc = -1.0;
-        mrw_T = -2.0;
-        d_safe = 0.0f;
-        dm_up = INFINITY;
-        n_int = 0;
-        ++pc_cross;
-      }
-    } else {
-      const int c = i * n_mu + j;
-      const float alpha = (float)rho * L.chi[k];
-      int face = 1;
-      float sb = 0.0f, tau_b = 0.0f;
-      // a flight shorter than the guaranteed distance to every face stays in
-      // the cell: the face distances are not needed for it
-      const bool inside = tau < alpha * d_safe;
-      if (!inside) {
-        sb = boundary32(an, L, n_mu, i, j, q, d, face);
-        tau_b = alpha * sb;
-      }
-      if (!inside && tau_b <= tau) {
-        d_safe = 0.0f;
-        dm_up = INFINITY;
-        if (cell_abs) { atomicAdd(&A.t.n_abs[c], cell_abs); cell_abs = 0; }
-        if (cell_mrw) { atomicAdd(&A.t.n_mrw[c], cell_mrw); cell_mrw = 0; }
-        E_seen = -1.0;
-        q[0] += sb * d[0]; q[1] += sb * d[1]; q[2] += sb * d[2];
-        tau -= tau_b;
-        if (tau < 0.0f) tau = 0.0f;
-        ++pc_cross;
-        bool entered = true;
-        if (face == 1) {
-          if (i + 1 == n_r) {
-            int m = (int)(fabsf(d[2]) * M.n_inc);
-            m = m < M.n_inc ? m : M.n_inc - 1;
-            unsafeAtomicAdd(&A.t.sed[k * M.n_inc + m], A.eps);
-            fate = 1;
-            entered = false;
-          } else {
-            ++i;
-          }
-        } else if (face == 0) {
-          --i;
-          if (i < 0) entered = false;
-        } else if (face == 2) {
-          --j;
-        } else {
-          ++j;
-        }
-        if (entered) {
-          int cn = i * n_mu + j;
-          rho = M.rho[cn];
-          im = M.inv4pim[cn];
-          if (fixT) Tfix = fixT[cn];
-          reanchor(an, q, L, n_mu, i, j);
-          if (L.vis) atomicAdd(&L.vis[cn], 1u); else atomicAdd(&A.t.visits[cn], 1u);
-        } else if (fate == 0) {
-          // into the hole: keep the FP64 position in the anchor
-          an.A[0] += (double)q[0]; an.A[1] += (double)q[1]; an.A[2] += (double)q[2];
-          q[0] = q[1] = q[2] = 0.0f;
-        }
-        Tc = -1.0;
-        mrw_T = -2.0;
-        n_int = 0;
-      } else {
-        float sint = tau / alpha;
-        q[0] += sint * d[0]; q[1] += sint * d[1]; q[2] += sint * d[2];
-        d_safe -= sint;
-        dm_up += 1.00001f * sint;
-        const double* fz = A.frozen_T;
-        if (rng.next() < L.omega[k]) {
-          ++pc_scat;
-          iso32(rng, d);
-        } else {
-          ++pc_abs;
-          ++cell_abs;
-          // the tally update is in flight while the next draws are made
-          double E_old = unsafeAtomicAdd(&A.t.E_abs[c], A.eps);
-          float xb = rng.next();
-          iso32(rng, d);
-          double T_old = -1.0, T_new;
-          if (fz) {
-            T_new = Tfix;
-          } else {
-            const double E_new = E_old + A.eps;
-            T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
-            T_new = T_of_g(L.tv, E_new * im);
-            E_seen = E_new;
-            T_seen = T_new;
-            Tc = T_new;
-          }
-          Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
-          k = reemit_search<float>(R, nl, xb);
-        }
-        ++n_int;
-        if (A.mrw) {
-          while (n_int >= A.n_int_min) {
-            double T_here;
-            if (fixT) T_here = Tfix;
-            else {
-              if (Tc < 0.0)
-                Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT) * im);
-              T_here = Tc;
-            }
-            if (T_here != mrw_T) {  // MRW coefficients of this cell at this T
-              mrw_T = T_here;
-              mrw_Drho = interp_T(L.tv, L.tv.Drho, T_here);
-              mrw_kbar = interp_T(L.tv, L.tv.kbar, T_here);
-              mrw_lim = (float)(A.gamma * 3.0 * mrw_Drho / rho);
-            }
-            const double Drho = mrw_Drho;
-            const float lim = mrw_lim;
-            if (dm_up <= lim) break;
-            {
-              float dm = min_boundary32(an, L, n_mu, i, j, q);
-              d_safe = 0.999f * dm;
-              dm_up = 1.00001f * dm;
-              if (!(dm > lim)) break;
-            }
-            // re-anchor so the sphere radius is exact to FP32 precision of itself
-            reanchor(an, q, L, n_mu, i, j);
-            float dmin = min_boundary32(an, L, n_mu, i, j, q);
-            if (!(dmin > lim)) break;
-            if (++events > A.max_events) break;
-            double R0 = (double)dmin * (1.0 - 1e-5);
-            double P0 = (double)rng.next();
-            double s = mrw_escape_s(L.mrw_tab, P0);
-            double ell = s * R0 * R0 * rho / Drho;
-            double dE = A.eps * rho * mrw_kbar * ell;
-            double E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
-            float nv[3];
-            iso32(rng, nv);
-            q[0] = (float)R0 * nv[0]; q[1] = (float)R0 * nv[1]; q[2] = (float)R0 * nv[2];
-            float xb = rng.next();
-            iso32(rng, d);
-            double T_old = -1.0, T_new;
-            if (fz) {
-              T_new = Tfix;
-            } else {
-              const double E_new = E_old + dE;
-              T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
-              T_new = T_of_g(L.tv, E_new * im);
-              E_seen = E_new;
-              T_seen = T_new;
-              Tc = T_new;
-            }
-            Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
-            k = reemit_search<float>(R, nl, xb);
-            d_safe = 0.0f;
-            dm_up = INFINITY;
-            ++pc_mrw;
-            ++cell_mrw;
-          }
-        }
-        tau = -__logf(rng.next());
+    // the wavefront's last packet, once all are handed out: all lanes on it
+    if (exhausted && A.wave_events > 0 && __popcll(live) == 1) {
+      const int src = __ffsll((long long)live) - 1;
+      if (bcast(P.events, src) >= A.wave_events) {
+        Pk S = bcast(P, src);
+        WaveRng wr;
+        wr.init(rng, src);
+        const uint64_t wpid = bcast(pid, src);
+        int f;
+        do {
+          f = event32<true>(S, wr, A, L, fixT, lane);
+        } while (f == 0);
+        finish32<true>(S, wr, f, wpid, A, tot, lane);
+        alive = false;
+        break;
       }
     }
+    if (!alive) continue;
+
+    const int fate = event32<false>(P, rng, A, L, fixT, lane);
     if (fate != 0) {
-      if (cell_abs | cell_mrw) {  // the packet ended in a cell (capped)
-        const int c = i * n_mu + j;
-        if (i >= 0 && cell_abs) atomicAdd(&A.t.n_abs[c], cell_abs);
-        if (i >= 0 && cell_mrw) atomicAdd(&A.t.n_mrw[c], cell_mrw);
-        cell_abs = cell_mrw = 0;
-      }
-      E_seen = -1.0;
-      if (fate == 1) tot[C_ESCAPED]++;
-      else if (fate == 2) { tot[C_STAR]++; unsafeAtomicAdd(A.t.E_star, A.eps); }
-      else tot[C_CAPPED]++;
-      tot[C_CROSS] += pc_cross;
-      tot[C_SCAT] += pc_scat;
-      tot[C_ABS] += pc_abs;
-      tot[C_MRW] += pc_mrw;
-      if (A.recs) {
-        int64_t r = (int64_t)(pid - A.offset);
-        if (r >= 0 && r < A.n_recs) {
-          mcrt_packet_rec& Rr = A.recs[r];
-          Rr.fate = fate;
-          Rr.k = k;
-          Rr.n_cross = pc_cross;
-          Rr.n_scat = pc_scat;
-          Rr.n_abs = pc_abs;
-          Rr.n_mrw = pc_mrw;
-          Rr.n_draws = (int64_t)rng.draws();
-          Rr.x = an.A[0] + q[0]; Rr.y = an.A[1] + q[1]; Rr.z = an.A[2] + q[2];
-          Rr.u = d[0]; Rr.v = d[1]; Rr.w = d[2];
-        }
-      }
+      finish32<false>(P, rng, fate, pid, A, tot, lane);
       alive = false;
       if (tot[C_CROSS] > 0x40000000u || tot[C_SCAT] > 0x40000000u || tot[C_ABS] > 0x40000000u ||
           tot[C_MRW] > 0x40000000u) {

@@ -295,3 +295,36 @@ def test_integer_tallies_exact(mcrt, torch_cuda, precision):
         runs.append((v, na, nm))
     for a, b in zip(runs[0], runs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mrw", [False, True])
+def test_fp32_wave_mode_same_events(mcrt, torch_cuda, mrw):
+    """The whole-wavefront mode (the last live packet of a wavefront traced by
+    all 64 lanes) follows the same events as the per-lane mode: packets traced
+    one per launch (so each runs in wave mode after its first event) against
+    the same packets in one launch with the mode off, frozen temperature."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=1e-1, n_r=14, n_mu=10, n_lambda=24)
+    Tf = torch.from_numpy(_frozen_field(d)).cuda()
+    n = 300
+    kw = dict(precision="fp32", mrw=mrw, gamma=2.0, n_int_min=5)
+    lanes = mcrt.Context(d, wave_events=0, **kw)
+    ref = mcrt.Context.records_numpy(lanes.trace(n, 31, n_total=n, frozen_T=Tf, n_recs=n))
+    wave = mcrt.Context(d, wave_events=1, **kw)
+    got = []
+    for p in range(n):
+        r = wave.trace(1, 31, n_total=n, offset=p, frozen_T=Tf, n_recs=1)
+        got.append(mcrt.Context.records_numpy(r)[0])
+    torch.cuda.synchronize()
+    got = np.array(got, dtype=ref.dtype)
+    same = np.ones(n, bool)
+    for f in ("fate", "k", "n_cross", "n_scat", "n_abs", "n_mrw", "n_draws"):
+        same &= got[f] == ref[f]
+    assert same.mean() >= 0.99, same.mean()
+    assert (ref["n_scat"] + ref["n_abs"]).sum() > 2 * n
+    if mrw:
+        assert ref["n_mrw"].sum() > 0
+    pos = np.stack([got["x"], got["y"], got["z"]], 1)
+    rpos = np.stack([ref["x"], ref["y"], ref["z"]], 1)
+    err = np.linalg.norm(pos - rpos, axis=1) / np.linalg.norm(rpos, axis=1)
+    assert np.mean(err[same] < 1e-5) >= 0.99
