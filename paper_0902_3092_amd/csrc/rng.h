@@ -64,7 +64,8 @@ struct Rng64 {
 };
 
 // FP32 streams: draw d uses output word d % 4 of block d / 4; its top 24 bits
-// x give (x + 1/2) / 2^24 in (0, 1).
+// x give (x + 1/2) / 2^24 rounded to FP32, in (0, 1] (x = 2^24 - 1 rounds up
+// to 1).
 struct Rng32 {
   uint32_t k0, k1;
   uint64_t pid;

@@ -129,17 +129,87 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   return dmin > 0.0f ? dmin : 0.0f;
 }
 
-template <class RNG>
-__device__ __forceinline__ void iso32(RNG& r, float d[3]) {
-  float w = 2.0f * r.next() - 1.0f;
-  float ph = 2.0f * (float)KPI * r.next();
-  float st = sqrtf(fmaxf(0.0f, 1.0f - w * w));
+// Functions of one draw u used by the transport; the whole-wave generator
+// evaluates them once per word, lane-parallel, so every caller gets the same
+// values from either generator.
+__device__ __forceinline__ float iso_mu(float u) { return 2.0f * u - 1.0f; }
+__device__ __forceinline__ float iso_st(float u) {
+  const float w = iso_mu(u);
+  return sqrtf(fmaxf(0.0f, 1.0f - w * w));
+}
+__device__ __forceinline__ void iso_phi(float u, float& sn, float& cs) {
+  __sincosf(2.0f * (float)KPI * u, &sn, &cs);
+}
+__device__ __forceinline__ float tau_of(float u) { return -__logf(u); }
+
+// MRW escape time in FP32 (eq. probability RW): s with P(s) = P0.  The
+// residual P(s) - P0 is formed from the series in P for s >= 0.1 and from
+// the theta form of Q = 1 - P below, against Q0 = 1 - P0 (exact for P0 >=
+// 1/2), so both long and short escapes keep their relative precision.
+// Start from the table in v = ln(-ln P0), then three Newton steps.
+__device__ __forceinline__ void mrw_resid32(float s, float P0, float Q0, float& r, float& dr) {
+  const float pi2 = (float)(KPI * KPI);
+  if (s >= 0.1f) {
+    const float x = pi2 * s;
+    float sum = 0.0f, dsum = 0.0f;
+#pragma unroll
+    for (int n = 1; n <= 7; ++n) {
+      const float n2 = (float)(n * n);
+      const float e = __expf(-n2 * x);
+      const float sg = (n & 1) ? 1.0f : -1.0f;
+      sum += sg * e;
+      dsum += sg * n2 * pi2 * e;
+    }
+    r = 2.0f * sum - P0;
+    dr = -2.0f * dsum;
+  } else {
+    const float inv_s = 1.0f / s;
+    float sum = 0.0f, dsum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float a = (float)((2 * k + 1) * (2 * k + 1)) * 0.25f;
+      const float e = __expf(-a * inv_s);
+      sum += e;
+      dsum += e * a * inv_s * inv_s;
+    }
+    const float pre = 2.0f * rsqrtf((float)KPI * s);
+    r = Q0 - pre * sum;
+    dr = -(pre * dsum - 0.5f * pre * inv_s * sum);
+  }
+}
+
+__device__ __forceinline__ float mrw_escape_s32(const double* tab, float P0) {
+  const float Q0 = 1.0f - P0;
+  const float mlnP = Q0 < 0.01f ? Q0 * (1.0f + 0.5f * Q0) : -__logf(P0);
+  const float v = __logf(mlnP);
+  float t = (v - (float)MRW_TAB_V0) * (float)((MRW_TAB_N - 1) / (MRW_TAB_V1 - MRW_TAB_V0));
+  t = fminf(fmaxf(t, 0.0f), (float)(MRW_TAB_N - 1) - 1e-3f);
+  const int q = (int)t;
+  const float f = t - (float)q;
+  const float s0 = (float)tab[q], s1 = (float)tab[q + 1];
+  float s = s0 + f * (s1 - s0);
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    float r, dr;
+    mrw_resid32(s, P0, Q0, r, dr);
+    const float sn = s - r / dr;
+    s = sn > 0.5f * s ? sn : 0.5f * s;
+  }
+  return s;
+}
+
+// isotropic direction from two draws; optical depth from one
+__device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
+  const float u1 = r.next();
+  const float u2 = r.next();
   float sn, cs;
-  __sincosf(ph, &sn, &cs);
+  iso_phi(u2, sn, cs);
+  const float st = iso_st(u1);
   d[0] = st * cs;
   d[1] = st * sn;
-  d[2] = w;
+  d[2] = iso_mu(u1);
 }
+__device__ __forceinline__ float tau32(Rng32& r) { return tau_of(r.next()); }
 
 // ------------------------------------------------------------------ packets
 // Transport state of one packet.
@@ -230,58 +300,70 @@ __device__ __forceinline__ Pk bcast(const Pk& P, int l) {
   return S;
 }
 
-// The stream of one packet (the same draws as Rng32) served to a wavefront.
+// The stream of one packet (the same draws as Rng32) served to a wavefront:
+// lane l holds block blk0 + l of the stream and, for each of its four words,
+// the draw u and the functions of it that the transport takes (optical
+// depth, direction cosine and sine terms), so a draw costs a read from its
+// lane instead of a generator call and transcendentals on the chain.
 struct WaveRng {
   uint64_t pid;
   uint32_t k0, k1;
-  uint32_t p0, p1, p2;  // words left from the block the lane stream had open
-  int npend;
-  uint32_t blk0;        // next block to generate
-  int pos;              // next word of the buffer (256: empty)
-  uint32_t w0, w1, w2, w3;  // this lane's block of the buffer
-  uint64_t nd;          // draws so far
+  uint32_t blk0;  // block held by lane 0
+  int pos;        // next word of the buffer, 0..255
+  uint64_t nd;    // draws so far
+  float u[4], tau[4], st[4], sn[4], cs[4];  // this lane's block
 
+  __device__ __forceinline__ void fill() {
+    uint32_t c[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), blk0 + (uint32_t)__lane_id(), 0u};
+    philox4x32_10(c[0], c[1], c[2], c[3], k0, k1);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      u[a] = Rng32::unit(c[a]);
+      tau[a] = tau_of(u[a]);
+      st[a] = iso_st(u[a]);
+      iso_phi(u[a], sn[a], cs[a]);
+    }
+  }
   __device__ __forceinline__ void init(const Rng32& r, int l) {
     pid = bcast(r.pid, l);
     k0 = bcast(r.k0, l);
     k1 = bcast(r.k1, l);
-    p0 = bcast(r.o1, l);
-    p1 = bcast(r.o2, l);
-    p2 = bcast(r.o3, l);
-    npend = (int)bcast(r.have, l);
-    blk0 = bcast(r.blk, l);
-    pos = 256;
-    w0 = w1 = w2 = w3 = 0u;
-    nd = bcast((uint64_t)r.draws(), l);
+    nd = bcast((uint64_t)r.draws(), l);  // index of the next word of the stream
+    blk0 = (uint32_t)(nd >> 2);
+    pos = (int)(nd & 3);
+    fill();
   }
-  __device__ __forceinline__ float next() {
-    ++nd;
-    if (npend > 0) {
-      const uint32_t w = p0;
-      p0 = p1;
-      p1 = p2;
-      --npend;
-      return Rng32::unit(w);
-    }
+  // value of word p of the buffer from table v
+  __device__ __forceinline__ float at(const float* v, int p) const {
+    const int comp = p & 3;
+    const float x = comp == 0 ? v[0] : comp == 1 ? v[1] : comp == 2 ? v[2] : v[3];
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), p >> 2));
+  }
+  __device__ __forceinline__ int take() {
     if (pos == 256) {
-      uint32_t c0 = (uint32_t)pid, c1 = (uint32_t)(pid >> 32), c2 = blk0 + (uint32_t)__lane_id(),
-               c3 = 0;
-      philox4x32_10(c0, c1, c2, c3, k0, k1);
-      w0 = c0;
-      w1 = c1;
-      w2 = c2;
-      w3 = c3;
       blk0 += 64u;
       pos = 0;
+      fill();
     }
-    const int comp = pos & 3;
-    const uint32_t x = comp == 0 ? w0 : comp == 1 ? w1 : comp == 2 ? w2 : w3;
-    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)x, pos >> 2);
-    ++pos;
-    return Rng32::unit(w);
+    ++nd;
+    return pos++;
+  }
+  __device__ __forceinline__ float next() { return at(u, take()); }
+  __device__ __forceinline__ float next_tau() { return at(tau, take()); }
+  __device__ __forceinline__ void next_iso(float d[3]) {
+    const int p1 = take();
+    const float w = iso_mu(at(u, p1)), s = at(st, p1);
+    const int p2 = take();
+    const float cs_ = at(cs, p2), sn_ = at(sn, p2);
+    d[0] = s * cs_;
+    d[1] = s * sn_;
+    d[2] = w;
   }
   __device__ __forceinline__ uint64_t draws() const { return nd; }
 };
+
+__device__ __forceinline__ void iso32(WaveRng& r, float d[3]) { r.next_iso(d); }
+__device__ __forceinline__ float tau32(WaveRng& r) { return r.next_tau(); }
 
 // Smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane.
 template <typename C>
@@ -477,8 +559,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           if (!(dmin > lim)) break;
           if (++P.events > A.max_events) break;
           double R0 = (double)dmin * (1.0 - 1e-5);
-          double P0 = (double)rng.next();
-          double s = mrw_escape_s(L.mrw_tab, P0);
+          double s = (double)mrw_escape_s32(L.mrw_tab, rng.next());
           double ell = s * R0 * R0 * P.rho / Drho;
           double dE = A.eps * P.rho * P.mrw_kbar * ell;
           double E_old = deposit(c, dE);
@@ -506,7 +587,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           ++P.cell_mrw;
         }
       }
-      P.tau = -__logf(rng.next());
+      P.tau = tau32(rng);
     }
   }
   return fate;
