@@ -49,6 +49,35 @@ HBM_PEAK = 8.0e12
 PCG_BYTES_PER_UNKNOWN = {0: 104, 1: 160}
 
 
+# Sources of the FP32 trace kernel; HBM traffic measured with rocprofv3
+# counters is reported only while they are unchanged.
+TRACE32_SOURCES = ("trace_fp32.hip", "trace_common.h", "rng.h", "mcrt_internal.h")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "trace_fp32_counters.json")
+
+
+def trace32_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE32_SOURCES:
+        with open(os.path.join(ROOT, "paper_0902_3092_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, packets):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it covers another kernel, launch size or source."""
+    try:
+        with open(COUNTERS_JSON) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (c.get("kernel") != kernel or c.get("packets") != packets or
+            c.get("source_sha256") != trace32_source_hash()):
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
+
 def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
@@ -72,6 +101,14 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-pda", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--large", type=int, default=0,
+                   help="only run the large disk (400 x 200 cells, 200 bins, 3 species) with this "
+                        "many packets, FP32 and FP64, and exit")
+    p.add_argument("--tail-probe", action="store_true",
+                   help="only time the longest packet of a frozen-temperature sample of the step, "
+                        "alone, per lane and in whole-wavefront mode, and exit")
+    p.add_argument("--source-hash", action="store_true",
+                   help="print the hash of the FP32 trace kernel sources and exit")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="only copy this many MiB device to device once (a plain copy kernel of "
                         "known size, to scale the HBM byte counters) and exit")
@@ -164,6 +201,84 @@ def ensemble(mcrt, disk, o, n_packets, K, torch):
             "pda_region_cells_max": int(max(x["n_region"] for x in st))}
 
 
+def large(mcrt, W, torch, n_packets):
+    """The large disk: one pass (trace, T, PDA) with FP32 tracking and with the
+    all-FP64 path at the same packet count; their temperature difference
+    against the photon noise of both runs."""
+    import numpy as np
+    d, o = W.config("large")
+    out = {"workload": "disk 1e-1 Msun, 0.1-500 AU, 400 r x 200 theta, 200 lambda bins, "
+                       "3 species, MRW gamma=3, PDA < 100 visits", "packets": n_packets}
+    T, NA, VIS = {}, {}, {}
+    for prec in ("fp32", "fp64"):
+        ctx = mcrt.Context(d, precision=prec, mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                           pda_visits=o.pda_visits, n_T=o.n_T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.reset()
+        chunk = 10000000
+        for off in range(0, n_packets, chunk):
+            ctx.trace(min(chunk, n_packets - off), o.seed, n_total=n_packets, offset=off)
+            torch.cuda.synchronize()
+            log("large %s: %d packets traced (%.1f s)" % (prec, min(off + chunk, n_packets),
+                                                        time.perf_counter() - t0))
+        ctx.update_T()
+        st = ctx.pda_solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        T[prec] = ctx.get(mcrt.GET_T).cpu().numpy()
+        NA[prec] = ctx.get(mcrt.GET_N_ABS).cpu().numpy().view(np.uint32).astype(np.float64)
+        VIS[prec] = ctx.get(mcrt.GET_VISITS).cpu().numpy().view(np.uint32)
+        out[prec] = {"value": n_packets / dt, "unit": "photon packets/s", "s": dt,
+                     "pda_region": st["n_region"], "counters": ctx.counters()}
+        del ctx
+    ok = (NA["fp32"] >= 100) & (NA["fp64"] >= 100) & (T["fp64"] > 0)
+    rel = np.abs(T["fp32"][ok] / T["fp64"][ok] - 1.0)
+    noise = np.sqrt(1.0 / (16.0 * NA["fp32"][ok]) + 1.0 / (16.0 * NA["fp64"][ok]))
+    out["T_fp32_vs_fp64"] = {"cells": int(ok.sum()), "median_rel": float(np.median(rel)),
+                             "median_photon_noise": float(np.median(noise)),
+                             "frac_within_3_noise": float(np.mean(rel <= 3 * noise))}
+    return out
+
+
+def tail_probe(mcrt, W, torch):
+    """Latency of one long random walk: on the step's disk with a frozen
+    power-law temperature field (so a packet's events do not depend on the
+    others), find the longest of 3e5 packets, then trace it alone, once per
+    lane (wave_events = 0) and once in whole-wavefront mode."""
+    import numpy as np
+    d, o = W.config("mrw_pda")
+    rc = 0.5 * (d.r_edges[:-1] + d.r_edges[1:]) / W.AU
+    Tf = torch.from_numpy(np.ascontiguousarray(
+        (300.0 * rc[:, None] ** -0.5 * (1 + 0.3 * d.mu_edges[None, 1:])).reshape(-1))).cuda()
+    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, frozen T = 300 K (r/AU)^-1/2 (1 + 0.3 mu)"}
+    for prec in ("fp32", "fp64"):
+        kw = dict(precision=prec, mrw=True, gamma=o.gamma, n_int_min=o.n_int_min, n_T=o.n_T)
+        ctx = mcrt.Context(d, **kw)
+        n = 300000
+        recs = mcrt.Context.records_numpy(ctx.trace(n, 7, n_total=1000000, frozen_T=Tf, n_recs=n))
+        ev = recs["n_cross"] + recs["n_scat"] + recs["n_abs"] + recs["n_mrw"]
+        pid = int(np.argmax(ev))
+        modes = (("per_lane", 0), ("whole_wave", 32)) if prec == "fp32" else (("per_lane", 0),)
+        res = {"pid": pid}
+        for name, we in modes:
+            c1 = mcrt.Context(d, wave_events=we, **kw)
+            c1.trace(1, 7, n_total=1000000, offset=pid, frozen_T=Tf)   # warm-up
+            c1.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c1.trace(1, 7, n_total=1000000, offset=pid, frozen_T=Tf)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c = c1.counters()
+            e = c["cross"] + c["scat"] + c["abs"] + c["mrw"]
+            res[name] = {"events": e, "s": dt, "us_per_event": dt / e * 1e6,
+                         "counters": {k: c[k] for k in ("cross", "scat", "abs", "mrw")}}
+            log("tail probe %s %s: %d events, %.2f us/event" % (prec, name, e, dt / e * 1e6))
+        out[prec] = res
+    return out
+
+
 def pda_grad(mcrt, W, torch):
     import numpy as np
     d, _ = W.config("pda_grad")
@@ -196,6 +311,9 @@ def pda_grad(mcrt, W, torch):
 
 def main():
     a = parse()
+    if a.source_hash:
+        print(trace32_source_hash())
+        return
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported" % a.gpus,
               file=sys.stderr)
@@ -215,6 +333,13 @@ def main():
 
     from paper_0902_3092_amd import mcrt
     from paper_0902_3092_amd import workloads as W
+
+    if a.tail_probe:
+        print(json.dumps({"tail_probe": tail_probe(mcrt, W, torch)}), flush=True)
+        return
+    if a.large > 0:
+        print(json.dumps({"large": large(mcrt, W, torch, a.large)}), flush=True)
+        return
 
     disk, o = W.config("mrw_pda")
     N = a.packets
@@ -273,7 +398,9 @@ def main():
                                "1e6 packets, MRW gamma=3, PDA on cells with <100 visits",
                    "precision": a.precision, "packets_per_step": N},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": (measured_traffic("trace_fp32_kernel", N)
+                                 if a.precision == "fp32" else None),
                      "kernel": "trace_%s_kernel" % a.precision,
                      "kernel_ms": float(np.mean(trace_ms)),
                      "flops_per_launch": flops},
