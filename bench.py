@@ -259,7 +259,7 @@ def tail_probe(mcrt, W, torch):
         recs = mcrt.Context.records_numpy(ctx.trace(n, 7, n_total=1000000, frozen_T=Tf, n_recs=n))
         ev = recs["n_cross"] + recs["n_scat"] + recs["n_abs"] + recs["n_mrw"]
         pid = int(np.argmax(ev))
-        modes = (("per_lane", 0), ("whole_wave", 32)) if prec == "fp32" else (("per_lane", 0),)
+        modes = (("per_lane", 0), ("whole_wave", 32))
         res = {"pid": pid}
         for name, we in modes:
             c1 = mcrt.Context(d, wave_events=we, **kw)

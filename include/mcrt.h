@@ -105,10 +105,10 @@ typedef struct {
                             diagonal), 1 block Jacobi on the theta lines of each radius
                             (tridiagonal blocks, solved exactly) (1); the grid-wide solver
                             uses the diagonal */
-  int64_t wave_events;   /* FP32 tracking: once every packet of a launch is handed out, a
-                            wavefront whose only live packet has had at least this many
-                            events runs it with all 64 lanes (same draws, same events);
-                            0 = never (32) */
+  int64_t wave_events;   /* once every packet of a launch is handed out, packets that have
+                            had at least this many events move to a second launch that
+                            runs each with all 64 lanes of a wavefront (same draws, same
+                            events); 0 = never (2048).  Single-disk traces only. */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);

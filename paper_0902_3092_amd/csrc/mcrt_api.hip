@@ -182,6 +182,11 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
   a.recs = recs;
   a.n_recs = n_recs;
   a.wave_events = ctx->opt.wave_events;
+  if (ctx->opt.wave_events > 0 && ctx->d_tail) {
+    a.tail = ctx->d_tail;
+    a.tail_count = (unsigned int*)((char*)ctx->d_tail + (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES);
+    a.tail_cap = mcrt::TAIL_CAP;
+  }
   return a;
 }
 
@@ -214,7 +219,7 @@ void mcrt_default_options(mcrt_options* o) {
   o->blocks_per_cu = 0;
   o->pda_solver = 0;
   o->pda_precond = 1;
-  o->wave_events = 32;
+  o->wave_events = 2048;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -459,6 +464,10 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   ctx->d_T = (double*)q; q += al(nd);
   ctx->d_T_prev = (double*)q; q += al(nd);
   ctx->d_region = (uint8_t*)q;
+  if (hipMalloc(&ctx->d_tail, (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES + 256) != hipSuccess) {
+    mcrt_destroy(ctx);
+    return fail(nullptr, MCRT_E_OOM, "device allocation of the hand-off buffer failed");
+  }
   if (hipMemset(ctx->d_tally_blob, 0, tb) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     mcrt_destroy(ctx);
     return fail(nullptr, MCRT_E_HIP, "clearing the tallies failed");
@@ -473,6 +482,7 @@ void mcrt_destroy(mcrt_ctx* ctx) {
   if (ctx->d_tally_blob) hipFree(ctx->d_tally_blob);
   if (ctx->d_pda_blob) hipFree(ctx->d_pda_blob);
   if (ctx->d_lin_args) hipFree(ctx->d_lin_args);
+  if (ctx->d_tail) hipFree(ctx->d_tail);
   delete ctx;
 }
 
@@ -494,7 +504,8 @@ int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t see
   mcrt::TraceArgs a = mcrt::make_trace_args(ctx, n_packets, n_total, seed, offset, frozen_T_dev,
                                             rec_dev, n_recs);
   int rc = mcrt::launch_zero(ctx->d_next, 8, stream);
-  if (rc) return fail(ctx, rc, "clearing the work counter failed");
+  if (!rc && a.tail_count) rc = mcrt::launch_zero(a.tail_count, 4, stream);
+  if (rc) return fail(ctx, rc, "clearing the work counters failed");
   return mcrt::launch_trace(ctx, a, stream);
 }
 

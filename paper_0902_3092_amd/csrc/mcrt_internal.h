@@ -78,8 +78,14 @@ struct TraceArgs {
   mcrt_packet_rec* recs;       // nullable
   int64_t n_recs;
   int vis_lds;                 // FP32 path: visit counts in a per-workgroup LDS histogram
-  long long wave_events;       // FP32 path: whole-wavefront mode for a lone last packet (0: off)
+  // hand-off of long packets to the whole-wavefront tail launch (tail null: off)
+  long long wave_events;       // events after which a packet is handed off
+  void* tail;                  // [tail_cap] packet states
+  unsigned int* tail_count;    // states written (may exceed tail_cap: the rest stay)
+  int tail_cap;
 };
+constexpr int TAIL_STATE_BYTES = 512;
+constexpr int TAIL_CAP = 8192;
 
 }  // namespace mcrt
 
@@ -96,6 +102,7 @@ struct mcrt_ctx {
   double* d_T_prev = nullptr;   // temperature of the previous pass (MRW coefficients)
   uint8_t* d_region = nullptr;
   unsigned long long* d_next = nullptr;
+  void* d_tail = nullptr;             // hand-off buffer of long packets (TAIL_CAP states + count)
   void* d_blob = nullptr;       // model + tables
   void* d_tally_blob = nullptr;
   void* d_pda_blob = nullptr;   // PDA solver scratch
@@ -130,8 +137,9 @@ size_t trace_fp32_lds(const DevModel& M, bool with_cdf);
 size_t trace_fp32_lds_cap();
 int trace_fp32_blocks_per_cu(size_t lds, bool cdf_lds);
 int prepare_trace_fp32_batch(size_t lds, bool cdf_lds);
-int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk, int n_blocks,
-                            size_t lds, bool cdf_lds, hipStream_t s);
+int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk,
+                            const int* d_block_first, int n_blocks, size_t lds, bool cdf_lds,
+                            hipStream_t s);
 TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
                           uint64_t offset, const double* frozen_T, mcrt_packet_rec* recs,
                           int64_t n_recs);

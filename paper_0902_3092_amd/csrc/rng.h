@@ -61,6 +61,7 @@ struct Rng64 {
     ++d;
     return unit(c0, c1);
   }
+  __device__ __forceinline__ uint64_t nd_value() const { return d; }
 };
 
 // FP32 streams: draw d uses output word d % 4 of block d / 4; its top 24 bits

@@ -210,6 +210,7 @@ __device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
   d[2] = iso_mu(u1);
 }
 __device__ __forceinline__ float tau32(Rng32& r) { return tau_of(r.next()); }
+__device__ __forceinline__ void ensure_draws(Rng32&, int) {}
 
 // ------------------------------------------------------------------ packets
 // Transport state of one packet.
@@ -235,69 +236,28 @@ struct Pk {
   double E_seen, T_seen;
 };
 
-// ------------------------------------------------------ whole-wave mode
-// Once every packet of the launch has been handed out, a wavefront whose
-// last live packet is still going runs that packet with all 64 lanes: the
-// control flow is uniform, lane l generates Philox block blk0 + l so one
-// pass of the generator yields 256 draws, and the reemission bin is found by
-// a 64-wide ballot.  A lone lane issues about one instruction per ten
-// cycles, so these cuts in instruction count are what shortens the longest
-// random walks, which set the length of a launch.
-__device__ __forceinline__ int bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ uint32_t bcast(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
-__device__ __forceinline__ float bcast(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ long long bcast(long long v, int l) {
-  const uint32_t lo = bcast((uint32_t)v, l), hi = bcast((uint32_t)((unsigned long long)v >> 32), l);
-  return (long long)(((unsigned long long)hi << 32) | lo);
-}
-__device__ __forceinline__ uint64_t bcast(uint64_t v, int l) {
-  return (uint64_t)bcast((long long)v, l);
-}
-__device__ __forceinline__ double bcast(double v, int l) {
-  return __longlong_as_double(bcast((long long)__double_as_longlong(v), l));
-}
+// A packet handed over to the whole-wavefront launch.
+struct TailState32 {
+  Pk P;
+  Rng32 rng;
+  uint64_t pid;
+};
+static_assert(sizeof(TailState32) <= TAIL_STATE_BYTES, "hand-off slot");
 
-__device__ __forceinline__ Pk bcast(const Pk& P, int l) {
-  Pk S;
-  for (int a = 0; a < 3; ++a) {
-    S.an.A[a] = bcast(P.an.A[a], l);
-    S.an.Af[a] = bcast(P.an.Af[a], l);
-    S.q[a] = bcast(P.q[a], l);
-    S.d[a] = bcast(P.d[a], l);
-  }
-  S.an.K_in = bcast(P.an.K_in, l);
-  S.an.K_out = bcast(P.an.K_out, l);
-  S.an.L_lo = bcast(P.an.L_lo, l);
-  S.an.L_hi = bcast(P.an.L_hi, l);
-  S.tau = bcast(P.tau, l);
-  S.k = bcast(P.k, l);
-  S.i = bcast(P.i, l);
-  S.j = bcast(P.j, l);
-  S.n_int = bcast(P.n_int, l);
-  S.events = bcast(P.events, l);
-  S.pc_cross = bcast(P.pc_cross, l);
-  S.pc_scat = bcast(P.pc_scat, l);
-  S.pc_abs = bcast(P.pc_abs, l);
-  S.pc_mrw = bcast(P.pc_mrw, l);
-  S.rho = bcast(P.rho, l);
-  S.im = bcast(P.im, l);
-  S.Tc = bcast(P.Tc, l);
-  S.Tfix = bcast(P.Tfix, l);
-  S.mrw_T = bcast(P.mrw_T, l);
-  S.mrw_Drho = bcast(P.mrw_Drho, l);
-  S.mrw_kbar = bcast(P.mrw_kbar, l);
-  S.mrw_lim = bcast(P.mrw_lim, l);
-  S.d_safe = bcast(P.d_safe, l);
-  S.dm_up = bcast(P.dm_up, l);
-  S.cell_abs = bcast(P.cell_abs, l);
-  S.cell_mrw = bcast(P.cell_mrw, l);
-  S.E_seen = bcast(P.E_seen, l);
-  S.T_seen = bcast(P.T_seen, l);
-  return S;
+// ------------------------------------------------------ whole-wave mode
+// Once every packet of a launch has been handed out, packets that are still
+// going after wave_events events are saved and continued by a second launch
+// in which a whole wavefront runs each of them: the control flow is uniform,
+// lane l generates Philox block blk0 + l so one pass of the generator yields
+// 256 draws, and the reemission bin is found by a 64-wide ballot.  A lone
+// lane issues about one instruction per ten cycles, so these cuts in
+// instruction count are what shortens the longest random walks, which set
+// the length of a launch.
+__device__ __forceinline__ double wave_bcast0(double v) {
+  const long long x = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 0);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((unsigned long long)x >> 32), 0);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // The stream of one packet (the same draws as Rng32) served to a wavefront:
@@ -324,11 +284,11 @@ struct WaveRng {
       iso_phi(u[a], sn[a], cs[a]);
     }
   }
-  __device__ __forceinline__ void init(const Rng32& r, int l) {
-    pid = bcast(r.pid, l);
-    k0 = bcast(r.k0, l);
-    k1 = bcast(r.k1, l);
-    nd = bcast((uint64_t)r.draws(), l);  // index of the next word of the stream
+  __device__ __forceinline__ void init(const Rng32& r) {
+    pid = r.pid;
+    k0 = r.k0;
+    k1 = r.k1;
+    nd = (uint64_t)r.draws();  // index of the next word of the stream
     blk0 = (uint32_t)(nd >> 2);
     pos = (int)(nd & 3);
     fill();
@@ -339,12 +299,17 @@ struct WaveRng {
     const float x = comp == 0 ? v[0] : comp == 1 ? v[1] : comp == 2 ? v[2] : v[3];
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), p >> 2));
   }
-  __device__ __forceinline__ int take() {
-    if (pos == 256) {
-      blk0 += 64u;
-      pos = 0;
+  // at least n draws left in the buffer: else restart it at the block of
+  // the next draw (called where a segment of at most n draws begins, so the
+  // generator is inlined in two places only)
+  __device__ __forceinline__ void ensure(int n) {
+    if (pos + n > 256) {
+      blk0 += (uint32_t)(pos >> 2);
+      pos &= 3;
       fill();
     }
+  }
+  __device__ __forceinline__ int take() {
     ++nd;
     return pos++;
   }
@@ -364,6 +329,7 @@ struct WaveRng {
 
 __device__ __forceinline__ void iso32(WaveRng& r, float d[3]) { r.next_iso(d); }
 __device__ __forceinline__ float tau32(WaveRng& r) { return r.next_tau(); }
+__device__ __forceinline__ void ensure_draws(WaveRng& r, int n) { r.ensure(n); }
 
 // Smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane.
 template <typename C>
@@ -378,7 +344,6 @@ __device__ __forceinline__ int reemit_search_wave(const Reemit<C>& R, int nl, C 
   return nl - 1;
 }
 
-__device__ __forceinline__ double wave_bcast0(double v) { return bcast(v, 0); }
 
 // One event of packet P: a flight through the central hole, a face
 // crossing, or an interaction (scattering, or absorption with immediate
@@ -503,6 +468,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       P.d_safe -= sint;
       P.dm_up += 1.00001f * sint;
       const double* fz = A.frozen_T;
+      ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
       if (rng.next() < L.omega[P.k]) {
         ++P.pc_scat;
         iso32(rng, P.d);
@@ -558,6 +524,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           float dmin = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
           if (!(dmin > lim)) break;
           if (++P.events > A.max_events) break;
+          ensure_draws(rng, 7);  // escape time, jump, bin, direction, optical depth
           double R0 = (double)dmin * (1.0 - 1e-5);
           double s = (double)mrw_escape_s32(L.mrw_tab, rng.next());
           double ell = s * R0 * R0 * P.rho / Drho;
@@ -632,8 +599,9 @@ __device__ __forceinline__ void finish32(Pk& P, const RNG& rng, int fate, uint64
   P.E_seen = -1.0;
 }
 
+// Tables of the workgroup's disk into LDS (and the visit histogram, cleared).
 template <bool CDF_LDS>
-__device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
+__device__ __forceinline__ Lds32 setup_lds32(const TraceArgs& A) {
   extern __shared__ double smem[];
   const DevModel& M = A.m;
   const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda, n_T = M.n_T;
@@ -685,6 +653,14 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
     }
   }
   __syncthreads();
+  return L;
+}
+
+template <bool CDF_LDS>
+__device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
+  const DevModel& M = A.m;
+  const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda;
+  const Lds32 L = setup_lds32<CDF_LDS>(A);
 
   const int lane = __lane_id();
   const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
@@ -694,6 +670,7 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   P.i = -1;
   P.events = 0;
   uint64_t pid = 0;
+  bool handed = false;  // this packet tried the hand-off already
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   for (;;) {
@@ -751,6 +728,7 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
           P.E_seen = -1.0;
           P.T_seen = 0.0;
           tot[C_LAUNCH]++;
+          handed = false;
           alive = true;
         }
       }
@@ -760,24 +738,32 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
       if (exhausted) break;
       continue;
     }
-    // the wavefront's last packet, once all are handed out: all lanes on it
-    if (exhausted && A.wave_events > 0 && __popcll(live) == 1) {
-      const int src = __ffsll((long long)live) - 1;
-      if (bcast(P.events, src) >= A.wave_events) {
-        Pk S = bcast(P, src);
-        WaveRng wr;
-        wr.init(rng, src);
-        const uint64_t wpid = bcast(pid, src);
-        int f;
-        do {
-          f = event32<true>(S, wr, A, L, fixT, lane);
-        } while (f == 0);
-        finish32<true>(S, wr, f, wpid, A, tot, lane);
-        alive = false;
-        break;
+    if (!alive) continue;
+    if (A.tail) {
+      // a wavefront whose lanes never fall idle learns that the launch's
+      // packets are all handed out from the counter itself, now and then
+      if (!exhausted && __ballot((P.events & 1023) == 1023)) {
+        const int leader = __ffsll((long long)__ballot(true)) - 1;
+        unsigned long long nx = 0;
+        if (lane == leader)
+          nx = __hip_atomic_load(A.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nx = __shfl(nx, leader);
+        if (nx >= A.n_packets) exhausted = true;
+      }
+      // then a long packet moves to the whole-wavefront launch
+      if (exhausted && !handed && P.events >= A.wave_events) {
+        handed = true;
+        const unsigned slot = atomicAdd(A.tail_count, 1u);
+        if (slot < (unsigned)A.tail_cap) {
+          TailState32& ts = ((TailState32*)A.tail)[slot];
+          ts.P = P;
+          ts.rng = rng;
+          ts.pid = pid;
+          alive = false;
+          continue;
+        }
       }
     }
-    if (!alive) continue;
 
     const int fate = event32<false>(P, rng, A, L, fixT, lane);
     if (fate != 0) {
@@ -807,6 +793,47 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
   trace_fp32_body<CDF_LDS>(A);
 }
 
+// The packets handed over by the trace launch, one wavefront each; this
+// workgroup is number `rank` of the `nblk` serving the disk.
+template <bool CDF_LDS>
+__device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigned rank,
+                                                     unsigned nblk) {
+  const unsigned wpb = BS32 / 64;
+  const unsigned count = min(*A.tail_count, (unsigned)A.tail_cap);
+  if (rank * wpb >= count) return;  // the whole workgroup
+  const Lds32 L = setup_lds32<CDF_LDS>(A);
+  const int n_r = A.m.n_r, n_mu = A.m.n_mu;
+  const int lane = __lane_id();
+  const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
+  uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (unsigned slot = rank * wpb + wave; slot < count; slot += nblk * wpb) {
+    const TailState32& ts = ((const TailState32*)A.tail)[slot];
+    Pk S = ts.P;
+    WaveRng wr;
+    wr.init(ts.rng);
+    const uint64_t pid = ts.pid;
+    int f;
+    do {
+      f = event32<true>(S, wr, A, L, fixT, lane);
+    } while (f == 0);
+    finish32<true>(S, wr, f, pid, A, tot, lane);
+  }
+  flush_counters(A.t.counters, tot, N_COUNTERS);
+  if (L.vis) {
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_r * n_mu; a += blockDim.x) {
+      uint32_t v = L.vis[a];
+      if (v) atomicAdd(&A.t.visits[a], v);
+    }
+  }
+}
+
+template <bool CDF_LDS>
+__global__ void __launch_bounds__(BS32) trace_fp32_tail_kernel(TraceArgs A) {
+  trace_fp32_tail_body<CDF_LDS>(A, blockIdx.x, gridDim.x);
+}
+
 // Many disks in one launch: workgroup b works on disk block_disk[b] for the
 // whole launch (its tables stay in LDS), taking packets from that disk's
 // counter; workgroups are shared out in proportion to the disks' packets.
@@ -816,12 +843,27 @@ __global__ void __launch_bounds__(BS32) trace_fp32_batch_kernel(const TraceArgs*
   trace_fp32_body<CDF_LDS>(As[block_disk[blockIdx.x]]);
 }
 
+// Hand-offs of a batched launch: the same workgroups per disk; block_first
+// [n_disks + 1] gives each disk's first workgroup.
+template <bool CDF_LDS>
+__global__ void __launch_bounds__(BS32)
+    trace_fp32_batch_tail_kernel(const TraceArgs* __restrict__ As, const int* __restrict__ block_disk,
+                                 const int* __restrict__ block_first) {
+  const int dsk = block_disk[blockIdx.x];
+  trace_fp32_tail_body<CDF_LDS>(As[dsk], blockIdx.x - block_first[dsk],
+                                block_first[dsk + 1] - block_first[dsk]);
+}
+
 template <bool CDF_LDS>
 int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   auto kern = trace_fp32_kernel<CDF_LDS>;
-  if (lds > 64 * 1024)
+  auto tail = trace_fp32_tail_kernel<CDF_LDS>;
+  if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
+    (void)hipFuncSetAttribute((const void*)tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  }
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, BS32, lds) != hipSuccess || occ < 1)
     occ = 1;
@@ -830,6 +872,13 @@ int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   long long need = ((long long)a.n_packets + BS32 - 1) / BS32;
   if (nb > need) nb = need < 1 ? 1 : need;
   hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS32), lds, s, a);
+  if (a.tail) {
+    // enough workgroups for every slot, one workgroup per compute unit at a time
+    long long tb = (long long)ctx->n_cu * per_cu;
+    const long long slots = ((long long)a.tail_cap + BS32 / 64 - 1) / (BS32 / 64);
+    if (tb > slots) tb = slots;
+    hipLaunchKernelGGL(tail, dim3((unsigned)tb), dim3(BS32), lds, s, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(ctx, std::string("trace launch: ") + hipGetErrorString(e));
@@ -880,18 +929,29 @@ int prepare_trace_fp32_batch(size_t lds, bool cdf_lds) {
                          : hipFuncSetAttribute((const void*)trace_fp32_batch_kernel<false>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)e;  // not needed on every runtime; a real limit shows at launch
+  e = cdf_lds ? hipFuncSetAttribute((const void*)trace_fp32_batch_tail_kernel<true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+              : hipFuncSetAttribute((const void*)trace_fp32_batch_tail_kernel<false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)e;
   (void)hipGetLastError();
   return MCRT_OK;
 }
 
-int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk, int n_blocks,
-                            size_t lds, bool cdf_lds, hipStream_t s) {
-  if (cdf_lds)
+int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk,
+                            const int* d_block_first, int n_blocks, size_t lds, bool cdf_lds,
+                            hipStream_t s) {
+  if (cdf_lds) {
     hipLaunchKernelGGL(trace_fp32_batch_kernel<true>, dim3(n_blocks), dim3(BS32), lds, s, d_args,
                        d_block_disk);
-  else
+    hipLaunchKernelGGL(trace_fp32_batch_tail_kernel<true>, dim3(n_blocks), dim3(BS32), lds, s,
+                       d_args, d_block_disk, d_block_first);
+  } else {
     hipLaunchKernelGGL(trace_fp32_batch_kernel<false>, dim3(n_blocks), dim3(BS32), lds, s, d_args,
                        d_block_disk);
+    hipLaunchKernelGGL(trace_fp32_batch_tail_kernel<false>, dim3(n_blocks), dim3(BS32), lds, s,
+                       d_args, d_block_disk, d_block_first);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(nullptr, std::string("batched trace launch: ") + hipGetErrorString(e));

@@ -105,19 +105,392 @@ __device__ __forceinline__ double min_boundary64(const Lds64& L, int n_mu, int i
   return dmin > 0.0 ? dmin : 0.0;
 }
 
+// Functions of one draw u used by the transport (both generators evaluate
+// them with these functions, so they give the same values).
+__device__ __forceinline__ double iso_mu64(double u) { return 2.0 * u - 1.0; }
+__device__ __forceinline__ double iso_st64(double u) {
+  const double w = iso_mu64(u);
+  return sqrt(fmax(0.0, 1.0 - w * w));
+}
+__device__ __forceinline__ void iso_phi64(double u, double& sn, double& cs) {
+  sincos(2.0 * KPI * u, &sn, &cs);
+}
+__device__ __forceinline__ double tau_of64(double u) { return -log(u); }
+
 __device__ __forceinline__ void iso64(Rng64& r, double d[3]) {
-  double w = 2.0 * r.next() - 1.0;
-  double ph = 2.0 * KPI * r.next();
-  double st = sqrt(fmax(0.0, 1.0 - w * w));
+  const double u1 = r.next();
+  const double u2 = r.next();
   double sn, cs;
-  sincos(ph, &sn, &cs);
+  iso_phi64(u2, sn, cs);
+  const double st = iso_st64(u1);
   d[0] = st * cs;
   d[1] = st * sn;
-  d[2] = w;
+  d[2] = iso_mu64(u1);
+}
+__device__ __forceinline__ double tau64(Rng64& r) { return tau_of64(r.next()); }
+__device__ __forceinline__ void ensure_draws(Rng64&, int) {}
+
+// ------------------------------------------------------------------ packets
+struct Pk64 {
+  double p[3], d[3], tau;
+  int k, i, j, n_int;
+  long long events;
+  uint32_t pc_cross, pc_scat, pc_abs, pc_mrw;
+  double rho;                        // density of the cell
+  double im;                         // 1 / (4 pi m) of the cell
+  double Tc;                         // running temperature of the cell (< 0: not known)
+  double Tfix;                       // the cell's fixed temperature (frozen or MRW field)
+  double mrw_T, mrw_Drho, mrw_kbar, mrw_lim;  // MRW coefficients at mrw_T
+  // bounds of the distance to the cell boundary: d_safe below (a flight
+  // shorter than it stays in the cell, so the face distances are not needed),
+  // dm_up above (the last computed distance plus the path flown since: while
+  // it is within the MRW limit the criterion cannot hold)
+  double d_safe, dm_up;
+  // absorptions and MRW steps in this stay in the cell, added to the tallies
+  // when the packet leaves it; the cell's tally after this packet's last
+  // deposit and its temperature (reused when nobody deposited in between)
+  uint32_t cell_abs, cell_mrw;
+  double E_seen, T_seen;
+};
+
+// A packet handed over to the whole-wavefront launch.
+struct TailState64 {
+  Pk64 P;
+  Rng64 rng;
+  uint64_t pid;
+};
+static_assert(sizeof(TailState64) <= TAIL_STATE_BYTES, "hand-off slot");
+
+// ------------------------------------------------------ whole-wave mode
+// As in the FP32 tracker: once all packets are handed out, long packets are
+// continued by a second launch, a whole wavefront each (uniform control
+// flow, one Philox pass for 128 draws with their logarithms, square roots
+// and sines computed lane-parallel, 64-wide reemission search).
+__device__ __forceinline__ double bcd0(double v) {
+  const long long x = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 0);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((unsigned long long)x >> 32), 0);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double bcd(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((unsigned long long)x >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int CDF_MODE>  // 2: FP64 CDF in LDS; 1: FP32 guide copy in LDS; 0: global only
-__global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
+// One packet's stream (the same draws as Rng64) for a wavefront: lane l holds
+// block blk0 + l, i.e. draws 2 (blk0 + l) and 2 (blk0 + l) + 1.
+struct WaveRng64 {
+  uint64_t pid;
+  uint32_t k0, k1;
+  uint64_t blk0;
+  int pos;        // next draw of the buffer, 0..127
+  uint64_t nd;    // draws so far
+  double u[2], tau[2], st[2], sn[2], cs[2];
+
+  __device__ __forceinline__ void fill() {
+    const uint64_t blk = blk0 + (uint64_t)__lane_id();
+    uint32_t c0 = (uint32_t)pid, c1 = (uint32_t)(pid >> 32), c2 = (uint32_t)blk,
+             c3 = (uint32_t)(blk >> 32);
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    u[0] = Rng64::unit(c0, c1);
+    u[1] = Rng64::unit(c2, c3);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      tau[a] = tau_of64(u[a]);
+      st[a] = iso_st64(u[a]);
+      iso_phi64(u[a], sn[a], cs[a]);
+    }
+  }
+  __device__ __forceinline__ void init(const Rng64& r) {
+    pid = r.pid;
+    k0 = r.k0;
+    k1 = r.k1;
+    nd = r.d;  // index of the next draw
+    blk0 = nd >> 1;
+    pos = (int)(nd & 1);
+    fill();
+  }
+  __device__ __forceinline__ double at(const double* v, int p) const {
+    const double x = (p & 1) ? v[1] : v[0];
+    return bcd(x, p >> 1);
+  }
+  // at least n draws left in the buffer: else restart it at the block of
+  // the next draw (the generator is inlined where a segment begins only)
+  __device__ __forceinline__ void ensure(int n) {
+    if (pos + n > 128) {
+      blk0 += (uint64_t)(pos >> 1);
+      pos &= 1;
+      fill();
+    }
+  }
+  __device__ __forceinline__ int take() {
+    ++nd;
+    return pos++;
+  }
+  __device__ __forceinline__ double next() { return at(u, take()); }
+  __device__ __forceinline__ double next_tau() { return at(tau, take()); }
+  __device__ __forceinline__ void next_iso(double d[3]) {
+    const int p1 = take();
+    const double w = iso_mu64(at(u, p1)), s = at(st, p1);
+    const int p2 = take();
+    const double cs_ = at(cs, p2), sn_ = at(sn, p2);
+    d[0] = s * cs_;
+    d[1] = s * sn_;
+    d[2] = w;
+  }
+  __device__ __forceinline__ uint64_t nd_value() const { return nd; }
+};
+
+__device__ __forceinline__ void iso64(WaveRng64& r, double d[3]) { r.next_iso(d); }
+__device__ __forceinline__ double tau64(WaveRng64& r) { return r.next_tau(); }
+__device__ __forceinline__ void ensure_draws(WaveRng64& r, int n) { r.ensure(n); }
+
+// smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane
+__device__ __forceinline__ int reemit64_wave(const Lds64& L, double T_old, double T_new, double xi) {
+  const int nl = L.tv.nl;
+  Reemit<double> R = reemit_setup<double>(L.tv, L.cdf64, T_old, T_new);
+  const double target = xi * R.D(nl - 1);
+  const int lane = __lane_id();
+  for (int base = 0; base < nl; base += 64) {
+    const int kk = base + lane < nl ? base + lane : nl - 1;
+    const unsigned long long m = __ballot(base + lane < nl && R.D(kk) > target);
+    if (m) return base + __ffsll((long long)m) - 1;
+  }
+  return nl - 1;
+}
+
+// One event of packet P (see the FP32 tracker for the structure).  WAVE: all
+// lanes hold P; lane 0 issues the memory updates.
+template <bool WAVE, class RNG>
+__device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, const Lds64& L,
+                                       const double* fixT, int lane) {
+  const DevModel& M = A.m;
+  const int n_r = M.n_r, n_mu = M.n_mu;
+  const bool issuer = !WAVE || lane == 0;
+  auto visit = [&](int cn) {
+    if (issuer) {
+      if (L.vis) atomicAdd(&L.vis[cn], 1u); else atomicAdd(&A.t.visits[cn], 1u);
+    }
+  };
+  auto deposit = [&](int c, double dE) -> double {
+    double E_old = 0.0;
+    if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    if (WAVE) E_old = bcd0(E_old);
+    return E_old;
+  };
+  auto reemit = [&](double T_old, double T_new, double xb) -> int {
+    if (WAVE) return reemit64_wave(L, T_old, T_new, xb);
+    return reemit64(L, T_old, T_new, xb);
+  };
+  int fate = 0;
+  if (++P.events > A.max_events) {
+    fate = 3;
+  } else if (P.i < 0) {
+    // central hole: free flight to the star or to the inner grid sphere
+    double pd = P.p[0] * P.d[0] + P.p[1] * P.d[1] + P.p[2] * P.d[2];
+    double rr = P.p[0] * P.p[0] + P.p[1] * P.p[1] + P.p[2] * P.p[2];
+    double s = enter_sphere<double>(pd, rr - M.R_star * M.R_star);
+    if (s >= 0.0) {
+      P.p[0] += s * P.d[0]; P.p[1] += s * P.d[1]; P.p[2] += s * P.d[2];
+      fate = 2;
+    } else {
+      s = exit_sphere<double>(pd, rr - L.r2[0]);
+      P.p[0] += s * P.d[0]; P.p[1] += s * P.d[1]; P.p[2] += s * P.d[2];
+      P.i = 0;
+      double r2 = (P.p[0] * P.p[0] + P.p[1] * P.p[1]) + P.p[2] * P.p[2];
+      P.j = mu_row(L.mu2, n_mu, r2, P.p[2] * P.p[2]);
+      P.rho = M.rho[P.j];
+      P.im = M.inv4pim[P.j];
+      if (fixT) P.Tfix = fixT[P.j];
+      visit(P.j);
+      P.Tc = -1.0;
+      P.mrw_T = -2.0;
+      P.d_safe = 0.0;
+      P.dm_up = INFINITY;
+      P.n_int = 0;
+      ++P.pc_cross;
+    }
+  } else {
+    const int c = P.i * n_mu + P.j;
+    const double alpha = P.rho * L.chi[P.k];
+    int face = 1;
+    double sb = 0.0, tau_b = 0.0;
+    const bool inside = P.tau < alpha * P.d_safe;
+    if (!inside) {
+      sb = boundary64(L, n_mu, P.i, P.j, P.p, P.d, face);
+      tau_b = alpha * sb;
+    }
+    if (!inside && tau_b <= P.tau) {
+      if (issuer && P.cell_abs) atomicAdd(&A.t.n_abs[c], P.cell_abs);
+      if (issuer && P.cell_mrw) atomicAdd(&A.t.n_mrw[c], P.cell_mrw);
+      P.cell_abs = P.cell_mrw = 0;
+      P.E_seen = -1.0;
+      P.d_safe = 0.0;
+      P.dm_up = INFINITY;
+      P.p[0] += sb * P.d[0]; P.p[1] += sb * P.d[1]; P.p[2] += sb * P.d[2];
+      P.tau -= tau_b;
+      ++P.pc_cross;
+      bool entered = true;
+      if (face == 1) {
+        if (P.i + 1 == n_r) {
+          int m = (int)(fabs(P.d[2]) * M.n_inc);
+          m = m < M.n_inc ? m : M.n_inc - 1;
+          if (issuer) unsafeAtomicAdd(&A.t.sed[P.k * M.n_inc + m], A.eps);
+          fate = 1;
+          entered = false;
+        } else {
+          ++P.i;
+        }
+      } else if (face == 0) {
+        --P.i;
+        if (P.i < 0) entered = false;
+      } else if (face == 2) {
+        --P.j;
+      } else {
+        ++P.j;
+      }
+      if (entered) {
+        int cn = P.i * n_mu + P.j;
+        P.rho = M.rho[cn];
+        P.im = M.inv4pim[cn];
+        if (fixT) P.Tfix = fixT[cn];
+        visit(cn);
+      }
+      P.Tc = -1.0;
+      P.mrw_T = -2.0;
+      P.n_int = 0;
+    } else {
+      // interaction in the cell
+      double sint = P.tau / alpha;
+      P.p[0] += sint * P.d[0]; P.p[1] += sint * P.d[1]; P.p[2] += sint * P.d[2];
+      P.d_safe -= sint;
+      P.dm_up += 1.000001 * sint;
+      const double* fz = A.frozen_T;
+      ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
+      if (rng.next() < L.omega[P.k]) {
+        ++P.pc_scat;
+        iso64(rng, P.d);
+      } else {
+        ++P.pc_abs;
+        ++P.cell_abs;
+        // the tally update is in flight while the next draws are made
+        double E_old = deposit(c, A.eps);
+        double xb = rng.next();
+        iso64(rng, P.d);
+        if (fz) {
+          P.k = reemit(-1.0, P.Tfix, xb);
+        } else {
+          const double E_new = E_old + A.eps;
+          double T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
+          double T_new = T_of_g(L.tv, E_new * P.im);
+          P.E_seen = E_new;
+          P.T_seen = T_new;
+          P.Tc = T_new;
+          P.k = reemit(T_old, T_new, xb);
+        }
+      }
+      ++P.n_int;
+      if (A.mrw) {
+        // modified random walk while the start criterion holds
+        while (P.n_int >= A.n_int_min) {
+          double T_here;
+          if (fixT) T_here = P.Tfix;
+          else {
+            if (P.Tc < 0.0)
+              P.Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT) * P.im);
+            T_here = P.Tc;
+          }
+          if (T_here != P.mrw_T) {  // MRW coefficients of this cell at this T
+            P.mrw_T = T_here;
+            P.mrw_Drho = interp_T(L.tv, L.tv.Drho, T_here);
+            P.mrw_kbar = interp_T(L.tv, L.tv.kbar, T_here);
+            double lam_R = 3.0 * P.mrw_Drho / P.rho;
+            P.mrw_lim = A.gamma * lam_R;
+          }
+          const double Drho = P.mrw_Drho;
+          if (P.dm_up <= P.mrw_lim) break;
+          double dmin = min_boundary64(L, n_mu, P.i, P.j, P.p);
+          P.d_safe = 0.999 * dmin;
+          P.dm_up = 1.000001 * dmin;
+          if (!(dmin > P.mrw_lim)) break;
+          if (++P.events > A.max_events) break;
+          ensure_draws(rng, 7);  // escape time, jump, bin, direction, optical depth
+          double R0 = dmin * (1.0 - 1e-6);
+          double s = mrw_escape_s(L.mrw_tab, rng.next());
+          double ell = s * R0 * R0 * P.rho / Drho;  // c t = s R0^2 / D
+          double dE = A.eps * P.rho * P.mrw_kbar * ell;
+          double E_old = deposit(c, dE);
+          double nrm[3];
+          iso64(rng, nrm);
+          P.p[0] += R0 * nrm[0]; P.p[1] += R0 * nrm[1]; P.p[2] += R0 * nrm[2];
+          double xb = rng.next();
+          iso64(rng, P.d);
+          if (fz) {
+            P.k = reemit(-1.0, P.Tfix, xb);
+          } else {
+            const double E_new = E_old + dE;
+            double T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
+            double T_new = T_of_g(L.tv, E_new * P.im);
+            P.E_seen = E_new;
+            P.T_seen = T_new;
+            P.Tc = T_new;
+            P.k = reemit(T_old, T_new, xb);
+          }
+          P.d_safe = 0.0;
+          P.dm_up = INFINITY;
+          ++P.pc_mrw;
+          ++P.cell_mrw;
+        }
+      }
+      P.tau = tau64(rng);
+    }
+  }
+  return fate;
+}
+
+template <bool WAVE, class RNG>
+__device__ __forceinline__ void finish64(Pk64& P, const RNG& rng_draws, int fate, uint64_t pid,
+                                         const TraceArgs& A, uint32_t* tot, int lane) {
+  const int n_mu = A.m.n_mu;
+  if (!WAVE || lane == 0) {
+    if (P.i >= 0 && (P.cell_abs | P.cell_mrw)) {  // the packet ended in a cell (capped)
+      const int c = P.i * n_mu + P.j;
+      if (P.cell_abs) atomicAdd(&A.t.n_abs[c], P.cell_abs);
+      if (P.cell_mrw) atomicAdd(&A.t.n_mrw[c], P.cell_mrw);
+    }
+    if (fate == 1) tot[C_ESCAPED]++;
+    else if (fate == 2) { tot[C_STAR]++; unsafeAtomicAdd(A.t.E_star, A.eps); }
+    else tot[C_CAPPED]++;
+    tot[C_CROSS] += P.pc_cross;
+    tot[C_SCAT] += P.pc_scat;
+    tot[C_ABS] += P.pc_abs;
+    tot[C_MRW] += P.pc_mrw;
+    if (A.recs) {
+      int64_t r = (int64_t)(pid - A.offset);
+      if (r >= 0 && r < A.n_recs) {
+        mcrt_packet_rec& R = A.recs[r];
+        R.fate = fate;
+        R.k = P.k;
+        R.n_cross = P.pc_cross;
+        R.n_scat = P.pc_scat;
+        R.n_abs = P.pc_abs;
+        R.n_mrw = P.pc_mrw;
+        R.n_draws = (int64_t)rng_draws.nd_value();
+        R.x = P.p[0]; R.y = P.p[1]; R.z = P.p[2];
+        R.u = P.d[0]; R.v = P.d[1]; R.w = P.d[2];
+      }
+    }
+  }
+  P.cell_abs = P.cell_mrw = 0;
+  P.E_seen = -1.0;
+}
+
+// Tables of the disk into LDS (and the visit histogram, cleared).
+template <int CDF_MODE>
+__device__ __forceinline__ Lds64 setup_lds64(const TraceArgs& A) {
   extern __shared__ double smem[];
   const DevModel& M = A.m;
   const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda, n_T = M.n_T;
@@ -171,31 +544,24 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
     }
   }
   __syncthreads();
+  return L;
+}
+
+template <int CDF_MODE>  // 2: FP64 CDF in LDS; 1: FP32 guide copy in LDS; 0: global only
+__global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
+  const DevModel& M = A.m;
+  const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda;
+  const Lds64 L = setup_lds64<CDF_MODE>(A);
 
   const int lane = __lane_id();
+  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
   bool alive = false, exhausted = false;
   Rng64 rng;
-  double p[3] = {0, 0, 0}, d[3] = {0, 0, 1}, tau = 0.0;
-  int k = 0, i = -1, j = 0, n_int = 0;
-  long long events = 0;
+  Pk64 P;
+  P.i = -1;
+  P.events = 0;
   uint64_t pid = 0;
-  uint32_t pc_cross = 0, pc_scat = 0, pc_abs = 0, pc_mrw = 0;
-  double rho = 0.0;    // density of the current cell
-  double im = 0.0;     // 1 / (4 pi m) of the current cell
-  double Tc = -1.0;    // running temperature of the current cell (< 0: not known)
-  double Tfix = 0.0;   // the cell's fixed temperature (frozen field or MRW coefficient field)
-  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
-  double mrw_T = -2.0, mrw_Drho = 0.0, mrw_kbar = 0.0, mrw_lim = 0.0;  // MRW coefficients
-  // bounds of the distance to the cell boundary: d_safe below (a flight
-  // shorter than it stays in the cell, so the face distances are not needed),
-  // dm_up above (the last computed distance plus the path flown since: while
-  // it is within the MRW limit the criterion cannot hold)
-  double d_safe = 0.0, dm_up = INFINITY;
-  // absorptions and MRW steps in the current cell, added to the tallies when
-  // the packet leaves it; the cell's tally after this lane's last deposit and
-  // its temperature (reused when no other packet deposited in between)
-  uint32_t cell_abs = 0, cell_mrw = 0;
-  double E_seen = -1.0, T_seen = 0.0;
+  bool handed = false;  // this packet tried the hand-off already
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   for (;;) {
@@ -217,232 +583,80 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
           rng.init(A.key0, A.key1, pid);
           double ws = 2.0 * rng.next() - 1.0;
           double st = sqrt(fmax(0.0, 1.0 - ws * ws));
-          p[0] = M.R_star * st;
-          p[1] = 0.0;
-          p[2] = M.R_star * ws;
+          P.p[0] = M.R_star * st;
+          P.p[1] = 0.0;
+          P.p[2] = M.R_star * ws;
           double mup = sqrt(rng.next());
           double php = 2.0 * KPI * rng.next();
           double sp = sqrt(fmax(0.0, 1.0 - mup * mup));
           double sn, cs;
           sincos(php, &sn, &cs);
-          d[0] = mup * st + sp * cs * ws;
-          d[1] = sp * sn;
-          d[2] = mup * ws - sp * cs * st;
+          P.d[0] = mup * st + sp * cs * ws;
+          P.d[1] = sp * sn;
+          P.d[2] = mup * ws - sp * cs * st;
           double xs = rng.next();
           int lo = 0, hi = nl - 1;
           while (lo < hi) {
             int mid = (lo + hi) >> 1;
             if (L.star_cdf[mid] > xs) hi = mid; else lo = mid + 1;
           }
-          k = lo;
-          tau = -log(rng.next());
-          i = -1;
-          j = 0;
-          n_int = 0;
-          events = 0;
-          pc_cross = pc_scat = pc_abs = pc_mrw = 0;
+          P.k = lo;
+          P.tau = -log(rng.next());
+          P.i = -1;
+          P.j = 0;
+          P.n_int = 0;
+          P.events = 0;
+          P.pc_cross = P.pc_scat = P.pc_abs = P.pc_mrw = 0;
+          P.rho = P.im = P.Tfix = 0.0;
+          P.Tc = -1.0;
+          P.mrw_T = -2.0;
+          P.mrw_Drho = P.mrw_kbar = P.mrw_lim = 0.0;
+          P.d_safe = 0.0;
+          P.dm_up = INFINITY;
+          P.cell_abs = P.cell_mrw = 0;
+          P.E_seen = -1.0;
+          P.T_seen = 0.0;
           tot[C_LAUNCH]++;
+          handed = false;
           alive = true;
         }
       }
     }
-    if (__ballot(alive) == 0ull) {
+    const unsigned long long live = __ballot(alive);
+    if (live == 0ull) {
       if (exhausted) break;
       continue;
     }
     if (!alive) continue;
-
-    int fate = 0;
-    if (++events > A.max_events) {
-      fate = 3;
-    } else if (i < 0) {
-      // central hole: free flight to the star or to the inner grid sphere
-      double pd = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
-      double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-      double s = enter_sphere<double>(pd, rr - M.R_star * M.R_star);
-      if (s >= 0.0) {
-        p[0] += s * d[0]; p[1] += s * d[1]; p[2] += s * d[2];
-        fate = 2;
-      } else {
-        s = exit_sphere<double>(pd, rr - L.r2[0]);
-        p[0] += s * d[0]; p[1] += s * d[1]; p[2] += s * d[2];
-        i = 0;
-        double r2 = (p[0] * p[0] + p[1] * p[1]) + p[2] * p[2];
-        j = mu_row(L.mu2, n_mu, r2, p[2] * p[2]);
-        rho = M.rho[j];
-        im = M.inv4pim[j];
-        if (fixT) Tfix = fixT[j];
-        if (L.vis) atomicAdd(&L.vis[j], 1u); else atomicAdd(&A.t.visits[j], 1u);
-        Tc = -1.0;
-        mrw_T = -2.0;
-        d_safe = 0.0;
-        dm_up = INFINITY;
-        n_int = 0;
-        ++pc_cross;
+    if (A.tail) {
+      // a wavefront whose lanes never fall idle learns that the launch's
+      // packets are all handed out from the counter itself, now and then
+      if (!exhausted && __ballot((P.events & 1023) == 1023)) {
+        const int leader = __ffsll((long long)__ballot(true)) - 1;
+        unsigned long long nx = 0;
+        if (lane == leader)
+          nx = __hip_atomic_load(A.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nx = __shfl(nx, leader);
+        if (nx >= A.n_packets) exhausted = true;
       }
-    } else {
-      const int c = i * n_mu + j;
-      const double alpha = rho * L.chi[k];
-      int face = 1;
-      double sb = 0.0, tau_b = 0.0;
-      const bool inside = tau < alpha * d_safe;
-      if (!inside) {
-        sb = boundary64(L, n_mu, i, j, p, d, face);
-        tau_b = alpha * sb;
-      }
-      if (!inside && tau_b <= tau) {
-        if (cell_abs) { atomicAdd(&A.t.n_abs[c], cell_abs); cell_abs = 0; }
-        if (cell_mrw) { atomicAdd(&A.t.n_mrw[c], cell_mrw); cell_mrw = 0; }
-        E_seen = -1.0;
-        d_safe = 0.0;
-        dm_up = INFINITY;
-        p[0] += sb * d[0]; p[1] += sb * d[1]; p[2] += sb * d[2];
-        tau -= tau_b;
-        ++pc_cross;
-        bool entered = true;
-        if (face == 1) {
-          if (i + 1 == n_r) {
-            int m = (int)(fabs(d[2]) * M.n_inc);
-            m = m < M.n_inc ? m : M.n_inc - 1;
-            unsafeAtomicAdd(&A.t.sed[k * M.n_inc + m], A.eps);
-            fate = 1;
-            entered = false;
-          } else {
-            ++i;
-          }
-        } else if (face == 0) {
-          --i;
-          if (i < 0) entered = false;
-        } else if (face == 2) {
-          --j;
-        } else {
-          ++j;
+      // then a long packet moves to the whole-wavefront launch
+      if (exhausted && !handed && P.events >= A.wave_events) {
+        handed = true;
+        const unsigned slot = atomicAdd(A.tail_count, 1u);
+        if (slot < (unsigned)A.tail_cap) {
+          TailState64& ts = ((TailState64*)A.tail)[slot];
+          ts.P = P;
+          ts.rng = rng;
+          ts.pid = pid;
+          alive = false;
+          continue;
         }
-        if (entered) {
-          int cn = i * n_mu + j;
-          rho = M.rho[cn];
-          im = M.inv4pim[cn];
-          if (fixT) Tfix = fixT[cn];
-          if (L.vis) atomicAdd(&L.vis[cn], 1u); else atomicAdd(&A.t.visits[cn], 1u);
-        }
-        Tc = -1.0;
-        mrw_T = -2.0;
-        n_int = 0;
-      } else {
-        // interaction in the cell
-        double sint = tau / alpha;
-        p[0] += sint * d[0]; p[1] += sint * d[1]; p[2] += sint * d[2];
-        d_safe -= sint;
-        dm_up += 1.000001 * sint;
-        const double* fz = A.frozen_T;
-        if (rng.next() < L.omega[k]) {
-          ++pc_scat;
-          iso64(rng, d);
-        } else {
-          ++pc_abs;
-          ++cell_abs;
-          // the tally update is in flight while the next draws are made
-          double E_old = unsafeAtomicAdd(&A.t.E_abs[c], A.eps);
-          double xb = rng.next();
-          iso64(rng, d);
-          if (fz) {
-            k = reemit64(L, -1.0, Tfix, xb);
-          } else {
-            const double E_new = E_old + A.eps;
-            double T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
-            double T_new = T_of_g(L.tv, E_new * im);
-            E_seen = E_new;
-            T_seen = T_new;
-            Tc = T_new;
-            k = reemit64(L, T_old, T_new, xb);
-          }
-        }
-        ++n_int;
-        if (A.mrw) {
-          // modified random walk while the start criterion holds
-          while (n_int >= A.n_int_min) {
-            double T_here;
-            if (fixT) T_here = Tfix;
-            else {
-              if (Tc < 0.0)
-                Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT) * im);
-              T_here = Tc;
-            }
-            if (T_here != mrw_T) {  // MRW coefficients of this cell at this T
-              mrw_T = T_here;
-              mrw_Drho = interp_T(L.tv, L.tv.Drho, T_here);
-              mrw_kbar = interp_T(L.tv, L.tv.kbar, T_here);
-              double lam_R = 3.0 * mrw_Drho / rho;
-              mrw_lim = A.gamma * lam_R;
-            }
-            const double Drho = mrw_Drho;
-            if (dm_up <= mrw_lim) break;
-            double dmin = min_boundary64(L, n_mu, i, j, p);
-            d_safe = 0.999 * dmin;
-            dm_up = 1.000001 * dmin;
-            if (!(dmin > mrw_lim)) break;
-            if (++events > A.max_events) break;
-            double R0 = dmin * (1.0 - 1e-6);
-            double s = mrw_escape_s(L.mrw_tab, rng.next());
-            double ell = s * R0 * R0 * rho / Drho;  // c t = s R0^2 / D
-            double dE = A.eps * rho * mrw_kbar * ell;
-            double E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
-            double nrm[3];
-            iso64(rng, nrm);
-            p[0] += R0 * nrm[0]; p[1] += R0 * nrm[1]; p[2] += R0 * nrm[2];
-            double xb = rng.next();
-            iso64(rng, d);
-            if (fz) {
-              k = reemit64(L, -1.0, Tfix, xb);
-            } else {
-              const double E_new = E_old + dE;
-              double T_old = E_old == E_seen ? T_seen : T_of_g(L.tv, E_old * im);
-              double T_new = T_of_g(L.tv, E_new * im);
-              E_seen = E_new;
-              T_seen = T_new;
-              Tc = T_new;
-              k = reemit64(L, T_old, T_new, xb);
-            }
-            d_safe = 0.0;
-            dm_up = INFINITY;
-            ++pc_mrw;
-            ++cell_mrw;
-          }
-        }
-        tau = -log(rng.next());
       }
     }
+
+    const int fate = event64<false>(P, rng, A, L, fixT, lane);
     if (fate != 0) {
-      if (cell_abs | cell_mrw) {  // the packet ended in a cell (capped)
-        const int c = i * n_mu + j;
-        if (i >= 0 && cell_abs) atomicAdd(&A.t.n_abs[c], cell_abs);
-        if (i >= 0 && cell_mrw) atomicAdd(&A.t.n_mrw[c], cell_mrw);
-        cell_abs = cell_mrw = 0;
-      }
-      E_seen = -1.0;
-      if (fate == 1) tot[C_ESCAPED]++;
-      else if (fate == 2) { tot[C_STAR]++; unsafeAtomicAdd(A.t.E_star, A.eps); }
-      else tot[C_CAPPED]++;
-      tot[C_CROSS] += pc_cross;
-      tot[C_SCAT] += pc_scat;
-      tot[C_ABS] += pc_abs;
-      tot[C_MRW] += pc_mrw;
-      if (A.recs) {
-        int64_t r = (int64_t)(pid - A.offset);
-        if (r >= 0 && r < A.n_recs) {
-          mcrt_packet_rec& R = A.recs[r];
-          R.fate = fate;
-          R.k = k;
-          R.n_cross = pc_cross;
-          R.n_scat = pc_scat;
-          R.n_abs = pc_abs;
-          R.n_mrw = pc_mrw;
-          R.n_draws = (int64_t)rng.d;
-          R.x = p[0]; R.y = p[1]; R.z = p[2];
-          R.u = d[0]; R.v = d[1]; R.w = d[2];
-        }
-      }
+      finish64<false>(P, rng, fate, pid, A, tot, lane);
       alive = false;
       // flush lane totals before they can overflow
       if (tot[C_CROSS] > 0x40000000u || tot[C_SCAT] > 0x40000000u || tot[C_ABS] > 0x40000000u ||
@@ -453,6 +667,40 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
         }
       }
     }
+  }
+  flush_counters(A.t.counters, tot, N_COUNTERS);
+  if (L.vis) {
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_r * n_mu; a += blockDim.x) {
+      uint32_t v = L.vis[a];
+      if (v) atomicAdd(&A.t.visits[a], v);
+    }
+  }
+}
+
+// The packets handed over by trace_fp64_kernel, one wavefront each.
+template <int CDF_MODE>
+__global__ void __launch_bounds__(BS64) trace_fp64_tail_kernel(TraceArgs A) {
+  const unsigned wpb = BS64 / 64;
+  const unsigned count = min(*A.tail_count, (unsigned)A.tail_cap);
+  if (blockIdx.x * wpb >= count) return;  // the whole workgroup
+  const Lds64 L = setup_lds64<CDF_MODE>(A);
+  const int n_r = A.m.n_r, n_mu = A.m.n_mu;
+  const int lane = __lane_id();
+  const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
+  uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (unsigned slot = blockIdx.x * wpb + wave; slot < count; slot += gridDim.x * wpb) {
+    const TailState64& ts = ((const TailState64*)A.tail)[slot];
+    Pk64 S = ts.P;
+    WaveRng64 wr;
+    wr.init(ts.rng);
+    const uint64_t pid = ts.pid;
+    int f;
+    do {
+      f = event64<true>(S, wr, A, L, fixT, lane);
+    } while (f == 0);
+    finish64<true>(S, wr, f, pid, A, tot, lane);
   }
   flush_counters(A.t.counters, tot, N_COUNTERS);
   if (L.vis) {
@@ -486,9 +734,13 @@ __global__ void locate_kernel(const double* r2e, const double* mu2e, int n_r, in
 template <int MODE>
 int launch_mode(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   auto kern = trace_fp64_kernel<MODE>;
+  auto tail = trace_fp64_tail_kernel<MODE>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
     if (e != hipSuccess) {
       set_error(ctx, std::string("LDS attribute: ") + hipGetErrorString(e));
       return MCRT_E_HIP;
@@ -502,6 +754,12 @@ int launch_mode(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   long long need = ((long long)a.n_packets + BS64 - 1) / BS64;
   if (nb > need) nb = need < 1 ? 1 : need;
   hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS64), lds, s, a);
+  if (a.tail) {
+    long long tb = (long long)ctx->n_cu * per_cu;
+    const long long slots = ((long long)a.tail_cap + BS64 / 64 - 1) / (BS64 / 64);
+    if (tb > slots) tb = slots;
+    hipLaunchKernelGGL(tail, dim3((unsigned)tb), dim3(BS64), lds, s, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(ctx, std::string("trace launch: ") + hipGetErrorString(e));

@@ -141,7 +141,7 @@ class Context:
                  n_inc: int = 10, max_events: int = 1 << 30, pda_visits: int = 100,
                  pda_max_sweeps: int = 50, pda_tol: float = 1e-8, cg_max_iter: int = 20000,
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
-                 blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 32, rho=None):
+                 blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()

@@ -297,8 +297,9 @@ def test_integer_tallies_exact(mcrt, torch_cuda, precision):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("mrw", [False, True])
-def test_fp32_wave_mode_same_events(mcrt, torch_cuda, mrw):
+def test_wave_mode_same_events(mcrt, torch_cuda, mrw, precision):
     """The whole-wavefront mode (the last live packet of a wavefront traced by
     all 64 lanes) follows the same events as the per-lane mode: packets traced
     one per launch (so each runs in wave mode after its first event) against
@@ -307,7 +308,7 @@ def test_fp32_wave_mode_same_events(mcrt, torch_cuda, mrw):
     d = W.small_disk(M_dust_msun=1e-1, n_r=14, n_mu=10, n_lambda=24)
     Tf = torch.from_numpy(_frozen_field(d)).cuda()
     n = 300
-    kw = dict(precision="fp32", mrw=mrw, gamma=2.0, n_int_min=5)
+    kw = dict(precision=precision, mrw=mrw, gamma=2.0, n_int_min=5)
     lanes = mcrt.Context(d, wave_events=0, **kw)
     ref = mcrt.Context.records_numpy(lanes.trace(n, 31, n_total=n, frozen_T=Tf, n_recs=n))
     wave = mcrt.Context(d, wave_events=1, **kw)
