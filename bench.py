@@ -85,7 +85,7 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     p.add_argument("--packets", type=int, default=1000000)
@@ -401,7 +401,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": (measured_traffic("trace_fp32_kernel", N)
                                  if a.precision == "fp32" else None),
-                     "kernel": "trace_%s_kernel" % a.precision,
+                     "kernel": "trace_%s_kernel + trace_%s_tail_kernel (one mcrt_trace call)"
+                               % (a.precision, a.precision),
                      "kernel_ms": float(np.mean(trace_ms)),
                      "flops_per_launch": flops},
         "events_per_step": c,

@@ -43,6 +43,44 @@ __host__ __device__ inline size_t lds32_bytes(int n_r, int n_mu, int n_T, int nl
   return dbl * 8 + N_GUIDE * 4 + ((flt * 4 + 7) & ~(size_t)7);
 }
 
+// Hardware reciprocal and square root (about 1 ulp, no range scaling: the
+// operands here are normal numbers well inside the FP32 range).
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Face distances (as exit_sphere, enter_sphere, exit_cone) with those.
+__device__ __forceinline__ float exit_sphere32(float pd, float c) {
+  float disc = pd * pd - c;
+  if (c >= 0.0f && (pd > 0.0f || disc < 0.0f)) return 0.0f;
+  disc = disc < 0.0f ? 0.0f : disc;
+  const float sq = fsqrt(disc);
+  return pd > 0.0f ? -fdiv(c, pd + sq) : -pd + sq;
+}
+__device__ __forceinline__ float enter_sphere32(float pd, float c) {
+  if (c <= 0.0f && pd < 0.0f) return 0.0f;
+  if (pd >= 0.0f) return -1.0f;
+  const float disc = pd * pd - c;
+  if (disc < 0.0f) return -1.0f;
+  return fdiv(c, -pd + fsqrt(disc));
+}
+__device__ __forceinline__ float exit_cone32(float A, float B, float C, bool toward_pole) {
+  if (toward_pole) {
+    if (C >= 0.0f && B > 0.0f) return 0.0f;
+  } else {
+    if (C <= 0.0f && B < 0.0f) return 0.0f;
+  }
+  const float disc = B * B - A * C;
+  if (disc < 0.0f) return -1.0f;
+  const float sq = fsqrt(disc);
+  float v;
+  if (toward_pole)
+    v = (B > 0.0f) ? fdiv(C, -B - sq) : fdiv(-B + sq, A);
+  else
+    v = (B < 0.0f) ? fdiv(C, -B + sq) : fdiv(-B - sq, A);
+  if (!(v > 0.0f) || __builtin_isinf(v)) return -1.0f;
+  return v;
+}
+
 // Per-anchor constants of the four faces of cell (i, j).
 struct Anchor {
   double A[3];
@@ -79,9 +117,9 @@ __device__ __forceinline__ float boundary32(const Anchor& a, const Lds32& L, int
   float Aq = a.Af[0] * q[0] + a.Af[1] * q[1] + a.Af[2] * q[2];
   float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
   float pd = Ad + qd;
-  float best = exit_sphere<float>(pd, a.K_out + 2.0f * Aq + qq);
+  float best = exit_sphere32(pd, a.K_out + 2.0f * Aq + qq);
   face = 1;
-  float s = enter_sphere<float>(pd, a.K_in + 2.0f * Aq + qq);
+  float s = enter_sphere32(pd, a.K_in + 2.0f * Aq + qq);
   if (s >= 0.0f && s < best) { best = s; face = 0; }
   float z = a.Af[2] + q[2];
   float dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -90,13 +128,13 @@ __device__ __forceinline__ float boundary32(const Anchor& a, const Lds32& L, int
   if (j >= 1) {
     float m2 = (float)L.mu2[j];
     float C = a.L_lo + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    s = exit_cone<float>(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, false);
+    s = exit_cone32(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, false);
     if (s >= 0.0f && s < best) { best = s; face = 2; }
   }
   if (j + 1 < n_mu) {
     float m2 = (float)L.mu2[j + 1];
     float C = a.L_hi + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    s = exit_cone<float>(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, true);
+    s = exit_cone32(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, true);
     if (s >= 0.0f && s < best) { best = s; face = 3; }
   }
   return best;
@@ -110,21 +148,21 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   float Aq = a.Af[0] * q[0] + a.Af[1] * q[1] + a.Af[2] * q[2];
   float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
   float x = a.Af[0] + q[0], y = a.Af[1] + q[1], z = a.Af[2] + q[2];
-  float R = sqrtf(x * x + y * y);
-  float r = sqrtf(R * R + z * z);
-  float ri = sqrtf((float)L.r2[i]), ro = sqrtf((float)L.r2[i + 1]);
-  float dmin = fminf((a.K_in + 2.0f * Aq + qq) / (r + ri), -(a.K_out + 2.0f * Aq + qq) / (r + ro));
+  float R = fsqrt(x * x + y * y);
+  float r = fsqrt(R * R + z * z);
+  float ri = fsqrt((float)L.r2[i]), ro = fsqrt((float)L.r2[i + 1]);
+  float dmin = fminf(fdiv(a.K_in + 2.0f * Aq + qq, r + ri), -fdiv(a.K_out + 2.0f * Aq + qq, r + ro));
   float az = fabsf(z);
   float zq = a.Af[2] * q[2], qz2 = q[2] * q[2];
   if (j >= 1) {
     float m2 = (float)L.mu2[j];
     float f = a.L_lo + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    dmin = fminf(dmin, f / (L.smu32[j] * az + L.mu32[j] * R));
+    dmin = fminf(dmin, fdiv(f, L.smu32[j] * az + L.mu32[j] * R));
   }
   if (j + 1 < n_mu) {
     float m2 = (float)L.mu2[j + 1];
     float f = a.L_hi + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    dmin = fminf(dmin, -f / (L.smu32[j + 1] * az + L.mu32[j + 1] * R));
+    dmin = fminf(dmin, -fdiv(f, L.smu32[j + 1] * az + L.mu32[j + 1] * R));
   }
   return dmin > 0.0f ? dmin : 0.0f;
 }
@@ -135,7 +173,7 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
 __device__ __forceinline__ float iso_mu(float u) { return 2.0f * u - 1.0f; }
 __device__ __forceinline__ float iso_st(float u) {
   const float w = iso_mu(u);
-  return sqrtf(fmaxf(0.0f, 1.0f - w * w));
+  return fsqrt(fmaxf(0.0f, 1.0f - w * w));
 }
 __device__ __forceinline__ void iso_phi(float u, float& sn, float& cs) {
   __sincosf(2.0f * (float)KPI * u, &sn, &cs);
@@ -463,7 +501,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       P.mrw_T = -2.0;
       P.n_int = 0;
     } else {
-      float sint = P.tau / alpha;
+      float sint = fdiv(P.tau, alpha);
       P.q[0] += sint * P.d[0]; P.q[1] += sint * P.d[1]; P.q[2] += sint * P.d[2];
       P.d_safe -= sint;
       P.dm_up += 1.00001f * sint;
