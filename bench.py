@@ -53,6 +53,8 @@ PCG_BYTES_PER_UNKNOWN = {0: 104, 1: 160}
 # counters is reported only while they are unchanged.
 TRACE32_SOURCES = ("trace_fp32.hip", "trace_common.h", "rng.h", "mcrt_internal.h")
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "trace_fp32_counters.json")
+# the two kernels of one FP32 trace call, whose counters the summary adds up
+TRACE32_KERNELS = "trace_fp32_kernel + trace_fp32_tail_kernel"
 
 
 def trace32_source_hash():
@@ -399,7 +401,7 @@ def main():
                    "precision": a.precision, "packets_per_step": N},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": (measured_traffic("trace_fp32_kernel", N)
+                     "traffic": (measured_traffic(TRACE32_KERNELS, N)
                                  if a.precision == "fp32" else None),
                      "kernel": "trace_%s_kernel + trace_%s_tail_kernel (one mcrt_trace call)"
                                % (a.precision, a.precision),

@@ -108,7 +108,7 @@ typedef struct {
   int64_t wave_events;   /* once every packet of a launch is handed out, packets that have
                             had at least this many events move to a second launch that
                             runs each with all 64 lanes of a wavefront (same draws, same
-                            events); 0 = never (2048).  Single-disk traces only. */
+                            events); 0 = never (2048).  Batched runs use each disk's value. */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
