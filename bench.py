@@ -194,6 +194,7 @@ def ensemble(mcrt, disk, o, n_packets, K, torch):
     seeds = [o.seed + 5000 + q for q in range(K)]
     mcrt.batch_run(ctxs, [n_packets] * K, seeds, n_iter=1, use_graph=True)   # warm-up
     torch.cuda.synchronize()
+    log("batched: warm-up pass done")
     t0 = time.perf_counter()
     st = mcrt.batch_run(ctxs, [n_packets] * K, seeds, n_iter=1, use_graph=True)
     torch.cuda.synchronize()
