@@ -106,6 +106,12 @@ def parse():
     p.add_argument("--large", type=int, default=0,
                    help="only run the large disk (400 x 200 cells, 200 bins, 3 species) with this "
                         "many packets, FP32 and FP64, and exit")
+    p.add_argument("--c3", type=float, default=0.0,
+                   help="only run the 64-disk batched workload at this fraction of its drawn "
+                        "packets, --c3-passes passes in one graph, and exit")
+    p.add_argument("--c3-passes", type=int, default=5)
+    p.add_argument("--c3-plain", action="store_true",
+                   help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--tail-probe", action="store_true",
                    help="only time the longest packet of a frozen-temperature sample of the step, "
                         "alone, per lane and in whole-wavefront mode, and exit")
@@ -184,6 +190,50 @@ def batched(mcrt, W, scale, torch):
             "graph": True, "cells": int(sum(c.n_cells for c in ctxs)),
             "pda_region_cells": int(sum(s["n_region"] for s in st)),
             "pda_cg_iters_max": int(max(s["cg_iters_total"] for s in st))}
+
+
+def c3(mcrt, W, torch, scale, iters, plain):
+    """The 64-disk batched workload at `scale` of its drawn packets: `iters`
+    passes (trace, T, PDA) in one graph-captured submission, the MRW
+    coefficients of pass k > 0 taken from the temperature after pass k-1;
+    then, with `plain`, one pass of each disk alone on the FP64 path
+    (no graph), the same packet counts."""
+    draws = W.batch_draws()
+    npk = [max(1000, int(round(b["n_packets"] * scale))) for b in draws]
+    seeds = [b["seed"] for b in draws]
+    ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
+                         pda_visits=100, mrw_coef_T=1) for b in draws]
+    torch.cuda.synchronize()
+    log("c3: %d disks, %d packets per pass, %d passes in one graph" %
+        (len(ctxs), sum(npk), iters))
+    t0 = time.perf_counter()
+    st = mcrt.batch_run(ctxs, npk, seeds, n_iter=iters, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("c3: batched done (%.1f s)" % dt)
+    out = {"workload": "64 disks, log10 M ~ U(-5,-1), 50x40 to 200x120 cells, 100 bins, "
+                       "MRW gamma=3, PDA < 100 visits",
+           "packet_scale": scale, "packets_per_pass": sum(npk), "passes": iters,
+           "batched_fp32": {"value": iters * sum(npk) / dt, "unit": "photon packets/s",
+                            "s": dt, "graph": True, "mrw_coef_T": "previous pass",
+                            "pda_region_cells_last_pass": int(sum(x["n_region"] for x in st)),
+                            "pda_cg_iters_max": int(max(x["cg_iters_total"] for x in st))}}
+    del ctxs
+    if plain:
+        tp = 0.0
+        for q, (b, n, sd) in enumerate(zip(draws, npk, seeds)):
+            ctx = mcrt.Context(W.batch_disk(b), precision="fp64", mrw=True, gamma=3.0,
+                               n_int_min=20, pda_visits=100)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            run_once(ctx, n, sd)
+            torch.cuda.synchronize()
+            tp += time.perf_counter() - t1
+            del ctx
+            log("c3: plain FP64, %d disks done (%.1f s)" % (q + 1, tp))
+        out["plain_fp64_one_at_a_time"] = {"value": sum(npk) / tp, "unit": "photon packets/s",
+                                           "s": tp, "passes": 1, "graph": False}
+    return out
 
 
 def ensemble(mcrt, disk, o, n_packets, K, torch):
@@ -342,6 +392,9 @@ def main():
         return
     if a.large > 0:
         print(json.dumps({"large": large(mcrt, W, torch, a.large)}), flush=True)
+        return
+    if a.c3 > 0:
+        print(json.dumps({"c3": c3(mcrt, W, torch, a.c3, a.c3_passes, a.c3_plain)}), flush=True)
         return
 
     disk, o = W.config("mrw_pda")

@@ -96,8 +96,10 @@ typedef struct {
   double pda_tol;        /* Picard stop: max |dT/T| (1e-8) */
   int32_t cg_max_iter;   /* per solve (20000) */
   double cg_tol;         /* preconditioned relative residual (1e-12) */
-  int32_t mrw_coef_T;    /* 0: MRW uses the running cell T; 1: the T of the
-                            previous pass (set by mcrt_update_T) (0) */
+  int32_t mrw_coef_T;    /* 0: MRW uses the running cell T; 1: the T the
+                            context holds when a trace starts, once mcrt_update_T
+                            or mcrt_set_T has run (the previous pass's, PDA
+                            included) (0) */
   int32_t block_size;    /* trace workgroup size, 0 = library choice */
   int32_t blocks_per_cu; /* trace workgroups per compute unit, 0 = library choice */
   int32_t pda_solver;    /* 0 auto, 1 grid-wide CG kernels, 2 one workgroup per disk (0) */
@@ -227,7 +229,8 @@ int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
  * ALL disks in one persistent launch (workgroups shared out by packet
  * count), invert the temperatures, and solve each disk's PDA on its
  * low-visit cells with one workgroup per disk.  Contexts whose mrw_coef_T is
- * 1 take the MRW coefficients of pass k from the temperature after pass k-1.
+ * 1 take the MRW coefficients of pass k from the temperature after pass k-1
+ * (for the first pass: the T the context holds, if it holds one).
  * use_graph != 0 captures all passes in one HIP graph and submits it once.
  * Every context must use MCRT_FP32 and live on the current device.  stats
  * (host, nullable) receives each disk's PDA statistics of the last pass.

@@ -76,7 +76,7 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
                                                 nullptr, 0);
       // passes after the first may take the MRW coefficients from the
       // previous pass's (PDA-corrected) temperature
-      a.T_coef = (c->opt.mrw_coef_T == 1 && it > 0) ? c->d_T_prev : nullptr;
+      a.T_coef = (c->opt.mrw_coef_T == 1 && (it > 0 || c->have_T_prev)) ? c->d_T_prev : nullptr;
       a.vis_lds = mcrt::trace_fp32_lds(c->m, cdf_lds) + (size_t)4 * c->n_cells <= lds;
       ta[(size_t)it * n_disks + d] = a;
     }
@@ -120,7 +120,7 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
           r = mcrt::launch_zero(a.tail_count, 4, s);
           if (r) return r;
         }
-        if (it > 0 && c->opt.mrw_coef_T == 1) {
+        if (a.T_coef) {
           r = mcrt::launch_copy(c->d_T_prev, c->d_T, (size_t)c->n_cells, s);
           if (r) return r;
         }

@@ -506,15 +506,18 @@ int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t see
   int rc = mcrt::launch_zero(ctx->d_next, 8, stream);
   if (!rc && a.tail_count) rc = mcrt::launch_zero(a.tail_count, 4, stream);
   if (rc) return fail(ctx, rc, "clearing the work counters failed");
+  // the MRW coefficients take the temperature the context holds now (the
+  // last pass's, PDA included, or one set by the caller), kept apart from
+  // the T that a later update overwrites
+  if (a.T_coef) {
+    rc = mcrt::launch_copy(ctx->d_T_prev, ctx->d_T, (size_t)ctx->n_cells, stream);
+    if (rc) return fail(ctx, rc, "copying the MRW temperature failed");
+  }
   return mcrt::launch_trace(ctx, a, stream);
 }
 
 int mcrt_update_T(mcrt_ctx* ctx, double* T_dev, hipStream_t stream) {
   if (!ctx) return fail(nullptr, MCRT_E_ARG, "null context");
-  if (ctx->opt.mrw_coef_T == 1) {
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_T_prev, ctx->d_T, ctx->n_cells * sizeof(double),
-                               hipMemcpyDeviceToDevice, stream));
-  }
   int rc = mcrt::launch_update_T(ctx, stream);
   if (rc) return rc;
   if (ctx->opt.mrw_coef_T == 1) ctx->have_T_prev = true;
@@ -619,6 +622,7 @@ int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream) {
   if (!ctx || !T_dev) return fail(ctx, MCRT_E_ARG, "null argument");
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_T, T_dev, ctx->n_cells * sizeof(double),
                              hipMemcpyDeviceToDevice, stream));
+  if (ctx->opt.mrw_coef_T == 1) ctx->have_T_prev = true;
   return MCRT_OK;
 }
 

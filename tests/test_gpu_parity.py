@@ -329,3 +329,54 @@ def test_wave_mode_same_events(mcrt, torch_cuda, mrw, precision):
     rpos = np.stack([ref["x"], ref["y"], ref["z"]], 1)
     err = np.linalg.norm(pos - rpos, axis=1) / np.linalg.norm(rpos, axis=1)
     assert np.mean(err[same] < 1e-5) >= 0.99
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_mrw_coefficients_from_current_T(mcrt, torch_cuda, precision):
+    """mrw_coef_T = 1: a trace takes the MRW coefficients from the temperature
+    the context holds when it starts (after mcrt_update_T, or as set by
+    mcrt_set_T).  Packets traced one per launch are deterministic, so the
+    same field gives the same events and another field other events."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=1e-1, n_r=14, n_mu=10, n_lambda=24)
+    kw = dict(precision=precision, mrw=True, gamma=2.0, n_int_min=5, mrw_coef_T=1,
+              wave_events=0)
+    n = 40
+
+    def sequence(ctx):
+        ctx.reset()
+        out = []
+        for p in range(n):
+            r = ctx.trace(1, 77, n_total=n, offset=p, n_recs=1)
+            out.append(mcrt.Context.records_numpy(r)[0])
+        torch.cuda.synchronize()
+        return np.array(out, dtype=out[0].dtype)
+
+    def same(a, b):
+        return all(np.array_equal(a[f], b[f]) for f in ("fate", "k", "n_cross", "n_scat",
+                                                          "n_abs", "n_mrw", "n_draws"))
+
+    # a pass, then its temperature
+    a = mcrt.Context(d, **kw)
+    a.reset()
+    a.trace(20000, 5)
+    a.update_T()
+    T1 = a.get(mcrt.GET_T).clone()
+    got_a = sequence(a)
+    # the same field set by hand on a fresh context
+    b = mcrt.Context(d, **kw)
+    b.set_T(T1)
+    got_b = sequence(b)
+    assert same(got_a, got_b)
+    assert got_a["n_mrw"].sum() > 0
+    # after a pass, a field set by hand replaces the pass's
+    c = mcrt.Context(d, **kw)
+    c.reset()
+    c.trace(20000, 5)
+    c.update_T()
+    c.set_T(3.0 * T1)
+    got_c = sequence(c)
+    e = mcrt.Context(d, **kw)
+    e.set_T(3.0 * T1)
+    assert same(got_c, sequence(e))
+    assert not same(got_a, got_c)
