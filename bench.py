@@ -106,6 +106,9 @@ def parse():
     p.add_argument("--large", type=int, default=0,
                    help="only run the large disk (400 x 200 cells, 200 bins, 3 species) with this "
                         "many packets, FP32 and FP64, and exit")
+    p.add_argument("--autotune", action="store_true",
+                   help="time the tuner's candidates on the step's disk first (2e5-packet "
+                        "passes) and run the step with its choice")
     p.add_argument("--c3", type=float, default=0.0,
                    help="only run the 64-disk batched workload at this fraction of its drawn "
                         "packets, --c3-passes passes in one graph, and exit")
@@ -399,8 +402,16 @@ def main():
 
     disk, o = W.config("mrw_pda")
     N = a.packets
+    tuned = None
+    if a.autotune:
+        from paper_0902_3092_amd import autotune
+        log("autotune: timing candidates")
+        tuned = autotune.tune(disk, n_packets=200000, precision=a.precision, mrw=True,
+                              gamma=o.gamma, n_int_min=o.n_int_min, pda_visits=o.pda_visits,
+                              n_T=o.n_T, log=log)
     ctx = mcrt.Context(disk, precision=a.precision, mrw=True, gamma=o.gamma,
-                       n_int_min=o.n_int_min, pda_visits=o.pda_visits, n_T=o.n_T)
+                       n_int_min=o.n_int_min, pda_visits=o.pda_visits, n_T=o.n_T,
+                       **(tuned["options"] if tuned else {}))
     stream = torch.cuda.current_stream()
 
     def step(i, ev=None):
@@ -462,8 +473,11 @@ def main():
                      "kernel_ms": float(np.mean(trace_ms)),
                      "flops_per_launch": flops},
         "events_per_step": c,
+        "options": (tuned["options"] if tuned else "library defaults"),
         "pda": {k: pda[k] for k in ("sweeps", "cg_iters_total", "n_region")},
     }
+    if tuned:
+        out["autotune"] = {k: tuned[k] for k in ("trace_s", "pda_s", "pda_iters", "n_packets")}
     T64 = None
     if not a.no_plain and a.precision != "fp64":
         log("plain FP64 step")

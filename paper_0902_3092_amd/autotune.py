@@ -1,0 +1,174 @@
+"""Pick launch and solver options for a disk by timing them on the GPU, and
+cache the choice per problem shape.
+
+Knobs (all are `mcrt_options` fields, so a tuned context is an ordinary one):
+  * PDA: `pda_solver` (1 grid-wide CG kernels, 2 one workgroup) and, for the
+    one-workgroup solver, `pda_precond` (0 point Jacobi, 1 theta-line blocks).
+    Timed on the region and Monte Carlo temperature of a real pass, restored
+    before every solve, so every candidate solves the same system.
+  * Trace: `wave_events`, the event count after which a packet still going
+    once all packets are handed out moves to the whole-wavefront launch.
+    Timed as whole passes on the same seeds, so the candidates trace the same
+    packets.
+
+Nothing here runs implicitly: `options_for` only reads the cache, and
+`tune` is called by the user (or `bench.py --autotune`).
+"""
+import json
+import math
+import os
+import time
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+CACHE_ENV = "MCRT_AUTOTUNE_CACHE"
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_0902_3092_amd",
+                             "autotune.json")
+# physics options that must be equal between the tuned and the timed contexts
+PHYSICS = ("precision", "mrw", "gamma", "n_int_min", "n_T", "pda_visits")
+
+
+def cache_path(path: Optional[str] = None) -> str:
+    return path or os.environ.get(CACHE_ENV) or DEFAULT_CACHE
+
+
+def shape_key(disk, n_packets: int, **phys) -> str:
+    """Cache key: grid and bin counts, physics options, the density scale and
+    the packet count, both to the nearest decade."""
+    rho = np.asarray(disk.rho, dtype=np.float64)
+    top = float(rho.max()) if rho.size else 0.0
+    dec = "none" if top <= 0.0 else "%d" % round(math.log10(top))
+    n_r, n_mu = len(disk.r_edges) - 1, len(disk.mu_edges) - 1
+    n_l = len(disk.lambda_edges) - 1
+    ph = ",".join("%s=%s" % (k, phys[k]) for k in PHYSICS if k in phys)
+    return "%dx%dx%d|rho1e%s|pk1e%d|%s" % (n_r, n_mu, n_l, dec,
+                                           round(math.log10(max(n_packets, 1))), ph)
+
+
+def load(path: Optional[str] = None) -> Dict[str, dict]:
+    p = cache_path(path)
+    try:
+        with open(p) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    return data if isinstance(data, dict) else {}
+
+
+def store(key: str, entry: dict, path: Optional[str] = None) -> None:
+    p = cache_path(path)
+    data = load(p)
+    data[key] = entry
+    os.makedirs(os.path.dirname(p) or ".", exist_ok=True)
+    tmp = p + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def options_for(disk, n_packets: int, path: Optional[str] = None, **phys) -> dict:
+    """The cached options for this shape, or {} (library defaults)."""
+    e = load(path).get(shape_key(disk, n_packets, **phys))
+    return dict(e["options"]) if e else {}
+
+
+def pick(timings: Dict[str, float], ok: Dict[str, bool], default: str,
+         margin: float = 0.03) -> str:
+    """The fastest candidate that succeeded; the default unless another one is
+    faster by more than `margin` (timing noise must not flip the choice)."""
+    good = {k: t for k, t in timings.items() if ok.get(k, False) and math.isfinite(t)}
+    if not good:
+        return default
+    best = min(good, key=good.get)
+    if default in good and good[best] >= (1.0 - margin) * good[default]:
+        return default
+    return best
+
+
+def _label(opts: dict) -> str:
+    return ",".join("%s=%s" % kv for kv in sorted(opts.items()))
+
+
+def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
+         wave_events: Sequence[int] = (512, 2048, 8192), pda_repeats: int = 3,
+         path: Optional[str] = None, save: bool = True, log=None, **phys) -> dict:
+    """Time the candidates on this disk and return (and cache) the choice:
+    {"key", "options", "trace_s", "pda_s", "pda_iters"}."""
+    import torch
+    from . import mcrt as M
+
+    say = log or (lambda s: None)
+    phys = dict(phys)
+    phys.setdefault("precision", "fp32")
+    phys.setdefault("mrw", True)
+    key = shape_key(disk, n_packets, **phys)
+
+    # trace: whole passes on the same seeds
+    trace_s, trace_ok = {}, {}
+    for we in wave_events:
+        ctx = M.Context(disk, wave_events=int(we), **phys)
+        t = 0.0
+        for s in seeds:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.reset()
+            ctx.trace(n_packets, int(s))
+            ctx.update_T()
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+        c = ctx.counters()
+        trace_s[str(we)] = t
+        trace_ok[str(we)] = c["capped"] == 0 and c["launch"] == n_packets
+        say("autotune: wave_events=%d: %.3f s" % (we, t))
+        del ctx
+    we_best = int(pick(trace_s, trace_ok, str(2048 if 2048 in wave_events else wave_events[0])))
+
+    # PDA: the region and MC temperature of one pass, the same system for all
+    base = M.Context(disk, wave_events=we_best, **phys)
+    base.reset()
+    base.trace(n_packets, int(seeds[0]))
+    base.update_T()
+    T_mc = base.get(M.GET_T).clone()
+    base.pda_solve()
+    mask = (base.get(M.GET_REGION) == 1).to(torch.uint8).contiguous()
+    n_cells = base.n_cells
+    del base
+    cands = [dict(pda_solver=1, pda_precond=0)]
+    if n_cells <= 65536:
+        cands += [dict(pda_solver=2, pda_precond=0), dict(pda_solver=2, pda_precond=1)]
+    pda_s, pda_ok, pda_it = {}, {}, {}
+    for cand in cands:
+        ctx = M.Context(disk, wave_events=we_best, **phys, **cand)
+        best = float("inf")
+        st = None
+        for _ in range(pda_repeats):
+            ctx.set_T(T_mc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                st = ctx.pda_solve(mask)
+            except M.McrtError:  # not converged: this candidate fails
+                st = None
+                break
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        lab = _label(cand)
+        pda_s[lab] = best
+        pda_ok[lab] = st is not None and st["rc"] == M.OK and \
+            (st["n_region"] == 0 or st["last_change"] < 1e-6)
+        pda_it[lab] = int(st["cg_iters_total"]) if st is not None else -1
+        say("autotune: %s: %.4f s, %d CG iterations" % (lab, best, pda_it[lab]))
+        del ctx
+    default_pda = _label(dict(pda_solver=2, pda_precond=1)) if n_cells <= 65536 else \
+        _label(cands[0])
+    pda_best = pick(pda_s, pda_ok, default_pda)
+    opts = {"wave_events": we_best}
+    opts.update({k: int(v) for k, v in (kv.split("=") for kv in pda_best.split(","))})
+    entry = {"key": key, "options": opts, "trace_s": trace_s, "pda_s": pda_s,
+             "pda_iters": pda_it, "n_packets": n_packets, "seeds": list(seeds),
+             "device": torch.cuda.get_device_name(0),
+             "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    if save:
+        store(key, entry, path)
+    return entry

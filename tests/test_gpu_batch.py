@@ -83,3 +83,4 @@ def test_batch_rejects_fp64_contexts(torch_cuda):
     ctx = mcrt.Context(d, precision="fp64")
     with pytest.raises(mcrt.McrtError):
         mcrt.batch_run([ctx], [1000], [1], n_iter=1)
+
