@@ -61,6 +61,17 @@ __device__ __forceinline__ double T_of_g(const TabView& t, double g) {
   return t.Tn[n] + (g - t.G[n]) * t.g_slope[n];
 }
 
+// T_of_g that also returns the segment n the temperature lies in (up to
+// rounding at the nodes), so a reemission can skip locating it again.
+__device__ __forceinline__ double T_of_g_seg(const TabView& t, double g, int& n) {
+  if (g <= 0.0) {
+    n = 0;
+    return 0.0;
+  }
+  n = g_segment(t, g);
+  return t.Tn[n] + (g - t.G[n]) * t.g_slope[n];
+}
+
 __device__ __forceinline__ double interp_T(const TabView& t, const double* tab, double T) {
   int n = t_segment(t, T);
   double f = (T - t.Tn[n]) * t.inv_dT[n];
@@ -87,18 +98,20 @@ struct Reemit {
   }
 };
 
+// With nn_in / no_in >= 0 the segments of T_new / T_old are taken as given
+// (from the inversion that produced them) instead of located again.
 template <typename C>
 __device__ __forceinline__ Reemit<C> reemit_setup(const TabView& t, const C* cdf, double T_old,
-                                                  double T_new) {
+                                                  double T_new, int nn_in = -1, int no_in = -1) {
   Reemit<C> R;
   const int nl = t.nl;
-  int nn = t_segment(t, T_new);
+  int nn = nn_in >= 0 ? nn_in : t_segment(t, T_new);
   R.fn = (C)((T_new - t.Tn[nn]) * t.inv_dT[nn]);
   R.diff = (T_old >= 0.0) && (T_new > T_old);
   int no = 0;
   R.fo = (C)0;
   if (R.diff) {
-    no = t_segment(t, T_old);
+    no = no_in >= 0 ? no_in : t_segment(t, T_old);
     R.fo = (C)((T_old - t.Tn[no]) * t.inv_dT[no]);
   }
   R.an = cdf + (size_t)nn * nl;

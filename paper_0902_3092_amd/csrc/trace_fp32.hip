@@ -167,6 +167,121 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   return dmin > 0.0f ? dmin : 0.0f;
 }
 
+// ------------------------------------------- faces on four lanes
+// Whole-wave mode: every lane holds the same packet, so lane l works on face
+// l & 3 (0 inner sphere, 1 outer sphere, 2 lower cone, 3 upper cone) with the
+// arithmetic of the sequential functions above, case by case, and a quad
+// reduction over DPP picks the face the sequential scan picks (ties go to
+// faces 1, 0, 2, 3 in that order).
+__device__ __forceinline__ float dpp_f(float v, int ctrl_is_xor2) {
+  const int x = __float_as_int(v);
+  const int y = ctrl_is_xor2 ? __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true)   // quad [2,3,0,1]
+                             : __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // quad [1,0,3,2]
+  return __int_as_float(y);
+}
+__device__ __forceinline__ int dpp_i(int x, int ctrl_is_xor2) {
+  return ctrl_is_xor2 ? __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true)
+                      : __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ float boundary32_wave(const Anchor& a, const Lds32& L, int n_mu, int i,
+                                                 int j, const float q[3], const float d[3],
+                                                 int& face) {
+  const int f = __lane_id() & 3;
+  float Ad = a.Af[0] * d[0] + a.Af[1] * d[1] + a.Af[2] * d[2];
+  float qd = q[0] * d[0] + q[1] * d[1] + q[2] * d[2];
+  float Aq = a.Af[0] * q[0] + a.Af[1] * q[1] + a.Af[2] * q[2];
+  float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  float pd = Ad + qd;
+  float v;  // this lane's face distance, +inf where the face is not reached
+  if (f < 2) {
+    const bool outer = f == 1;
+    const float c = (outer ? a.K_out : a.K_in) + 2.0f * Aq + qq;
+    float disc = pd * pd - c;
+    const bool neg = disc < 0.0f;
+    const float sq = fsqrt(neg ? 0.0f : disc);
+    if (outer) {
+      if (c >= 0.0f && (pd > 0.0f || neg)) v = 0.0f;
+      else v = pd > 0.0f ? -fdiv(c, pd + sq) : -pd + sq;
+    } else {
+      if (c <= 0.0f && pd < 0.0f) v = 0.0f;
+      else if (pd >= 0.0f || neg) v = INFINITY;
+      else v = fdiv(c, -pd + sq);
+    }
+  } else {
+    const bool toward = f == 3;
+    const int e = toward ? j + 1 : j;
+    const bool has = toward ? j + 1 < n_mu : j >= 1;
+    float z = a.Af[2] + q[2];
+    float dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    float zq = a.Af[2] * q[2];
+    float qz2 = q[2] * q[2];
+    const float m2 = (float)L.mu2[has ? e : 0];
+    const float C = (toward ? a.L_hi : a.L_lo) + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
+    const float Aa = d[2] * d[2] - m2 * dd;
+    const float B = z * d[2] - m2 * pd;
+    if (!has) {
+      v = INFINITY;
+    } else if (toward ? (C >= 0.0f && B > 0.0f) : (C <= 0.0f && B < 0.0f)) {
+      v = 0.0f;
+    } else {
+      const float disc = B * B - Aa * C;
+      if (disc < 0.0f) {
+        v = INFINITY;
+      } else {
+        const float sq = fsqrt(disc);
+        const bool first = toward ? B > 0.0f : B < 0.0f;
+        const float num = first ? C : (toward ? -B + sq : -B - sq);
+        const float den = first ? (toward ? -B - sq : -B + sq) : Aa;
+        const float w = fdiv(num, den);
+        v = (!(w > 0.0f) || __builtin_isinf(w)) ? INFINITY : w;
+      }
+    }
+  }
+  // lexicographic minimum of (distance, rank) over the quad, rank 0..3 for
+  // faces 1, 0, 2, 3
+  int rank = f == 1 ? 0 : (f == 0 ? 1 : f);
+#pragma unroll
+  for (int x2 = 0; x2 < 2; ++x2) {
+    const float vo = dpp_f(v, x2);
+    const int ro = dpp_i(rank, x2);
+    const bool take = vo < v || (vo == v && ro < rank);
+    v = take ? vo : v;
+    rank = take ? ro : rank;
+  }
+  face = rank == 0 ? 1 : (rank == 1 ? 0 : rank);
+  return v;
+}
+
+__device__ __forceinline__ float min_boundary32_wave(const Anchor& a, const Lds32& L, int n_mu,
+                                                     int i, int j, const float q[3]) {
+  const int f = __lane_id() & 3;
+  float Aq = a.Af[0] * q[0] + a.Af[1] * q[1] + a.Af[2] * q[2];
+  float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  float x = a.Af[0] + q[0], y = a.Af[1] + q[1], z = a.Af[2] + q[2];
+  float R = fsqrt(x * x + y * y);
+  float v;
+  if (f < 2) {
+    float r = fsqrt(R * R + z * z);
+    const float re = fsqrt((float)L.r2[f == 0 ? i : i + 1]);
+    const float t = fdiv((f == 0 ? a.K_in : a.K_out) + 2.0f * Aq + qq, r + re);
+    v = f == 0 ? t : -t;
+  } else {
+    const bool hi = f == 3;
+    const bool has = hi ? j + 1 < n_mu : j >= 1;
+    const int e = has ? (hi ? j + 1 : j) : 0;
+    float az = fabsf(z);
+    float zq = a.Af[2] * q[2], qz2 = q[2] * q[2];
+    const float m2 = (float)L.mu2[e];
+    const float fn = (hi ? a.L_hi : a.L_lo) + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
+    const float t = fdiv(fn, L.smu32[e] * az + L.mu32[e] * R);
+    v = has ? (hi ? -t : t) : INFINITY;
+  }
+#pragma unroll
+  for (int x2 = 0; x2 < 2; ++x2) v = fminf(v, dpp_f(v, x2));
+  return v > 0.0f ? v : 0.0f;
+}
+
 // Functions of one draw u used by the transport; the whole-wave generator
 // evaluates them once per word, lane-parallel, so every caller gets the same
 // values from either generator.
@@ -262,7 +377,8 @@ struct Pk {
   double im;                         // 1 / (4 pi m) of the cell
   double Tc;                         // running temperature of the cell (< 0: from its tally)
   double Tfix;                       // the cell's fixed temperature (frozen or MRW field)
-  double mrw_T, mrw_Drho, mrw_kbar;  // MRW coefficients at mrw_T
+  double mrw_T, mrw_Drho, mrw_f;  // MRW coefficients at mrw_T: D rho, and the
+  int mrw_seg;                     // table segment and fraction of mrw_T
   float mrw_lim;
   float d_safe;   // lower bound of the distance to every face of the cell
   float dm_up;    // upper bound of it: the last computed one plus the path flown since
@@ -272,6 +388,8 @@ struct Pk {
   // deposit and its temperature (reused when nobody deposited in between)
   uint32_t cell_abs, cell_mrw;
   double E_seen, T_seen;
+  int seg_seen;   // table segment of T_seen
+  float lim_scale;  // 3 gamma / rho of the cell: the MRW limit is D rho times this
 };
 
 // A packet handed over to the whole-wavefront launch.
@@ -410,6 +528,29 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
     if (WAVE) return reemit_search_wave<float>(R, nl, xb);
     return reemit_search<float>(R, nl, xb);
   };
+  // Bin of the reemission after a deposit dE on top of the cell's tally
+  // E_old (immediate reemission, Sect. 2.1): the difference spectrum between
+  // the temperatures after and before, from the inversion of the tally; the
+  // spectrum interpolation reuses the inversion's table segments.
+  auto reemit_bin = [&](double E_old, double dE, float xb) -> int {
+    if (A.frozen_T) return search(reemit_setup<float>(L.tv, L.cdf, -1.0, P.Tfix), xb);
+    int n_old, n_new;
+    double T_old;
+    if (E_old == P.E_seen) {
+      T_old = P.T_seen;
+      n_old = P.seg_seen;
+    } else {
+      T_old = T_of_g_seg(L.tv, E_old * P.im, n_old);
+    }
+    const double E_new = E_old + dE;
+    const double T_new = T_of_g_seg(L.tv, E_new * P.im, n_new);
+    P.E_seen = E_new;
+    P.T_seen = T_new;
+    P.seg_seen = n_new;
+    P.Tc = T_new;
+    return search(reemit_setup<float>(L.tv, L.cdf, T_old, T_new, n_new, n_old), xb);
+  };
+  auto lim_scale_of = [&](double rho) -> float { return (float)(A.gamma * 3.0 / rho); };
   int fate = 0;
   if (++P.events > A.max_events) {
     fate = 3;
@@ -433,6 +574,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       P.j = mu_row(L.mu2, n_mu, r2, P.an.A[2] * P.an.A[2]);
       set_anchor(P.an, L, n_mu, P.i, P.j);
       P.rho = M.rho[P.j];
+      P.lim_scale = lim_scale_of(P.rho);
       P.im = M.inv4pim[P.j];
       if (fixT) P.Tfix = fixT[P.j];
       visit(P.j);
@@ -452,7 +594,8 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
     // the cell: the face distances are not needed for it
     const bool inside = P.tau < alpha * P.d_safe;
     if (!inside) {
-      sb = boundary32(P.an, L, n_mu, P.i, P.j, P.q, P.d, face);
+      sb = WAVE ? boundary32_wave(P.an, L, n_mu, P.i, P.j, P.q, P.d, face)
+                : boundary32(P.an, L, n_mu, P.i, P.j, P.q, P.d, face);
       tau_b = alpha * sb;
     }
     if (!inside && tau_b <= P.tau) {
@@ -488,6 +631,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       if (entered) {
         int cn = P.i * n_mu + P.j;
         P.rho = M.rho[cn];
+        P.lim_scale = lim_scale_of(P.rho);
         P.im = M.inv4pim[cn];
         if (fixT) P.Tfix = fixT[cn];
         reanchor(P.an, P.q, L, n_mu, P.i, P.j);
@@ -520,19 +664,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
         double E_old = deposit(c, A.eps);
         float xb = rng.next();
         iso32(rng, P.d);
-        double T_old = -1.0, T_new;
-        if (fz) {
-          T_new = P.Tfix;
-        } else {
-          const double E_new = E_old + A.eps;
-          T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
-          T_new = T_of_g(L.tv, E_new * P.im);
-          P.E_seen = E_new;
-          P.T_seen = T_new;
-          P.Tc = T_new;
-        }
-        Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
-        P.k = search(R, xb);
+        P.k = reemit_bin(E_old, A.eps, xb);
       }
       ++P.n_int;
       if (A.mrw) {
@@ -546,49 +678,45 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
             T_here = P.Tc;
           }
           if (T_here != P.mrw_T) {  // MRW coefficients of this cell at this T
+            // (the segment of the cell's running T is known from its inversion)
+            const int n = T_here == P.T_seen ? P.seg_seen : t_segment(L.tv, T_here);
+            const double f = (T_here - L.tv.Tn[n]) * L.tv.inv_dT[n];
             P.mrw_T = T_here;
-            P.mrw_Drho = interp_T(L.tv, L.tv.Drho, T_here);
-            P.mrw_kbar = interp_T(L.tv, L.tv.kbar, T_here);
-            P.mrw_lim = (float)(A.gamma * 3.0 * P.mrw_Drho / P.rho);
+            P.mrw_seg = n;
+            P.mrw_f = f;
+            P.mrw_Drho = L.tv.Drho[n] + f * (L.tv.Drho[n + 1] - L.tv.Drho[n]);
+            P.mrw_lim = (float)P.mrw_Drho * P.lim_scale;
           }
           const double Drho = P.mrw_Drho;
           const float lim = P.mrw_lim;
           if (P.dm_up <= lim) break;
           {
-            float dm = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
+            float dm = WAVE ? min_boundary32_wave(P.an, L, n_mu, P.i, P.j, P.q)
+                            : min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
             P.d_safe = 0.999f * dm;
             P.dm_up = 1.00001f * dm;
             if (!(dm > lim)) break;
           }
           // re-anchor so the sphere radius is exact to FP32 precision of itself
           reanchor(P.an, P.q, L, n_mu, P.i, P.j);
-          float dmin = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
+          float dmin = WAVE ? min_boundary32_wave(P.an, L, n_mu, P.i, P.j, P.q)
+                            : min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
           if (!(dmin > lim)) break;
           if (++P.events > A.max_events) break;
           ensure_draws(rng, 7);  // escape time, jump, bin, direction, optical depth
           double R0 = (double)dmin * (1.0 - 1e-5);
           double s = (double)mrw_escape_s32(L.mrw_tab, rng.next());
           double ell = s * R0 * R0 * P.rho / Drho;
-          double dE = A.eps * P.rho * P.mrw_kbar * ell;
+          const int ns = P.mrw_seg;
+          const double kbar = L.tv.kbar[ns] + P.mrw_f * (L.tv.kbar[ns + 1] - L.tv.kbar[ns]);
+          double dE = A.eps * P.rho * kbar * ell;
           double E_old = deposit(c, dE);
           float nv[3];
           iso32(rng, nv);
           P.q[0] = (float)R0 * nv[0]; P.q[1] = (float)R0 * nv[1]; P.q[2] = (float)R0 * nv[2];
           float xb = rng.next();
           iso32(rng, P.d);
-          double T_old = -1.0, T_new;
-          if (fz) {
-            T_new = P.Tfix;
-          } else {
-            const double E_new = E_old + dE;
-            T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
-            T_new = T_of_g(L.tv, E_new * P.im);
-            P.E_seen = E_new;
-            P.T_seen = T_new;
-            P.Tc = T_new;
-          }
-          Reemit<float> R = reemit_setup<float>(L.tv, L.cdf, T_old, T_new);
-          P.k = search(R, xb);
+          P.k = reemit_bin(E_old, dE, xb);
           P.d_safe = 0.0f;
           P.dm_up = INFINITY;
           ++P.pc_mrw;
@@ -759,9 +887,12 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
           P.events = 0;
           P.pc_cross = P.pc_scat = P.pc_abs = P.pc_mrw = 0;
           P.rho = P.im = P.Tfix = 0.0;
+          P.lim_scale = 0.0f;
+          P.seg_seen = 0;
           P.Tc = -1.0;
           P.mrw_T = -2.0;
-          P.mrw_Drho = P.mrw_kbar = 0.0;
+          P.mrw_Drho = P.mrw_f = 0.0;
+          P.mrw_seg = 0;
           P.mrw_lim = 0.0f;
           P.d_safe = 0.0f;
           P.dm_up = INFINITY;
