@@ -113,6 +113,8 @@ def parse():
                    help="only run the 64-disk batched workload at this fraction of its drawn "
                         "packets, --c3-passes passes in one graph, and exit")
     p.add_argument("--c3-passes", type=int, default=5)
+    p.add_argument("--c3-split", action="store_true",
+                   help="with --c3: submit each pass as a graph of its own")
     p.add_argument("--c3-plain", action="store_true",
                    help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--tail-probe", action="store_true",
@@ -195,7 +197,7 @@ def batched(mcrt, W, scale, torch):
             "pda_cg_iters_max": int(max(s["cg_iters_total"] for s in st))}
 
 
-def c3(mcrt, W, torch, scale, iters, plain):
+def c3(mcrt, W, torch, scale, iters, plain, split=False):
     """The 64-disk batched workload at `scale` of its drawn packets: `iters`
     passes (trace, T, PDA) in one graph-captured submission, the MRW
     coefficients of pass k > 0 taken from the temperature after pass k-1;
@@ -207,10 +209,19 @@ def c3(mcrt, W, torch, scale, iters, plain):
     ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
                          pda_visits=100, mrw_coef_T=1) for b in draws]
     torch.cuda.synchronize()
-    log("c3: %d disks, %d packets per pass, %d passes in one graph" %
-        (len(ctxs), sum(npk), iters))
+    log("c3: %d disks, %d packets per pass, %d passes in %s" %
+        (len(ctxs), sum(npk), iters, "one graph each" if split else "one graph"))
     t0 = time.perf_counter()
-    st = mcrt.batch_run(ctxs, npk, seeds, n_iter=iters, use_graph=True)
+    if split:
+        # one graph per pass (a pass takes the previous pass's T through the
+        # contexts), so that each pass reports when it ends
+        for it in range(iters):
+            st = mcrt.batch_run(ctxs, npk, [sd + (it << 32) for sd in seeds], n_iter=1,
+                                use_graph=True)
+            torch.cuda.synchronize()
+            log("c3: pass %d done (%.1f s)" % (it + 1, time.perf_counter() - t0))
+    else:
+        st = mcrt.batch_run(ctxs, npk, seeds, n_iter=iters, use_graph=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log("c3: batched done (%.1f s)" % dt)
@@ -218,7 +229,8 @@ def c3(mcrt, W, torch, scale, iters, plain):
                        "MRW gamma=3, PDA < 100 visits",
            "packet_scale": scale, "packets_per_pass": sum(npk), "passes": iters,
            "batched_fp32": {"value": iters * sum(npk) / dt, "unit": "photon packets/s",
-                            "s": dt, "graph": True, "mrw_coef_T": "previous pass",
+                            "s": dt, "graph": "one per pass" if split else "all passes",
+                            "mrw_coef_T": "previous pass",
                             "pda_region_cells_last_pass": int(sum(x["n_region"] for x in st)),
                             "pda_cg_iters_max": int(max(x["cg_iters_total"] for x in st))}}
     del ctxs
@@ -397,7 +409,8 @@ def main():
         print(json.dumps({"large": large(mcrt, W, torch, a.large)}), flush=True)
         return
     if a.c3 > 0:
-        print(json.dumps({"c3": c3(mcrt, W, torch, a.c3, a.c3_passes, a.c3_plain)}), flush=True)
+        print(json.dumps({"c3": c3(mcrt, W, torch, a.c3, a.c3_passes, a.c3_plain, a.c3_split)}),
+              flush=True)
         return
 
     disk, o = W.config("mrw_pda")
