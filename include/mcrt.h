@@ -43,7 +43,7 @@ extern "C" {
 #define MCRT_E_OOM (-2)             /* device allocation failed */
 #define MCRT_E_HIP (-3)             /* a HIP runtime call failed */
 #define MCRT_E_NOT_CONVERGED (-4)   /* PDA solver hit its iteration cap */
-#define MCRT_E_STUCK (-5)           /* packets hit the per-packet event cap */
+#define MCRT_E_STUCK (-5)           /* reserved: capped packets are counted, not reported */
 #define MCRT_E_SINGULAR_REGION (-6) /* a PDA region part has no Dirichlet neighbour (solved
                                        without it: informational) */
 
@@ -135,9 +135,11 @@ int mcrt_reset(mcrt_ctx* ctx, hipStream_t stream);
  * the context's.  frozen_T_dev (nullable, [n_cells] K): re-emit from the
  * full spectrum at these fixed temperatures instead (no coupling between
  * packets; a test mode).  rec_dev (nullable): mcrt_packet_rec for packets
- * [offset, offset + n_recs).  Returns MCRT_E_STUCK after the stream has
- * drained if any packet hit max_events (synchronous in that case only when
- * check_stuck != 0). */
+ * [offset, offset + n_recs).  A packet that reaches max_events events ends
+ * there and is counted as capped (MCRT_GET_COUNTERS, fate 3 in its record);
+ * the call does not wait for the stream, so it cannot report that itself.
+ * Errors: MCRT_E_ARG for a null context, n_total = 0 or a packet range
+ * outside [0, n_total); MCRT_E_HIP if a launch fails. */
 typedef struct {
   int32_t fate;                    /* 1 escaped, 2 hit the star, 3 capped */
   int32_t k;                       /* final wavelength bin */
@@ -159,9 +161,12 @@ int mcrt_update_T(mcrt_ctx* ctx, double* T_dev, hipStream_t stream);
  * entries), Dirichlet T from the Monte Carlo temperature of the neighbouring
  * cells, D = 1/(3 rho chi_R) with chi_R the Rosseland mean of the total
  * extinction (the diffusion coefficient of Sect. 2.2.3 with isotropic
- * scattering), Picard iteration on D(T), Jacobi-preconditioned CG.  Updates
- * the context's T.  stats (host, nullable) receives sweeps, CG iterations and
- * residuals; waits for the stream. */
+ * scattering), Picard iteration on D(T), preconditioned CG (pda_precond:
+ * exact theta-line blocks, or the diagonal).  Updates the context's T.
+ * stats (host, nullable) receives sweeps, CG iterations and residuals; waits
+ * for the stream.  MCRT_E_NOT_CONVERGED if CG hits cg_max_iter;
+ * MCRT_E_SINGULAR_REGION (informational) if a part of the region has no
+ * Dirichlet neighbour (left at its Monte Carlo T, flagged 2). */
 typedef struct {
   int32_t sweeps, cg_iters_total, cg_iters_last, n_region, n_isolated;
   double last_change, last_residual;
