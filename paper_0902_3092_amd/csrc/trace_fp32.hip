@@ -167,121 +167,6 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   return dmin > 0.0f ? dmin : 0.0f;
 }
 
-// ------------------------------------------- faces on four lanes
-// Whole-wave mode: every lane holds the same packet, so lane l works on face
-// l & 3 (0 inner sphere, 1 outer sphere, 2 lower cone, 3 upper cone) with the
-// arithmetic of the sequential functions above, case by case, and a quad
-// reduction over DPP picks the face the sequential scan picks (ties go to
-// faces 1, 0, 2, 3 in that order).
-__device__ __forceinline__ float dpp_f(float v, int ctrl_is_xor2) {
-  const int x = __float_as_int(v);
-  const int y = ctrl_is_xor2 ? __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true)   // quad [2,3,0,1]
-                             : __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // quad [1,0,3,2]
-  return __int_as_float(y);
-}
-__device__ __forceinline__ int dpp_i(int x, int ctrl_is_xor2) {
-  return ctrl_is_xor2 ? __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true)
-                      : __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
-}
-
-__device__ __forceinline__ float boundary32_wave(const Anchor& a, const Lds32& L, int n_mu, int i,
-                                                 int j, const float q[3], const float d[3],
-                                                 int& face) {
-  const int f = __lane_id() & 3;
-  float Ad = a.Af[0] * d[0] + a.Af[1] * d[1] + a.Af[2] * d[2];
-  float qd = q[0] * d[0] + q[1] * d[1] + q[2] * d[2];
-  float Aq = a.Af[0] * q[0] + a.Af[1] * q[1] + a.Af[2] * q[2];
-  float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-  float pd = Ad + qd;
-  float v;  // this lane's face distance, +inf where the face is not reached
-  if (f < 2) {
-    const bool outer = f == 1;
-    const float c = (outer ? a.K_out : a.K_in) + 2.0f * Aq + qq;
-    float disc = pd * pd - c;
-    const bool neg = disc < 0.0f;
-    const float sq = fsqrt(neg ? 0.0f : disc);
-    if (outer) {
-      if (c >= 0.0f && (pd > 0.0f || neg)) v = 0.0f;
-      else v = pd > 0.0f ? -fdiv(c, pd + sq) : -pd + sq;
-    } else {
-      if (c <= 0.0f && pd < 0.0f) v = 0.0f;
-      else if (pd >= 0.0f || neg) v = INFINITY;
-      else v = fdiv(c, -pd + sq);
-    }
-  } else {
-    const bool toward = f == 3;
-    const int e = toward ? j + 1 : j;
-    const bool has = toward ? j + 1 < n_mu : j >= 1;
-    float z = a.Af[2] + q[2];
-    float dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    float zq = a.Af[2] * q[2];
-    float qz2 = q[2] * q[2];
-    const float m2 = (float)L.mu2[has ? e : 0];
-    const float C = (toward ? a.L_hi : a.L_lo) + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    const float Aa = d[2] * d[2] - m2 * dd;
-    const float B = z * d[2] - m2 * pd;
-    if (!has) {
-      v = INFINITY;
-    } else if (toward ? (C >= 0.0f && B > 0.0f) : (C <= 0.0f && B < 0.0f)) {
-      v = 0.0f;
-    } else {
-      const float disc = B * B - Aa * C;
-      if (disc < 0.0f) {
-        v = INFINITY;
-      } else {
-        const float sq = fsqrt(disc);
-        const bool first = toward ? B > 0.0f : B < 0.0f;
-        const float num = first ? C : (toward ? -B + sq : -B - sq);
-        const float den = first ? (toward ? -B - sq : -B + sq) : Aa;
-        const float w = fdiv(num, den);
-        v = (!(w > 0.0f) || __builtin_isinf(w)) ? INFINITY : w;
-      }
-    }
-  }
-  // lexicographic minimum of (distance, rank) over the quad, rank 0..3 for
-  // faces 1, 0, 2, 3
-  int rank = f == 1 ? 0 : (f == 0 ? 1 : f);
-#pragma unroll
-  for (int x2 = 0; x2 < 2; ++x2) {
-    const float vo = dpp_f(v, x2);
-    const int ro = dpp_i(rank, x2);
-    const bool take = vo < v || (vo == v && ro < rank);
-    v = take ? vo : v;
-    rank = take ? ro : rank;
-  }
-  face = rank == 0 ? 1 : (rank == 1 ? 0 : rank);
-  return v;
-}
-
-__device__ __forceinline__ float min_boundary32_wave(const Anchor& a, const Lds32& L, int n_mu,
-                                                     int i, int j, const float q[3]) {
-  const int f = __lane_id() & 3;
-  float Aq = a.Af[0] * q[0] + a.Af[1] * q[1] + a.Af[2] * q[2];
-  float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-  float x = a.Af[0] + q[0], y = a.Af[1] + q[1], z = a.Af[2] + q[2];
-  float R = fsqrt(x * x + y * y);
-  float v;
-  if (f < 2) {
-    float r = fsqrt(R * R + z * z);
-    const float re = fsqrt((float)L.r2[f == 0 ? i : i + 1]);
-    const float t = fdiv((f == 0 ? a.K_in : a.K_out) + 2.0f * Aq + qq, r + re);
-    v = f == 0 ? t : -t;
-  } else {
-    const bool hi = f == 3;
-    const bool has = hi ? j + 1 < n_mu : j >= 1;
-    const int e = has ? (hi ? j + 1 : j) : 0;
-    float az = fabsf(z);
-    float zq = a.Af[2] * q[2], qz2 = q[2] * q[2];
-    const float m2 = (float)L.mu2[e];
-    const float fn = (hi ? a.L_hi : a.L_lo) + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    const float t = fdiv(fn, L.smu32[e] * az + L.mu32[e] * R);
-    v = has ? (hi ? -t : t) : INFINITY;
-  }
-#pragma unroll
-  for (int x2 = 0; x2 < 2; ++x2) v = fminf(v, dpp_f(v, x2));
-  return v > 0.0f ? v : 0.0f;
-}
-
 // Functions of one draw u used by the transport; the whole-wave generator
 // evaluates them once per word, lane-parallel, so every caller gets the same
 // values from either generator.
@@ -594,8 +479,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
     // the cell: the face distances are not needed for it
     const bool inside = P.tau < alpha * P.d_safe;
     if (!inside) {
-      sb = WAVE ? boundary32_wave(P.an, L, n_mu, P.i, P.j, P.q, P.d, face)
-                : boundary32(P.an, L, n_mu, P.i, P.j, P.q, P.d, face);
+      sb = boundary32(P.an, L, n_mu, P.i, P.j, P.q, P.d, face);
       tau_b = alpha * sb;
     }
     if (!inside && tau_b <= P.tau) {
@@ -691,16 +575,14 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           const float lim = P.mrw_lim;
           if (P.dm_up <= lim) break;
           {
-            float dm = WAVE ? min_boundary32_wave(P.an, L, n_mu, P.i, P.j, P.q)
-                            : min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
+            float dm = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
             P.d_safe = 0.999f * dm;
             P.dm_up = 1.00001f * dm;
             if (!(dm > lim)) break;
           }
           // re-anchor so the sphere radius is exact to FP32 precision of itself
           reanchor(P.an, P.q, L, n_mu, P.i, P.j);
-          float dmin = WAVE ? min_boundary32_wave(P.an, L, n_mu, P.i, P.j, P.q)
-                            : min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
+          float dmin = min_boundary32(P.an, L, n_mu, P.i, P.j, P.q);
           if (!(dmin > lim)) break;
           if (++P.events > A.max_events) break;
           ensure_draws(rng, 7);  // escape time, jump, bin, direction, optical depth

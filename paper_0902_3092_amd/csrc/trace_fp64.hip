@@ -47,9 +47,11 @@ __host__ __device__ inline size_t lds_small_bytes(int n_r, int n_mu, int n_T, in
          sizeof(int) * N_GUIDE;
 }
 
-__device__ __forceinline__ int reemit64(const Lds64& L, double T_old, double T_new, double xi) {
+// nn / no >= 0: the segments of T_new / T_old, known from their inversion
+__device__ __forceinline__ int reemit64(const Lds64& L, double T_old, double T_new, double xi,
+                                        int nn = -1, int no = -1) {
   const int nl = L.tv.nl;
-  Reemit<double> R = reemit_setup<double>(L.tv, L.cdf64, T_old, T_new);
+  Reemit<double> R = reemit_setup<double>(L.tv, L.cdf64, T_old, T_new, nn, no);
   if (L.cdf32 == nullptr) return reemit_search<double>(R, nl, xi);
   // locate with the FP32 copy, then confirm with the FP64 values
   Reemit<float> Rf;
@@ -140,7 +142,8 @@ struct Pk64 {
   double im;                         // 1 / (4 pi m) of the cell
   double Tc;                         // running temperature of the cell (< 0: not known)
   double Tfix;                       // the cell's fixed temperature (frozen or MRW field)
-  double mrw_T, mrw_Drho, mrw_kbar, mrw_lim;  // MRW coefficients at mrw_T
+  double mrw_T, mrw_Drho, mrw_f, mrw_lim;  // MRW coefficients at mrw_T (mrw_f: its
+  int mrw_seg, seg_seen;                    // fraction in segment mrw_seg); segment of T_seen
   // bounds of the distance to the cell boundary: d_safe below (a flight
   // shorter than it stays in the cell, so the face distances are not needed),
   // dm_up above (the last computed distance plus the path flown since: while
@@ -248,9 +251,10 @@ __device__ __forceinline__ double tau64(WaveRng64& r) { return r.next_tau(); }
 __device__ __forceinline__ void ensure_draws(WaveRng64& r, int n) { r.ensure(n); }
 
 // smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane
-__device__ __forceinline__ int reemit64_wave(const Lds64& L, double T_old, double T_new, double xi) {
+__device__ __forceinline__ int reemit64_wave(const Lds64& L, double T_old, double T_new, double xi,
+                                             int nn = -1, int no = -1) {
   const int nl = L.tv.nl;
-  Reemit<double> R = reemit_setup<double>(L.tv, L.cdf64, T_old, T_new);
+  Reemit<double> R = reemit_setup<double>(L.tv, L.cdf64, T_old, T_new, nn, no);
   const double target = xi * R.D(nl - 1);
   const int lane = __lane_id();
   for (int base = 0; base < nl; base += 64) {
@@ -280,9 +284,29 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
     if (WAVE) E_old = bcd0(E_old);
     return E_old;
   };
-  auto reemit = [&](double T_old, double T_new, double xb) -> int {
-    if (WAVE) return reemit64_wave(L, T_old, T_new, xb);
-    return reemit64(L, T_old, T_new, xb);
+  auto reemit = [&](double T_old, double T_new, double xb, int nn = -1, int no = -1) -> int {
+    if (WAVE) return reemit64_wave(L, T_old, T_new, xb, nn, no);
+    return reemit64(L, T_old, T_new, xb, nn, no);
+  };
+  // bin of the reemission after a deposit dE on top of the tally E_old: the
+  // temperatures before and after from the inversion, whose table segments
+  // the spectrum interpolation reuses
+  auto reemit_after = [&](double E_old, double dE, double xb) -> int {
+    int n_old, n_new;
+    double T_old;
+    if (E_old == P.E_seen) {
+      T_old = P.T_seen;
+      n_old = P.seg_seen;
+    } else {
+      T_old = T_of_g_seg(L.tv, E_old * P.im, n_old);
+    }
+    const double E_new = E_old + dE;
+    const double T_new = T_of_g_seg(L.tv, E_new * P.im, n_new);
+    P.E_seen = E_new;
+    P.T_seen = T_new;
+    P.seg_seen = n_new;
+    P.Tc = T_new;
+    return reemit(T_old, T_new, xb, n_new, n_old);
   };
   int fate = 0;
   if (++P.events > A.max_events) {
@@ -379,17 +403,7 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
         double E_old = deposit(c, A.eps);
         double xb = rng.next();
         iso64(rng, P.d);
-        if (fz) {
-          P.k = reemit(-1.0, P.Tfix, xb);
-        } else {
-          const double E_new = E_old + A.eps;
-          double T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
-          double T_new = T_of_g(L.tv, E_new * P.im);
-          P.E_seen = E_new;
-          P.T_seen = T_new;
-          P.Tc = T_new;
-          P.k = reemit(T_old, T_new, xb);
-        }
+        P.k = fz ? reemit(-1.0, P.Tfix, xb) : reemit_after(E_old, A.eps, xb);
       }
       ++P.n_int;
       if (A.mrw) {
@@ -404,9 +418,13 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
             T_here = P.Tc;
           }
           if (T_here != P.mrw_T) {  // MRW coefficients of this cell at this T
+            // (the segment of the running T is known from its inversion)
+            const int n = T_here == P.T_seen ? P.seg_seen : t_segment(L.tv, T_here);
+            const double f = (T_here - L.tv.Tn[n]) * L.tv.inv_dT[n];
             P.mrw_T = T_here;
-            P.mrw_Drho = interp_T(L.tv, L.tv.Drho, T_here);
-            P.mrw_kbar = interp_T(L.tv, L.tv.kbar, T_here);
+            P.mrw_seg = n;
+            P.mrw_f = f;
+            P.mrw_Drho = L.tv.Drho[n] + f * (L.tv.Drho[n + 1] - L.tv.Drho[n]);
             double lam_R = 3.0 * P.mrw_Drho / P.rho;
             P.mrw_lim = A.gamma * lam_R;
           }
@@ -421,24 +439,16 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
           double R0 = dmin * (1.0 - 1e-6);
           double s = mrw_escape_s(L.mrw_tab, rng.next());
           double ell = s * R0 * R0 * P.rho / Drho;  // c t = s R0^2 / D
-          double dE = A.eps * P.rho * P.mrw_kbar * ell;
+          const int ns = P.mrw_seg;
+          const double kbar = L.tv.kbar[ns] + P.mrw_f * (L.tv.kbar[ns + 1] - L.tv.kbar[ns]);
+          double dE = A.eps * P.rho * kbar * ell;
           double E_old = deposit(c, dE);
           double nrm[3];
           iso64(rng, nrm);
           P.p[0] += R0 * nrm[0]; P.p[1] += R0 * nrm[1]; P.p[2] += R0 * nrm[2];
           double xb = rng.next();
           iso64(rng, P.d);
-          if (fz) {
-            P.k = reemit(-1.0, P.Tfix, xb);
-          } else {
-            const double E_new = E_old + dE;
-            double T_old = E_old == P.E_seen ? P.T_seen : T_of_g(L.tv, E_old * P.im);
-            double T_new = T_of_g(L.tv, E_new * P.im);
-            P.E_seen = E_new;
-            P.T_seen = T_new;
-            P.Tc = T_new;
-            P.k = reemit(T_old, T_new, xb);
-          }
+          P.k = fz ? reemit(-1.0, P.Tfix, xb) : reemit_after(E_old, dE, xb);
           P.d_safe = 0.0;
           P.dm_up = INFINITY;
           ++P.pc_mrw;
@@ -610,7 +620,8 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
           P.rho = P.im = P.Tfix = 0.0;
           P.Tc = -1.0;
           P.mrw_T = -2.0;
-          P.mrw_Drho = P.mrw_kbar = P.mrw_lim = 0.0;
+          P.mrw_Drho = P.mrw_f = P.mrw_lim = 0.0;
+          P.mrw_seg = P.seg_seen = 0;
           P.d_safe = 0.0;
           P.dm_up = INFINITY;
           P.cell_abs = P.cell_mrw = 0;
