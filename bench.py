@@ -343,24 +343,6 @@ def tail_probe(mcrt, W, torch):
             res[name] = {"events": e, "s": dt, "us_per_event": dt / e * 1e6,
                          "counters": {k: c[k] for k in ("cross", "scat", "abs", "mrw")}}
             log("tail probe %s %s: %d events, %.2f us/event" % (prec, name, e, dt / e * 1e6))
-        # the same packet with the running temperature: packets [0, pid) first
-        # (one launch), then the packet alone; its events depend on the tallies
-        # the others left, so they differ a little from run to run
-        for name, we in modes:
-            c1 = mcrt.Context(d, wave_events=we, **kw)
-            c1.reset()
-            c1.trace(pid, 7, n_total=1000000)
-            torch.cuda.synchronize()
-            c0 = c1.counters()
-            t0 = time.perf_counter()
-            c1.trace(1, 7, n_total=1000000, offset=pid)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            c = c1.counters()
-            e = sum(c[k] - c0[k] for k in ("cross", "scat", "abs", "mrw"))
-            res[name + "_running_T"] = {"events": e, "s": dt, "us_per_event": dt / max(e, 1) * 1e6}
-            log("tail probe %s %s, running T: %d events, %.2f us/event" %
-                (prec, name, e, dt / max(e, 1) * 1e6))
         out[prec] = res
     return out
 
