@@ -117,6 +117,8 @@ def parse():
                    help="with --c3: submit each pass as a graph of its own")
     p.add_argument("--c3-plain", action="store_true",
                    help="with --c3: also one pass of each disk alone on the FP64 path")
+    p.add_argument("--large-chunk", type=int, default=0,
+                   help="with --large: packets per mcrt_trace call (0: all in one call)")
     p.add_argument("--tail-probe", action="store_true",
                    help="only time the longest packet of a frozen-temperature sample of the step, "
                         "alone, per lane and in whole-wavefront mode, and exit")
@@ -269,14 +271,15 @@ def ensemble(mcrt, disk, o, n_packets, K, torch):
             "pda_region_cells_max": int(max(x["n_region"] for x in st))}
 
 
-def large(mcrt, W, torch, n_packets):
+def large(mcrt, W, torch, n_packets, chunk_packets=0):
     """The large disk: one pass (trace, T, PDA) with FP32 tracking and with the
     all-FP64 path at the same packet count; their temperature difference
     against the photon noise of both runs."""
     import numpy as np
     d, o = W.config("large")
     out = {"workload": "disk 1e-1 Msun, 0.1-500 AU, 400 r x 200 theta, 200 lambda bins, "
-                       "3 species, MRW gamma=3, PDA < 100 visits", "packets": n_packets}
+                       "3 species, MRW gamma=3, PDA < 100 visits", "packets": n_packets,
+           "packets_per_call": chunk_packets if chunk_packets > 0 else n_packets}
     T, NA, VIS = {}, {}, {}
     for prec in ("fp32", "fp64"):
         ctx = mcrt.Context(d, precision=prec, mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
@@ -284,7 +287,8 @@ def large(mcrt, W, torch, n_packets):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.reset()
-        chunk = 10000000
+        # one call unless chunked: every call ends with its longest walks
+        chunk = chunk_packets if chunk_packets > 0 else n_packets
         for off in range(0, n_packets, chunk):
             ctx.trace(min(chunk, n_packets - off), o.seed, n_total=n_packets, offset=off)
             torch.cuda.synchronize()
@@ -406,7 +410,7 @@ def main():
         print(json.dumps({"tail_probe": tail_probe(mcrt, W, torch)}), flush=True)
         return
     if a.large > 0:
-        print(json.dumps({"large": large(mcrt, W, torch, a.large)}), flush=True)
+        print(json.dumps({"large": large(mcrt, W, torch, a.large, a.large_chunk)}), flush=True)
         return
     if a.c3 > 0:
         print(json.dumps({"c3": c3(mcrt, W, torch, a.c3, a.c3_passes, a.c3_plain, a.c3_split)}),

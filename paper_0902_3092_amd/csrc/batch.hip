@@ -117,7 +117,7 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
         if (r) return r;
         const mcrt::TraceArgs& a = ta[(size_t)it * n_disks + d];
         if (a.tail_count) {
-          r = mcrt::launch_zero(a.tail_count, 4, s);
+          r = mcrt::launch_zero(a.tail_count, 8, s);  // and tail_next
           if (r) return r;
         }
         if (a.T_coef) {

@@ -185,6 +185,7 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
   if (ctx->opt.wave_events > 0 && ctx->d_tail) {
     a.tail = ctx->d_tail;
     a.tail_count = (unsigned int*)((char*)ctx->d_tail + (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES);
+    a.tail_next = a.tail_count + 1;
     a.tail_cap = mcrt::TAIL_CAP;
   }
   return a;
@@ -504,7 +505,7 @@ int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t see
   mcrt::TraceArgs a = mcrt::make_trace_args(ctx, n_packets, n_total, seed, offset, frozen_T_dev,
                                             rec_dev, n_recs);
   int rc = mcrt::launch_zero(ctx->d_next, 8, stream);
-  if (!rc && a.tail_count) rc = mcrt::launch_zero(a.tail_count, 4, stream);
+  if (!rc && a.tail_count) rc = mcrt::launch_zero(a.tail_count, 8, stream);  // and tail_next
   if (rc) return fail(ctx, rc, "clearing the work counters failed");
   // the MRW coefficients take the temperature the context holds now (the
   // last pass's, PDA included, or one set by the caller), kept apart from

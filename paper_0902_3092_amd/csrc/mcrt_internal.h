@@ -82,6 +82,7 @@ struct TraceArgs {
   long long wave_events;       // events after which a packet is handed off
   void* tail;                  // [tail_cap] packet states
   unsigned int* tail_count;    // states written (may exceed tail_cap: the rest stay)
+  unsigned int* tail_next;     // next state for a tail wavefront to take (after tail_count)
   int tail_cap;
 };
 constexpr int TAIL_STATE_BYTES = 512;

@@ -848,20 +848,24 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
 }
 
 // The packets handed over by the trace launch, one wavefront each; this
-// workgroup is number `rank` of the `nblk` serving the disk.
+// workgroup is number `rank` of those serving the disk.
 template <bool CDF_LDS>
-__device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigned rank,
-                                                     unsigned nblk) {
+__device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigned rank) {
   const unsigned wpb = BS32 / 64;
   const unsigned count = min(*A.tail_count, (unsigned)A.tail_cap);
   if (rank * wpb >= count) return;  // the whole workgroup
   const Lds32 L = setup_lds32<CDF_LDS>(A);
   const int n_r = A.m.n_r, n_mu = A.m.n_mu;
   const int lane = __lane_id();
-  const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (unsigned slot = rank * wpb + wave; slot < count; slot += nblk * wpb) {
+  for (;;) {
+    // a wavefront takes the next state when it is done with one, so the
+    // longest walks do not queue behind others
+    unsigned slot = 0;
+    if (lane == 0) slot = atomicAdd(A.tail_next, 1u);
+    slot = (unsigned)__builtin_amdgcn_readfirstlane((int)slot);
+    if (slot >= count) break;
     const TailState32& ts = ((const TailState32*)A.tail)[slot];
     Pk S = ts.P;
     WaveRng wr;
@@ -885,7 +889,7 @@ __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigne
 
 template <bool CDF_LDS>
 __global__ void __launch_bounds__(BS32) trace_fp32_tail_kernel(TraceArgs A) {
-  trace_fp32_tail_body<CDF_LDS>(A, blockIdx.x, gridDim.x);
+  trace_fp32_tail_body<CDF_LDS>(A, blockIdx.x);
 }
 
 // Many disks in one launch: workgroup b works on disk block_disk[b] for the
@@ -904,8 +908,7 @@ __global__ void __launch_bounds__(BS32)
     trace_fp32_batch_tail_kernel(const TraceArgs* __restrict__ As, const int* __restrict__ block_disk,
                                  const int* __restrict__ block_first) {
   const int dsk = block_disk[blockIdx.x];
-  trace_fp32_tail_body<CDF_LDS>(As[dsk], blockIdx.x - block_first[dsk],
-                                block_first[dsk + 1] - block_first[dsk]);
+  trace_fp32_tail_body<CDF_LDS>(As[dsk], blockIdx.x - block_first[dsk]);
 }
 
 template <bool CDF_LDS>

@@ -698,10 +698,15 @@ __global__ void __launch_bounds__(BS64) trace_fp64_tail_kernel(TraceArgs A) {
   const Lds64 L = setup_lds64<CDF_MODE>(A);
   const int n_r = A.m.n_r, n_mu = A.m.n_mu;
   const int lane = __lane_id();
-  const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
   uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (unsigned slot = blockIdx.x * wpb + wave; slot < count; slot += gridDim.x * wpb) {
+  for (;;) {
+    // a wavefront takes the next state when it is done with one, so the
+    // longest walks do not queue behind others
+    unsigned slot = 0;
+    if (lane == 0) slot = atomicAdd(A.tail_next, 1u);
+    slot = (unsigned)__builtin_amdgcn_readfirstlane((int)slot);
+    if (slot >= count) break;
     const TailState64& ts = ((const TailState64*)A.tail)[slot];
     Pk64 S = ts.P;
     WaveRng64 wr;
