@@ -529,10 +529,11 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       P.mrw_T = -2.0;
       P.n_int = 0;
     } else {
-      // the flight ends before sb (or d_safe when inside); the bound also
-      // keeps it finite where alpha is so small that its reciprocal
-      // overflows (0 * inf for a packet arriving with no optical depth left)
-      const float sint = fminf(fdiv(P.tau, alpha), inside ? P.d_safe : sb);
+      // the flight ends before sb (or d_safe when inside).  Where alpha is so
+      // small that its reciprocal overflows, tau * rcp(alpha) is 0 * inf for
+      // a packet with no optical depth left (its flight is 0) and inf
+      // otherwise (bounded by the face it cannot reach)
+      const float sint = P.tau > 0.0f ? fminf(fdiv(P.tau, alpha), inside ? P.d_safe : sb) : 0.0f;
       P.q[0] += sint * P.d[0]; P.q[1] += sint * P.d[1]; P.q[2] += sint * P.d[2];
       P.d_safe -= sint;
       P.dm_up += 1.00001f * sint;

@@ -7,6 +7,7 @@ GPU's concurrency orders absorptions differently), with the tolerances of the
 method's photon noise.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -380,3 +381,28 @@ def test_mrw_coefficients_from_current_T(mcrt, torch_cuda, precision):
     e.set_T(3.0 * T1)
     assert same(got_c, sequence(e))
     assert not same(got_a, got_c)
+
+
+@pytest.mark.parametrize("wave_events", [0, 1])
+def test_zero_optical_depth_into_tiny_extinction(mcrt, torch_cuda, wave_events):
+    """A packet launched with exactly zero optical depth (its draw rounds to
+    1 in FP32) into cells whose FP32 extinction is denormal, so that its
+    reciprocal overflows: the flight is 0, the packet interacts where it
+    enters and leaves the disk with a finite position (per lane, and in the
+    whole-wavefront launch after its first event)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_philox_np import TAU_ZERO_PID, TAU_ZERO_SEED
+    torch = torch_cuda
+    d = W.small_disk(n_r=12, n_mu=8, n_lambda=16)
+    rho = np.full(d.rho.shape, 1e-44)
+    ctx = mcrt.Context(d, rho=rho, precision="fp32", mrw=True, max_events=100000,
+                       wave_events=wave_events)
+    ctx.reset()
+    recs = ctx.trace(1, TAU_ZERO_SEED, n_total=TAU_ZERO_PID + 1, offset=TAU_ZERO_PID, n_recs=1)
+    torch.cuda.synchronize()
+    r = mcrt.Context.records_numpy(recs)[0]
+    assert r["fate"] in (1, 2), r
+    assert np.all(np.isfinite([r["x"], r["y"], r["z"]]))
+    assert r["n_scat"] + r["n_abs"] >= 1
+    assert ctx.counters()["capped"] == 0
