@@ -119,6 +119,9 @@ def parse():
                    help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--large-chunk", type=int, default=0,
                    help="with --large: packets per mcrt_trace call (0: all in one call)")
+    p.add_argument("--event-mix", action="store_true",
+                   help="only fit the per-event cost of each event type from three albedos, "
+                        "and exit")
     p.add_argument("--tail-probe", action="store_true",
                    help="only time the longest packet of a frozen-temperature sample of the step, "
                         "alone, per lane and in whole-wavefront mode, and exit")
@@ -351,6 +354,53 @@ def tail_probe(mcrt, W, torch):
     return out
 
 
+def event_mix(mcrt, W, torch):
+    """Per-event cost by event type: the longest frozen-T walk (of 1e5
+    packets) on the step's disk with albedo 0.1, 0.5 and 0.9 at the same
+    extinction, traced alone per lane and in whole-wavefront mode; a
+    least-squares fit of the times against the event counts gives the cost
+    of a scattering, an absorption, and a crossing or MRW step."""
+    import numpy as np
+    rows = []
+    for om in (0.1, 0.5, 0.9):
+        d = W.make_disk("mix", M_dust_msun=1e-2, n_r=100, n_mu=60, n_lambda=100,
+                        species=(((1.0 - om) / 0.5, om),))
+        rc = 0.5 * (d.r_edges[:-1] + d.r_edges[1:]) / W.AU
+        Tf = torch.from_numpy(np.ascontiguousarray(
+            (300.0 * rc[:, None] ** -0.5 * (1 + 0.3 * d.mu_edges[None, 1:])).reshape(-1))).cuda()
+        for prec in ("fp32", "fp64"):
+            kw = dict(precision=prec, mrw=True, gamma=3.0, n_int_min=20)
+            ctx = mcrt.Context(d, **kw)
+            n = 100000
+            recs = mcrt.Context.records_numpy(ctx.trace(n, 7, n_total=1000000, frozen_T=Tf,
+                                                        n_recs=n))
+            ev = recs["n_cross"] + recs["n_scat"] + recs["n_abs"] + recs["n_mrw"]
+            pid = int(np.argmax(ev))
+            for name, we in (("per_lane", 0), ("whole_wave", 32)):
+                c1 = mcrt.Context(d, wave_events=we, **kw)
+                c1.trace(1, 7, n_total=1000000, offset=pid, frozen_T=Tf)   # warm-up
+                c1.reset()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c1.trace(1, 7, n_total=1000000, offset=pid, frozen_T=Tf)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                c = c1.counters()
+                rows.append(dict(albedo=om, precision=prec, mode=name, s=dt,
+                                 **{k: c[k] for k in ("cross", "scat", "abs", "mrw")}))
+                log("event mix: albedo %.1f %s %s: %.3f s" % (om, prec, name, dt))
+    fits = {}
+    for prec in ("fp32", "fp64"):
+        for name in ("per_lane", "whole_wave"):
+            sel = [r for r in rows if r["precision"] == prec and r["mode"] == name]
+            A = np.array([[r["scat"], r["abs"], r["cross"] + r["mrw"]] for r in sel], float)
+            t = np.array([r["s"] for r in sel])
+            x = np.linalg.lstsq(A, t, rcond=None)[0] * 1e6
+            fits["%s_%s" % (prec, name)] = {"us_scattering": x[0], "us_absorption": x[1],
+                                            "us_crossing_or_mrw": x[2]}
+    return {"rows": rows, "fit": fits}
+
+
 def pda_grad(mcrt, W, torch):
     import numpy as np
     d, _ = W.config("pda_grad")
@@ -408,6 +458,9 @@ def main():
 
     if a.tail_probe:
         print(json.dumps({"tail_probe": tail_probe(mcrt, W, torch)}), flush=True)
+        return
+    if a.event_mix:
+        print(json.dumps({"event_mix": event_mix(mcrt, W, torch)}), flush=True)
         return
     if a.large > 0:
         print(json.dumps({"large": large(mcrt, W, torch, a.large, a.large_chunk)}), flush=True)
