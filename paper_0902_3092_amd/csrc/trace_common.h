@@ -72,12 +72,6 @@ __device__ __forceinline__ double T_of_g_seg(const TabView& t, double g, int& n)
   return t.Tn[n] + (g - t.G[n]) * t.g_slope[n];
 }
 
-__device__ __forceinline__ double interp_T(const TabView& t, const double* tab, double T) {
-  int n = t_segment(t, T);
-  double f = (T - t.Tn[n]) * t.inv_dT[n];
-  return tab[n] + f * (tab[n + 1] - tab[n]);
-}
-
 // Reemission bin from the difference of the cumulative emission spectra at
 // T_new and T_old (linear in T between nodes); T_old < 0: the full spectrum
 // at T_new.  Smallest k with D(k) > xi * D(n_lambda - 1).
