@@ -67,17 +67,20 @@ def trace32_source_hash():
 
 
 def measured_traffic(kernel, packets):
-    """HBM bytes per launch from the committed counter summary, or None when
-    it covers another kernel, launch size or source."""
+    """(HBM bytes per launch from the committed counter summary, or None when
+    it covers another kernel, launch size or source; and why)."""
     try:
         with open(COUNTERS_JSON) as fh:
             c = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if (c.get("kernel") != kernel or c.get("packets") != packets or
-            c.get("source_sha256") != trace32_source_hash()):
-        return None
-    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+    except (OSError, ValueError) as e:
+        return None, "no counter summary (%s)" % type(e).__name__
+    if c.get("kernel") != kernel or c.get("packets") != packets:
+        return None, "the counter summary covers another kernel or launch size"
+    h = trace32_source_hash()
+    if c.get("source_sha256") != h:
+        return None, "the kernel sources changed since the counters were taken (%s)" % h[:12]
+    return (1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]),
+            "profiles/trace_fp32_counters.json")
 
 
 def log(msg):
@@ -515,6 +518,8 @@ def main():
     T_meas, vis_meas, reg_meas, nabs_meas = fields(ctx, mcrt)
     c = counters[-1]
     flops = sum(FLOPS_PER_EVENT[k] * c[k] for k in FLOPS_PER_EVENT)
+    traffic, traffic_src = (measured_traffic(TRACE32_KERNELS, N) if a.precision == "fp32"
+                            else (None, "counters are taken for the FP32 kernels only"))
     t_trace = float(np.mean(trace_ms)) * 1e-3
     achieved = flops / t_trace
     peak = PEAK[a.precision]
@@ -536,8 +541,8 @@ def main():
                    "precision": a.precision, "packets_per_step": N},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": (measured_traffic(TRACE32_KERNELS, N)
-                                 if a.precision == "fp32" else None),
+                     "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "kernel": "trace_%s_kernel + trace_%s_tail_kernel (one mcrt_trace call)"
                                % (a.precision, a.precision),
                      "kernel_ms": float(np.mean(trace_ms)),
