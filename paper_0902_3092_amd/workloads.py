@@ -100,6 +100,8 @@ def log_edges(lo: float, hi: float, n: int) -> np.ndarray:
 
 def mu_edges_for(n_mu: int, hr_min: float) -> np.ndarray:
     """mu_0 = 0, mu_1 = 0.05 * min(H/r), geometric from mu_1 up to mu_n = 1."""
+    if n_mu == 1:  # one row: the whole polar range
+        return np.array([0.0, 1.0])
     mu1 = 0.05 * hr_min
     e = np.empty(n_mu + 1)
     e[0] = 0.0

@@ -1,0 +1,161 @@
+"""Edge cases of the boundary on the GPU: empty and ragged launches, one run
+split at arbitrary packet offsets, a dust-free disk, a one-cell grid, an empty
+PDA region and batches smaller than a wavefront."""
+import numpy as np
+import pytest
+
+from paper_0902_3092_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mcrt(torch_cuda):
+    from paper_0902_3092_amd import mcrt as M
+    M.lib()
+    return M
+
+
+def _energy(ctx, mcrt):
+    sed = ctx.sed().cpu().numpy()
+    E_star = ctx.get(mcrt.GET_E_STAR).cpu().numpy()[0]
+    return (sed.sum() + E_star) / ctx.tables()["L_star"]
+
+
+def _frozen(d):
+    rc = 0.5 * (d.r_edges[:-1] + d.r_edges[1:]) / W.AU
+    return np.ascontiguousarray((300.0 * rc[:, None] ** -0.5 *
+                                 (1 + 0.3 * d.mu_edges[None, 1:])).reshape(-1))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 513, 131073])
+def test_ragged_launch_counts(mcrt, torch_cuda, precision, n):
+    """Every packet of a launch of any size is traced exactly once."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=3e-3, n_r=14, n_mu=10, n_lambda=24)
+    ctx = mcrt.Context(d, precision=precision, mrw=True, gamma=2.0, n_int_min=5)
+    ctx.reset()
+    if n == 0:
+        ctx.trace(0, 3, n_total=1)
+        torch.cuda.synchronize()
+        assert all(v == 0 for v in ctx.counters().values())
+        return
+    recs = mcrt.Context.records_numpy(ctx.trace(n, 3, n_recs=min(n, 4096)))
+    torch.cuda.synchronize()
+    c = ctx.counters()
+    assert c["launch"] == n and c["escaped"] + c["star"] == n and c["capped"] == 0
+    assert np.all((recs["fate"] == 1) | (recs["fate"] == 2))
+    assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_split_launches_match_one_launch(mcrt, torch_cuda, precision):
+    """Frozen T, per lane: packets [0, n) in one launch and in three launches
+    at ragged offsets give bit-identical packets."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=3e-3, n_r=14, n_mu=10, n_lambda=24)
+    Tf = torch.from_numpy(_frozen(d)).cuda()
+    kw = dict(precision=precision, mrw=True, gamma=2.0, n_int_min=5, wave_events=0)
+    n = 5000
+    one = mcrt.Context(d, **kw)
+    ref = mcrt.Context.records_numpy(one.trace(n, 11, frozen_T=Tf, n_recs=n))
+    parts = mcrt.Context(d, **kw)
+    got = []
+    for lo, hi in ((0, 1234), (1234, 3234), (3234, n)):
+        r = parts.trace(hi - lo, 11, n_total=n, offset=lo, frozen_T=Tf, n_recs=hi - lo)
+        got.append(mcrt.Context.records_numpy(r))
+    torch.cuda.synchronize()
+    got = np.concatenate(got)
+    for f in ref.dtype.names:
+        assert np.array_equal(got[f], ref[f]), f
+    assert np.array_equal(one.counters()["launch"], parts.counters()["launch"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_dust_free_disk(mcrt, torch_cuda, precision):
+    """No dust: no interaction, every packet escapes or returns to the star,
+    the temperature stays 0 and the PDA region is empty."""
+    torch = torch_cuda
+    d = W.small_disk(n_r=12, n_mu=8, n_lambda=16)
+    ctx = mcrt.Context(d, rho=np.zeros_like(d.rho), precision=precision, mrw=True)
+    ctx.reset()
+    ctx.trace(20000, 5)
+    ctx.update_T()
+    st = ctx.pda_solve()
+    torch.cuda.synchronize()
+    c = ctx.counters()
+    assert c["scat"] == 0 and c["abs"] == 0 and c["mrw"] == 0
+    assert c["escaped"] + c["star"] == 20000
+    assert float(ctx.get(mcrt.GET_E_ABS).abs().sum()) == 0.0
+    assert float(ctx.get(mcrt.GET_T).abs().sum()) == 0.0
+    assert st["n_region"] == 0
+    assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_one_cell_grid(mcrt, oracle_mod, torch_cuda, precision):
+    """A grid of one cell (one shell, the whole polar range)."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=1e-3, n_r=1, n_mu=1, n_lambda=16)
+    ctx = mcrt.Context(d, precision=precision, mrw=True, gamma=2.0, n_int_min=5)
+    ctx.reset()
+    ctx.trace(20000, 2)
+    ctx.update_T()
+    torch.cuda.synchronize()
+    c = ctx.counters()
+    assert c["launch"] == 20000 and c["escaped"] + c["star"] == 20000 and c["capped"] == 0
+    assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
+    assert float(ctx.get(mcrt.GET_T)[0]) > 0.0
+    rng = np.random.default_rng(4)
+    m = 2000
+    r = np.exp(rng.uniform(np.log(d.r_edges[0] * 0.5), np.log(d.r_edges[-1] * 2.0), m))
+    mu = rng.uniform(-1, 1, m)
+    ph = rng.uniform(0, 2 * np.pi, m)
+    st = np.sqrt(1 - mu * mu)
+    xyz = np.ascontiguousarray(np.stack([r * st * np.cos(ph), r * st * np.sin(ph), r * mu], 1))
+    got = ctx.locate(torch.from_numpy(xyz).cuda()).cpu().numpy()
+    assert np.array_equal(got, oracle_mod.Oracle(d).locate(xyz))
+    assert set(np.unique(got)) <= {-1, 0}
+
+
+def test_empty_pda_region(mcrt, torch_cuda):
+    """An all-zero mask: the solve does nothing and the temperature stays the
+    Monte Carlo one; without a mask a visits threshold of 0 is refused."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=3e-3, n_r=14, n_mu=10, n_lambda=24)
+    ctx = mcrt.Context(d, precision="fp32", mrw=True, pda_visits=0)
+    ctx.reset()
+    ctx.trace(20000, 6)
+    T_mc = ctx.update_T().clone()
+    st = ctx.pda_solve(torch.zeros(ctx.n_cells, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert st["n_region"] == 0
+    assert torch.equal(ctx.get(mcrt.GET_T), T_mc)
+    assert int((ctx.get(mcrt.GET_REGION) != 0).sum()) == 0
+    with pytest.raises(mcrt.McrtError):
+        ctx.pda_solve()
+
+
+def test_batch_smaller_than_a_wavefront(mcrt, torch_cuda):
+    """Two disks with 1 and 70 packets in one batched pass."""
+    torch = torch_cuda
+    ds = [W.small_disk(M_dust_msun=3e-3, n_r=14, n_mu=10, n_lambda=24),
+          W.make_disk("b", M_dust_msun=1e-4, n_r=20, n_mu=12, n_lambda=24)]
+    ctxs = [mcrt.Context(d, precision="fp32", mrw=True, gamma=3.0, n_int_min=20, pda_visits=30)
+            for d in ds]
+    npk = [1, 70]
+    mcrt.batch_run(ctxs, npk, [7, 8], n_iter=2, use_graph=True)
+    torch.cuda.synchronize()
+    for ctx, n in zip(ctxs, npk):
+        c = ctx.counters()
+        assert c["launch"] == n and c["escaped"] + c["star"] == n
+        assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
