@@ -232,7 +232,9 @@ int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
  * tallies of every context, trace n_packets[d] packets of context d (seed
  * seeds[d] + (pass << 32); each packet carries L_star / n_packets[d]) with
  * ALL disks in one persistent launch (workgroups shared out by packet
- * count), invert the temperatures, and solve each disk's PDA on its
+ * count; packets still going once their disk's packets are all out continue
+ * in a second launch whose workgroups are shared out by those packets),
+ * invert the temperatures, and solve each disk's PDA on its
  * low-visit cells with one workgroup per disk.  Contexts whose mrw_coef_T is
  * 1 take the MRW coefficients of pass k from the temperature after pass k-1
  * (for the first pass: the T the context holds, if it holds one).

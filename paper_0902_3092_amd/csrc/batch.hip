@@ -58,13 +58,10 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
     nb[d] = (int)std::max<long long>(1, std::min(want, need));
     used += nb[d];
   }
-  std::vector<int> block_disk, block_first(n_disks + 1, 0);
+  std::vector<int> block_disk;
   block_disk.reserve(used);
-  for (int d = 0; d < n_disks; ++d) {
-    block_first[d] = (int)block_disk.size();
+  for (int d = 0; d < n_disks; ++d)
     for (int b = 0; b < nb[d]; ++b) block_disk.push_back(d);
-  }
-  block_first[n_disks] = (int)block_disk.size();
   // arguments for every pass, uploaded before any work is queued
   const size_t targs = sizeof(mcrt::TraceArgs);
   std::vector<mcrt::TraceArgs> ta((size_t)n_iter * n_disks);
@@ -84,8 +81,7 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
   std::vector<char> pda_host(pda_bytes);
   int rc = mcrt::pda_batch_fill(ctxs, n_disks, pda_host.data());
   if (rc) return rc;
-  size_t bytes = al(ta.size() * targs) + al(block_disk.size() * sizeof(int)) +
-                 al(block_first.size() * sizeof(int)) + al(pda_bytes);
+  size_t bytes = al(ta.size() * targs) + al(block_disk.size() * sizeof(int)) + al(pda_bytes);
   void* blob = nullptr;
   if (hipMalloc(&blob, bytes) != hipSuccess) return fail_batch(MCRT_E_OOM, "batch arguments");
   char* q = (char*)blob;
@@ -93,14 +89,10 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
   q += al(ta.size() * targs);
   int* d_bd = (int*)q;
   q += al(block_disk.size() * sizeof(int));
-  int* d_bf = (int*)q;
-  q += al(block_first.size() * sizeof(int));
   void* d_pda = q;
   hipError_t e = hipMemcpy(d_ta, ta.data(), ta.size() * targs, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(d_bd, block_disk.data(), block_disk.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(d_bf, block_first.data(), block_first.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_pda, pda_host.data(), pda_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(blob);
@@ -125,7 +117,7 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
           if (r) return r;
         }
       }
-      int r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd, d_bf,
+      int r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd, n_disks,
                                             (int)block_disk.size(), lds, cdf_lds, s);
       if (r) return r;
       for (int d = 0; d < n_disks; ++d) {

@@ -138,9 +138,8 @@ size_t trace_fp32_lds(const DevModel& M, bool with_cdf);
 size_t trace_fp32_lds_cap();
 int trace_fp32_blocks_per_cu(size_t lds, bool cdf_lds);
 int prepare_trace_fp32_batch(size_t lds, bool cdf_lds);
-int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk,
-                            const int* d_block_first, int n_blocks, size_t lds, bool cdf_lds,
-                            hipStream_t s);
+int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk, int n_disks,
+                            int n_blocks, size_t lds, bool cdf_lds, hipStream_t s);
 TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
                           uint64_t offset, const double* frozen_T, mcrt_packet_rec* recs,
                           int64_t n_recs);

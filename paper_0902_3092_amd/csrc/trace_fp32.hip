@@ -853,6 +853,7 @@ __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
 template <bool CDF_LDS>
 __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigned rank) {
   const unsigned wpb = BS32 / 64;
+  if (!A.tail) return;  // traced without hand-off
   const unsigned count = min(*A.tail_count, (unsigned)A.tail_cap);
   if (rank * wpb >= count) return;  // the whole workgroup
   const Lds32 L = setup_lds32<CDF_LDS>(A);
@@ -902,14 +903,41 @@ __global__ void __launch_bounds__(BS32) trace_fp32_batch_kernel(const TraceArgs*
   trace_fp32_body<CDF_LDS>(As[block_disk[blockIdx.x]]);
 }
 
-// Hand-offs of a batched launch: the same workgroups per disk; block_first
-// [n_disks + 1] gives each disk's first workgroup.
+// Hand-offs of a batched launch.  The workgroups are shared out by the
+// packets each disk handed off (one wavefront per packet, BS32 / 64 per
+// workgroup): every disk with hand-offs gets one workgroup, and the rest go
+// in proportion to what each disk wants beyond that.  Every workgroup reads
+// the same counts and computes the same split.  The launch has at least one
+// workgroup per disk.
 template <bool CDF_LDS>
 __global__ void __launch_bounds__(BS32)
-    trace_fp32_batch_tail_kernel(const TraceArgs* __restrict__ As, const int* __restrict__ block_disk,
-                                 const int* __restrict__ block_first) {
-  const int dsk = block_disk[blockIdx.x];
-  trace_fp32_tail_body<CDF_LDS>(As[dsk], blockIdx.x - block_first[dsk]);
+    trace_fp32_batch_tail_kernel(const TraceArgs* __restrict__ As, int n_disks) {
+  const unsigned wpb = BS32 / 64;
+  long long n_nz = 0, extra = 0;
+  // disks traced without hand-off (wave_events = 0) have no hand-off buffer
+  auto handed = [&](int d) -> unsigned {
+    return As[d].tail ? min(*As[d].tail_count, (unsigned)As[d].tail_cap) : 0u;
+  };
+  for (int d = 0; d < n_disks; ++d) {
+    const unsigned c = handed(d);
+    if (c) {
+      ++n_nz;
+      extra += (long long)((c + wpb - 1) / wpb) - 1;
+    }
+  }
+  const long long spare = (long long)gridDim.x - n_nz;
+  long long first = 0;
+  for (int d = 0; d < n_disks; ++d) {
+    const unsigned c = handed(d);
+    if (!c) continue;
+    const long long want = (long long)((c + wpb - 1) / wpb) - 1;
+    const long long got = 1 + (extra <= spare ? want : (want * spare) / extra);
+    if ((long long)blockIdx.x < first + got) {
+      trace_fp32_tail_body<CDF_LDS>(As[d], (unsigned)(blockIdx.x - first));
+      return;
+    }
+    first += got;
+  }
 }
 
 template <bool CDF_LDS>
@@ -996,19 +1024,18 @@ int prepare_trace_fp32_batch(size_t lds, bool cdf_lds) {
   return MCRT_OK;
 }
 
-int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk,
-                            const int* d_block_first, int n_blocks, size_t lds, bool cdf_lds,
-                            hipStream_t s) {
+int launch_trace_fp32_batch(const TraceArgs* d_args, const int* d_block_disk, int n_disks,
+                            int n_blocks, size_t lds, bool cdf_lds, hipStream_t s) {
   if (cdf_lds) {
     hipLaunchKernelGGL(trace_fp32_batch_kernel<true>, dim3(n_blocks), dim3(BS32), lds, s, d_args,
                        d_block_disk);
     hipLaunchKernelGGL(trace_fp32_batch_tail_kernel<true>, dim3(n_blocks), dim3(BS32), lds, s,
-                       d_args, d_block_disk, d_block_first);
+                       d_args, n_disks);
   } else {
     hipLaunchKernelGGL(trace_fp32_batch_kernel<false>, dim3(n_blocks), dim3(BS32), lds, s, d_args,
                        d_block_disk);
     hipLaunchKernelGGL(trace_fp32_batch_tail_kernel<false>, dim3(n_blocks), dim3(BS32), lds, s,
-                       d_args, d_block_disk, d_block_first);
+                       d_args, n_disks);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

@@ -693,6 +693,7 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
 template <int CDF_MODE>
 __global__ void __launch_bounds__(BS64) trace_fp64_tail_kernel(TraceArgs A) {
   const unsigned wpb = BS64 / 64;
+  if (!A.tail) return;  // traced without hand-off (not launched then; kept safe)
   const unsigned count = min(*A.tail_count, (unsigned)A.tail_cap);
   if (blockIdx.x * wpb >= count) return;  // the whole workgroup
   const Lds64 L = setup_lds64<CDF_MODE>(A);

@@ -159,3 +159,19 @@ def test_batch_smaller_than_a_wavefront(mcrt, torch_cuda):
         c = ctx.counters()
         assert c["launch"] == n and c["escaped"] + c["star"] == n
         assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
+
+
+def test_batch_with_and_without_hand_off(mcrt, torch_cuda):
+    """A batch whose contexts differ in wave_events (0: no hand-off buffer):
+    the hand-off launch serves only the disks that handed packets off."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=1e-1, n_r=14, n_mu=10, n_lambda=24)
+    ctxs = [mcrt.Context(d, precision="fp32", mrw=True, gamma=2.0, n_int_min=5, pda_visits=30,
+                         wave_events=we) for we in (0, 64, 0)]
+    npk = [3000, 3000, 500]
+    mcrt.batch_run(ctxs, npk, [21, 22, 23], n_iter=1, use_graph=False)
+    torch.cuda.synchronize()
+    for ctx, n in zip(ctxs, npk):
+        c = ctx.counters()
+        assert c["launch"] == n and c["escaped"] + c["star"] == n and c["capped"] == 0
+        assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
