@@ -213,8 +213,9 @@ int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_d
 #define MCRT_GET_N_MRW 3    /* uint32 [n_cells], MRW steps */
 #define MCRT_GET_T 4        /* double [n_cells], K */
 #define MCRT_GET_REGION 5   /* uint8 [n_cells]: 1 PDA-solved, 2 isolated, 0 outside */
-#define MCRT_GET_COUNTERS 6 /* uint64 [8]: escaped, star, capped, crossings,
-                               scatterings, absorptions, MRW steps, launches */
+#define MCRT_GET_COUNTERS 6 /* uint64 [9]: escaped, star, capped, crossings,
+                               scatterings, absorptions, MRW steps, launches, packets
+                               handed off to the whole-wavefront launch */
 #define MCRT_GET_E_STAR 7   /* double [1], erg/s absorbed by the star */
 #define MCRT_GET_TABLES 8   /* double: T nodes [n_T], cdf [n_T][n_lambda], D*rho [n_T],
                                kappa-bar [n_T], star cdf [n_lambda], L_star [1] */

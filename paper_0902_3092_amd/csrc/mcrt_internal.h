@@ -12,7 +12,8 @@
 namespace mcrt {
 
 // Counters, in the order of MCRT_GET_COUNTERS.
-enum { C_ESCAPED = 0, C_STAR, C_CAPPED, C_CROSS, C_SCAT, C_ABS, C_MRW, C_LAUNCH, N_COUNTERS };
+enum { C_ESCAPED = 0, C_STAR, C_CAPPED, C_CROSS, C_SCAT, C_ABS, C_MRW, C_LAUNCH, C_HANDED,
+       N_COUNTERS };
 
 // Nodes of the MRW escape-time table: s as a function of v = ln(-ln P0).
 constexpr int MRW_TAB_N = 512;

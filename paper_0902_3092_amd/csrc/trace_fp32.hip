@@ -723,7 +723,7 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   P.events = 0;
   uint64_t pid = 0;
   bool handed = false;  // this packet tried the hand-off already
-  uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t tot[N_COUNTERS] = {};
 
   for (;;) {
     unsigned long long idle = __ballot(!alive);
@@ -814,6 +814,7 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
           ts.P = P;
           ts.rng = rng;
           ts.pid = pid;
+          tot[C_HANDED]++;
           alive = false;
           continue;
         }
@@ -860,7 +861,7 @@ __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigne
   const int n_r = A.m.n_r, n_mu = A.m.n_mu;
   const int lane = __lane_id();
   const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
-  uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t tot[N_COUNTERS] = {};
   for (;;) {
     // a wavefront takes the next state when it is done with one, so the
     // longest walks do not queue behind others

@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
   P.events = 0;
   uint64_t pid = 0;
   bool handed = false;  // this packet tried the hand-off already
-  uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t tot[N_COUNTERS] = {};
 
   for (;;) {
     // ---- refill idle lanes (one atomic per wavefront)
@@ -659,6 +659,7 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
           ts.P = P;
           ts.rng = rng;
           ts.pid = pid;
+          tot[C_HANDED]++;
           alive = false;
           continue;
         }
@@ -700,7 +701,7 @@ __global__ void __launch_bounds__(BS64) trace_fp64_tail_kernel(TraceArgs A) {
   const int n_r = A.m.n_r, n_mu = A.m.n_mu;
   const int lane = __lane_id();
   const double* fixT = A.frozen_T ? A.frozen_T : A.T_coef;
-  uint32_t tot[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t tot[N_COUNTERS] = {};
   for (;;) {
     // a wavefront takes the next state when it is done with one, so the
     // longest walks do not queue behind others

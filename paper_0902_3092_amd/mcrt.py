@@ -21,7 +21,7 @@ OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2
 FP64, FP32 = 0, 1
 GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
     GET_TABLES = range(9)
-COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch"]
+COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch", "handed"]
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",

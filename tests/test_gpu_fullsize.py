@@ -103,6 +103,7 @@ def test_bench_step_invariants(mcrt, torch_cuda):
     c = ctx.counters()
     assert c["launch"] == o.n_packets and c["escaped"] + c["star"] == o.n_packets
     assert c["capped"] == 0
+    assert 0 < c["handed"] <= 8192   # long walks go to the whole-wavefront launch
     assert _energy(ctx, mcrt) == pytest.approx(1.0, abs=1e-6)
     na = ctx.get(mcrt.GET_N_ABS).cpu().numpy().view(np.uint32).astype(np.int64)
     nm = ctx.get(mcrt.GET_N_MRW).cpu().numpy().view(np.uint32).astype(np.int64)
