@@ -81,7 +81,8 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
   std::vector<char> pda_host(pda_bytes);
   int rc = mcrt::pda_batch_fill(ctxs, n_disks, pda_host.data());
   if (rc) return rc;
-  size_t bytes = al(ta.size() * targs) + al(block_disk.size() * sizeof(int)) + al(pda_bytes);
+  size_t bytes = al(ta.size() * targs) + al(block_disk.size() * sizeof(int)) + al(pda_bytes) +
+                 al(16);
   void* blob = nullptr;
   if (hipMalloc(&blob, bytes) != hipSuccess) return fail_batch(MCRT_E_OOM, "batch arguments");
   char* q = (char*)blob;
@@ -90,6 +91,19 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
   int* d_bd = (int*)q;
   q += al(block_disk.size() * sizeof(int));
   void* d_pda = q;
+  q += al(pda_bytes);
+  // one live count for the whole batch: hand-offs wait until all disks'
+  // packets are out and no more are live than the hand-off launch has
+  // wavefronts
+  long long* d_live = (long long*)q;
+  unsigned int* d_waves_in = (unsigned int*)(d_live + 1);
+  const unsigned waves = (unsigned)block_disk.size() * 8u;  // 512-thread workgroups
+  for (auto& a : ta) {
+    a.live = d_live;
+    a.waves_in = d_waves_in;
+    a.n_waves = sumN <= (double)waves ? 0u : waves;  // a small batch needs no count
+    a.live_handoff = waves;
+  }
   hipError_t e = hipMemcpy(d_ta, ta.data(), ta.size() * targs, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(d_bd, block_disk.data(), block_disk.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -117,7 +131,9 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
           if (r) return r;
         }
       }
-      int r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd, n_disks,
+      int r = mcrt::launch_zero(d_live, 16, s);  // the live count and its wavefronts
+      if (r) return r;
+      r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd, n_disks,
                                             (int)block_disk.size(), lds, cdf_lds, s);
       if (r) return r;
       for (int d = 0; d < n_disks; ++d) {

@@ -187,6 +187,10 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
     a.tail_count = (unsigned int*)((char*)ctx->d_tail + (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES);
     a.tail_next = a.tail_count + 1;
     a.tail_cap = mcrt::TAIL_CAP;
+    // after the two counters: the live count (8-byte aligned) and the
+    // wavefronts counted into it; the launch sets n_waves and live_handoff
+    a.live = (long long*)(a.tail_count + 2);
+    a.waves_in = (unsigned int*)(a.live + 1);
   }
   return a;
 }
@@ -505,7 +509,8 @@ int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t see
   mcrt::TraceArgs a = mcrt::make_trace_args(ctx, n_packets, n_total, seed, offset, frozen_T_dev,
                                             rec_dev, n_recs);
   int rc = mcrt::launch_zero(ctx->d_next, 8, stream);
-  if (!rc && a.tail_count) rc = mcrt::launch_zero(a.tail_count, 8, stream);  // and tail_next
+  // tail_count, tail_next, live and waves_in
+  if (!rc && a.tail_count) rc = mcrt::launch_zero(a.tail_count, 24, stream);
   if (rc) return fail(ctx, rc, "clearing the work counters failed");
   // the MRW coefficients take the temperature the context holds now (the
   // last pass's, PDA included, or one set by the caller), kept apart from

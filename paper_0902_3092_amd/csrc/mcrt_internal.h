@@ -85,6 +85,13 @@ struct TraceArgs {
   unsigned int* tail_count;    // states written (may exceed tail_cap: the rest stay)
   unsigned int* tail_next;     // next state for a tail wavefront to take (after tail_count)
   int tail_cap;
+  // hand-offs wait until few packets are left: once the launch's packets are
+  // all out, each wavefront adds its live packets to *live (and itself to
+  // *waves_in) and subtracts those that leave; packets are handed off once
+  // all n_waves wavefronts are counted and *live <= live_handoff
+  long long* live;
+  unsigned int* waves_in;
+  unsigned int n_waves, live_handoff;
 };
 constexpr int TAIL_STATE_BYTES = 512;
 constexpr int TAIL_CAP = 8192;

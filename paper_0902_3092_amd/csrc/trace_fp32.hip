@@ -723,6 +723,9 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   P.events = 0;
   uint64_t pid = 0;
   bool handed = false;  // this packet tried the hand-off already
+  // hand-off bookkeeping: this wavefront's packets are counted in *A.live;
+  // hand-offs are allowed (both wave-uniform); the lane's packet was live
+  bool counted = false, allow = false, polled = false, was_alive = false;
   uint32_t tot[N_COUNTERS] = {};
 
   for (;;) {
@@ -788,6 +791,23 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
         }
       }
     }
+    if (A.live && exhausted) {
+      // count this wavefront's live packets once, then the ones that leave
+      const unsigned long long now = __ballot(alive);
+      if (!counted) {
+        if (lane == 0) {
+          atomicAdd((unsigned long long*)A.live, (unsigned long long)__popcll(now));
+          atomicAdd(A.waves_in, 1u);
+        }
+        counted = true;
+      } else {
+        const unsigned long long gone = __ballot(was_alive && !alive);
+        if (gone && lane == 0)
+          atomicAdd((unsigned long long*)A.live,
+                    (unsigned long long)(-(long long)__popcll(gone)));
+      }
+      was_alive = alive;
+    }
     const unsigned long long live = __ballot(alive);
     if (live == 0ull) {
       if (exhausted) break;
@@ -805,8 +825,24 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
         nx = __shfl(nx, leader);
         if (nx >= A.n_packets) exhausted = true;
       }
+      // hand-offs wait until every wavefront is counted and no more packets
+      // are live than the hand-off launch has wavefronts: until then the
+      // long packets run 64 to a wavefront here
+      if (exhausted && !allow && (!polled || __ballot((P.events & 255) == 255))) {
+        polled = true;
+        const int leader = __ffsll((long long)__ballot(true)) - 1;
+        long long lv = 0;
+        unsigned wi = 0;
+        if (lane == leader) {
+          lv = __hip_atomic_load(A.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wi = __hip_atomic_load(A.waves_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        lv = __shfl(lv, leader);
+        wi = __shfl(wi, leader);
+        if (wi >= A.n_waves && lv <= (long long)A.live_handoff) allow = true;
+      }
       // then a long packet moves to the whole-wavefront launch
-      if (exhausted && !handed && P.events >= A.wave_events) {
+      if (allow && !handed && P.events >= A.wave_events) {
         handed = true;
         const unsigned slot = atomicAdd(A.tail_count, 1u);
         if (slot < (unsigned)A.tail_cap) {
@@ -958,14 +994,18 @@ int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   long long nb = (long long)ctx->n_cu * per_cu;
   long long need = ((long long)a.n_packets + BS32 - 1) / BS32;
   if (nb > need) nb = need < 1 ? 1 : need;
-  hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS32), lds, s, a);
-  if (a.tail) {
-    // enough workgroups for every slot, one workgroup per compute unit at a time
-    long long tb = (long long)ctx->n_cu * per_cu;
-    const long long slots = ((long long)a.tail_cap + BS32 / 64 - 1) / (BS32 / 64);
-    if (tb > slots) tb = slots;
-    hipLaunchKernelGGL(tail, dim3((unsigned)tb), dim3(BS32), lds, s, a);
-  }
+  // the hand-off launch: enough workgroups for every slot, one workgroup
+  // per compute unit at a time; packets are handed off once no more are
+  // left than it has wavefronts
+  long long tb = (long long)ctx->n_cu * per_cu;
+  const long long slots = ((long long)a.tail_cap + BS32 / 64 - 1) / (BS32 / 64);
+  if (tb > slots) tb = slots;
+  TraceArgs b = a;
+  b.live_handoff = (unsigned)(tb * (BS32 / 64));
+  // a launch with no more packets than that needs no count
+  b.n_waves = a.n_packets <= b.live_handoff ? 0u : (unsigned)(nb * (BS32 / 64));
+  hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS32), lds, s, b);
+  if (a.tail) hipLaunchKernelGGL(tail, dim3((unsigned)tb), dim3(BS32), lds, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(ctx, std::string("trace launch: ") + hipGetErrorString(e));
