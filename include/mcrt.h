@@ -107,10 +107,13 @@ typedef struct {
                             diagonal), 1 block Jacobi on the theta lines of each radius
                             (tridiagonal blocks, solved exactly) (1); the grid-wide solver
                             uses the diagonal */
-  int64_t wave_events;   /* once every packet of a launch is handed out, packets that have
-                            had at least this many events move to a second launch that
-                            runs each with all 64 lanes of a wavefront (same draws, same
-                            events); 0 = never (2048).  Batched runs use each disk's value. */
+  int64_t wave_events;   /* once every packet of a launch is handed out and no
+                            more packets are live than the second launch has
+                            wavefronts, packets that have had at least this many
+                            events move to that launch, which runs each with all
+                            64 lanes of a wavefront (same draws, same events);
+                            0 = never (2048).  Batched runs use each disk's value
+                            and one live count over all disks. */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
