@@ -274,6 +274,7 @@ struct Pk {
   uint32_t cell_abs, cell_mrw;
   double E_seen, T_seen;
   int seg_seen;   // table segment of T_seen
+  float alpha, omega;  // extinction rho chi_k of the cell at bin k, and the albedo at k
   float lim_scale;  // 3 gamma / rho of the cell: the MRW limit is D rho times this
 };
 
@@ -459,6 +460,8 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       P.j = mu_row(L.mu2, n_mu, r2, P.an.A[2] * P.an.A[2]);
       set_anchor(P.an, L, n_mu, P.i, P.j);
       P.rho = M.rho[P.j];
+      P.alpha = (float)P.rho * L.chi[P.k];
+      P.omega = L.omega[P.k];
       P.lim_scale = lim_scale_of(P.rho);
       P.im = M.inv4pim[P.j];
       if (fixT) P.Tfix = fixT[P.j];
@@ -472,7 +475,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
     }
   } else {
     const int c = P.i * n_mu + P.j;
-    const float alpha = (float)P.rho * L.chi[P.k];
+    const float alpha = P.alpha;
     int face = 1;
     float sb = 0.0f, tau_b = 0.0f;
     // a flight shorter than the guaranteed distance to every face stays in
@@ -515,6 +518,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       if (entered) {
         int cn = P.i * n_mu + P.j;
         P.rho = M.rho[cn];
+        P.alpha = (float)P.rho * L.chi[P.k];
         P.lim_scale = lim_scale_of(P.rho);
         P.im = M.inv4pim[cn];
         if (fixT) P.Tfix = fixT[cn];
@@ -539,7 +543,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       P.dm_up += 1.00001f * sint;
       const double* fz = A.frozen_T;
       ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
-      if (rng.next() < L.omega[P.k]) {
+      if (rng.next() < P.omega) {
         ++P.pc_scat;
         iso32(rng, P.d);
       } else {
@@ -550,6 +554,8 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
         float xb = rng.next();
         iso32(rng, P.d);
         P.k = reemit_bin(E_old, A.eps, xb);
+        P.alpha = (float)P.rho * L.chi[P.k];
+        P.omega = L.omega[P.k];
       }
       ++P.n_int;
       if (A.mrw) {
@@ -600,6 +606,8 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           float xb = rng.next();
           iso32(rng, P.d);
           P.k = reemit_bin(E_old, dE, xb);
+          P.alpha = (float)P.rho * L.chi[P.k];
+          P.omega = L.omega[P.k];
           P.d_safe = 0.0f;
           P.dm_up = INFINITY;
           ++P.pc_mrw;
@@ -773,6 +781,8 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
           P.events = 0;
           P.pc_cross = P.pc_scat = P.pc_abs = P.pc_mrw = 0;
           P.rho = P.im = P.Tfix = 0.0;
+          P.alpha = 0.0f;
+          P.omega = L.omega[P.k];
           P.lim_scale = 0.0f;
           P.seg_seen = 0;
           P.Tc = -1.0;
