@@ -144,6 +144,7 @@ struct Pk64 {
   double Tfix;                       // the cell's fixed temperature (frozen or MRW field)
   double mrw_T, mrw_Drho, mrw_f, mrw_lim;  // MRW coefficients at mrw_T (mrw_f: its
   int mrw_seg, seg_seen;                    // fraction in segment mrw_seg); segment of T_seen
+  double alpha, omega;  // extinction rho chi_k of the cell at bin k, and the albedo at k
   // bounds of the distance to the cell boundary: d_safe below (a flight
   // shorter than it stays in the cell, so the face distances are not needed),
   // dm_up above (the last computed distance plus the path flown since: while
@@ -326,6 +327,8 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
       double r2 = (P.p[0] * P.p[0] + P.p[1] * P.p[1]) + P.p[2] * P.p[2];
       P.j = mu_row(L.mu2, n_mu, r2, P.p[2] * P.p[2]);
       P.rho = M.rho[P.j];
+      P.alpha = P.rho * L.chi[P.k];
+      P.omega = L.omega[P.k];
       P.im = M.inv4pim[P.j];
       if (fixT) P.Tfix = fixT[P.j];
       visit(P.j);
@@ -338,7 +341,7 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
     }
   } else {
     const int c = P.i * n_mu + P.j;
-    const double alpha = P.rho * L.chi[P.k];
+    const double alpha = P.alpha;
     int face = 1;
     double sb = 0.0, tau_b = 0.0;
     const bool inside = P.tau < alpha * P.d_safe;
@@ -378,6 +381,7 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
       if (entered) {
         int cn = P.i * n_mu + P.j;
         P.rho = M.rho[cn];
+        P.alpha = P.rho * L.chi[P.k];
         P.im = M.inv4pim[cn];
         if (fixT) P.Tfix = fixT[cn];
         visit(cn);
@@ -393,7 +397,7 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
       P.dm_up += 1.000001 * sint;
       const double* fz = A.frozen_T;
       ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
-      if (rng.next() < L.omega[P.k]) {
+      if (rng.next() < P.omega) {
         ++P.pc_scat;
         iso64(rng, P.d);
       } else {
@@ -404,6 +408,8 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
         double xb = rng.next();
         iso64(rng, P.d);
         P.k = fz ? reemit(-1.0, P.Tfix, xb) : reemit_after(E_old, A.eps, xb);
+        P.alpha = P.rho * L.chi[P.k];
+        P.omega = L.omega[P.k];
       }
       ++P.n_int;
       if (A.mrw) {
@@ -449,6 +455,8 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
           double xb = rng.next();
           iso64(rng, P.d);
           P.k = fz ? reemit(-1.0, P.Tfix, xb) : reemit_after(E_old, dE, xb);
+          P.alpha = P.rho * L.chi[P.k];
+          P.omega = L.omega[P.k];
           P.d_safe = 0.0;
           P.dm_up = INFINITY;
           ++P.pc_mrw;
@@ -621,6 +629,8 @@ __global__ void __launch_bounds__(BS64) trace_fp64_kernel(TraceArgs A) {
           P.events = 0;
           P.pc_cross = P.pc_scat = P.pc_abs = P.pc_mrw = 0;
           P.rho = P.im = P.Tfix = 0.0;
+          P.alpha = 0.0;
+          P.omega = L.omega[P.k];
           P.Tc = -1.0;
           P.mrw_T = -2.0;
           P.mrw_Drho = P.mrw_f = P.mrw_lim = 0.0;
