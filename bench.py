@@ -122,6 +122,10 @@ def parse():
                    help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--large-chunk", type=int, default=0,
                    help="with --large: packets per mcrt_trace call (0: all in one call)")
+    p.add_argument("--accuracy", type=int, default=0,
+                   help="only compare MRW gamma = 1/3/10 and PDA on/off runs of --packets "
+                        "packets with an FP64 no-MRW, no-PDA reference of this many packets, "
+                        "and exit")
     p.add_argument("--event-mix", action="store_true",
                    help="only fit the per-event cost of each event type from three albedos, "
                         "and exit")
@@ -357,6 +361,62 @@ def tail_probe(mcrt, W, torch):
     return out
 
 
+def accuracy(mcrt, W, torch, n_ref, n_run):
+    """Synthetic analogue of the paper's accuracy study (Sect. 4): on the step's
+    disk, runs of n_run packets with MRW at gamma = 1, 3, 10 (PDA on), with
+    gamma = 3 and no PDA, and with no MRW, against an FP64 reference of n_ref
+    packets with neither MRW nor PDA.  Reported over the cells the reference
+    entered at least 1000 times: the mass-weighted mean |T/T_ref - 1|, its
+    signed mean, and the same on the midplane row."""
+    import numpy as np
+    d, o = W.config("mrw_pda")
+    m = d.rho * W.cell_volumes(d)
+    ref = mcrt.Context(d, precision="fp64", mrw=False, n_T=o.n_T)
+    ref.reset()
+    t0 = time.perf_counter()
+    chunk = 2000000
+    for off in range(0, n_ref, chunk):
+        ref.trace(min(chunk, n_ref - off), o.seed + 99, n_total=n_ref, offset=off)
+        torch.cuda.synchronize()
+        log("accuracy: reference %d of %d packets (%.1f s)" % (min(off + chunk, n_ref), n_ref,
+                                                              time.perf_counter() - t0))
+    T_ref = ref.update_T().cpu().numpy()
+    vis_ref = ref.get(mcrt.GET_VISITS).cpu().numpy().view(np.uint32)
+    ok = (vis_ref >= 1000) & (T_ref > 0) & (m > 0)
+    mid = np.zeros_like(ok)
+    mid[0::d.n_mu] = True
+    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins", "reference":
+           {"packets": n_ref, "precision": "fp64", "mrw": False, "pda": False,
+            "s": time.perf_counter() - t0, "cells": int(ok.sum())}, "runs": []}
+    cases = [("no MRW, PDA", False, 3.0, True), ("MRW gamma=1, PDA", True, 1.0, True),
+             ("MRW gamma=3, PDA", True, 3.0, True), ("MRW gamma=10, PDA", True, 10.0, True),
+             ("MRW gamma=3, no PDA", True, 3.0, False)]
+    for name, mrw, gamma, pda in cases:
+        ctx = mcrt.Context(d, precision="fp32", mrw=mrw, gamma=gamma, n_int_min=o.n_int_min,
+                           pda_visits=o.pda_visits, n_T=o.n_T)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.reset()
+        ctx.trace(n_run, o.seed + 7)
+        T = ctx.update_T().clone()
+        if pda:
+            ctx.pda_solve()
+            T = ctx.get(mcrt.GET_T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        T = T.cpu().numpy()
+        rel = T / np.where(T_ref > 0, T_ref, 1.0) - 1.0
+        row = {"case": name, "packets": n_run, "s": dt}
+        for tag, sel in (("all", ok), ("midplane", ok & mid)):
+            if sel.any():
+                w = m[sel] / m[sel].sum()
+                row[tag] = {"mean_abs": float((np.abs(rel[sel]) * w).sum()),
+                            "mean_signed": float((rel[sel] * w).sum()), "cells": int(sel.sum())}
+        out["runs"].append(row)
+        log("accuracy: %s: %.1f s, mean |dT/T| %.4f" % (name, dt, row["all"]["mean_abs"]))
+    return out
+
+
 def event_mix(mcrt, W, torch):
     """Per-event cost by event type: the longest frozen-T walk (of 1e5
     packets) on the step's disk with albedo 0.1, 0.5 and 0.9 at the same
@@ -464,6 +524,10 @@ def main():
         return
     if a.event_mix:
         print(json.dumps({"event_mix": event_mix(mcrt, W, torch)}), flush=True)
+        return
+    if a.accuracy > 0:
+        print(json.dumps({"accuracy": accuracy(mcrt, W, torch, a.accuracy, a.packets)}),
+              flush=True)
         return
     if a.large > 0:
         print(json.dumps({"large": large(mcrt, W, torch, a.large, a.large_chunk)}), flush=True)
