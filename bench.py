@@ -11,7 +11,7 @@ midplane radial optical depth 1e5 (inputs synthetic and seeded).
 Printed: one JSON line with packets/s of the whole step, the roofline of the
 trace kernel (events x FP operations per event over the HIP-event duration of
 the kernel), the midplane-temperature error of the timed run against a
-reference run (FP64, no random walk, 10x the packets), the plain FP64 path on
+reference run (FP64, no random walk, 4x the packets), the plain FP64 path on
 the same step, the batched form over the 64-disk workload at reduced packet
 counts, the PDA and its adjoint on the 200 x 120 differentiation workload,
 and the CPU oracle timed on a bounded sample of the same step on this host.
