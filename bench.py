@@ -367,27 +367,39 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
     gamma = 3 and no PDA, and with no MRW, against an FP64 reference of n_ref
     packets with neither MRW nor PDA.  Reported over the cells the reference
     entered at least 1000 times: the mass-weighted mean |T/T_ref - 1|, its
-    signed mean, and the same on the midplane row."""
+    signed mean, its 5th and 95th percentiles, the photon noise 1/(4 sqrt N_abs)
+    of both runs (mass-weighted), and the same on the midplane row.  Runs are
+    traced in calls of at most 1e7 packets, one log line each."""
     import numpy as np
     d, o = W.config("mrw_pda")
     m = d.rho * W.cell_volumes(d)
+    chunk = 10000000
+
+    def trace_all(ctx, n, seed, tag):
+        t0 = time.perf_counter()
+        for off in range(0, n, chunk):
+            ctx.trace(min(chunk, n - off), seed, n_total=n, offset=off)
+            torch.cuda.synchronize()
+            log("accuracy: %s: %d of %d packets (%.1f s)" % (tag, min(off + chunk, n), n,
+                                                            time.perf_counter() - t0))
+
+    def noise(n_abs):
+        return 1.0 / (4.0 * np.sqrt(np.maximum(n_abs, 1)))
+
     ref = mcrt.Context(d, precision="fp64", mrw=False, n_T=o.n_T)
     ref.reset()
     t0 = time.perf_counter()
-    chunk = 2000000
-    for off in range(0, n_ref, chunk):
-        ref.trace(min(chunk, n_ref - off), o.seed + 99, n_total=n_ref, offset=off)
-        torch.cuda.synchronize()
-        log("accuracy: reference %d of %d packets (%.1f s)" % (min(off + chunk, n_ref), n_ref,
-                                                              time.perf_counter() - t0))
+    trace_all(ref, n_ref, o.seed + 99, "reference")
     T_ref = ref.update_T().cpu().numpy()
     vis_ref = ref.get(mcrt.GET_VISITS).cpu().numpy().view(np.uint32)
+    nz_ref = noise(ref.get(mcrt.GET_N_ABS).cpu().numpy())
     ok = (vis_ref >= 1000) & (T_ref > 0) & (m > 0)
     mid = np.zeros_like(ok)
     mid[0::d.n_mu] = True
     out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins", "reference":
            {"packets": n_ref, "precision": "fp64", "mrw": False, "pda": False,
             "s": time.perf_counter() - t0, "cells": int(ok.sum())}, "runs": []}
+    del ref
     cases = [("no MRW, PDA", False, 3.0, True), ("MRW gamma=1, PDA", True, 1.0, True),
              ("MRW gamma=3, PDA", True, 3.0, True), ("MRW gamma=10, PDA", True, 10.0, True),
              ("MRW gamma=3, no PDA", True, 3.0, False)]
@@ -397,23 +409,31 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ctx.reset()
-        ctx.trace(n_run, o.seed + 7)
+        trace_all(ctx, n_run, o.seed + 7, name)
         T = ctx.update_T().clone()
+        n_reg = 0
         if pda:
-            ctx.pda_solve()
+            n_reg = ctx.pda_solve()["n_region"]
             T = ctx.get(mcrt.GET_T)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         T = T.cpu().numpy()
+        nz = noise(ctx.get(mcrt.GET_N_ABS).cpu().numpy())
         rel = T / np.where(T_ref > 0, T_ref, 1.0) - 1.0
-        row = {"case": name, "packets": n_run, "s": dt}
+        row = {"case": name, "packets": n_run, "s": dt, "pda_cells": int(n_reg)}
         for tag, sel in (("all", ok), ("midplane", ok & mid)):
             if sel.any():
                 w = m[sel] / m[sel].sum()
                 row[tag] = {"mean_abs": float((np.abs(rel[sel]) * w).sum()),
-                            "mean_signed": float((rel[sel] * w).sum()), "cells": int(sel.sum())}
+                            "mean_signed": float((rel[sel] * w).sum()),
+                            "p05": float(np.percentile(rel[sel], 5)),
+                            "p95": float(np.percentile(rel[sel], 95)),
+                            "noise_run": float((nz[sel] * w).sum()),
+                            "noise_ref": float((nz_ref[sel] * w).sum()),
+                            "cells": int(sel.sum())}
         out["runs"].append(row)
         log("accuracy: %s: %.1f s, mean |dT/T| %.4f" % (name, dt, row["all"]["mean_abs"]))
+        del ctx
     return out
 
 
