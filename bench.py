@@ -11,7 +11,7 @@ midplane radial optical depth 1e5 (inputs synthetic and seeded).
 Printed: one JSON line with packets/s of the whole step, the roofline of the
 trace kernel (events x FP operations per event over the HIP-event duration of
 the kernel), the midplane-temperature error of the timed run against a
-reference run (FP64, no random walk, 4x the packets), the plain FP64 path on
+reference run (FP64, no random walk, 10x the packets), the plain FP64 path on
 the same step, the batched form over the 64-disk workload at reduced packet
 counts, the PDA and its adjoint on the 200 x 120 differentiation workload,
 and the CPU oracle timed on a bounded sample of the same step on this host.
@@ -94,7 +94,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     p.add_argument("--packets", type=int, default=1000000)
-    p.add_argument("--ref-factor", type=int, default=4,
+    p.add_argument("--ref-factor", type=int, default=10,
                    help="packets of the reference run (FP64, no MRW) as a multiple of --packets")
     p.add_argument("--batch-scale", type=float, default=0.01,
                    help="packets of the 64-disk batched workload as a fraction of its draws")
@@ -656,13 +656,14 @@ def main():
         ref = mcrt.Context(disk, precision="fp64", mrw=False, pda_visits=o.pda_visits, n_T=o.n_T)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        # one run of nref packets, traced in chunks of N (same tallies)
+        # one run of nref packets, traced in calls of at most 1e7 (same tallies)
         ref.reset()
-        for k in range(a.ref_factor):
-            ref.trace(N, o.seed + 4242, n_total=nref, offset=k * N)
+        chunk = 10000000
+        for off in range(0, nref, chunk):
+            ref.trace(min(chunk, nref - off), o.seed + 4242, n_total=nref, offset=off)
             torch.cuda.synchronize()
-            log("reference chunk %d/%d done (%.1f s)" % (k + 1, a.ref_factor,
-                                                          time.perf_counter() - t0))
+            log("reference: %d of %d packets (%.1f s)" % (min(off + chunk, nref), nref,
+                                                         time.perf_counter() - t0))
         ref.update_T()
         ref.pda_solve()
         torch.cuda.synchronize()
