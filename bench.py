@@ -12,8 +12,9 @@ Printed: one JSON line with packets/s of the whole step, the roofline of the
 trace kernel (events x FP operations per event over the HIP-event duration of
 the kernel), the midplane-temperature error of the timed run against a
 reference run (FP64, no random walk, 10x the packets), the plain FP64 path on
-the same step, the batched form over the 64-disk workload at reduced packet
-counts, the PDA and its adjoint on the 200 x 120 differentiation workload,
+the same step, one step of 1e8 packets in one call (the count at which the
+midplane-T photon noise is ~1 %), the batched form over the 64-disk workload at
+reduced packet counts, the PDA and its adjoint on the 200 x 120 differentiation workload,
 and the CPU oracle timed on a bounded sample of the same step on this host.
 Stage lines go to stderr.
 """
@@ -101,6 +102,9 @@ def parse():
     p.add_argument("--ensemble", type=int, default=16,
                    help="independent passes of the same step in one batched launch")
     p.add_argument("--cpu-packets", type=int, default=1000000)
+    p.add_argument("--at-1pct", type=int, default=100000000,
+                   help="packets of one extra step in one call, the count at which the "
+                        "midplane-T noise is ~1 %% (0: skip)")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-ref", action="store_true")
     p.add_argument("--no-batch", action="store_true")
@@ -621,7 +625,7 @@ def main():
         "dtype": "f64" if a.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": "disk 1e-2 Msun, 100 r x 60 theta cells, 100 lambda bins, "
-                               "1e6 packets, MRW gamma=3, PDA on cells with <100 visits",
+                               "%.3g packets, MRW gamma=3, PDA on cells with <100 visits" % N,
                    "precision": a.precision, "packets_per_step": N},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
@@ -637,6 +641,18 @@ def main():
     }
     if tuned:
         out["autotune"] = {k: tuned[k] for k in ("trace_s", "pda_s", "pda_iters", "n_packets")}
+    if a.at_1pct > 0:
+        n1 = a.at_1pct
+        log("one step of %d packets in one call" % n1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_once(ctx, n1, o.seed + 555)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["at_1pct_midplane"] = {
+            "value": n1 / dt, "unit": "photon packets/s", "packets": n1, "s": dt, "steps": 1,
+            "basis": "the packet count at which each run's midplane-T photon noise is ~1 % "
+                     "(bench.py --accuracy 100000000 --packets 100000000)"}
     T64 = None
     if not a.no_plain and a.precision != "fp64":
         log("plain FP64 step")
