@@ -49,36 +49,33 @@ __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_a
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Face distances (as exit_sphere, enter_sphere, exit_cone) with those.
+// Both sides of every case are evaluated and the result selected, which
+// gives the same values as branching: uniform branches cost a compare, a
+// mask operation and a jump each, a select one instruction.  The discarded
+// side may divide by zero; its value is never used.
 __device__ __forceinline__ float exit_sphere32(float pd, float c) {
-  float disc = pd * pd - c;
-  if (c >= 0.0f && (pd > 0.0f || disc < 0.0f)) return 0.0f;
-  disc = disc < 0.0f ? 0.0f : disc;
-  const float sq = fsqrt(disc);
-  return pd > 0.0f ? -fdiv(c, pd + sq) : -pd + sq;
+  const float disc = pd * pd - c;
+  const float sq = fsqrt(fmaxf(disc, 0.0f));
+  const float v = pd > 0.0f ? -fdiv(c, pd + sq) : -pd + sq;
+  return (c >= 0.0f && (pd > 0.0f || disc < 0.0f)) ? 0.0f : v;
 }
 __device__ __forceinline__ float enter_sphere32(float pd, float c) {
-  if (c <= 0.0f && pd < 0.0f) return 0.0f;
-  if (pd >= 0.0f) return -1.0f;
   const float disc = pd * pd - c;
-  if (disc < 0.0f) return -1.0f;
-  return fdiv(c, -pd + fsqrt(disc));
+  float v = fdiv(c, -pd + fsqrt(fmaxf(disc, 0.0f)));
+  v = (pd >= 0.0f || disc < 0.0f) ? -1.0f : v;
+  return (c <= 0.0f && pd < 0.0f) ? 0.0f : v;
 }
 __device__ __forceinline__ float exit_cone32(float A, float B, float C, bool toward_pole) {
-  if (toward_pole) {
-    if (C >= 0.0f && B > 0.0f) return 0.0f;
-  } else {
-    if (C <= 0.0f && B < 0.0f) return 0.0f;
-  }
+  const bool at_face = toward_pole ? (C >= 0.0f && B > 0.0f) : (C <= 0.0f && B < 0.0f);
   const float disc = B * B - A * C;
-  if (disc < 0.0f) return -1.0f;
-  const float sq = fsqrt(disc);
-  float v;
-  if (toward_pole)
-    v = (B > 0.0f) ? fdiv(C, -B - sq) : fdiv(-B + sq, A);
-  else
-    v = (B < 0.0f) ? fdiv(C, -B + sq) : fdiv(-B - sq, A);
-  if (!(v > 0.0f) || __builtin_isinf(v)) return -1.0f;
-  return v;
+  const float sq = fsqrt(fmaxf(disc, 0.0f));
+  // the root of the quadratic in the stable form for the sign of B
+  const bool first = toward_pole ? B > 0.0f : B < 0.0f;
+  const float num = first ? C : (toward_pole ? -B + sq : -B - sq);
+  const float den = first ? (toward_pole ? -B - sq : -B + sq) : A;
+  const float v = fdiv(num, den);
+  const bool none = disc < 0.0f || !(v > 0.0f) || __builtin_isinf(v);
+  return at_face ? 0.0f : none ? -1.0f : v;
 }
 
 // Per-anchor constants of the four faces of cell (i, j).
@@ -125,17 +122,18 @@ __device__ __forceinline__ float boundary32(const Anchor& a, const Lds32& L, int
   float dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
   float zq = a.Af[2] * q[2];
   float qz2 = q[2] * q[2];
-  if (j >= 1) {
+  // the cone below (none in the midplane row) and above (none in the polar row)
+  {
     float m2 = (float)L.mu2[j];
     float C = a.L_lo + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
     s = exit_cone32(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, false);
-    if (s >= 0.0f && s < best) { best = s; face = 2; }
+    if (j >= 1 && s >= 0.0f && s < best) { best = s; face = 2; }
   }
-  if (j + 1 < n_mu) {
+  {
     float m2 = (float)L.mu2[j + 1];
     float C = a.L_hi + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
     s = exit_cone32(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, true);
-    if (s >= 0.0f && s < best) { best = s; face = 3; }
+    if (j + 1 < n_mu && s >= 0.0f && s < best) { best = s; face = 3; }
   }
   return best;
 }
@@ -154,15 +152,17 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   float dmin = fminf(fdiv(a.K_in + 2.0f * Aq + qq, r + ri), -fdiv(a.K_out + 2.0f * Aq + qq, r + ro));
   float az = fabsf(z);
   float zq = a.Af[2] * q[2], qz2 = q[2] * q[2];
-  if (j >= 1) {
+  {
     float m2 = (float)L.mu2[j];
     float f = a.L_lo + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    dmin = fminf(dmin, fdiv(f, L.smu32[j] * az + L.mu32[j] * R));
+    const float dl = fdiv(f, L.smu32[j] * az + L.mu32[j] * R);
+    dmin = j >= 1 ? fminf(dmin, dl) : dmin;
   }
-  if (j + 1 < n_mu) {
+  {
     float m2 = (float)L.mu2[j + 1];
     float f = a.L_hi + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
-    dmin = fminf(dmin, -fdiv(f, L.smu32[j + 1] * az + L.mu32[j + 1] * R));
+    const float dh = -fdiv(f, L.smu32[j + 1] * az + L.mu32[j + 1] * R);
+    dmin = j + 1 < n_mu ? fminf(dmin, dh) : dmin;
   }
   return dmin > 0.0f ? dmin : 0.0f;
 }
@@ -290,8 +290,8 @@ static_assert(sizeof(TailState32) <= TAIL_STATE_BYTES, "hand-off slot");
 // Once every packet of a launch has been handed out, packets that are still
 // going after wave_events events are saved and continued by a second launch
 // in which a whole wavefront runs each of them: the control flow is uniform,
-// lane l generates Philox block blk0 + l so one pass of the generator yields
-// 256 draws, and the reemission bin is found by a 64-wide ballot.  A lone
+// the lanes generate 64 draws in one pass of the generator, and the
+// reemission bin is found by a 64-wide ballot.  A lone
 // lane issues about one instruction per ten cycles, so these cuts in
 // instruction count are what shortens the longest random walks, which set
 // the length of a launch.
@@ -303,28 +303,31 @@ __device__ __forceinline__ double wave_bcast0(double v) {
 }
 
 // The stream of one packet (the same draws as Rng32) served to a wavefront:
-// lane l holds block blk0 + l of the stream and, for each of its four words,
-// the draw u and the functions of it that the transport takes (optical
-// depth, direction cosine and sine terms), so a draw costs a read from its
-// lane instead of a generator call and transcendentals on the chain.
+// the buffer is the 64 words of Philox blocks blk0 .. blk0 + 15, word p held
+// by lane p (lanes 4b .. 4b + 3 generate block blk0 + b and keep one word
+// each), with the functions of it that the transport takes (optical depth,
+// direction cosine and sine terms).  A draw is then one read from a fixed
+// register of a lane given by a uniform index, with no choice among
+// registers, and the generator and transcendentals run once per 64 draws
+// off the chain.
 struct WaveRng {
   uint64_t pid;
   uint32_t k0, k1;
-  uint32_t blk0;  // block held by lane 0
-  int pos;        // next word of the buffer, 0..255
+  uint32_t blk0;  // block of buffer words 0..3
+  int pos;        // next word of the buffer, 0..63
   uint64_t nd;    // draws so far
-  float u[4], tau[4], st[4], sn[4], cs[4];  // this lane's block
+  float u, tau, st, sn, cs;  // this lane's word
 
   __device__ __forceinline__ void fill() {
-    uint32_t c[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), blk0 + (uint32_t)__lane_id(), 0u};
+    const uint32_t lane = (uint32_t)__lane_id();
+    uint32_t c[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), blk0 + (lane >> 2), 0u};
     philox4x32_10(c[0], c[1], c[2], c[3], k0, k1);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      u[a] = Rng32::unit(c[a]);
-      tau[a] = tau_of(u[a]);
-      st[a] = iso_st(u[a]);
-      iso_phi(u[a], sn[a], cs[a]);
-    }
+    const uint32_t a = lane & 3u;
+    const uint32_t w = a == 0u ? c[0] : a == 1u ? c[1] : a == 2u ? c[2] : c[3];
+    u = Rng32::unit(w);
+    tau = tau_of(u);
+    st = iso_st(u);
+    iso_phi(u, sn, cs);
   }
   __device__ __forceinline__ void init(const Rng32& r) {
     pid = r.pid;
@@ -335,17 +338,15 @@ struct WaveRng {
     pos = (int)(nd & 3);
     fill();
   }
-  // value of word p of the buffer from table v
-  __device__ __forceinline__ float at(const float* v, int p) const {
-    const int comp = p & 3;
-    const float x = comp == 0 ? v[0] : comp == 1 ? v[1] : comp == 2 ? v[2] : v[3];
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), p >> 2));
+  // value of word p of the buffer from this lane's x
+  __device__ __forceinline__ float at(float x, int p) const {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), p));
   }
   // at least n draws left in the buffer: else restart it at the block of
   // the next draw (called where a segment of at most n draws begins, so the
   // generator is inlined in two places only)
   __device__ __forceinline__ void ensure(int n) {
-    if (pos + n > 256) {
+    if (pos + n > 64) {
       blk0 += (uint32_t)(pos >> 2);
       pos &= 3;
       fill();
