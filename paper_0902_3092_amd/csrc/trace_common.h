@@ -225,11 +225,11 @@ __device__ __forceinline__ R exit_cone(R A, R B, R C, bool toward_pole) {
   R disc = B * B - A * C;
   if (disc < (R)0) return (R)-1;
   R sq = sqrt(disc);
-  R v;
-  if (toward_pole)
-    v = (B > (R)0) ? C / (-B - sq) : (-B + sq) / A;
-  else
-    v = (B < (R)0) ? C / (-B + sq) : (-B - sq) / A;
+  // the root in the stable form for the sign of B, one division either way
+  const bool first = toward_pole ? B > (R)0 : B < (R)0;
+  const R num = first ? C : (toward_pole ? -B + sq : -B - sq);
+  const R den = first ? (toward_pole ? -B - sq : -B + sq) : A;
+  const R v = num / den;
   if (!(v > (R)0) || __builtin_isinf(v)) return (R)-1;
   return v;
 }

@@ -168,7 +168,7 @@ static_assert(sizeof(TailState64) <= TAIL_STATE_BYTES, "hand-off slot");
 // ------------------------------------------------------ whole-wave mode
 // As in the FP32 tracker: once all packets are handed out, long packets are
 // continued by a second launch, a whole wavefront each (uniform control
-// flow, one Philox pass for 128 draws with their logarithms, square roots
+// flow, one Philox pass for 64 draws with their logarithms, square roots
 // and sines computed lane-parallel, 64-wide reemission search).
 __device__ __forceinline__ double bcd0(double v) {
   const long long x = __double_as_longlong(v);
@@ -183,29 +183,28 @@ __device__ __forceinline__ double bcd(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One packet's stream (the same draws as Rng64) for a wavefront: lane l holds
-// block blk0 + l, i.e. draws 2 (blk0 + l) and 2 (blk0 + l) + 1.
+// One packet's stream (the same draws as Rng64) for a wavefront: the buffer is
+// the 64 draws of Philox blocks blk0 .. blk0 + 31, draw p held by lane p
+// (lanes 2b and 2b + 1 generate block blk0 + b and keep one draw each), so a
+// draw is read from a fixed register at a uniform lane index.
 struct WaveRng64 {
   uint64_t pid;
   uint32_t k0, k1;
   uint64_t blk0;
-  int pos;        // next draw of the buffer, 0..127
+  int pos;        // next draw of the buffer, 0..63
   uint64_t nd;    // draws so far
-  double u[2], tau[2], st[2], sn[2], cs[2];
+  double u, tau, st, sn, cs;  // this lane's draw
 
   __device__ __forceinline__ void fill() {
-    const uint64_t blk = blk0 + (uint64_t)__lane_id();
+    const uint32_t lane = (uint32_t)__lane_id();
+    const uint64_t blk = blk0 + (uint64_t)(lane >> 1);
     uint32_t c0 = (uint32_t)pid, c1 = (uint32_t)(pid >> 32), c2 = (uint32_t)blk,
              c3 = (uint32_t)(blk >> 32);
     philox4x32_10(c0, c1, c2, c3, k0, k1);
-    u[0] = Rng64::unit(c0, c1);
-    u[1] = Rng64::unit(c2, c3);
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      tau[a] = tau_of64(u[a]);
-      st[a] = iso_st64(u[a]);
-      iso_phi64(u[a], sn[a], cs[a]);
-    }
+    u = (lane & 1u) ? Rng64::unit(c2, c3) : Rng64::unit(c0, c1);
+    tau = tau_of64(u);
+    st = iso_st64(u);
+    iso_phi64(u, sn, cs);
   }
   __device__ __forceinline__ void init(const Rng64& r) {
     pid = r.pid;
@@ -216,14 +215,11 @@ struct WaveRng64 {
     pos = (int)(nd & 1);
     fill();
   }
-  __device__ __forceinline__ double at(const double* v, int p) const {
-    const double x = (p & 1) ? v[1] : v[0];
-    return bcd(x, p >> 1);
-  }
+  __device__ __forceinline__ double at(double x, int p) const { return bcd(x, p); }
   // at least n draws left in the buffer: else restart it at the block of
   // the next draw (the generator is inlined where a segment begins only)
   __device__ __forceinline__ void ensure(int n) {
-    if (pos + n > 128) {
+    if (pos + n > 64) {
       blk0 += (uint64_t)(pos >> 1);
       pos &= 1;
       fill();
