@@ -31,6 +31,7 @@ constexpr int BS32 = 512;
 struct Lds32 {
   double *r2, *mu2, *mrw_tab;
   float *mu32, *smu32, *star_cdf, *chi, *omega;
+  float *re32, *mu2f;  // FP32 radial edges and squared cone cosines
   TabView tv;
   const float* cdf;
   uint32_t* vis;  // per-workgroup visit histogram [n_cells], or null
@@ -39,7 +40,8 @@ struct Lds32 {
 // Bytes of the tables; a visit histogram, when used, follows at this offset.
 __host__ __device__ inline size_t lds32_bytes(int n_r, int n_mu, int n_T, int nl, bool with_cdf) {
   size_t dbl = (size_t)(n_r + 1) + (n_mu + 1) + MRW_TAB_N + 6 * (size_t)n_T;
-  size_t flt = (size_t)2 * (n_mu + 1) + (size_t)3 * nl + (with_cdf ? (size_t)n_T * nl : 0);
+  size_t flt = (size_t)3 * (n_mu + 1) + (size_t)(n_r + 1) + (size_t)3 * nl +
+               (with_cdf ? (size_t)n_T * nl : 0);
   return dbl * 8 + N_GUIDE * 4 + ((flt * 4 + 7) & ~(size_t)7);
 }
 
@@ -124,13 +126,13 @@ __device__ __forceinline__ float boundary32(const Anchor& a, const Lds32& L, int
   float qz2 = q[2] * q[2];
   // the cone below (none in the midplane row) and above (none in the polar row)
   {
-    float m2 = (float)L.mu2[j];
+    float m2 = L.mu2f[j];
     float C = a.L_lo + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
     s = exit_cone32(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, false);
     if (j >= 1 && s >= 0.0f && s < best) { best = s; face = 2; }
   }
   {
-    float m2 = (float)L.mu2[j + 1];
+    float m2 = L.mu2f[j + 1];
     float C = a.L_hi + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
     s = exit_cone32(d[2] * d[2] - m2 * dd, z * d[2] - m2 * pd, C, true);
     if (j + 1 < n_mu && s >= 0.0f && s < best) { best = s; face = 3; }
@@ -148,18 +150,18 @@ __device__ __forceinline__ float min_boundary32(const Anchor& a, const Lds32& L,
   float x = a.Af[0] + q[0], y = a.Af[1] + q[1], z = a.Af[2] + q[2];
   float R = fsqrt(x * x + y * y);
   float r = fsqrt(R * R + z * z);
-  float ri = fsqrt((float)L.r2[i]), ro = fsqrt((float)L.r2[i + 1]);
+  float ri = L.re32[i], ro = L.re32[i + 1];
   float dmin = fminf(fdiv(a.K_in + 2.0f * Aq + qq, r + ri), -fdiv(a.K_out + 2.0f * Aq + qq, r + ro));
   float az = fabsf(z);
   float zq = a.Af[2] * q[2], qz2 = q[2] * q[2];
   {
-    float m2 = (float)L.mu2[j];
+    float m2 = L.mu2f[j];
     float f = a.L_lo + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
     const float dl = fdiv(f, L.smu32[j] * az + L.mu32[j] * R);
     dmin = j >= 1 ? fminf(dmin, dl) : dmin;
   }
   {
-    float m2 = (float)L.mu2[j + 1];
+    float m2 = L.mu2f[j + 1];
     float f = a.L_hi + 2.0f * (zq - m2 * Aq) + (qz2 - m2 * qq);
     const float dh = -fdiv(f, L.smu32[j + 1] * az + L.mu32[j + 1] * R);
     dmin = j + 1 < n_mu ? fminf(dmin, dh) : dmin;
@@ -709,6 +711,8 @@ __device__ __forceinline__ Lds32 setup_lds32(const TraceArgs& A) {
     takef(L.star_cdf, nl, [&](int a) { return M.star_cdf32[a]; });
     takef(L.chi, nl, [&](int a) { return M.chi32[a]; });
     takef(L.omega, nl, [&](int a) { return M.omega32[a]; });
+    takef(L.re32, n_r + 1, [&](int a) { return (float)M.r_edges[a]; });
+    takef(L.mu2f, n_mu + 1, [&](int a) { return (float)M.mu2[a]; });
     if (CDF_LDS) {
       float* c = f;
       for (int a = threadIdx.x; a < n_T * nl; a += blockDim.x) c[a] = M.cdf32[a];
