@@ -316,8 +316,7 @@ struct WaveRng {
   uint64_t pid;
   uint32_t k0, k1;
   uint32_t blk0;  // block of buffer words 0..3
-  int pos;        // next word of the buffer, 0..63
-  uint64_t nd;    // draws so far
+  int pos;        // next word of the buffer, 0..63 (the stream's draw 4 blk0 + pos)
   float u, tau, st, sn, cs;  // this lane's word
 
   __device__ __forceinline__ void fill() {
@@ -335,7 +334,7 @@ struct WaveRng {
     pid = r.pid;
     k0 = r.k0;
     k1 = r.k1;
-    nd = (uint64_t)r.draws();  // index of the next word of the stream
+    const uint64_t nd = (uint64_t)r.draws();  // index of the next word of the stream
     blk0 = (uint32_t)(nd >> 2);
     pos = (int)(nd & 3);
     fill();
@@ -354,10 +353,7 @@ struct WaveRng {
       fill();
     }
   }
-  __device__ __forceinline__ int take() {
-    ++nd;
-    return pos++;
-  }
+  __device__ __forceinline__ int take() { return pos++; }
   __device__ __forceinline__ float next() { return at(u, take()); }
   __device__ __forceinline__ float next_tau() { return at(tau, take()); }
   __device__ __forceinline__ void next_iso(float d[3]) {
@@ -369,7 +365,7 @@ struct WaveRng {
     d[1] = s * sn_;
     d[2] = w;
   }
-  __device__ __forceinline__ uint64_t draws() const { return nd; }
+  __device__ __forceinline__ uint64_t draws() const { return (uint64_t)blk0 * 4u + (uint64_t)pos; }
 };
 
 __device__ __forceinline__ void iso32(WaveRng& r, float d[3]) { r.next_iso(d); }

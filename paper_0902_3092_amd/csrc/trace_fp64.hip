@@ -191,8 +191,7 @@ struct WaveRng64 {
   uint64_t pid;
   uint32_t k0, k1;
   uint64_t blk0;
-  int pos;        // next draw of the buffer, 0..63
-  uint64_t nd;    // draws so far
+  int pos;        // next draw of the buffer, 0..63 (the stream's draw 2 blk0 + pos)
   double u, tau, st, sn, cs;  // this lane's draw
 
   __device__ __forceinline__ void fill() {
@@ -210,7 +209,7 @@ struct WaveRng64 {
     pid = r.pid;
     k0 = r.k0;
     k1 = r.k1;
-    nd = r.d;  // index of the next draw
+    const uint64_t nd = r.d;  // index of the next draw
     blk0 = nd >> 1;
     pos = (int)(nd & 1);
     fill();
@@ -225,10 +224,7 @@ struct WaveRng64 {
       fill();
     }
   }
-  __device__ __forceinline__ int take() {
-    ++nd;
-    return pos++;
-  }
+  __device__ __forceinline__ int take() { return pos++; }
   __device__ __forceinline__ double next() { return at(u, take()); }
   __device__ __forceinline__ double next_tau() { return at(tau, take()); }
   __device__ __forceinline__ void next_iso(double d[3]) {
@@ -240,7 +236,7 @@ struct WaveRng64 {
     d[1] = s * sn_;
     d[2] = w;
   }
-  __device__ __forceinline__ uint64_t nd_value() const { return nd; }
+  __device__ __forceinline__ uint64_t nd_value() const { return blk0 * 2u + (uint64_t)pos; }
 };
 
 __device__ __forceinline__ void iso64(WaveRng64& r, double d[3]) { r.next_iso(d); }
