@@ -72,6 +72,19 @@ __device__ __forceinline__ double T_of_g_seg(const TabView& t, double g, int& n)
   return t.Tn[n] + (g - t.G[n]) * t.g_slope[n];
 }
 
+// T_of_g_seg with a guess of the segment (the one of a nearby g): when
+// G[h] <= g < G[h+1] the segment is h, read in one round of table loads;
+// otherwise the guide search.  The same n and T as T_of_g_seg.
+__device__ __forceinline__ double T_of_g_seg_near(const TabView& t, double g, int h, int& n) {
+  if (g > 0.0 && h >= 0 && h <= t.n_T - 2) {
+    const double Gh = t.G[h], Gh1 = t.G[h + 1], Th = t.Tn[h], Sh = t.g_slope[h];
+    if (Gh <= g && g < Gh1) {
+      n = h;
+      return Th + (g - Gh) * Sh;
+    }
+  }
+  return T_of_g_seg(t, g, n);
+}
 // Reemission bin from the difference of the cumulative emission spectra at
 // T_new and T_old (linear in T between nodes); T_old < 0: the full spectrum
 // at T_new.  Smallest k with D(k) > xi * D(n_lambda - 1).

@@ -291,10 +291,10 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
       T_old = P.T_seen;
       n_old = P.seg_seen;
     } else {
-      T_old = T_of_g_seg(L.tv, E_old * P.im, n_old);
+      T_old = T_of_g_seg_near(L.tv, E_old * P.im, P.seg_seen, n_old);
     }
     const double E_new = E_old + dE;
-    const double T_new = T_of_g_seg(L.tv, E_new * P.im, n_new);
+    const double T_new = T_of_g_seg_near(L.tv, E_new * P.im, n_old, n_new);
     P.E_seen = E_new;
     P.T_seen = T_new;
     P.seg_seen = n_new;
