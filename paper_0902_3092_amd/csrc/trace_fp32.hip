@@ -272,7 +272,8 @@ struct Pk {
                   // (while it is within the MRW limit the criterion cannot hold)
   // absorptions and MRW steps in this stay in the cell, added to the tallies
   // when the packet leaves it; the cell's tally after this packet's last
-  // deposit and its temperature (reused when nobody deposited in between)
+  // deposit (or as last read) and its temperature (reused when nobody
+  // deposited in between)
   uint32_t cell_abs, cell_mrw;
   double E_seen, T_seen;
   int seg_seen;   // table segment of T_seen
@@ -573,9 +574,18 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           double T_here;
           if (fixT) T_here = P.Tfix;
           else {
-            if (P.Tc < 0.0)
-              P.Tc = T_of_g(L.tv, __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT) * P.im);
+            if (P.Tc < 0.0) {
+              // the cell's running T from its tally, kept as the last tally
+              // seen so the coefficients and the next reemission reuse its
+              // segment (a neighbouring cell's segment is the first guess)
+              const double E_c = __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+              int n_c;
+              P.Tc = T_of_g_seg_near(L.tv, E_c * P.im, P.seg_seen, n_c);
+              P.E_seen = E_c;
+              P.T_seen = P.Tc;
+              P.seg_seen = n_c;
+            }
             T_here = P.Tc;
           }
           if (T_here != P.mrw_T) {  // MRW coefficients of this cell at this T
