@@ -43,7 +43,8 @@ class _Model(C.Structure):
     _fields_ = [("n_r", C.c_int), ("n_mu", C.c_int), ("n_lambda", C.c_int),
                 ("r_edges", C.c_void_p), ("mu_edges", C.c_void_p), ("rho", C.c_void_p),
                 ("lambda_edges", C.c_void_p), ("kappa_abs", C.c_void_p),
-                ("kappa_sca", C.c_void_p), ("T_star", C.c_double), ("R_star", C.c_double)]
+                ("kappa_sca", C.c_void_p), ("T_star", C.c_double), ("R_star", C.c_double),
+                ("g_asym", C.c_double)]
 
 
 class _Tables(C.Structure):
@@ -73,6 +74,8 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         vp, i64, u64, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_double
         L.ora_philox4x32_10.argtypes = [vp, vp]
+        L.ora_scatter_dirs.argtypes = [dbl, vp, vp, vp, C.c_int]
+        L.ora_scatter_dirs.restype = None
         L.ora_uniforms.argtypes = [u64, u64, u64, i64, vp]
         L.ora_planck_bins.argtypes = [vp, C.c_int, dbl, vp, vp]
         L.ora_build_tables.argtypes = [vp, vp]
@@ -115,6 +118,16 @@ def uniforms(seed: int, pid: int, d0: int, n: int) -> np.ndarray:
     return out
 
 
+def scatter_dirs(g: float, u, din) -> np.ndarray:
+    """Directions after one scattering each with asymmetry parameter g, from
+    the draw pairs u [n, 2] and incoming directions din [n, 3]."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    din = np.ascontiguousarray(din, dtype=np.float64)
+    out = np.empty_like(din)
+    lib().ora_scatter_dirs(float(g), _p(u), _p(din), _p(out), int(len(din)))
+    return out
+
+
 def planck_bins(lambda_edges, T):
     le = np.ascontiguousarray(lambda_edges, dtype=np.float64)
     nl = len(le) - 1
@@ -135,7 +148,7 @@ class Oracle:
     """The oracle bound to one disk model (any object with the Disk fields)."""
 
     def __init__(self, disk, n_T: int = 256, T_lo: float = 1.0, T_hi: float = 1.0e4,
-                 rho=None):
+                 rho=None, g_asym: float = 0.0):
         self.disk = disk
         f = np.asarray(disk.mass_frac, dtype=np.float64)
         self.kabs = np.ascontiguousarray((f[:, None] * np.asarray(disk.kappa_abs)).sum(0))
@@ -148,7 +161,9 @@ class Oracle:
         self.n_cells = self.n_r * self.n_mu
         self.model = _Model(self.n_r, self.n_mu, self.n_lambda, _p(self.r_edges),
                             _p(self.mu_edges), _p(self.rho), _p(self.lam), _p(self.kabs),
-                            _p(self.ksca), float(disk.T_star), float(disk.R_star))
+                            _p(self.ksca), float(disk.T_star), float(disk.R_star),
+                            float(g_asym))
+        self.g_asym = float(g_asym)
         nl = self.n_lambda
         self.T_nodes = np.zeros(n_T)
         self.cdf = np.zeros((n_T, nl))

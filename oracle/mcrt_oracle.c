@@ -153,20 +153,24 @@ int ora_build_tables(const ora_model* m, ora_tables* t) {
     }
     if (n == 0) continue;
     /* eq:eta nu iter: eta_k <- kappa_k dB_k * (sum eta kappa/chi)/(sum eta)
-     *                         + (sigma_k/chi_k) eta_k, from eta = kappa dB */
+     *                         + (sigma_k/chi_k) eta_k, from eta = kappa dB.
+     * Anisotropic scattering enters the diffusion quantities through the
+     * isotropic equivalent sigma' = (1 - g) sigma (Sect. 2.2.3). */
+    const double sim = 1.0 - m->g_asym;
     for (int k = 0; k < nl; ++k) eta[k] = m->kappa_abs[k] * dBb[k];
     int it;
     for (it = 0; it < 20000; ++it) {
       double num = 0.0, den = 0.0;
       for (int k = 0; k < nl; ++k) {
-        double chi = m->kappa_abs[k] + m->kappa_sca[k];
+        double chi = m->kappa_abs[k] + m->kappa_sca[k] * sim;
         num += eta[k] * m->kappa_abs[k] / chi;
         den += eta[k];
       }
       double ratio = num / den, change = 0.0;
       for (int k = 0; k < nl; ++k) {
-        double chi = m->kappa_abs[k] + m->kappa_sca[k];
-        eta_new[k] = m->kappa_abs[k] * dBb[k] * ratio + (m->kappa_sca[k] / chi) * eta[k];
+        double sca = m->kappa_sca[k] * sim;
+        double chi = m->kappa_abs[k] + sca;
+        eta_new[k] = m->kappa_abs[k] * dBb[k] * ratio + (sca / chi) * eta[k];
         double rel = fabs(eta_new[k] - eta[k]) / (fabs(eta_new[k]) + 1e-300);
         if (eta_new[k] != 0.0 && rel > change) change = rel;
       }
@@ -177,7 +181,7 @@ int ora_build_tables(const ora_model* m, ora_tables* t) {
     /* eq:avd, eq:avd2 (per unit rho), eq:diffusion coeff, kappa-bar */
     double s_eta = 0.0, s_d = 0.0, s_d2 = 0.0, s_kc = 0.0, s_ic = 0.0;
     for (int k = 0; k < nl; ++k) {
-      double chi = m->kappa_abs[k] + m->kappa_sca[k];
+      double chi = m->kappa_abs[k] + m->kappa_sca[k] * sim;
       s_eta += eta[k];
       s_d += eta[k] / chi;
       s_d2 += eta[k] / (chi * chi);
@@ -475,6 +479,54 @@ static void iso_dir(rng_t* r, double d[3]) {
   d[2] = w;
 }
 
+/* New direction after a scattering with asymmetry parameter g, from two
+ * draws.  g = 0: isotropic, as iso_dir.  Otherwise the cosine of the
+ * scattering angle follows the Henyey-Greenstein phase function, from the
+ * inverse of its cumulative distribution, and the azimuth is uniform; the
+ * new direction is that rotation of d. */
+static void scatter_dir_u(double g, double u1, double u2, double d[3]) {
+  double ph = 2.0 * PI * u2;
+  if (g == 0.0) {
+    double w = 2.0 * u1 - 1.0, st = sqrt(fmax(0.0, 1.0 - w * w));
+    d[0] = st * cos(ph);
+    d[1] = st * sin(ph);
+    d[2] = w;
+    return;
+  }
+  double q = (1.0 - g * g) / (1.0 - g + 2.0 * g * u1);
+  double mu = (1.0 + g * g - q * q) / (2.0 * g);
+  mu = fmin(1.0, fmax(-1.0, mu));
+  double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  double cp = cos(ph), sp = sin(ph);
+  double x = d[0], y = d[1], z = d[2];
+  double s = sqrt(x * x + y * y); /* sin of the polar angle of d */
+  if (s == 0.0) {
+    d[0] = st * cp;
+    d[1] = st * sp;
+    d[2] = z > 0.0 ? mu : -mu;
+  } else {
+    d[0] = st * (x * z * cp - y * sp) / s + x * mu;
+    d[1] = st * (y * z * cp + x * sp) / s + y * mu;
+    d[2] = -st * cp * s + z * mu;
+  }
+}
+
+static void scatter_dir(rng_t* r, double g, double d[3]) {
+  double u1 = rng_next(r);
+  double u2 = rng_next(r);
+  scatter_dir_u(g, u1, u2, d);
+}
+
+void ora_scatter_dirs(double g, const double* u, const double* din, double* dout, int n) {
+  for (int a = 0; a < n; ++a) {
+    double d[3] = {din[3 * a], din[3 * a + 1], din[3 * a + 2]};
+    scatter_dir_u(g, u[2 * a], u[2 * a + 1], d);
+    dout[3 * a] = d[0];
+    dout[3 * a + 1] = d[1];
+    dout[3 * a + 2] = d[2];
+  }
+}
+
 void ora_cell_volumes(const ora_model* m, double* V) {
   for (int i = 0; i < m->n_r; ++i) {
     double a = m->r_edges[i], b = m->r_edges[i + 1];
@@ -603,6 +655,7 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
       double omega = m->kappa_sca[k] / chi;
       if (rng_next(&rng) < omega) {
         ++n_scat;
+        scatter_dir(&rng, m->g_asym, d);
       } else {
         ++n_ab;
         n_abs[c]++;
@@ -616,8 +669,8 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
           double T_new = T_of_g(t, nl, E_abs[c] * inv4pim[c]);
           k = reemit_bin(t, nl, T_old, T_new, xb);
         }
+        iso_dir(&rng, d);
       }
-      iso_dir(&rng, d);
       ++n_int;
       /* modified random walk (eqs. modified RW .. criterion) */
       if (o->mrw) {

@@ -28,6 +28,8 @@ typedef struct {
   const double* kappa_abs;     /* [n_lambda] mixture absorption opacity, cm^2/g */
   const double* kappa_sca;     /* [n_lambda] mixture scattering opacity */
   double T_star, R_star;
+  double g_asym;               /* asymmetry parameter of the Henyey-Greenstein
+                                  phase function of scattering (0: isotropic) */
 } ora_model;
 
 typedef struct {
@@ -117,6 +119,11 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
                         const double* T_bc, const double* kscale, const uint8_t* region,
                         const double* dJdT, const int* cells, int n_req, double* g_logrho,
                         double* g_kscale);
+
+/* Directions after scattering n times by the phase function of model g_asym:
+ * for packet a, from direction din[3a..3a+2] with the two draws u[2a], u[2a+1]
+ * (cosine of the scattering angle, azimuth), into dout[3a..3a+2]. */
+void ora_scatter_dirs(double g, const double* u, const double* din, double* dout, int n);
 
 #ifdef __cplusplus
 }
