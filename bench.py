@@ -126,6 +126,9 @@ def parse():
                    help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--large-chunk", type=int, default=0,
                    help="with --large: packets per mcrt_trace call (0: all in one call)")
+    p.add_argument("--aniso", type=float, default=0.0,
+                   help="only time the step with Henyey-Greenstein scattering of this asymmetry "
+                        "parameter beside the isotropic one, and exit")
     p.add_argument("--accuracy", type=int, default=0,
                    help="only compare MRW gamma = 1/3/10 and PDA on/off runs of --packets "
                         "packets with an FP64 no-MRW, no-PDA reference of this many packets, "
@@ -441,6 +444,30 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
     return out
 
 
+def aniso(mcrt, W, torch, g, steps):
+    """The step (1e6 packets, FP32 tracking, MRW, PDA) on the step's disk with
+    Henyey-Greenstein scattering of asymmetry g, and the same step with
+    isotropic scattering, `steps` timed steps each after one warm-up."""
+    d, o = W.config("mrw_pda")
+    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins, 1e6 packets, MRW gamma=3, "
+                       "PDA < 100 visits", "g": g}
+    for name, gg in (("hg", g), ("isotropic", 0.0)):
+        ctx = mcrt.Context(d, precision="fp32", mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                           pda_visits=o.pda_visits, n_T=o.n_T, g_asym=gg)
+        run_once(ctx, o.n_packets, o.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            run_once(ctx, o.n_packets, o.seed + 1000 * (i + 1))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        c = ctx.counters()
+        out[name] = {"value": o.n_packets / dt, "unit": "photon packets/s", "ms_per_step": dt * 1e3,
+                     "steps": steps, "events_last_step": c}
+        log("aniso: %s: %.3g packets/s" % (name, o.n_packets / dt))
+    return out
+
+
 def event_mix(mcrt, W, torch):
     """Per-event cost by event type: the longest frozen-T walk (of 1e5
     packets) on the step's disk with albedo 0.1, 0.5 and 0.9 at the same
@@ -548,6 +575,9 @@ def main():
         return
     if a.event_mix:
         print(json.dumps({"event_mix": event_mix(mcrt, W, torch)}), flush=True)
+        return
+    if a.aniso != 0.0:
+        print(json.dumps({"aniso": aniso(mcrt, W, torch, a.aniso, a.steps)}), flush=True)
         return
     if a.accuracy > 0:
         print(json.dumps({"accuracy": accuracy(mcrt, W, torch, a.accuracy, a.packets)}),

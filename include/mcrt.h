@@ -114,6 +114,11 @@ typedef struct {
                             64 lanes of a wavefront (same draws, same events);
                             0 = never (2048).  Batched runs use each disk's value
                             and one live count over all disks. */
+  double g_asym;         /* asymmetry parameter g of scattering, |g| < 1 (0): the
+                            scattering angle follows the Henyey-Greenstein phase
+                            function, and the diffusion quantities (MRW and PDA)
+                            take the isotropic-equivalent scattering opacity
+                            (1 - g) sigma (Sect. 2.2.3).  Batched runs need 0. */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
@@ -243,7 +248,8 @@ int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
  * 1 take the MRW coefficients of pass k from the temperature after pass k-1
  * (for the first pass: the T the context holds, if it holds one).
  * use_graph != 0 captures all passes in one HIP graph and submits it once.
- * Every context must use MCRT_FP32 and live on the current device.  stats
+ * Every context must use MCRT_FP32 with g_asym = 0 and live on the current
+ * device (else MCRT_E_ARG).  stats
  * (host, nullable) receives each disk's PDA statistics of the last pass.
  * Synchronous: returns after the stream has drained.  The n-iteration
  * outer loop of the method (Sect. 2.5: radiative transfer repeated on an

@@ -30,6 +30,8 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
     if (!ctxs[d] || n_packets[d] == 0) return fail_batch(MCRT_E_ARG, "bad context or packet count");
     if (ctxs[d]->opt.precision != MCRT_FP32)
       return fail_batch(MCRT_E_ARG, "batched runs use FP32 tracking (precision = MCRT_FP32)");
+    if (ctxs[d]->opt.g_asym != 0.0)
+      return fail_batch(MCRT_E_ARG, "batched runs scatter isotropically (g_asym = 0)");
     if (ctxs[d]->device != ctxs[0]->device) return fail_batch(MCRT_E_ARG, "contexts on one device");
   }
   mcrt_ctx* c0 = ctxs[0];

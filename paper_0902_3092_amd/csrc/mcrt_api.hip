@@ -182,6 +182,7 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
   a.recs = recs;
   a.n_recs = n_recs;
   a.wave_events = ctx->opt.wave_events;
+  a.g_asym = ctx->opt.g_asym;
   if (ctx->opt.wave_events > 0 && ctx->d_tail) {
     a.tail = ctx->d_tail;
     a.tail_count = (unsigned int*)((char*)ctx->d_tail + (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES);
@@ -225,6 +226,7 @@ void mcrt_default_options(mcrt_options* o) {
   o->pda_solver = 0;
   o->pda_precond = 1;
   o->wave_events = 2048;
+  o->g_asym = 0.0;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -251,7 +253,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   if (opt->n_T < 3 || !(opt->T_lo > 0.0) || !(opt->T_hi > opt->T_lo) || opt->n_inc < 1 ||
       opt->max_events < 1 || opt->n_int_min < 0 || !(opt->gamma >= 0.0) ||
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
-      opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0)
+      opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0 ||
+      !(opt->g_asym > -1.0 && opt->g_asym < 1.0))
     return fail(nullptr, MCRT_E_ARG, "bad options");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)
@@ -317,10 +320,12 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
     // The emission-weighted means of Sect. 2.2.3 at the fixed point of the
     // eta equation, eta ~ chi dB/dT: D rho = 1/(3 chi_R) with the Rosseland
     // mean of the extinction, and kappa-bar = <kappa> weighted by dB/dT.
+    // Anisotropic scattering enters as the isotropic-equivalent scattering
+    // opacity (1 - g) sigma.
     double s_dB = 0.0, s_dBchi = 0.0, s_kdB = 0.0;
     for (int k = 0; k < nl; ++k) {
       s_dB += dB[k];
-      s_dBchi += dB[k] / chi[k];
+      s_dBchi += dB[k] / (kabs[k] + ksca[k] * (1.0 - opt->g_asym));
       s_kdB += kabs[k] * dB[k];
     }
     Drho[n] = s_dBchi / s_dB / 3.0;

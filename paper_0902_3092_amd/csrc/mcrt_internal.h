@@ -92,6 +92,7 @@ struct TraceArgs {
   long long* live;
   unsigned int* waves_in;
   unsigned int n_waves, live_handoff;
+  double g_asym;               // Henyey-Greenstein asymmetry parameter (0: isotropic)
 };
 constexpr int TAIL_STATE_BYTES = 512;
 constexpr int TAIL_CAP = 8192;

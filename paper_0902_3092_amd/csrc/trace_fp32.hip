@@ -251,6 +251,41 @@ __device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
 }
 __device__ __forceinline__ float tau32(Rng32& r) { return tau_of(r.next()); }
 __device__ __forceinline__ void ensure_draws(Rng32&, int) {}
+// the two draws of a scattering: the first raw (the scattering angle), the
+// second as the sine and cosine of its azimuth
+__device__ __forceinline__ void scat_draws(Rng32& r, float& u1, float& sn, float& cs) {
+  u1 = r.next();
+  iso_phi(r.next(), sn, cs);
+}
+
+// Direction after a scattering by the Henyey-Greenstein phase function with
+// asymmetry g != 0: the cosine of the scattering angle from the inverse of
+// its cumulative distribution at u1, the azimuth (sine sn, cosine cs) about
+// the old direction; the result is renormalised, since the rotation
+// compounds over a walk in FP32.
+__device__ __forceinline__ void hg_turn32(float g, float u1, float sn, float cs, float d[3]) {
+  const float q = fdiv(1.0f - g * g, 1.0f - g + 2.0f * g * u1);
+  const float mu = fminf(1.0f, fmaxf(-1.0f, fdiv(1.0f + g * g - q * q, 2.0f * g)));
+  const float st = fsqrt(fmaxf(0.0f, 1.0f - mu * mu));
+  const float x = d[0], y = d[1], z = d[2];
+  const float s2 = x * x + y * y;
+  float nx, ny, nz;
+  if (s2 > 0.0f) {
+    const float is = __builtin_amdgcn_rsqf(s2);
+    const float s = s2 * is;
+    nx = st * (x * z * cs - y * sn) * is + x * mu;
+    ny = st * (y * z * cs + x * sn) * is + y * mu;
+    nz = -st * cs * s + z * mu;
+  } else {
+    nx = st * cs;
+    ny = st * sn;
+    nz = z > 0.0f ? mu : -mu;
+  }
+  const float nn = __builtin_amdgcn_rsqf(nx * nx + ny * ny + nz * nz);
+  d[0] = nx * nn;
+  d[1] = ny * nn;
+  d[2] = nz * nn;
+}
 
 // ------------------------------------------------------------------ packets
 // Transport state of one packet.
@@ -366,12 +401,22 @@ struct WaveRng {
     d[1] = s * sn_;
     d[2] = w;
   }
+  __device__ __forceinline__ void next_scat(float& u1, float& sn_, float& cs_) {
+    const int p1 = take();
+    u1 = at(u, p1);
+    const int p2 = take();
+    cs_ = at(cs, p2);
+    sn_ = at(sn, p2);
+  }
   __device__ __forceinline__ uint64_t draws() const { return (uint64_t)blk0 * 4u + (uint64_t)pos; }
 };
 
 __device__ __forceinline__ void iso32(WaveRng& r, float d[3]) { r.next_iso(d); }
 __device__ __forceinline__ float tau32(WaveRng& r) { return r.next_tau(); }
 __device__ __forceinline__ void ensure_draws(WaveRng& r, int n) { r.ensure(n); }
+__device__ __forceinline__ void scat_draws(WaveRng& r, float& u1, float& sn, float& cs) {
+  r.next_scat(u1, sn, cs);
+}
 
 // Smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane.
 template <typename C>
@@ -393,7 +438,7 @@ __device__ __forceinline__ int reemit_search_wave(const Reemit<C>& R, int nl, C 
 // (Sect. 2.2.2).  Returns the fate (0 going on, 1 escaped, 2 star, 3 capped).
 // WAVE: the whole wavefront works on P (all lanes hold the same state) and
 // lane 0 issues the memory updates.
-template <bool WAVE, class RNG>
+template <bool WAVE, bool HG, class RNG>
 __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, const Lds32& L,
                                        const double* fixT, int lane) {
   const DevModel& M = A.m;
@@ -556,7 +601,13 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
       if (rng.next() < P.omega) {
         ++P.pc_scat;
-        iso32(rng, P.d);
+        if constexpr (HG) {
+          float u1, sn, cs;
+          scat_draws(rng, u1, sn, cs);
+          hg_turn32((float)A.g_asym, u1, sn, cs, P.d);
+        } else {
+          iso32(rng, P.d);
+        }
       } else {
         ++P.pc_abs;
         ++P.cell_abs;
@@ -738,7 +789,7 @@ __device__ __forceinline__ Lds32 setup_lds32(const TraceArgs& A) {
   return L;
 }
 
-template <bool CDF_LDS>
+template <bool CDF_LDS, bool HG>
 __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   const DevModel& M = A.m;
   const int n_r = M.n_r, n_mu = M.n_mu, nl = M.n_lambda;
@@ -889,7 +940,7 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
       }
     }
 
-    const int fate = event32<false>(P, rng, A, L, fixT, lane);
+    const int fate = event32<false, HG>(P, rng, A, L, fixT, lane);
     if (fate != 0) {
       finish32<false>(P, rng, fate, pid, A, tot, lane);
       alive = false;
@@ -912,14 +963,14 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   }
 }
 
-template <bool CDF_LDS>
+template <bool CDF_LDS, bool HG>
 __global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
-  trace_fp32_body<CDF_LDS>(A);
+  trace_fp32_body<CDF_LDS, HG>(A);
 }
 
 // The packets handed over by the trace launch, one wavefront each; this
 // workgroup is number `rank` of those serving the disk.
-template <bool CDF_LDS>
+template <bool CDF_LDS, bool HG>
 __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigned rank) {
   const unsigned wpb = BS32 / 64;
   if (!A.tail) return;  // traced without hand-off
@@ -944,7 +995,7 @@ __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigne
     const uint64_t pid = ts.pid;
     int f;
     do {
-      f = event32<true>(S, wr, A, L, fixT, lane);
+      f = event32<true, HG>(S, wr, A, L, fixT, lane);
     } while (f == 0);
     finish32<true>(S, wr, f, pid, A, tot, lane);
   }
@@ -958,9 +1009,9 @@ __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigne
   }
 }
 
-template <bool CDF_LDS>
+template <bool CDF_LDS, bool HG>
 __global__ void __launch_bounds__(BS32) trace_fp32_tail_kernel(TraceArgs A) {
-  trace_fp32_tail_body<CDF_LDS>(A, blockIdx.x);
+  trace_fp32_tail_body<CDF_LDS, HG>(A, blockIdx.x);
 }
 
 // Many disks in one launch: workgroup b works on disk block_disk[b] for the
@@ -969,7 +1020,7 @@ __global__ void __launch_bounds__(BS32) trace_fp32_tail_kernel(TraceArgs A) {
 template <bool CDF_LDS>
 __global__ void __launch_bounds__(BS32) trace_fp32_batch_kernel(const TraceArgs* __restrict__ As,
                                                                 const int* __restrict__ block_disk) {
-  trace_fp32_body<CDF_LDS>(As[block_disk[blockIdx.x]]);
+  trace_fp32_body<CDF_LDS, false>(As[block_disk[blockIdx.x]]);
 }
 
 // Hand-offs of a batched launch.  The workgroups are shared out by the
@@ -1002,17 +1053,17 @@ __global__ void __launch_bounds__(BS32)
     const long long want = (long long)((c + wpb - 1) / wpb) - 1;
     const long long got = 1 + (extra <= spare ? want : (want * spare) / extra);
     if ((long long)blockIdx.x < first + got) {
-      trace_fp32_tail_body<CDF_LDS>(As[d], (unsigned)(blockIdx.x - first));
+      trace_fp32_tail_body<CDF_LDS, false>(As[d], (unsigned)(blockIdx.x - first));
       return;
     }
     first += got;
   }
 }
 
-template <bool CDF_LDS>
+template <bool CDF_LDS, bool HG>
 int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
-  auto kern = trace_fp32_kernel<CDF_LDS>;
-  auto tail = trace_fp32_tail_kernel<CDF_LDS>;
+  auto kern = trace_fp32_kernel<CDF_LDS, HG>;
+  auto tail = trace_fp32_tail_kernel<CDF_LDS, HG>;
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -1058,11 +1109,15 @@ int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
   size_t with = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, true);
   if (with <= cap) {
     b.vis_lds = with + vis <= cap;
-    return launch32<true>(ctx, b, b.vis_lds ? with + vis : with, s);
+    const size_t lds = b.vis_lds ? with + vis : with;
+    return a.g_asym != 0.0 ? launch32<true, true>(ctx, b, lds, s)
+                           : launch32<true, false>(ctx, b, lds, s);
   }
   size_t without = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, false);
   b.vis_lds = without + vis <= cap;
-  return launch32<false>(ctx, b, b.vis_lds ? without + vis : without, s);
+  const size_t lds = b.vis_lds ? without + vis : without;
+  return a.g_asym != 0.0 ? launch32<false, true>(ctx, b, lds, s)
+                         : launch32<false, false>(ctx, b, lds, s);
 }
 
 size_t trace_fp32_lds(const DevModel& M, bool with_cdf) {

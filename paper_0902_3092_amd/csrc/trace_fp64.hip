@@ -130,6 +130,33 @@ __device__ __forceinline__ void iso64(Rng64& r, double d[3]) {
   d[2] = iso_mu64(u1);
 }
 __device__ __forceinline__ double tau64(Rng64& r) { return tau_of64(r.next()); }
+// the two draws of a scattering: the first raw (the scattering angle), the
+// second as the sine and cosine of its azimuth
+__device__ __forceinline__ void scat_draws(Rng64& r, double& u1, double& sn, double& cs) {
+  u1 = r.next();
+  iso_phi64(r.next(), sn, cs);
+}
+
+// Direction after a scattering by the Henyey-Greenstein phase function with
+// asymmetry g != 0: the cosine of the scattering angle from the inverse of
+// its cumulative distribution at u1, the azimuth (sine sn, cosine cs) about
+// the old direction.
+__device__ __forceinline__ void hg_turn64(double g, double u1, double sn, double cs, double d[3]) {
+  const double q = (1.0 - g * g) / (1.0 - g + 2.0 * g * u1);
+  const double mu = fmin(1.0, fmax(-1.0, (1.0 + g * g - q * q) / (2.0 * g)));
+  const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  const double x = d[0], y = d[1], z = d[2];
+  const double s = sqrt(x * x + y * y);  // sine of the polar angle of d
+  if (s == 0.0) {
+    d[0] = st * cs;
+    d[1] = st * sn;
+    d[2] = z > 0.0 ? mu : -mu;
+  } else {
+    d[0] = st * (x * z * cs - y * sn) / s + x * mu;
+    d[1] = st * (y * z * cs + x * sn) / s + y * mu;
+    d[2] = -st * cs * s + z * mu;
+  }
+}
 __device__ __forceinline__ void ensure_draws(Rng64&, int) {}
 
 // ------------------------------------------------------------------ packets
@@ -237,12 +264,22 @@ struct WaveRng64 {
     d[1] = s * sn_;
     d[2] = w;
   }
+  __device__ __forceinline__ void next_scat(double& u1, double& sn_, double& cs_) {
+    const int p1 = take();
+    u1 = at(u, p1);
+    const int p2 = take();
+    cs_ = at(cs, p2);
+    sn_ = at(sn, p2);
+  }
   __device__ __forceinline__ uint64_t nd_value() const { return blk0 * 2u + (uint64_t)pos; }
 };
 
 __device__ __forceinline__ void iso64(WaveRng64& r, double d[3]) { r.next_iso(d); }
 __device__ __forceinline__ double tau64(WaveRng64& r) { return r.next_tau(); }
 __device__ __forceinline__ void ensure_draws(WaveRng64& r, int n) { r.ensure(n); }
+__device__ __forceinline__ void scat_draws(WaveRng64& r, double& u1, double& sn, double& cs) {
+  r.next_scat(u1, sn, cs);
+}
 
 // smallest k with D(k) > xi D(nl-1) (nl - 1 if none), one bin per lane
 __device__ __forceinline__ int reemit64_wave(const Lds64& L, double T_old, double T_new, double xi,
@@ -392,7 +429,13 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
       ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
       if (rng.next() < P.omega) {
         ++P.pc_scat;
-        iso64(rng, P.d);
+        if (A.g_asym != 0.0) {
+          double u1, sn, cs;
+          scat_draws(rng, u1, sn, cs);
+          hg_turn64(A.g_asym, u1, sn, cs, P.d);
+        } else {
+          iso64(rng, P.d);
+        }
       } else {
         ++P.pc_abs;
         ++P.cell_abs;

@@ -59,7 +59,8 @@ class Options(C.Structure):
                 ("pda_tol", C.c_double), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
                 ("mrw_coef_T", C.c_int32), ("block_size", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("pda_solver", C.c_int32),
-                ("pda_precond", C.c_int32), ("wave_events", C.c_int64)]
+                ("pda_precond", C.c_int32), ("wave_events", C.c_int64),
+                ("g_asym", C.c_double)]
 
 
 class PdaStats(C.Structure):
@@ -141,7 +142,8 @@ class Context:
                  n_inc: int = 10, max_events: int = 1 << 30, pda_visits: int = 100,
                  pda_max_sweeps: int = 50, pda_tol: float = 1e-8, cg_max_iter: int = 20000,
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
-                 blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None):
+                 blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None,
+                 g_asym: float = 0.0):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()
@@ -155,6 +157,7 @@ class Context:
         o.pda_solver = pda_solver
         o.pda_precond = pda_precond
         o.wave_events = wave_events
+        o.g_asym = g_asym
         self.options = o
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
