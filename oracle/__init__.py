@@ -75,6 +75,8 @@ def lib():
         vp, i64, u64, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_double
         L.ora_philox4x32_10.argtypes = [vp, vp]
         L.ora_scatter_dirs.argtypes = [dbl, vp, vp, vp, C.c_int]
+        L.ora_hydrostatic.argtypes = [vp, vp, dbl, dbl, dbl, vp]
+        L.ora_hydrostatic.restype = None
         L.ora_scatter_dirs.restype = None
         L.ora_uniforms.argtypes = [u64, u64, u64, i64, vp]
         L.ora_planck_bins.argtypes = [vp, C.c_int, dbl, vp, vp]
@@ -227,6 +229,15 @@ class Oracle:
 
     def counters(self, state) -> dict:
         return dict(zip(COUNTER_NAMES, (int(v) for v in state["counters"])))
+
+    def hydrostatic(self, T, M_star: float, mu_mol: float = 2.3, T_floor: float = 1.0):
+        """Density in vertical hydrostatic equilibrium for the temperatures T,
+        each radial shell keeping the mass of the model's density."""
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        out = np.empty(self.n_cells)
+        lib().ora_hydrostatic(C.byref(self.model), _p(T), float(M_star), float(mu_mol),
+                              float(T_floor), _p(out))
+        return out
 
     def update_T(self, E_abs) -> np.ndarray:
         E = np.ascontiguousarray(E_abs, dtype=np.float64)

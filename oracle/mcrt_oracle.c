@@ -536,6 +536,57 @@ void ora_cell_volumes(const ora_model* m, double* V) {
   }
 }
 
+/* Vertical hydrostatic equilibrium (Sect. 3.4, eq. balance): dP/dz =
+ * -rho G M z / R^3 with P = k rho T / (mu_mol m_p), along each radial shell
+ * of the grid at its mid radius r (z = r mu, R = r sqrt(1 - mu^2)) through
+ * the cell centres:
+ *   ln(rho_j T_j) - ln(rho_{j-1} T_{j-1}) = -(mu_mol m_p G M / k) * integral of
+ *   z / (R^3 T) dz, by the trapezoidal rule between consecutive centres,
+ * with T floored at T_floor.  Each shell keeps its mass (the surface density
+ * is held fixed while the vertical profile is solved). */
+static const double G_GRAV = 6.67430e-8;
+static const double M_PROTON = 1.67262192369e-24;
+
+void ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
+                     double T_floor, double* rho_out) {
+  const int nmu = m->n_mu;
+  const double A = mu_mol * M_PROTON * G_GRAV * M_star / K_BOLTZ;
+  double* lnf = (double*)malloc(sizeof(double) * nmu);
+  double* V = (double*)malloc(sizeof(double) * (size_t)m->n_r * nmu);
+  ora_cell_volumes(m, V);
+  for (int i = 0; i < m->n_r; ++i) {
+    const double r = 0.5 * (m->r_edges[i] + m->r_edges[i + 1]);
+    double z_prev = 0.0, h_prev = 0.0, T0 = 0.0, acc = 0.0;
+    for (int j = 0; j < nmu; ++j) {
+      const double mc = 0.5 * (m->mu_edges[j] + m->mu_edges[j + 1]);
+      const double z = r * mc;
+      const double R = r * sqrt(1.0 - mc * mc);
+      const double Tj = fmax(T[(size_t)i * nmu + j], T_floor);
+      const double h = z / (R * R * R * Tj);
+      if (j == 0) {
+        T0 = Tj;
+      } else {
+        acc += 0.5 * (h_prev + h) * (z - z_prev);
+      }
+      lnf[j] = log(T0 / Tj) - A * acc;
+      z_prev = z;
+      h_prev = h;
+    }
+    double mass = 0.0, s = 0.0;
+    for (int j = 0; j < nmu; ++j) {
+      const size_t c = (size_t)i * nmu + j;
+      mass += m->rho[c] * V[c];
+      s += exp(lnf[j]) * V[c];
+    }
+    for (int j = 0; j < nmu; ++j) {
+      const size_t c = (size_t)i * nmu + j;
+      rho_out[c] = s > 0.0 ? mass * exp(lnf[j]) / s : 0.0;
+    }
+  }
+  free(lnf);
+  free(V);
+}
+
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {
   int nc = m->n_r * m->n_mu;
   double* V = (double*)malloc(sizeof(double) * nc);

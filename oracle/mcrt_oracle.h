@@ -120,6 +120,13 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
                         const double* dJdT, const int* cells, int n_req, double* g_logrho,
                         double* g_kscale);
 
+/* Vertical hydrostatic equilibrium of each radial shell for the cell
+ * temperatures T [n_cells] (floored at T_floor), star mass M_star (g) and mean
+ * molecular weight mu_mol; each shell keeps the mass of m->rho.  rho_out
+ * [n_cells]. */
+void ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
+                     double T_floor, double* rho_out);
+
 /* Directions after scattering n times by the phase function of model g_asym:
  * for packet a, from direction din[3a..3a+2] with the two draws u[2a], u[2a+1]
  * (cosine of the scattering angle, azimuth), into dout[3a..3a+2]. */
