@@ -126,6 +126,9 @@ def parse():
                    help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--large-chunk", type=int, default=0,
                    help="with --large: packets per mcrt_trace call (0: all in one call)")
+    p.add_argument("--hydro", type=int, default=0,
+                   help="only run this many passes of the vertical-structure loop (trace, T, "
+                        "PDA, hydrostatic equilibrium) and exit")
     p.add_argument("--aniso", type=float, default=0.0,
                    help="only time the step with Henyey-Greenstein scattering of this asymmetry "
                         "parameter beside the isotropic one, and exit")
@@ -468,6 +471,45 @@ def aniso(mcrt, W, torch, g, steps):
     return out
 
 
+def hydro(mcrt, W, torch, n_iter):
+    """The vertical-structure loop of the method (Sect. 3.4) on the step's disk:
+    n_iter passes of trace (1e6 packets, FP32, MRW) -> T -> PDA -> hydrostatic
+    equilibrium (M_star = 2.5 Msun, mu = 2.3, shell masses kept).  After each
+    pass: its time, the hydrostatic kernel's, and the convergence statistic,
+    the mean over cells with >= 100 absorptions of |T_k - T_k-1| / sigma with
+    sigma^2 the sum of both passes' 1 / (16 N_abs) T^2 (converged below 3)."""
+    import numpy as np
+    d, o = W.config("mrw_pda")
+    ctx = mcrt.Context(d, precision="fp32", mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                       pda_visits=o.pda_visits, n_T=o.n_T)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins, 1e6 packets per pass, MRW "
+                       "gamma=3, PDA < 100 visits; M_star 2.5 Msun, mu 2.3", "passes": []}
+    prev = None
+    for k in range(n_iter):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_once(ctx, o.n_packets, o.seed + 100 * k)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        T = ctx.get(mcrt.GET_T).cpu().numpy()
+        nab = ctx.get(mcrt.GET_N_ABS).cpu().numpy().astype(np.float64)
+        e0.record(stream)
+        ctx.hydrostatic(2.5 * W.M_SUN, 2.3)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        row = {"s": time.perf_counter() - t0, "hydrostatic_ms": e0.elapsed_time(e1)}
+        if prev is not None:
+            Tp, np_ = prev
+            ok = (nab >= 100) & (np_ >= 100) & (T > 0) & (Tp > 0)
+            sig = np.sqrt(T[ok] ** 2 / (16 * nab[ok]) + Tp[ok] ** 2 / (16 * np_[ok]))
+            row["mean_dT_over_sigma"] = float(np.mean(np.abs(T[ok] - Tp[ok]) / sig))
+            row["cells"] = int(ok.sum())
+        prev = (T, nab)
+        out["passes"].append(row)
+        log("hydro: pass %d: %.1f s %s" % (k, row["s"], row.get("mean_dT_over_sigma", "")))
+    return out
+
+
 def event_mix(mcrt, W, torch):
     """Per-event cost by event type: the longest frozen-T walk (of 1e5
     packets) on the step's disk with albedo 0.1, 0.5 and 0.9 at the same
@@ -575,6 +617,9 @@ def main():
         return
     if a.event_mix:
         print(json.dumps({"event_mix": event_mix(mcrt, W, torch)}), flush=True)
+        return
+    if a.hydro > 0:
+        print(json.dumps({"hydro": hydro(mcrt, W, torch, a.hydro)}), flush=True)
         return
     if a.aniso != 0.0:
         print(json.dumps({"aniso": aniso(mcrt, W, torch, a.aniso, a.steps)}), flush=True)

@@ -237,6 +237,20 @@ int64_t mcrt_get_size(mcrt_ctx* ctx, int what);
  * field): T_dev [n_cells] double. */
 int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
 
+/* Vertical hydrostatic equilibrium (Sect. 3.4, eq. balance: dP/dz =
+ * -rho G M_star z / R^3, P = k rho T / (mu_mol m_p)) for the context's
+ * current temperature (floored at T_lo): along each radial shell at its mid
+ * radius r, through the cell centres (z = r mu, R = r sqrt(1 - mu^2)),
+ * ln(rho T) falls by mu_mol m_p G M_star / k times the trapezoidal integral
+ * of z / (R^3 T) between consecutive centres, and each shell keeps its mass
+ * (the surface density stays fixed).  Replaces the context's density (and
+ * the cell masses the temperature inversion uses); rho_dev (nullable)
+ * [n_cells] double receives a copy.  M_star in g.  One iteration of the
+ * method's vertical-structure loop; tracing again gives the next T.
+ * Errors: MCRT_E_ARG for a null context, M_star < 0 or mu_mol <= 0. */
+int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_dev,
+                     hipStream_t stream);
+
 /* Batched passes over many disks: for each of n_iter passes, clear the
  * tallies of every context, trace n_packets[d] packets of context d (seed
  * seeds[d] + (pass << 32); each packet carries L_star / n_packets[d]) with

@@ -629,6 +629,22 @@ int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream) {
   return MCRT_OK;
 }
 
+int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_dev,
+                     hipStream_t stream) {
+  if (!ctx) return fail(nullptr, MCRT_E_ARG, "null context");
+  if (!(M_star >= 0.0) || !(mu_mol > 0.0))
+    return fail(ctx, MCRT_E_ARG, "need M_star >= 0 and mu_mol > 0");
+  const double G = 6.67430e-8, M_P = 1.67262192369e-24;
+  const double A = mu_mol * M_P * G * M_star / K_B;
+  int rc = mcrt::launch_hydrostatic(ctx, A, ctx->opt.T_lo, stream);
+  if (rc) return rc;
+  ctx->lin_ready = false;
+  if (rho_dev)
+    HIPCHK(ctx, hipMemcpyAsync(rho_dev, ctx->m.rho, ctx->n_cells * sizeof(double),
+                               hipMemcpyDeviceToDevice, stream));
+  return MCRT_OK;
+}
+
 int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream) {
   if (!ctx || !T_dev) return fail(ctx, MCRT_E_ARG, "null argument");
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_T, T_dev, ctx->n_cells * sizeof(double),

@@ -63,6 +63,51 @@ __global__ void update_T_kernel(DevModel M, const double* E, double* T, int nc) 
   T[c] = T_from_g(M.G, M.Tn, M.n_T, E[c] * M.inv4pim[c]);
 }
 
+// Vertical hydrostatic equilibrium (Sect. 3.4, eq. balance), one thread per
+// radial shell at its mid radius r, through the cell centres (z = r mu,
+// R = r sqrt(1 - mu^2)): ln(rho T) falls by A times the trapezoidal integral
+// of z / (R^3 T) between consecutive centres, A = mu_mol m_p G M / k, T
+// floored at T_floor.  The shell keeps its mass; the cell masses'
+// 1 / (4 pi m) follow.
+__global__ void hydro_kernel(DevModel M, const double* T, double* rho, double* inv4pim, double A,
+                             double T_floor) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.n_r) return;
+  const int n_mu = M.n_mu;
+  const double PI_ = 3.14159265358979323846;
+  const double a = M.r_edges[i], b = M.r_edges[i + 1];
+  const double dr3 = b * b * b - a * a * a;
+  const double r = 0.5 * (a + b);
+  double mass = 0.0;
+  for (int j = 0; j < n_mu; ++j) {
+    const double V = 4.0 * PI_ / 3.0 * dr3 * (M.mu_edges[j + 1] - M.mu_edges[j]);
+    mass += rho[i * n_mu + j] * V;
+  }
+  double z_prev = 0.0, h_prev = 0.0, T0 = 0.0, acc = 0.0, s = 0.0;
+  for (int j = 0; j < n_mu; ++j) {
+    const double mc = 0.5 * (M.mu_edges[j] + M.mu_edges[j + 1]);
+    const double z = r * mc;
+    const double R = r * sqrt(1.0 - mc * mc);
+    const double Tj = fmax(T[i * n_mu + j], T_floor);
+    const double h = z / (R * R * R * Tj);
+    if (j == 0) T0 = Tj; else acc += 0.5 * (h_prev + h) * (z - z_prev);
+    const double f = exp(log(T0 / Tj) - A * acc);
+    const double V = 4.0 * PI_ / 3.0 * dr3 * (M.mu_edges[j + 1] - M.mu_edges[j]);
+    s += f * V;
+    rho[i * n_mu + j] = f;  // the profile, scaled below
+    z_prev = z;
+    h_prev = h;
+  }
+  for (int j = 0; j < n_mu; ++j) {
+    const int c = i * n_mu + j;
+    const double V = 4.0 * PI_ / 3.0 * dr3 * (M.mu_edges[j + 1] - M.mu_edges[j]);
+    const double rn = s > 0.0 ? mass * rho[c] / s : 0.0;
+    rho[c] = rn;
+    const double mc_ = rn * V;
+    inv4pim[c] = mc_ > 0.0 ? 1.0 / (4.0 * PI_ * mc_) : 0.0;
+  }
+}
+
 __global__ void fill_kernel(uint32_t* p, size_t n_words) {
   size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -788,6 +833,18 @@ int launch_update_T(mcrt_ctx* ctx, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(ctx, std::string("update_T launch: ") + hipGetErrorString(e));
+    return MCRT_E_HIP;
+  }
+  return MCRT_OK;
+}
+
+int launch_hydrostatic(mcrt_ctx* ctx, double A, double T_floor, hipStream_t s) {
+  const int n_r = ctx->n_r;
+  hipLaunchKernelGGL(hydro_kernel, dim3((n_r + 63) / 64), dim3(64), 0, s, ctx->m, ctx->d_T,
+                     (double*)ctx->m.rho, (double*)ctx->m.inv4pim, A, T_floor);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(ctx, std::string("hydrostatic launch: ") + hipGetErrorString(e));
     return MCRT_E_HIP;
   }
   return MCRT_OK;

@@ -25,7 +25,7 @@ COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "la
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
-           "mcrt_get_size", "mcrt_set_T", "mcrt_strerror", "mcrt_last_error",
+           "mcrt_get_size", "mcrt_set_T", "mcrt_hydrostatic", "mcrt_strerror", "mcrt_last_error",
            "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint"]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.mcrt_get_size.argtypes = [vp, C.c_int]
         L.mcrt_get_size.restype = i64
         L.mcrt_set_T.argtypes = [vp, vp, vp]
+        L.mcrt_hydrostatic.argtypes = [vp, C.c_double, C.c_double, vp, vp]
         L.mcrt_strerror.argtypes = [C.c_int]
         L.mcrt_strerror.restype = C.c_char_p
         L.mcrt_last_error.argtypes = []
@@ -266,6 +267,15 @@ class Context:
 
     def set_T(self, T, stream=None):
         _check(lib().mcrt_set_T(self.handle, _ptr(T), _stream(stream)), "mcrt_set_T")
+
+    def hydrostatic(self, M_star: float, mu_mol: float = 2.3, stream=None):
+        """mcrt_hydrostatic: density in vertical hydrostatic equilibrium for the
+        current T (replaces the context's); returns a copy [n_cells]."""
+        import torch
+        rho = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_hydrostatic(self.handle, float(M_star), float(mu_mol), _ptr(rho),
+                                      _stream(stream)), "mcrt_hydrostatic")
+        return rho
 
     def pda_linear(self, mask, T_D, T_bc, rho=None, kscale=None, stream=None):
         """mcrt_pda_linear: one PDA solve with D frozen at T_D; returns (T, stats)."""
