@@ -593,7 +593,7 @@ def main():
         print(trace32_source_hash())
         return
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported" % a.gpus,
+        print("bench.py: the benchmark runs on one GPU; --gpus %d is not supported" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
