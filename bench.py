@@ -126,6 +126,8 @@ def parse():
                    help="with --c3: also one pass of each disk alone on the FP64 path")
     p.add_argument("--large-chunk", type=int, default=0,
                    help="with --large: packets per mcrt_trace call (0: all in one call)")
+    p.add_argument("--accuracy-g", type=float, default=0.0,
+                   help="asymmetry parameter of the accuracy study's scattering")
     p.add_argument("--hydro", type=int, default=0,
                    help="only run this many passes of the vertical-structure loop (trace, T, "
                         "PDA, hydrostatic equilibrium) and exit")
@@ -371,7 +373,7 @@ def tail_probe(mcrt, W, torch):
     return out
 
 
-def accuracy(mcrt, W, torch, n_ref, n_run):
+def accuracy(mcrt, W, torch, n_ref, n_run, g=0.0):
     """Synthetic analogue of the paper's accuracy study (Sect. 4): on the step's
     disk, runs of n_run packets with MRW at gamma = 1, 3, 10 (PDA on), with
     gamma = 3 and no PDA, and with no MRW, against an FP64 reference of n_ref
@@ -379,7 +381,9 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
     entered at least 1000 times: the mass-weighted mean |T/T_ref - 1|, its
     signed mean, its 5th and 95th percentiles, the photon noise 1/(4 sqrt N_abs)
     of both runs (mass-weighted), and the same on the midplane row.  Runs are
-    traced in calls of at most 1e7 packets, one log line each."""
+    traced in calls of at most 1e7 packets, one log line each.  g != 0: every
+    run and the reference scatter by the Henyey-Greenstein phase function, so
+    the MRW rows test the diffusion coefficient's (1 - g) sigma correction."""
     import numpy as np
     d, o = W.config("mrw_pda")
     m = d.rho * W.cell_volumes(d)
@@ -396,7 +400,7 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
     def noise(n_abs):
         return 1.0 / (4.0 * np.sqrt(np.maximum(n_abs, 1)))
 
-    ref = mcrt.Context(d, precision="fp64", mrw=False, n_T=o.n_T)
+    ref = mcrt.Context(d, precision="fp64", mrw=False, n_T=o.n_T, g_asym=g)
     ref.reset()
     t0 = time.perf_counter()
     trace_all(ref, n_ref, o.seed + 99, "reference")
@@ -406,7 +410,7 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
     ok = (vis_ref >= 1000) & (T_ref > 0) & (m > 0)
     mid = np.zeros_like(ok)
     mid[0::d.n_mu] = True
-    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins", "reference":
+    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins", "g": g, "reference":
            {"packets": n_ref, "precision": "fp64", "mrw": False, "pda": False,
             "s": time.perf_counter() - t0, "cells": int(ok.sum())}, "runs": []}
     del ref
@@ -415,7 +419,7 @@ def accuracy(mcrt, W, torch, n_ref, n_run):
              ("MRW gamma=3, no PDA", True, 3.0, False)]
     for name, mrw, gamma, pda in cases:
         ctx = mcrt.Context(d, precision="fp32", mrw=mrw, gamma=gamma, n_int_min=o.n_int_min,
-                           pda_visits=o.pda_visits, n_T=o.n_T)
+                           pda_visits=o.pda_visits, n_T=o.n_T, g_asym=g)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ctx.reset()
@@ -625,8 +629,8 @@ def main():
         print(json.dumps({"aniso": aniso(mcrt, W, torch, a.aniso, a.steps)}), flush=True)
         return
     if a.accuracy > 0:
-        print(json.dumps({"accuracy": accuracy(mcrt, W, torch, a.accuracy, a.packets)}),
-              flush=True)
+        print(json.dumps({"accuracy": accuracy(mcrt, W, torch, a.accuracy, a.packets,
+                                               a.accuracy_g)}), flush=True)
         return
     if a.large > 0:
         print(json.dumps({"large": large(mcrt, W, torch, a.large, a.large_chunk)}), flush=True)
