@@ -44,17 +44,17 @@ def test_tables_match_oracle_with_g(mcrt, oracle_mod):
     assert np.all(t["Drho"][1:] > mcrt.Context(d, n_T=96).tables()["Drho"][1:])
 
 
-@pytest.mark.parametrize("mrw", [False, True])
-def test_frozen_T_packet_parity_hg(mcrt, oracle_mod, torch_cuda, mrw):
+@pytest.mark.parametrize("mrw,gg", [(False, G), (True, G), (True, -0.4)])
+def test_frozen_T_packet_parity_hg(mcrt, oracle_mod, torch_cuda, mrw, gg):
     torch = torch_cuda
     d = W.small_disk(M_dust_msun=3e-3, n_r=14, n_mu=10, n_lambda=24)
     Tf = _frozen_field(d)
     n = 4000
-    ctx = mcrt.Context(d, mrw=mrw, gamma=2.0, n_int_min=5, g_asym=G)
+    ctx = mcrt.Context(d, mrw=mrw, gamma=2.0, n_int_min=5, g_asym=gg)
     g = mcrt.Context.records_numpy(ctx.trace(n, 17, frozen_T=torch.from_numpy(Tf).cuda(), n_recs=n))
     torch.cuda.synchronize()
-    o = oracle_mod.Oracle(d, g_asym=G).run(n, 17, frozen_T=Tf, n_recs=n, mrw=mrw, gamma=2.0,
-                                           n_int_min=5)["recs"]
+    o = oracle_mod.Oracle(d, g_asym=gg).run(n, 17, frozen_T=Tf, n_recs=n, mrw=mrw, gamma=2.0,
+                                            n_int_min=5)["recs"]
     same = np.ones(n, bool)
     for f in ("fate", "k", "n_cross", "n_scat", "n_abs", "n_mrw", "n_draws"):
         same &= g[f] == o[f]

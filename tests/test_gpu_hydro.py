@@ -93,6 +93,20 @@ def test_vertical_structure_iterations(mcrt, oracle_mod, torch_cuda):
         assert np.allclose((rho * V).reshape(d.n_r, -1).sum(1), m0, rtol=1e-12)
 
 
+def test_no_gravity_keeps_rho_T(mcrt, torch_cuda):
+    """M_star = 0: pressure balance alone, rho T constant along each shell."""
+    torch = torch_cuda
+    d = W.make_disk("h", M_dust_msun=1e-3, n_r=20, n_mu=16, n_lambda=20)
+    T = _T_field(d, seed=9)
+    ctx = mcrt.Context(d, n_T=64)
+    ctx.set_T(torch.from_numpy(T).cuda())
+    rho = ctx.hydrostatic(0.0).cpu().numpy()
+    pT = (rho * T).reshape(d.n_r, -1)
+    live = pT[:, 0] > 0
+    assert live.sum() > 5
+    assert np.allclose(pT[live], pT[live, :1], rtol=1e-12)
+
+
 def test_hydrostatic_arguments(mcrt):
     d = W.small_disk(M_dust_msun=1e-3, n_r=8, n_mu=6, n_lambda=16)
     ctx = mcrt.Context(d)
