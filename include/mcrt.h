@@ -119,6 +119,10 @@ typedef struct {
                             function, and the diffusion quantities (MRW and PDA)
                             take the isotropic-equivalent scattering opacity
                             (1 - g) sigma (Sect. 2.2.3).  Batched runs need 0. */
+  double hydro_M_star;   /* > 0: each pass of mcrt_batch_run ends with the vertical
+                            hydrostatic equilibrium of this disk for that star mass
+                            (g), as mcrt_hydrostatic (0: off) */
+  double hydro_mu;       /* mean molecular weight of that step (2.3) */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
@@ -225,6 +229,7 @@ int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_d
                                scatterings, absorptions, MRW steps, launches, packets
                                handed off to the whole-wavefront launch */
 #define MCRT_GET_E_STAR 7   /* double [1], erg/s absorbed by the star */
+#define MCRT_GET_RHO 9      /* double [n_cells], the context's current dust density */
 #define MCRT_GET_TABLES 8   /* double: T nodes [n_T], cdf [n_T][n_lambda], D*rho [n_T],
                                kappa-bar [n_T], star cdf [n_lambda], L_star [1] */
 
@@ -262,6 +267,9 @@ int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_de
  * 1 take the MRW coefficients of pass k from the temperature after pass k-1
  * (for the first pass: the T the context holds, if it holds one).
  * use_graph != 0 captures all passes in one HIP graph and submits it once.
+ * Contexts whose hydro_M_star is > 0 end every pass with the vertical
+ * hydrostatic equilibrium of their density for that pass's final T (the
+ * method's vertical-structure loop, Sect. 3.4).
  * Every context must use MCRT_FP32 with g_asym = 0 and live on the current
  * device (else MCRT_E_ARG).  stats
  * (host, nullable) receives each disk's PDA statistics of the last pass.

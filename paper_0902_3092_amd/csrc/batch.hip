@@ -144,6 +144,14 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
       }
       r = mcrt::pda_batch_launch(d_pda, n_disks, s);
       if (r) return r;
+      for (int d = 0; d < n_disks; ++d) {
+        mcrt_ctx* c = ctxs[d];
+        if (c->opt.hydro_M_star > 0.0) {
+          r = mcrt::launch_hydrostatic(
+              c, mcrt::hydro_A(c->opt.hydro_M_star, c->opt.hydro_mu), c->opt.T_lo, s);
+          if (r) return r;
+        }
+      }
     }
     return MCRT_OK;
   };

@@ -202,6 +202,13 @@ int launch_trace(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
 }
 }  // namespace mcrt
 
+namespace mcrt {
+double hydro_A(double M_star, double mu_mol) {
+  const double G = 6.67430e-8, M_P = 1.67262192369e-24;
+  return mu_mol * M_P * G * M_star / K_B;
+}
+}  // namespace mcrt
+
 extern "C" {
 
 void mcrt_default_options(mcrt_options* o) {
@@ -227,6 +234,8 @@ void mcrt_default_options(mcrt_options* o) {
   o->pda_precond = 1;
   o->wave_events = 2048;
   o->g_asym = 0.0;
+  o->hydro_M_star = 0.0;
+  o->hydro_mu = 2.3;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -254,7 +263,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       opt->max_events < 1 || opt->n_int_min < 0 || !(opt->gamma >= 0.0) ||
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
       opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0 ||
-      !(opt->g_asym > -1.0 && opt->g_asym < 1.0))
+      !(opt->g_asym > -1.0 && opt->g_asym < 1.0) || !(opt->hydro_M_star >= 0.0) ||
+      !(opt->hydro_mu > 0.0))
     return fail(nullptr, MCRT_E_ARG, "bad options");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)
@@ -589,6 +599,7 @@ int64_t mcrt_get_size(mcrt_ctx* ctx, int what) {
     case MCRT_GET_COUNTERS: return mcrt::N_COUNTERS * 8;
     case MCRT_GET_E_STAR: return 8;
     case MCRT_GET_TABLES: return (nT + nT * nl + nT + nT + nl + 1) * 8;
+    case MCRT_GET_RHO: return nc * 8;
     default: return -1;
   }
 }
@@ -604,6 +615,7 @@ int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream) {
     case MCRT_GET_T: src = ctx->d_T; break;
     case MCRT_GET_REGION: src = ctx->d_region; break;
     case MCRT_GET_COUNTERS: src = ctx->t.counters; break;
+    case MCRT_GET_RHO: src = ctx->m.rho; break;
     case MCRT_GET_E_STAR: src = ctx->t.E_star; break;
     case MCRT_GET_TABLES: {
       int64_t nT = ctx->opt.n_T, nl = ctx->n_lambda;
@@ -634,9 +646,7 @@ int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_de
   if (!ctx) return fail(nullptr, MCRT_E_ARG, "null context");
   if (!(M_star >= 0.0) || !(mu_mol > 0.0))
     return fail(ctx, MCRT_E_ARG, "need M_star >= 0 and mu_mol > 0");
-  const double G = 6.67430e-8, M_P = 1.67262192369e-24;
-  const double A = mu_mol * M_P * G * M_star / K_B;
-  int rc = mcrt::launch_hydrostatic(ctx, A, ctx->opt.T_lo, stream);
+  int rc = mcrt::launch_hydrostatic(ctx, mcrt::hydro_A(M_star, mu_mol), ctx->opt.T_lo, stream);
   if (rc) return rc;
   ctx->lin_ready = false;
   if (rho_dev)

@@ -131,6 +131,7 @@ int launch_locate(mcrt_ctx* ctx, const double* xyz, int64_t n, int32_t* cell, hi
 int launch_update_T(mcrt_ctx* ctx, hipStream_t s);
 int launch_zero(void* p, size_t bytes, hipStream_t s);
 int launch_hydrostatic(mcrt_ctx* ctx, double A, double T_floor, hipStream_t s);
+double hydro_A(double M_star, double mu_mol);  // mu_mol m_p G M_star / k
 int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s);
 void set_error(mcrt_ctx* ctx, const std::string& msg);
 int pda_linear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const double* kscale,

@@ -20,7 +20,7 @@ _lib = None
 OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
-    GET_TABLES = range(9)
+    GET_TABLES, GET_RHO = range(10)
 COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch", "handed"]
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
@@ -60,7 +60,7 @@ class Options(C.Structure):
                 ("mrw_coef_T", C.c_int32), ("block_size", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("pda_solver", C.c_int32),
                 ("pda_precond", C.c_int32), ("wave_events", C.c_int64),
-                ("g_asym", C.c_double)]
+                ("g_asym", C.c_double), ("hydro_M_star", C.c_double), ("hydro_mu", C.c_double)]
 
 
 class PdaStats(C.Structure):
@@ -144,7 +144,7 @@ class Context:
                  pda_max_sweeps: int = 50, pda_tol: float = 1e-8, cg_max_iter: int = 20000,
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
                  blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None,
-                 g_asym: float = 0.0):
+                 g_asym: float = 0.0, hydro_M_star: float = 0.0, hydro_mu: float = 2.3):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()
@@ -159,6 +159,7 @@ class Context:
         o.pda_precond = pda_precond
         o.wave_events = wave_events
         o.g_asym = g_asym
+        o.hydro_M_star, o.hydro_mu = hydro_M_star, hydro_mu
         self.options = o
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
@@ -246,7 +247,7 @@ class Context:
         dt = {GET_E_ABS: torch.float64, GET_VISITS: torch.int32, GET_N_ABS: torch.int32,
               GET_N_MRW: torch.int32, GET_T: torch.float64, GET_REGION: torch.uint8,
               GET_COUNTERS: torch.int64, GET_E_STAR: torch.float64,
-              GET_TABLES: torch.float64}[what]
+              GET_TABLES: torch.float64, GET_RHO: torch.float64}[what]
         return buf.view(dt)
 
     def counters(self) -> dict:

@@ -47,10 +47,10 @@ def test_hydrostatic_matches_oracle(mcrt, oracle_mod, torch_cuda):
     want = ora.hydrostatic(T, M_STAR, 2.3, 1.0)
     nz = want > 1e-300
     assert np.array_equal(rho > 0, want > 0) or np.all(rho[~nz] < 1e-280)
-    assert np.allclose(rho[nz], want[nz], rtol=1e-10)
+    assert np.allclose(rho[nz], want[nz], rtol=1e-10, atol=0)
     m_old = (d.rho * ora.volumes).reshape(d.n_r, -1).sum(1)
     m_new = (rho * ora.volumes).reshape(d.n_r, -1).sum(1)
-    assert np.allclose(m_new, m_old, rtol=1e-12)
+    assert np.allclose(m_new, m_old, rtol=1e-12, atol=0)
 
 
 def test_hydrostatic_updates_cell_masses(mcrt, oracle_mod, torch_cuda):
@@ -90,7 +90,7 @@ def test_vertical_structure_iterations(mcrt, oracle_mod, torch_cuda):
         assert np.all(np.isfinite(rho)) and np.all(rho >= 0) and not np.any((rho > 0) & (d.rho <= 0))
         mid = rho.reshape(d.n_r, -1)[:, 0]
         assert np.all(mid[m0 > 0] > 0)
-        assert np.allclose((rho * V).reshape(d.n_r, -1).sum(1), m0, rtol=1e-12)
+        assert np.allclose((rho * V).reshape(d.n_r, -1).sum(1), m0, rtol=1e-12, atol=0)
 
 
 def test_no_gravity_keeps_rho_T(mcrt, torch_cuda):
@@ -104,7 +104,7 @@ def test_no_gravity_keeps_rho_T(mcrt, torch_cuda):
     pT = (rho * T).reshape(d.n_r, -1)
     live = pT[:, 0] > 0
     assert live.sum() > 5
-    assert np.allclose(pT[live], pT[live, :1], rtol=1e-12)
+    assert np.allclose(pT[live], pT[live, :1], rtol=1e-12, atol=0)
 
 
 def test_hydrostatic_arguments(mcrt):
@@ -114,3 +114,33 @@ def test_hydrostatic_arguments(mcrt):
         ctx.hydrostatic(-1.0)
     with pytest.raises(mcrt.McrtError):
         ctx.hydrostatic(M_STAR, mu_mol=0.0)
+
+
+def test_batched_passes_with_hydrostatic_step(mcrt, oracle_mod, torch_cuda):
+    """mcrt_batch_run with the hydrostatic step on one of two disks (captured
+    graph, two passes): the final density of that disk is the oracle's
+    equilibrium for the final temperature (the shell masses being those of
+    the initial disk), and the other disk's density is untouched."""
+    torch = torch_cuda
+    d1 = W.small_disk(M_dust_msun=3e-3, n_r=14, n_mu=10, n_lambda=24)
+    d2 = W.small_disk(M_dust_msun=1e-3, n_r=10, n_mu=8, n_lambda=24)
+    kw = dict(precision="fp32", mrw=True, gamma=3.0, n_int_min=20, pda_visits=30)
+    c1 = mcrt.Context(d1, hydro_M_star=M_STAR, **kw)
+    c2 = mcrt.Context(d2, **kw)
+    mcrt.batch_run([c1, c2], [100000, 50000], [5, 6], n_iter=2, use_graph=True)
+    torch.cuda.synchronize()
+    T = c1.get(mcrt.GET_T).cpu().numpy()
+    rho = c1.get(mcrt.GET_RHO).cpu().numpy()
+    ora = oracle_mod.Oracle(d1)
+    want = ora.hydrostatic(T, M_STAR, 2.3, 1.0)
+    big = want > 1e-250
+    assert big.sum() > d1.n_r * 3
+    assert np.allclose(rho[big], want[big], rtol=1e-9, atol=0)
+    assert np.all(rho[~big] < 1e-240)
+    V = ora.volumes
+    m0 = (d1.rho * V).reshape(d1.n_r, -1).sum(1)
+    assert np.allclose((rho * V).reshape(d1.n_r, -1).sum(1), m0, rtol=1e-12, atol=0)
+    assert not np.allclose(rho, d1.rho, rtol=1e-3, atol=0)
+    assert np.array_equal(c2.get(mcrt.GET_RHO).cpu().numpy(), d2.rho)
+    c = c1.counters()
+    assert c["escaped"] + c["star"] == 100000
