@@ -131,6 +131,9 @@ def parse():
     p.add_argument("--hydro", type=int, default=0,
                    help="only run this many passes of the vertical-structure loop (trace, T, "
                         "PDA, hydrostatic equilibrium) and exit")
+    p.add_argument("--hydro-batched", type=int, default=0,
+                   help="only run this many passes of that loop as one graph-captured "
+                        "mcrt_batch_run call and exit")
     p.add_argument("--aniso", type=float, default=0.0,
                    help="only time the step with Henyey-Greenstein scattering of this asymmetry "
                         "parameter beside the isotropic one, and exit")
@@ -514,6 +517,30 @@ def hydro(mcrt, W, torch, n_iter):
     return out
 
 
+def hydro_batched(mcrt, W, torch, n_iter):
+    """The same loop as one mcrt_batch_run call: n_iter passes of trace (1e6
+    packets) -> T -> PDA -> hydrostatic equilibrium captured in one HIP graph
+    on the step's disk; the call's time and the shell masses kept."""
+    import numpy as np
+    d, o = W.config("mrw_pda")
+    ctx = mcrt.Context(d, precision="fp32", mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                       pda_visits=o.pda_visits, n_T=o.n_T, hydro_M_star=2.5 * W.M_SUN,
+                       hydro_mu=2.3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = mcrt.batch_run([ctx], [o.n_packets], [o.seed], n_iter=n_iter, use_graph=True)
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t0
+    rho = ctx.get(mcrt.GET_RHO).cpu().numpy()
+    return {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins, 1e6 packets per pass, MRW "
+                        "gamma=3, PDA < 100 visits; M_star 2.5 Msun, mu 2.3; one graph",
+            "passes": n_iter, "s": s, "packets_per_s": n_iter * o.n_packets / s,
+            "pda_region_last_pass": stats[0]["n_region"],
+            "rho_finite": bool(np.all(np.isfinite(rho))),
+            "midplane_rho_ratio_max": float(np.max(rho.reshape(d.n_r, -1)[:, 0] /
+                                                   np.maximum(d.rho.reshape(d.n_r, -1)[:, 0], 1e-300)))}
+
+
 def event_mix(mcrt, W, torch):
     """Per-event cost by event type: the longest frozen-T walk (of 1e5
     packets) on the step's disk with albedo 0.1, 0.5 and 0.9 at the same
@@ -624,6 +651,10 @@ def main():
         return
     if a.hydro > 0:
         print(json.dumps({"hydro": hydro(mcrt, W, torch, a.hydro)}), flush=True)
+        return
+    if a.hydro_batched > 0:
+        print(json.dumps({"hydro_batched": hydro_batched(mcrt, W, torch, a.hydro_batched)}),
+              flush=True)
         return
     if a.aniso != 0.0:
         print(json.dumps({"aniso": aniso(mcrt, W, torch, a.aniso, a.steps)}), flush=True)
