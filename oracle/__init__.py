@@ -23,6 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mcrt_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
+_override = None
 
 N_COUNTERS = 8
 COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch"]
@@ -66,17 +67,42 @@ REC_DTYPE = np.dtype([("fate", np.int32), ("k", np.int32), ("n_cross", np.int64)
                       ("w", np.float64)])
 
 
+def use_library(path=None):
+    """Bind the module to another build of the oracle (``path``), e.g. one
+    compiled by a test from a deliberately altered source; None: the default
+    liboracle.so."""
+    global _lib, _override
+    _override = path
+    _lib = None
+
+
+def build_variant(src_text: str, path: str) -> str:
+    """Compile ``src_text`` (a version of mcrt_oracle.c) into ``path`` with
+    the flags of build(); the header is taken from this package."""
+    src = os.path.splitext(path)[0] + ".c"
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-I" + _HERE, "-o", path, src, "-lm"])
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = _override or _LIB_PATH
+        if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
             build(force=False)
-        L = C.CDLL(_LIB_PATH)
+        L = C.CDLL(path)
         vp, i64, u64, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_double
         L.ora_philox4x32_10.argtypes = [vp, vp]
         L.ora_scatter_dirs.argtypes = [dbl, vp, vp, vp, C.c_int]
         L.ora_hydrostatic.argtypes = [vp, vp, dbl, dbl, dbl, vp]
-        L.ora_hydrostatic.restype = None
+        L.ora_hydrostatic.restype = C.c_int
+        L.ora_pda_region.argtypes = [vp, vp, vp, vp, C.c_int, dbl, vp]
+        L.ora_pda_region.restype = None
+        L.ora_mrw_deposit.argtypes = [vp, vp, i64, dbl, dbl, dbl]
+        L.ora_mrw_deposit.restype = dbl
         L.ora_scatter_dirs.restype = None
         L.ora_uniforms.argtypes = [u64, u64, u64, i64, vp]
         L.ora_planck_bins.argtypes = [vp, C.c_int, dbl, vp, vp]
@@ -230,14 +256,35 @@ class Oracle:
     def counters(self, state) -> dict:
         return dict(zip(COUNTER_NAMES, (int(v) for v in state["counters"])))
 
-    def hydrostatic(self, T, M_star: float, mu_mol: float = 2.3, T_floor: float = 1.0):
+    def hydrostatic(self, T, M_star: float, mu_mol: float = 2.3, T_floor: float = 1.0,
+                    return_cold: bool = False):
         """Density in vertical hydrostatic equilibrium for the temperatures T,
-        each radial shell keeping the mass of the model's density."""
+        each radial shell keeping the mass of the model's density; shells with
+        a dusty cell at T <= 0 keep their density (their count is returned
+        with return_cold)."""
         T = np.ascontiguousarray(T, dtype=np.float64)
         out = np.empty(self.n_cells)
-        lib().ora_hydrostatic(C.byref(self.model), _p(T), float(M_star), float(mu_mol),
-                              float(T_floor), _p(out))
+        n_cold = lib().ora_hydrostatic(C.byref(self.model), _p(T), float(M_star), float(mu_mol),
+                                       float(T_floor), _p(out))
+        return (out, n_cold) if return_cold else out
+
+    def pda_region(self, visits, n_abs, n_mrw, visits_min: int = 100, sigma_max: float = 0.0):
+        """PDA region of a run: dusty cells with fewer than visits_min entries,
+        or (sigma_max > 0) with photon noise 1/(4 sqrt(N_abs + N_mrw)) above
+        sigma_max."""
+        v = np.ascontiguousarray(visits, dtype=np.uint32)
+        a = np.ascontiguousarray(n_abs, dtype=np.uint32)
+        m = np.ascontiguousarray(n_mrw, dtype=np.uint32)
+        out = np.empty(self.n_cells, np.uint8)
+        lib().ora_pda_region(C.byref(self.model), _p(v), _p(a), _p(m), int(visits_min),
+                             float(sigma_max), _p(out))
         return out
+
+    def mrw_deposit(self, cell: int, Tc: float, R0: float, s: float) -> float:
+        """Energy per unit packet energy that one MRW step (escape variable s,
+        sphere radius R0) deposits in `cell` at the temperature Tc."""
+        return lib().ora_mrw_deposit(C.byref(self.model), C.byref(self.tables), int(cell),
+                                     float(Tc), float(R0), float(s))
 
     def update_T(self, E_abs) -> np.ndarray:
         E = np.ascontiguousarray(E_abs, dtype=np.float64)

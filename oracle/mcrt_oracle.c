@@ -357,6 +357,17 @@ double ora_mrw_escape_s(double P0) {
   return 0.5 * (lo + hi);
 }
 
+/* Energy one MRW step deposits in cell c, per unit packet energy: the
+ * packet travels c t = s R0^2 / D inside the sphere (s from eq. probability
+ * RW, D = 1/(rho chi_R) / 3 from the table at Tc, Sect. 2.2.3) and is absorbed
+ * along that path at the rate rho kappa-bar(Tc) per unit length. */
+double ora_mrw_deposit(const ora_model* m, const ora_tables* t, int64_t c, double Tc, double R0,
+                       double s) {
+  double D = t_interp(t, t->Drho, Tc) / m->rho[c];
+  double ell = s * R0 * R0 / D; /* c t */
+  return m->rho[c] * t_interp(t, t->kbar, Tc) * ell;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: folded spherical grid.  Cell (i, j) is r_i <= r < r_{i+1} and    */
 /* mu_j <= |z|/r < mu_{j+1}; both mirror halves belong to the cell.  Faces:   */
@@ -543,18 +554,34 @@ void ora_cell_volumes(const ora_model* m, double* V) {
  *   ln(rho_j T_j) - ln(rho_{j-1} T_{j-1}) = -(mu_mol m_p G M / k) * integral of
  *   z / (R^3 T) dz, by the trapezoidal rule between consecutive centres,
  * with T floored at T_floor.  Each shell keeps its mass (the surface density
- * is held fixed while the vertical profile is solved). */
+ * is held fixed while the vertical profile is solved).  A shell holding a
+ * dust-bearing cell without a temperature (T <= 0: no packet was absorbed
+ * there) cannot be balanced -- a zero temperature would collapse its scale
+ * height, which is why the paper first fills such cells by the PDA
+ * (Sect. 4, Case 3 of the vertical-structure study) -- so it keeps its
+ * density; the count of such shells is returned. */
 static const double G_GRAV = 6.67430e-8;
 static const double M_PROTON = 1.67262192369e-24;
 
-void ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
-                     double T_floor, double* rho_out) {
+int ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
+                    double T_floor, double* rho_out) {
   const int nmu = m->n_mu;
   const double A = mu_mol * M_PROTON * G_GRAV * M_star / K_BOLTZ;
   double* lnf = (double*)malloc(sizeof(double) * nmu);
   double* V = (double*)malloc(sizeof(double) * (size_t)m->n_r * nmu);
   ora_cell_volumes(m, V);
+  int n_cold = 0;
   for (int i = 0; i < m->n_r; ++i) {
+    int cold = 0;
+    for (int j = 0; j < nmu; ++j) {
+      const size_t c = (size_t)i * nmu + j;
+      if (m->rho[c] > 0.0 && !(T[c] > 0.0)) cold = 1;
+    }
+    if (cold) {
+      for (int j = 0; j < nmu; ++j) rho_out[(size_t)i * nmu + j] = m->rho[(size_t)i * nmu + j];
+      ++n_cold;
+      continue;
+    }
     const double r = 0.5 * (m->r_edges[i] + m->r_edges[i + 1]);
     double z_prev = 0.0, h_prev = 0.0, T0 = 0.0, acc = 0.0;
     for (int j = 0; j < nmu; ++j) {
@@ -585,6 +612,7 @@ void ora_hydrostatic(const ora_model* m, const double* T, double M_star, double 
   }
   free(lnf);
   free(V);
+  return n_cold;
 }
 
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {
@@ -735,9 +763,7 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
           if (++events > o->max_events) break;
           double R0 = dmin * (1.0 - 1e-6);
           double s = ora_mrw_escape_s(rng_next(&rng));
-          double D = Drho / m->rho[c];
-          double ell = s * R0 * R0 / D; /* c t */
-          double dE = eps * m->rho[c] * t_interp(t, t->kbar, Tc) * ell;
+          double dE = eps * ora_mrw_deposit(m, t, c, Tc, R0, s);
           double nrm[3];
           iso_dir(&rng, nrm);
           for (int a = 0; a < 3; ++a) p[a] += R0 * nrm[a];
@@ -975,6 +1001,27 @@ static void pda_components(const ora_model* m, uint8_t* reg) {
   }
   free(comp);
   free(stack);
+}
+
+/* Region of the PDA (Sect. 2.2.1): the cells whose Monte Carlo temperature
+ * is not trusted.  Sect. 4 uses two tests: few packets entered the cell, or
+ * the photon statistics leave a large relative error in its temperature.
+ * With N absorption events the absorbed energy has relative error 1/sqrt(N)
+ * and T ~ E^(1/4) has 1/(4 sqrt(N)); a cell without events has no estimate. */
+void ora_pda_region(const ora_model* m, const uint32_t* visits, const uint32_t* n_abs,
+                    const uint32_t* n_mrw, int visits_min, double sigma_max, uint8_t* region) {
+  int n = m->n_r * m->n_mu;
+  for (int c = 0; c < n; ++c) {
+    int in = 0;
+    if (m->rho[c] > 0.0) {
+      if ((int64_t)visits[c] < (int64_t)visits_min) in = 1;
+      if (sigma_max > 0.0) {
+        double N = (double)n_abs[c] + (double)n_mrw[c];
+        if (N == 0.0 || 1.0 / (4.0 * sqrt(N)) > sigma_max) in = 1;
+      }
+    }
+    region[c] = (uint8_t)in;
+  }
 }
 
 int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc, const uint8_t* region_in,

@@ -123,9 +123,23 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
 /* Vertical hydrostatic equilibrium of each radial shell for the cell
  * temperatures T [n_cells] (floored at T_floor), star mass M_star (g) and mean
  * molecular weight mu_mol; each shell keeps the mass of m->rho.  rho_out
- * [n_cells]. */
-void ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
-                     double T_floor, double* rho_out);
+ * [n_cells].  Shells with a dust-bearing cell at T <= 0 keep m->rho; returns
+ * their number. */
+int ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
+                    double T_floor, double* rho_out);
+
+/* The PDA region of a finished Monte Carlo run (Sect. 2.2.1; Sect. 4): a
+ * dust-bearing cell joins when fewer than visits_min packets entered it, or
+ * when the relative photon noise of its temperature, 1 / (4 sqrt(N)) with N
+ * its absorption events (absorptions plus MRW deposits), exceeds sigma_max
+ * (sigma_max <= 0: that branch off).  region [n_cells] gets 1 or 0. */
+void ora_pda_region(const ora_model* m, const uint32_t* visits, const uint32_t* n_abs,
+                    const uint32_t* n_mrw, int visits_min, double sigma_max, uint8_t* region);
+
+/* Energy one MRW step with escape variable s in a sphere of radius R0
+ * deposits in cell c at the temperature Tc, per unit packet energy. */
+double ora_mrw_deposit(const ora_model* m, const ora_tables* t, int64_t c, double Tc, double R0,
+                       double s);
 
 /* Directions after scattering n times by the phase function of model g_asym:
  * for packet a, from direction din[3a..3a+2] with the two draws u[2a], u[2a+1]

@@ -68,3 +68,28 @@ def test_shell_mass_kept(oracle_mod):
     r1 = rho.reshape(d.n_r, -1)
     top = rho2[:, -1] / rho2[:, 0] >= r1[:, -1] / r1[:, 0]
     assert top.all()
+
+
+def test_cold_shell_keeps_its_density(oracle_mod):
+    """A dust-bearing cell with no temperature (T = 0: nothing was absorbed
+    there) cannot be balanced: a zero temperature would collapse the scale
+    height, which the paper avoids by filling such cells with the PDA first
+    (Sect. 4, vertical-structure Case 3).  Its shell keeps the input density
+    and is counted; the other shells are solved as usual."""
+    d = W.small_disk(M_dust_msun=1e-3, n_r=12, n_mu=10, n_lambda=16)
+    ora = oracle_mod.Oracle(d, n_T=16)
+    T = np.random.default_rng(3).uniform(20.0, 500.0, ora.n_cells).reshape(d.n_r, -1)
+    T[4, 0] = 0.0          # a cold midplane cell
+    T[7, 5] = 0.0
+    rho, n_cold = ora.hydrostatic(T.reshape(-1), M_STAR, 2.3, return_cold=True)
+    assert n_cold == 2
+    rho = rho.reshape(d.n_r, -1)
+    rho0 = d.rho.reshape(d.n_r, -1)
+    assert np.array_equal(rho[4], rho0[4]) and np.array_equal(rho[7], rho0[7])
+    warm = [i for i in range(d.n_r) if i not in (4, 7)]
+    assert not np.allclose(rho[warm], rho0[warm], rtol=1e-3, atol=0)
+    # the warm shells match a run where the cold shells are given temperatures
+    T2 = T.copy()
+    T2[4, 0], T2[7, 5] = 100.0, 100.0
+    rho2 = ora.hydrostatic(T2.reshape(-1), M_STAR, 2.3).reshape(d.n_r, -1)
+    assert np.array_equal(rho[warm], rho2[warm])

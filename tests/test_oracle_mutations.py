@@ -1,0 +1,54 @@
+"""The pins must catch a plausible slip in the step they cover.  Each case
+plants one mistake in a copy of the oracle source (on the CPU), builds it and
+runs the pin against it: the pin has to fail.  The unaltered oracle passes the
+same pins in their own test modules."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import test_oracle_deposit_launch_picard as P  # noqa: E402
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "mcrt_oracle.c")
+
+MUTANTS = {
+    # the deposit loses its density factor
+    "deposit_without_rho": ("  return m->rho[c] * t_interp(t, t->kbar, Tc) * ell;",
+                            "  return t_interp(t, t->kbar, Tc) * ell;"),
+    # the deposit takes the Rosseland extinction instead of kappa-bar
+    "deposit_chi_for_kbar": ("  return m->rho[c] * t_interp(t, t->kbar, Tc) * ell;",
+                             "  return m->rho[c] / (3.0 * t_interp(t, t->Drho, Tc)) * ell;"),
+    # the diffusion coefficient loses its 1/3
+    "deposit_D_times_3": ("  double D = t_interp(t, t->Drho, Tc) / m->rho[c];",
+                          "  double D = 3.0 * t_interp(t, t->Drho, Tc) / m->rho[c];"),
+    # the launch bin is shifted by one
+    "launch_bin_shift": ("    while (k < nl - 1 && !(t->star_cdf[k] > xs)) ++k;",
+                         "    while (k < nl - 1 && !(t->star_cdf[k + 1] > xs)) ++k;"),
+    # Picard keeps D at the Monte Carlo temperature
+    "picard_frozen_D": ("    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, u);",
+                        "    rc = pda_solve_once(m, t, &g, region_out, T_mc, T_mc, NULL, u);"),
+}
+
+PIN = {
+    "deposit_without_rho": lambda o: P.test_mrw_deposit_vs_explicit_walk(o, 10.0, 20000),
+    "deposit_chi_for_kbar": lambda o: P.test_mrw_deposit_vs_explicit_walk(o, 10.0, 20000),
+    "deposit_D_times_3": lambda o: P.test_mrw_deposit_vs_explicit_walk(o, 10.0, 20000),
+    "launch_bin_shift": lambda o: P.test_launch_spectrum_is_stellar(o),
+    "picard_frozen_D": lambda o: P.test_pda_picard_on_temperature_dependent_D(o),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pin_catches_mutant(oracle_mod, tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "the mutation site moved: " + name
+    path = oracle_mod.build_variant(src.replace(old, new), str(tmp_path / ("lib_%s.so" % name)))
+    oracle_mod.use_library(path)
+    try:
+        with pytest.raises(AssertionError):
+            PIN[name](oracle_mod)
+    finally:
+        oracle_mod.use_library(None)

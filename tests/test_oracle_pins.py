@@ -309,3 +309,27 @@ def test_philox_known_answer_vectors(oracle_mod):
         key = np.array([int(x, 16) for x in case["key"]], dtype=np.uint32)
         out = oracle_mod.philox4x32_10(ctr, key)
         assert ["%08x" % v for v in out] == case["out"]
+
+
+def test_pda_region_rule_boundaries(oracle_mod):
+    """The PDA region of Sect. 4: fewer than the minimum number of packet
+    entries, or a temperature photon noise 1/(4 sqrt(N)) above 5 %.  The
+    boundaries worked out by hand: 1/(4 sqrt(25)) = 0.05 exactly (not above),
+    1/(4 sqrt(24)) = 0.051 (above); N counts absorptions plus MRW deposits;
+    N = 0 has no temperature at all; dust-free cells never join."""
+    d = W.small_disk(n_r=2, n_mu=6)
+    rho = np.full(12, 1e-15)
+    rho[11] = 0.0
+    ora = oracle_mod.Oracle(d, rho=rho)
+    visits = np.array([99, 100, 500, 500, 500, 500, 500, 500, 500, 500, 500, 0])
+    n_abs = np.array([900, 900, 25, 24, 0, 20, 13, 400, 0, 10, 30, 0])
+    n_mrw = np.array([0, 0, 0, 0, 0, 5, 12, 0, 0, 14, 0, 0])
+    # branch 1 only
+    got = ora.pda_region(visits, n_abs, n_mrw, visits_min=100, sigma_max=0.0)
+    assert got.tolist() == [1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0]
+    # both branches: 5 % (N < 25)
+    got = ora.pda_region(visits, n_abs, n_mrw, visits_min=100, sigma_max=0.05)
+    assert got.tolist() == [1, 0, 0, 1, 1, 0, 0, 0, 1, 1, 0, 0]
+    # the paper's own run: fewer than 30 entries, or above 5 %
+    got = ora.pda_region(visits, n_abs, n_mrw, visits_min=30, sigma_max=0.05)
+    assert got.tolist() == [0, 0, 0, 1, 1, 0, 0, 0, 1, 1, 0, 0]
