@@ -43,7 +43,9 @@ extern "C" {
 #define MCRT_E_OOM (-2)             /* device allocation failed */
 #define MCRT_E_HIP (-3)             /* a HIP runtime call failed */
 #define MCRT_E_NOT_CONVERGED (-4)   /* PDA solver hit its iteration cap */
-#define MCRT_E_STUCK (-5)           /* reserved: capped packets are counted, not reported */
+#define MCRT_E_STUCK (-5)           /* packets hit the per-packet event cap (reported by the
+                                       synchronous mcrt_batch_run; mcrt_trace only counts
+                                       them, MCRT_GET_COUNTERS) */
 #define MCRT_E_SINGULAR_REGION (-6) /* a PDA region part has no Dirichlet neighbour (solved
                                        without it: informational) */
 
@@ -123,6 +125,13 @@ typedef struct {
                             hydrostatic equilibrium of this disk for that star mass
                             (g), as mcrt_hydrostatic (0: off) */
   double hydro_mu;       /* mean molecular weight of that step (2.3) */
+  double pda_sigma;      /* > 0: the PDA region also takes the opaque cells (optical width
+                            >= 1 at the most opaque wavelength, rho chi_max times the
+                            cell's smallest width) whose temperature photon noise
+                            1 / (4 sqrt(N)) exceeds this, N = absorptions + MRW deposits in
+                            the cell, so every such cell without an absorption (T = 0)
+                            joins (the second test of Sect. 3.1; the paper uses 0.05;
+                            transparent cells are not diffusive); 0: visits rule only (0) */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
@@ -163,25 +172,36 @@ int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t see
                uint64_t offset, const double* frozen_T_dev, mcrt_packet_rec* rec_dev,
                int64_t n_recs, hipStream_t stream);
 
-/* Radiative equilibrium per cell: 4 pi m_i G(T_i) = E_i with G the emission
- * per unit mass and steradian, linear in T between table nodes.  Updates the
- * context's T and, if T_dev != NULL, copies it there ([n_cells] double). */
+/* Radiative equilibrium per cell (Sect. 2.1: with immediate reemission a
+ * cell's temperature follows from the energy it absorbed): 4 pi m_i G(T_i) =
+ * E_i with G the emission per unit mass and steradian (the sum over bins of
+ * kappa_k Bbar_k(T)), linear in T between table nodes; T = 0 where nothing was
+ * absorbed.  Updates the context's T and, if T_dev != NULL, copies it there
+ * ([n_cells] double).  Errors: MCRT_E_ARG for a null context, MCRT_E_HIP if the
+ * launch fails. */
 int mcrt_update_T(mcrt_ctx* ctx, double* T_dev, hipStream_t stream);
 
 /* Partial diffusion approximation (Sect. 2.2.1): solve div(D grad T^4) = 0
  * on the region (mask_dev[c] = 1; NULL: cells with fewer than pda_visits
- * entries), Dirichlet T from the Monte Carlo temperature of the neighbouring
- * cells, D = 1/(3 rho chi_R) with chi_R the Rosseland mean of the total
+ * entries, and the pda_sigma test), Dirichlet T from the Monte Carlo
+ * temperature of the neighbouring dust cells that have one (a neighbour in
+ * which nothing was absorbed, T = 0, gives no boundary value: its face carries
+ * no flux), D = 1/(3 rho chi_R) with chi_R the Rosseland mean of the total
  * extinction (the diffusion coefficient of Sect. 2.2.3 with isotropic
  * scattering), Picard iteration on D(T), preconditioned CG (pda_precond:
  * exact theta-line blocks, or the diagonal).  Updates the context's T.
  * stats (host, nullable) receives sweeps, CG iterations and residuals; waits
- * for the stream.  MCRT_E_NOT_CONVERGED if CG hits cg_max_iter;
+ * for the stream.  MCRT_E_NOT_CONVERGED if CG hits cg_max_iter or the Picard
+ * sweeps end unconverged (stats.converged);
  * MCRT_E_SINGULAR_REGION (informational) if a part of the region has no
  * Dirichlet neighbour (left at its Monte Carlo T, flagged 2). */
 typedef struct {
   int32_t sweeps, cg_iters_total, cg_iters_last, n_region, n_isolated;
   double last_change, last_residual;
+  int32_t converged;     /* 1: the Picard sweeps' largest relative change of T fell
+                            below pda_tol, or stalled below sqrt(pda_tol) (a sweep
+                            that changes T no less than the one before has reached
+                            the rounding floor of the linear solve) */
 } mcrt_pda_stats;
 
 int mcrt_pda_solve(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats,
@@ -209,13 +229,18 @@ int mcrt_pda_linear(mcrt_ctx* ctx, const uint8_t* mask_dev, const double* rho_de
 int mcrt_pda_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev,
                      double* g_kscale_dev, hipStream_t stream);
 
-/* Escaped luminosity per wavelength bin and |cos i| bin: sed_dev
- * [n_lambda][n_inc] double, erg/s (not divided by the solid angle). */
+/* The spectral energy distribution from the escaping packets (Sect. 3.3
+ * studies it at fixed inclination): escaped luminosity per wavelength bin and
+ * |cos i| bin of the packet's direction, sed_dev [n_lambda][n_inc] double,
+ * erg/s (not divided by the solid angle; each bin is 1/n_inc of the folded
+ * |cos i| range).  Errors: MCRT_E_ARG for a null argument. */
 int mcrt_sed(mcrt_ctx* ctx, double* sed_dev, hipStream_t stream);
 
-/* Cell of each point: xyz_dev [n][3] double, cell_dev [n] int32 (-1 outside
- * the grid).  r^2 = (x*x + y*y) + z*z and z*z against mu_e^2 r^2, no fused
- * multiply-add, half-open cells [r_e, r_e+1) x [mu_e, mu_e+1). */
+/* Cell of each point on the axisymmetric (r, theta) grid the transport steps
+ * through (Sect. 2.1; the disk of Sect. 2.4): xyz_dev [n][3] double, cell_dev
+ * [n] int32 (-1 outside the grid).  r^2 = (x*x + y*y) + z*z and z*z against
+ * mu_e^2 r^2, no fused multiply-add, half-open cells [r_e, r_e+1) x
+ * [mu_e, mu_e+1).  Errors: MCRT_E_ARG for n < 0 or a null pointer with n > 0. */
 int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_dev,
                 hipStream_t stream);
 
@@ -232,8 +257,14 @@ int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_d
 #define MCRT_GET_RHO 9      /* double [n_cells], the context's current dust density */
 #define MCRT_GET_TABLES 8   /* double: T nodes [n_T], cdf [n_T][n_lambda], D*rho [n_T],
                                kappa-bar [n_T], star cdf [n_lambda], L_star [1] */
+#define MCRT_GET_HYDRO_COLD 10 /* uint32 [1]: shells the last hydrostatic step left
+                                  unchanged (an opaque dust cell at T <= 0) */
 
-/* Copy a context array into caller device memory (async, device to device). */
+/* Copy a context array into caller device memory (async, device to device):
+ * the Monte Carlo tallies of Sect. 2.1 (absorbed energy, visits, absorption
+ * and MRW counts), the temperature, the PDA region of Sect. 2.2.1, the event
+ * counters, the tables of Sect. 2.2.3 and the density.  Errors: MCRT_E_ARG for
+ * a null argument or an unknown `what`. */
 int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream);
 /* Size in bytes of what mcrt_get(what) writes. */
 int64_t mcrt_get_size(mcrt_ctx* ctx, int what);
@@ -242,7 +273,7 @@ int64_t mcrt_get_size(mcrt_ctx* ctx, int what);
  * field): T_dev [n_cells] double. */
 int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
 
-/* Vertical hydrostatic equilibrium (Sect. 3.4, eq. balance: dP/dz =
+/* Vertical hydrostatic equilibrium (Sect. 2.5, eq. balance: dP/dz =
  * -rho G M_star z / R^3, P = k rho T / (mu_mol m_p)) for the context's
  * current temperature (floored at T_lo): along each radial shell at its mid
  * radius r, through the cell centres (z = r mu, R = r sqrt(1 - mu^2)),
@@ -251,7 +282,12 @@ int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream);
  * (the surface density stays fixed).  Replaces the context's density (and
  * the cell masses the temperature inversion uses); rho_dev (nullable)
  * [n_cells] double receives a copy.  M_star in g.  One iteration of the
- * method's vertical-structure loop; tracing again gives the next T.
+ * method's vertical-structure loop; tracing again gives the next T.  A shell
+ * holding an opaque dust cell (optical width >= 1, as for pda_sigma) at T <= 0
+ * has no temperature to balance and keeps its density (counted in
+ * MCRT_GET_HYDRO_COLD): the region rule with pda_sigma > 0 fills such cells by
+ * the PDA first, as the paper does (Sect. 3.4, Case 3).  Transparent cold
+ * cells are floored at T_lo like any lower temperature.
  * Errors: MCRT_E_ARG for a null context, M_star < 0 or mu_mol <= 0. */
 int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_dev,
                      hipStream_t stream);
@@ -269,16 +305,32 @@ int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_de
  * use_graph != 0 captures all passes in one HIP graph and submits it once.
  * Contexts whose hydro_M_star is > 0 end every pass with the vertical
  * hydrostatic equilibrium of their density for that pass's final T (the
- * method's vertical-structure loop, Sect. 3.4).
+ * method's vertical-structure loop, Sect. 2.5).
  * Every context must use MCRT_FP32 with g_asym = 0 and live on the current
  * device (else MCRT_E_ARG).  stats
  * (host, nullable) receives each disk's PDA statistics of the last pass.
- * Synchronous: returns after the stream has drained.  The n-iteration
- * outer loop of the method (Sect. 2.5: radiative transfer repeated on an
- * updated structure) run for a batch of models. */
+ * Synchronous: returns after the stream has drained, then reports, over every
+ * pass and disk: MCRT_E_NOT_CONVERGED if a PDA solve hit cg_max_iter or its
+ * Picard sweeps did not reach pda_tol, else MCRT_E_STUCK if packets hit
+ * max_events (the tallies of the last pass stay readable either way).  A
+ * linear PDA solve kept for mcrt_pda_adjoint is dropped (its scratch is
+ * reused).  The n-iteration outer loop of the method (Sect. 2.5: radiative
+ * transfer repeated on an updated structure) run for a batch of models. */
 int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
                    const uint64_t* seeds, int n_iter, int use_graph, mcrt_pda_stats* stats,
                    hipStream_t stream);
+
+/* The PDA step of mcrt_batch_run alone (Sect. 2.2.1, eq. T diffusion; the
+ * region rule of each context, Sect. 3.1): every context's region solved from
+ * the temperature the context holds (Dirichlet data and first guess), one
+ * workgroup per disk, all disks in one launch, in place on each context's T
+ * and region.  Every context needs pda_visits > 0 or pda_sigma > 0 and the
+ * current device (else MCRT_E_ARG).  stats (host, nullable) [n_disks].
+ * Synchronous.  Returns MCRT_E_NOT_CONVERGED if a solve hit a cap, else
+ * MCRT_E_SINGULAR_REGION (informational) if a region part of some disk had no
+ * Dirichlet neighbour.  A linear PDA solve kept for mcrt_pda_adjoint is
+ * dropped. */
+int mcrt_batch_pda(mcrt_ctx** ctxs, int n_disks, mcrt_pda_stats* stats, hipStream_t stream);
 
 const char* mcrt_strerror(int code);
 const char* mcrt_last_error(void);

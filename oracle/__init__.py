@@ -57,7 +57,8 @@ class _Tables(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("mrw", C.c_int), ("gamma", C.c_double), ("n_int_min", C.c_int),
-                ("n_inc", C.c_int), ("max_events", C.c_longlong), ("frozen_T", C.c_void_p)]
+                ("n_inc", C.c_int), ("max_events", C.c_longlong), ("frozen_T", C.c_void_p),
+                ("coef_T", C.c_void_p)]
 
 
 REC_DTYPE = np.dtype([("fate", np.int32), ("k", np.int32), ("n_cross", np.int64),
@@ -122,7 +123,7 @@ def lib():
         L.ora_run.argtypes = [vp, vp, vp, u64, u64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         L.ora_cell_volumes.argtypes = [vp, vp]
         L.ora_update_T.argtypes = [vp, vp, vp, vp]
-        L.ora_pda.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, dbl, vp, vp]
+        L.ora_pda.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, dbl, vp, vp, vp]
         L.ora_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ora_pda_grad_direct.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
         _lib = L
@@ -229,9 +230,12 @@ class Oracle:
     # -- transport --------------------------------------------------------
     def run(self, n_packets: int, seed: int, *, n_total: int = None, offset: int = 0,
             mrw: bool = False, gamma: float = 3.0, n_int_min: int = 20, n_inc: int = 10,
-            max_events: int = 1 << 30, frozen_T=None, n_recs: int = 0, state=None):
+            max_events: int = 1 << 30, frozen_T=None, n_recs: int = 0, state=None,
+            coef_T=None):
         """Trace packets [offset, offset+n_packets) of a run of n_total packets.
-        `state` (a previous result) accumulates tallies across calls."""
+        `state` (a previous result) accumulates tallies across calls.  coef_T:
+        temperatures for the MRW's coefficients and criterion (a previous
+        pass's) instead of the running cell temperature."""
         n_total = n_packets if n_total is None else n_total
         nc, nl = self.n_cells, self.n_lambda
         if state is None:
@@ -242,8 +246,11 @@ class Oracle:
         fz = None
         if frozen_T is not None:
             fz = np.ascontiguousarray(frozen_T, dtype=np.float64)
+        ct = None
+        if coef_T is not None:
+            ct = np.ascontiguousarray(coef_T, dtype=np.float64)
         opts = _Opts(int(mrw), float(gamma), int(n_int_min), int(n_inc), int(max_events),
-                     _p(fz) if fz is not None else None)
+                     _p(fz) if fz is not None else None, _p(ct) if ct is not None else None)
         recs = np.zeros(max(n_recs, 1), REC_DTYPE)
         lib().ora_run(C.byref(self.model), C.byref(self.tables), C.byref(opts), n_packets,
                       n_total, seed, offset, _p(state["E_abs"]), _p(state["visits"]),
@@ -300,11 +307,13 @@ class Oracle:
         reg_out = np.empty(self.n_cells, np.uint8)
         sweeps = C.c_int(0)
         change = C.c_double(0.0)
+        conv = C.c_int(0)
         rc = lib().ora_pda(C.byref(self.model), C.byref(self.tables), _p(T_mc), _p(reg),
                            _p(T_out), _p(reg_out), max_sweeps, tol, C.byref(sweeps),
-                           C.byref(change))
+                           C.byref(change), C.byref(conv))
         if rc != 0:
             raise RuntimeError("oracle PDA: matrix not positive definite")
+        self.last_pda_converged = bool(conv.value)
         return T_out, reg_out, sweeps.value, change.value
 
     def pda_linear(self, T_D, T_bc, region, kscale=None):

@@ -547,19 +547,38 @@ void ora_cell_volumes(const ora_model* m, double* V) {
   }
 }
 
-/* Vertical hydrostatic equilibrium (Sect. 3.4, eq. balance): dP/dz =
+/* Optical width of cell c at its most opaque wavelength: rho chi_max l with
+ * l the cell's smallest width -- radial r_{i+1} - r_i, or polar r_c times its
+ * angular width (the midplane row spans both hemispheres: twice its half
+ * width).  Below 1 the cell is transparent at every wavelength. */
+static double cell_optical_width(const ora_model* m, int c) {
+  int i = c / m->n_mu, j = c % m->n_mu;
+  double chi = 0.0;
+  for (int k = 0; k < m->n_lambda; ++k) {
+    double x = m->kappa_abs[k] + m->kappa_sca[k];
+    if (x > chi) chi = x;
+  }
+  double rc = 0.5 * (m->r_edges[i] + m->r_edges[i + 1]);
+  double wr = m->r_edges[i + 1] - m->r_edges[i];
+  double wt = rc * (acos(m->mu_edges[j]) - acos(m->mu_edges[j + 1])) * (j == 0 ? 2.0 : 1.0);
+  return m->rho[c] * chi * (wr < wt ? wr : wt);
+}
+
+/* Vertical hydrostatic equilibrium (Sect. 2.5, eq. balance): dP/dz =
  * -rho G M z / R^3 with P = k rho T / (mu_mol m_p), along each radial shell
  * of the grid at its mid radius r (z = r mu, R = r sqrt(1 - mu^2)) through
  * the cell centres:
  *   ln(rho_j T_j) - ln(rho_{j-1} T_{j-1}) = -(mu_mol m_p G M / k) * integral of
  *   z / (R^3 T) dz, by the trapezoidal rule between consecutive centres,
  * with T floored at T_floor.  Each shell keeps its mass (the surface density
- * is held fixed while the vertical profile is solved).  A shell holding a
- * dust-bearing cell without a temperature (T <= 0: no packet was absorbed
- * there) cannot be balanced -- a zero temperature would collapse its scale
- * height, which is why the paper first fills such cells by the PDA
- * (Sect. 4, Case 3 of the vertical-structure study) -- so it keeps its
- * density; the count of such shells is returned. */
+ * is held fixed while the vertical profile is solved).  A shell holding an
+ * optically thick dust cell without a temperature (T <= 0: no packet was
+ * absorbed there) cannot be balanced -- a zero temperature would collapse
+ * its scale height, which is why the paper first fills such cells by the PDA
+ * (Sect. 3.4, Case 3 of the vertical-structure study) -- so it keeps its
+ * density; the count of such shells is returned.  A cold cell transparent at
+ * every wavelength holds no mass worth the name and is floored like any T
+ * below T_floor. */
 static const double G_GRAV = 6.67430e-8;
 static const double M_PROTON = 1.67262192369e-24;
 
@@ -575,7 +594,7 @@ int ora_hydrostatic(const ora_model* m, const double* T, double M_star, double m
     int cold = 0;
     for (int j = 0; j < nmu; ++j) {
       const size_t c = (size_t)i * nmu + j;
-      if (m->rho[c] > 0.0 && !(T[c] > 0.0)) cold = 1;
+      if (m->rho[c] > 0.0 && !(T[c] > 0.0) && cell_optical_width(m, (int)c) >= 1.0) cold = 1;
     }
     if (cold) {
       for (int j = 0; j < nmu; ++j) rho_out[(size_t)i * nmu + j] = m->rho[(size_t)i * nmu + j];
@@ -755,7 +774,8 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
       if (o->mrw) {
         for (;;) {
           if (n_int < o->n_int_min) break;
-          double Tc = o->frozen_T ? o->frozen_T[c] : T_of_g(t, nl, E_abs[c] * inv4pim[c]);
+          double Tc = o->frozen_T ? o->frozen_T[c]
+                      : o->coef_T ? o->coef_T[c] : T_of_g(t, nl, E_abs[c] * inv4pim[c]);
           double Drho = t_interp(t, t->Drho, Tc);
           double lam_R = 3.0 * Drho / m->rho[c]; /* 1/(rho chi_R) */
           double dmin = min_face_distance(m, i, j, p);
@@ -923,7 +943,7 @@ static int band_cholesky_solve(int n, int bw, double* band, double* x) {
  * Dirichlet = T_bc^4.  kscale scales chi per cell (NULL = 1). */
 static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geom* g,
                           const uint8_t* reg, const double* T_D, const double* T_bc,
-                          const double* kscale, double* u) {
+                          const double* kscale, int skip_cold, double* u) {
   int nr = m->n_r, nmu = m->n_mu, n = nr * nmu, bw = nmu;
   double* band = (double*)calloc((size_t)n * (bw + 1), sizeof(double));
   double* R = (double*)malloc(sizeof(double) * n);
@@ -949,6 +969,8 @@ static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geo
       if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
       int cb = ib * nmu + jb;
       if (!(m->rho[cb] > 0.0)) continue;
+      /* a neighbour without a temperature gives no boundary value */
+      if (skip_cold && reg[cb] != 1 && !(T_bc[cb] > 0.0)) continue;
       double a = face_cond(g, i, j, ib, jb, R[c], R[cb]);
       diag += a;
       if (reg[cb] == 1) {
@@ -966,8 +988,9 @@ static int pda_solve_once(const ora_model* m, const ora_tables* t, const pda_geo
 }
 
 /* cells of `reg` (value 1) whose connected component touches no usable
- * Dirichlet neighbour are set to 2 */
-static void pda_components(const ora_model* m, uint8_t* reg) {
+ * Dirichlet neighbour (dust-bearing, outside the region, and with T > 0 when
+ * T is given) are set to 2 */
+static void pda_components(const ora_model* m, const double* T, uint8_t* reg) {
   int nr = m->n_r, nmu = m->n_mu, n = nr * nmu;
   int* comp = (int*)malloc(sizeof(int) * n);
   int* stack = (int*)malloc(sizeof(int) * n);
@@ -990,7 +1013,7 @@ static void pda_components(const ora_model* m, uint8_t* reg) {
         if (!(m->rho[cb] > 0.0)) continue;
         if (reg[cb] == 1) {
           if (comp[cb] < 0) { comp[cb] = c0; stack[top++] = cb; }
-        } else {
+        } else if (!T || T[cb] > 0.0) {
           touches = 1;
         }
       }
@@ -1004,10 +1027,15 @@ static void pda_components(const ora_model* m, uint8_t* reg) {
 }
 
 /* Region of the PDA (Sect. 2.2.1): the cells whose Monte Carlo temperature
- * is not trusted.  Sect. 4 uses two tests: few packets entered the cell, or
+ * is not trusted.  Sect. 3.1 uses two tests: few packets entered the cell, or
  * the photon statistics leave a large relative error in its temperature.
  * With N absorption events the absorbed energy has relative error 1/sqrt(N)
- * and T ~ E^(1/4) has 1/(4 sqrt(N)); a cell without events has no estimate. */
+ * and T ~ E^(1/4) has 1/(4 sqrt(N)); a cell without events has no estimate.
+ * The diffusion approximation holds only in opaque matter, so the second
+ * test takes only cells of optical width >= 1 at their most opaque
+ * wavelength (the first test's few-visit cells are shielded anyway): a
+ * nearly empty cell of the disk's atmosphere absorbs few packets because it
+ * is transparent, not because it is shielded. */
 void ora_pda_region(const ora_model* m, const uint32_t* visits, const uint32_t* n_abs,
                     const uint32_t* n_mrw, int visits_min, double sigma_max, uint8_t* region) {
   int n = m->n_r * m->n_mu;
@@ -1015,7 +1043,7 @@ void ora_pda_region(const ora_model* m, const uint32_t* visits, const uint32_t* 
     int in = 0;
     if (m->rho[c] > 0.0) {
       if ((int64_t)visits[c] < (int64_t)visits_min) in = 1;
-      if (sigma_max > 0.0) {
+      if (sigma_max > 0.0 && cell_optical_width(m, c) >= 1.0) {
         double N = (double)n_abs[c] + (double)n_mrw[c];
         if (N == 0.0 || 1.0 / (4.0 * sqrt(N)) > sigma_max) in = 1;
       }
@@ -1026,10 +1054,10 @@ void ora_pda_region(const ora_model* m, const uint32_t* visits, const uint32_t* 
 
 int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc, const uint8_t* region_in,
             double* T_out, uint8_t* region_out, int max_sweeps, double tol, int* n_sweeps,
-            double* last_change) {
+            double* last_change, int* converged) {
   int nr = m->n_r, nmu = m->n_mu, n = nr * nmu;
   for (int c = 0; c < n; ++c) region_out[c] = (region_in[c] && m->rho[c] > 0.0) ? 1 : 0;
-  pda_components(m, region_out);
+  pda_components(m, T_mc, region_out);
   /* floor for the initial guess: the smallest Dirichlet temperature */
   double Tfloor = INFINITY;
   for (int c = 0; c < n; ++c) {
@@ -1040,7 +1068,8 @@ int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc, const u
       int ib = nb[q][0], jb = nb[q][1];
       if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
       int cb = ib * nmu + jb;
-      if (m->rho[cb] > 0.0 && region_out[cb] != 1 && T_mc[cb] < Tfloor) Tfloor = T_mc[cb];
+      if (m->rho[cb] > 0.0 && region_out[cb] != 1 && T_mc[cb] > 0.0 && T_mc[cb] < Tfloor)
+        Tfloor = T_mc[cb];
     }
   }
   if (!isfinite(Tfloor)) Tfloor = 0.0;
@@ -1049,10 +1078,15 @@ int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc, const u
   pda_geom g;
   pda_geom_init(m, &g);
   double* u = (double*)malloc(sizeof(double) * n);
-  int sweeps = 0, rc = 0;
-  double change = 0.0;
+  /* Picard sweeps: D from the current T, one linear solve, new T.  They stop
+   * when the largest relative change falls below tol, or when it stalls below
+   * sqrt(tol): a sweep that changes T no less than the previous one has
+   * reached the rounding floor of the linear solve (the operator couples thin
+   * and thick cells with conductances many orders apart). */
+  int sweeps = 0, rc = 0, conv = 0;
+  double change = 0.0, prev = INFINITY;
   for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
-    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, u);
+    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, 1, u);
     if (rc) break;
     change = 0.0;
     for (int c = 0; c < n; ++c) {
@@ -1062,11 +1096,16 @@ int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc, const u
       if (ch > change) change = ch;
       T_out[c] = Tn;
     }
-    if (change < tol) break;
+    if (change < tol || (change < sqrt(tol) && change >= prev)) {
+      conv = 1;
+      break;
+    }
+    prev = change;
   }
   if (sweeps > max_sweeps) sweeps = max_sweeps;
   *n_sweeps = sweeps;
   *last_change = change;
+  *converged = conv;
   free(u);
   pda_geom_free(&g);
   return rc;
@@ -1080,8 +1119,8 @@ int ora_pda_linear(const ora_model* m, const ora_tables* t, const double* T_D, c
   double* u = (double*)malloc(sizeof(double) * n);
   uint8_t* reg = (uint8_t*)malloc(n);
   for (int c = 0; c < n; ++c) reg[c] = (region[c] && m->rho[c] > 0.0) ? 1 : 0;
-  pda_components(m, reg);
-  int rc = pda_solve_once(m, t, &g, reg, T_D, T_bc, kscale, u);
+  pda_components(m, NULL, reg);
+  int rc = pda_solve_once(m, t, &g, reg, T_D, T_bc, kscale, 0, u);
   for (int c = 0; c < n; ++c) T_out[c] = reg[c] == 1 ? pow(fmax(u[c], 0.0), 0.25) : T_bc[c];
   free(u);
   free(reg);
@@ -1104,7 +1143,7 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
   pda_geom_init(m, &g);
   uint8_t* reg = (uint8_t*)malloc(n);
   for (int c = 0; c < n; ++c) reg[c] = (region_in[c] && m->rho[c] > 0.0) ? 1 : 0;
-  pda_components(m, reg);
+  pda_components(m, NULL, reg);
   double* R = (double*)malloc(sizeof(double) * n);
   double* ks = (double*)malloc(sizeof(double) * n);
   double* ubc = (double*)malloc(sizeof(double) * n);

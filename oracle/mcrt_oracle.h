@@ -51,6 +51,9 @@ typedef struct {
   int n_inc;                   /* SED inclination bins */
   long long max_events;        /* per-packet cap */
   const double* frozen_T;      /* NULL: running (immediate reemission) mode */
+  const double* coef_T;        /* NULL: the MRW takes D, kappa-bar and its criterion at
+                                  the running cell T; else at these temperatures (a
+                                  previous pass's), reemission still running */
 } ora_opts;
 
 typedef struct {
@@ -101,10 +104,11 @@ void ora_cell_volumes(const ora_model* m, double* V);
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T);
 
 /* PDA: region_in[c] = 1 marks candidate cells.  region_out: 1 solved, 2 left at
- * the MC value (no Dirichlet neighbour), 0 outside. */
+ * the MC value (no Dirichlet neighbour), 0 outside.  converged: the Picard
+ * change fell below tol, or stalled below sqrt(tol). */
 int ora_pda(const ora_model* m, const ora_tables* t, const double* T_mc,
             const uint8_t* region_in, double* T_out, uint8_t* region_out,
-            int max_sweeps, double tol, int* n_sweeps, double* last_change);
+            int max_sweeps, double tol, int* n_sweeps, double* last_change, int* converged);
 
 /* One linear PDA solve with the diffusion coefficient frozen at T_D (the
  * differentiation workload): u = T^4 on the region, Dirichlet T_bc outside. */
@@ -123,15 +127,16 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
 /* Vertical hydrostatic equilibrium of each radial shell for the cell
  * temperatures T [n_cells] (floored at T_floor), star mass M_star (g) and mean
  * molecular weight mu_mol; each shell keeps the mass of m->rho.  rho_out
- * [n_cells].  Shells with a dust-bearing cell at T <= 0 keep m->rho; returns
- * their number. */
+ * [n_cells].  Shells with an optically thick (width >= 1 at the most opaque
+ * wavelength) dust cell at T <= 0 keep m->rho; returns their number. */
 int ora_hydrostatic(const ora_model* m, const double* T, double M_star, double mu_mol,
                     double T_floor, double* rho_out);
 
-/* The PDA region of a finished Monte Carlo run (Sect. 2.2.1; Sect. 4): a
+/* The PDA region of a finished Monte Carlo run (Sect. 2.2.1; Sect. 3.1): a
  * dust-bearing cell joins when fewer than visits_min packets entered it, or
- * when the relative photon noise of its temperature, 1 / (4 sqrt(N)) with N
- * its absorption events (absorptions plus MRW deposits), exceeds sigma_max
+ * when it is optically thick (width >= 1 at its most opaque wavelength) and
+ * the relative photon noise of its temperature, 1 / (4 sqrt(N)) with N its
+ * absorption events (absorptions plus MRW deposits), exceeds sigma_max
  * (sigma_max <= 0: that branch off).  region [n_cells] gets 1 or 0. */
 void ora_pda_region(const ora_model* m, const uint32_t* visits, const uint32_t* n_abs,
                     const uint32_t* n_mrw, int visits_min, double sigma_max, uint8_t* region);

@@ -20,11 +20,17 @@ class PDAFunction(torch.autograd.Function):
         ks = kscale.detach().contiguous()
         T, _ = ctx.pda_linear(mask, T_D.contiguous(), T_bc.contiguous(), rho=rho, kscale=ks)
         fctx.mcrt_ctx = ctx
-        fctx.keep = (rho, ks)   # the saved solve refers to these buffers
+        fctx.gen = ctx._lin_gen  # the context keeps only its latest linear solve
+        fctx.keep = (rho, ks)    # the saved solve refers to these buffers
         return T
 
     @staticmethod
     def backward(fctx, grad_T):
+        if fctx.mcrt_ctx._lin_gen != fctx.gen:
+            raise RuntimeError(
+                "pda_temperature: the context has run another PDA solve, batch or hydrostatic "
+                "step since this forward; its adjoint would differentiate that instead "
+                "(use one context per forward kept for backward)")
         g_logrho, g_ks = fctx.mcrt_ctx.pda_adjoint(grad_T.contiguous())
         return g_logrho, g_ks, None, None, None, None
 

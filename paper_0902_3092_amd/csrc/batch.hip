@@ -19,6 +19,12 @@ int fail_batch(int code, const std::string& msg) {
   mcrt::set_error(nullptr, msg);
   return code;
 }
+
+// After a pass's trace: add its capped packets to the context's running sum
+// (the pass's counters are cleared when the next pass starts).
+__global__ void add_capped_kernel(const unsigned long long* counters, mcrt::DevHealth* h) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) h->capped += counters[mcrt::C_CAPPED];
+}
 }  // namespace
 
 extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
@@ -115,6 +121,16 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
     return fail_batch(MCRT_E_HIP, "batch argument upload");
   }
   mcrt::prepare_trace_fp32_batch(lds, cdf_lds);
+  // outcome counters of this batch; the batch overwrites the PDA scratch (and,
+  // with the hydrostatic step, the density) that a linear PDA solve left for
+  // its adjoint
+  for (int d = 0; d < n_disks; ++d) {
+    ctxs[d]->lin_ready = false;
+    if (mcrt::launch_zero(ctxs[d]->d_health, sizeof(mcrt::DevHealth), s) != MCRT_OK) {
+      (void)hipFree(blob);
+      return fail_batch(MCRT_E_HIP, "clearing the batch counters failed");
+    }
+  }
   // the passes
   auto enqueue = [&](hipStream_t s) -> int {
     for (int it = 0; it < n_iter; ++it) {
@@ -138,6 +154,11 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
       r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd, n_disks,
                                             (int)block_disk.size(), lds, cdf_lds, s);
       if (r) return r;
+      for (int d = 0; d < n_disks; ++d) {
+        hipLaunchKernelGGL(add_capped_kernel, dim3(1), dim3(64), 0, s, ctxs[d]->t.counters,
+                           ctxs[d]->d_health);
+        if (hipGetLastError() != hipSuccess) return MCRT_E_HIP;
+      }
       for (int d = 0; d < n_disks; ++d) {
         r = mcrt::launch_update_T(ctxs[d], s);
         if (r) return r;
@@ -195,6 +216,85 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
   if (status == MCRT_OK)
     for (int d = 0; d < n_disks; ++d)
       if (ctxs[d]->opt.mrw_coef_T == 1) ctxs[d]->have_T_prev = true;
+  // the outcome of every pass: a PDA solve that hit its iteration cap, or
+  // packets that hit the event cap, in any pass of any disk
+  if (status == MCRT_OK) {
+    unsigned long long fails = 0, capped = 0;
+    int first_fail = -1, first_capped = -1;
+    for (int d = 0; d < n_disks && status == MCRT_OK; ++d) {
+      mcrt::DevHealth h{};
+      if (hipMemcpy(&h, ctxs[d]->d_health, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+        status = MCRT_E_HIP;
+        break;
+      }
+      if (h.pda_fails && first_fail < 0) first_fail = d;
+      if (h.capped && first_capped < 0) first_capped = d;
+      fails += h.pda_fails;
+      capped += h.capped;
+    }
+    if (status == MCRT_OK && fails) {
+      status = fail_batch(MCRT_E_NOT_CONVERGED,
+                          std::to_string(fails) + " PDA solve(s) hit an iteration cap (first: disk " +
+                              std::to_string(first_fail) + ")");
+    } else if (status == MCRT_OK && capped) {
+      status = fail_batch(MCRT_E_STUCK, std::to_string(capped) +
+                                            " packet(s) hit the event cap (first: disk " +
+                                            std::to_string(first_capped) + ")");
+    }
+  }
   (void)hipFree(blob);
+  return status;
+}
+
+// The PDA step of a batched pass alone: every context's region (its rule on
+// its current tallies) solved from its current temperature, one workgroup per
+// disk, all disks in one launch.
+extern "C" int mcrt_batch_pda(mcrt_ctx** ctxs, int n_disks, mcrt_pda_stats* stats,
+                              hipStream_t s) {
+  if (!ctxs || n_disks < 1) return fail_batch(MCRT_E_ARG, "bad batch arguments");
+  for (int d = 0; d < n_disks; ++d) {
+    if (!ctxs[d]) return fail_batch(MCRT_E_ARG, "null context");
+    if (ctxs[d]->device != ctxs[0]->device) return fail_batch(MCRT_E_ARG, "contexts on one device");
+    if (ctxs[d]->opt.pda_visits <= 0 && !(ctxs[d]->opt.pda_sigma > 0.0))
+      return fail_batch(MCRT_E_ARG, "a context has no PDA region rule (pda_visits, pda_sigma)");
+  }
+  const size_t pda_bytes = mcrt::pda_wg_args_size() * n_disks;
+  std::vector<char> host(pda_bytes);
+  int rc = mcrt::pda_batch_fill(ctxs, n_disks, host.data());
+  if (rc) return rc;
+  void* blob = nullptr;
+  if (hipMalloc(&blob, pda_bytes) != hipSuccess) return fail_batch(MCRT_E_OOM, "batch arguments");
+  int status = MCRT_OK;
+  if (hipMemcpy(blob, host.data(), pda_bytes, hipMemcpyHostToDevice) != hipSuccess)
+    status = fail_batch(MCRT_E_HIP, "batch argument upload");
+  for (int d = 0; d < n_disks && status == MCRT_OK; ++d) {
+    ctxs[d]->lin_ready = false;
+    if (mcrt::launch_zero(ctxs[d]->d_health, sizeof(mcrt::DevHealth), s) != MCRT_OK)
+      status = fail_batch(MCRT_E_HIP, "clearing the batch counters failed");
+  }
+  if (status == MCRT_OK && mcrt::pda_batch_launch(blob, n_disks, s) != MCRT_OK)
+    status = fail_batch(MCRT_E_HIP, "batched PDA launch failed");
+  if (hipStreamSynchronize(s) != hipSuccess && status == MCRT_OK)
+    status = fail_batch(MCRT_E_HIP, "batched PDA failed");
+  bool isolated = false;
+  unsigned fails = 0;
+  for (int d = 0; d < n_disks && status == MCRT_OK; ++d) {
+    mcrt_pda_stats st{};
+    mcrt::DevHealth h{};
+    if (hipMemcpy(&st, mcrt::pda_stats_slot(ctxs[d]), sizeof(st), hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(&h, ctxs[d]->d_health, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+      status = fail_batch(MCRT_E_HIP, "reading the batched PDA statistics failed");
+      break;
+    }
+    if (stats) stats[d] = st;
+    isolated |= st.n_isolated > 0;
+    fails += h.pda_fails;
+  }
+  (void)hipFree(blob);
+  if (status == MCRT_OK && fails)
+    status = fail_batch(MCRT_E_NOT_CONVERGED,
+                        std::to_string(fails) + " PDA solve(s) hit an iteration cap");
+  if (status == MCRT_OK && isolated) status = MCRT_E_SINGULAR_REGION;
   return status;
 }

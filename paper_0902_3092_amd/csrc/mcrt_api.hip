@@ -236,6 +236,7 @@ void mcrt_default_options(mcrt_options* o) {
   o->g_asym = 0.0;
   o->hydro_M_star = 0.0;
   o->hydro_mu = 2.3;
+  o->pda_sigma = 0.0;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -264,7 +265,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
       opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0 ||
       !(opt->g_asym > -1.0 && opt->g_asym < 1.0) || !(opt->hydro_M_star >= 0.0) ||
-      !(opt->hydro_mu > 0.0))
+      !(opt->hydro_mu > 0.0) || !(opt->pda_sigma >= 0.0))
     return fail(nullptr, MCRT_E_ARG, "bad options");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)
@@ -390,6 +391,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
     mu2[e] = grid->mu_edges[e] * grid->mu_edges[e];
     smu[e] = std::sqrt(1.0 - grid->mu_edges[e] * grid->mu_edges[e]);
   }
+  std::vector<double> cell_len(nc);
   for (int i = 0; i < n_r; ++i) {
     double a = grid->r_edges[i], b = grid->r_edges[i + 1];
     double dr3 = b * b * b - a * a * a;
@@ -397,8 +399,14 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       double V = 4.0 * PI / 3.0 * dr3 * (grid->mu_edges[j + 1] - grid->mu_edges[j]);
       double mass = rho[i * n_mu + j] * V;
       inv4pim[i * n_mu + j] = mass > 0.0 ? 1.0 / (4.0 * PI * mass) : 0.0;
+      const double rc = 0.5 * (a + b), wr = b - a;
+      const double wt = rc * (std::acos(grid->mu_edges[j]) - std::acos(grid->mu_edges[j + 1])) *
+                        (j == 0 ? 2.0 : 1.0);
+      cell_len[i * n_mu + j] = wr < wt ? wr : wt;
     }
   }
+  double chi_max = 0.0;
+  for (int k = 0; k < nl; ++k) chi_max = std::max(chi_max, chi[k]);
 
   // ---------------- device blob
   struct Part {
@@ -420,6 +428,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   M.inv_du = inv_du;
   M.R_star = star->R_star;
   M.L_star = ctx->L_star;
+  M.chi_max = chi_max;
   std::vector<Part> parts = {
       {grid->r_edges, (n_r + 1) * sizeof(double), (void**)&M.r_edges},
       {r2.data(), (n_r + 1) * sizeof(double), (void**)&M.r2},
@@ -444,6 +453,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       {guide.data(), guide.size() * sizeof(int), (void**)&M.g_guide},
       {inv_dT.data(), nT * sizeof(double), (void**)&M.inv_dT},
       {g_slope.data(), nT * sizeof(double), (void**)&M.g_slope},
+      {cell_len.data(), nc * sizeof(double), (void**)&M.cell_len},
   };
   size_t total = 0;
   for (auto& p : parts) total += al(p.bytes);
@@ -467,7 +477,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   // tallies + state
   size_t nd = nc * sizeof(double), nu = nc * sizeof(uint32_t);
   size_t tb = al(nd) + 3 * al(nu) + al((size_t)nl * opt->n_inc * sizeof(double)) + al(8) +
-              al(mcrt::N_COUNTERS * 8) + al(8) + 2 * al(nd) + al(nc);
+              al(mcrt::N_COUNTERS * 8) + al(8) + 2 * al(nd) + al(nc) + al(sizeof(mcrt::DevHealth));
   if (hipMalloc(&ctx->d_tally_blob, tb) != hipSuccess) {
     mcrt_destroy(ctx);
     return fail(nullptr, MCRT_E_OOM, "device allocation of the tallies failed");
@@ -483,7 +493,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   ctx->d_next = (unsigned long long*)q; q += al(8);
   ctx->d_T = (double*)q; q += al(nd);
   ctx->d_T_prev = (double*)q; q += al(nd);
-  ctx->d_region = (uint8_t*)q;
+  ctx->d_region = (uint8_t*)q; q += al(nc);
+  ctx->d_health = (mcrt::DevHealth*)q;
   if (hipMalloc(&ctx->d_tail, (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES + 256) != hipSuccess) {
     mcrt_destroy(ctx);
     return fail(nullptr, MCRT_E_OOM, "device allocation of the hand-off buffer failed");
@@ -551,8 +562,8 @@ int mcrt_update_T(mcrt_ctx* ctx, double* T_dev, hipStream_t stream) {
 int mcrt_pda_solve(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats,
                    hipStream_t stream) {
   if (!ctx) return fail(nullptr, MCRT_E_ARG, "null context");
-  if (!mask_dev && ctx->opt.pda_visits <= 0)
-    return fail(ctx, MCRT_E_ARG, "no PDA mask and pda_visits <= 0");
+  if (!mask_dev && ctx->opt.pda_visits <= 0 && !(ctx->opt.pda_sigma > 0.0))
+    return fail(ctx, MCRT_E_ARG, "no PDA mask, pda_visits <= 0 and pda_sigma = 0");
   return mcrt::pda_solve(ctx, mask_dev, stats, stream);
 }
 
@@ -600,6 +611,7 @@ int64_t mcrt_get_size(mcrt_ctx* ctx, int what) {
     case MCRT_GET_E_STAR: return 8;
     case MCRT_GET_TABLES: return (nT + nT * nl + nT + nT + nl + 1) * 8;
     case MCRT_GET_RHO: return nc * 8;
+    case MCRT_GET_HYDRO_COLD: return 4;
     default: return -1;
   }
 }
@@ -616,6 +628,7 @@ int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream) {
     case MCRT_GET_REGION: src = ctx->d_region; break;
     case MCRT_GET_COUNTERS: src = ctx->t.counters; break;
     case MCRT_GET_RHO: src = ctx->m.rho; break;
+    case MCRT_GET_HYDRO_COLD: src = &ctx->d_health->hydro_cold; break;
     case MCRT_GET_E_STAR: src = ctx->t.E_star; break;
     case MCRT_GET_TABLES: {
       int64_t nT = ctx->opt.n_T, nl = ctx->n_lambda;

@@ -46,6 +46,10 @@ struct DevModel {
   const int* g_guide;      // [N_GUIDE] largest n with G[n] <= exp(lnG0 + b / inv_du)
   const double* inv_dT;    // [n_T] 1 / (T[n+1] - T[n])  (last entry unused)
   const double* g_slope;   // [n_T] (T[n+1] - T[n]) / (G[n+1] - G[n])
+  const double* cell_len;  // [n_cells] smallest width of the cell (radial, or polar with
+                           // the midplane row spanning both hemispheres)
+  double chi_max;          // largest extinction per mass over the bins: a cell's optical
+                           // width at its most opaque wavelength is (rho chi_max) cell_len
   double lnT_lo, inv_dlnT; // T nodes 1..n_T-1 = T_lo exp((n-1) dlnT)
   double lnG0, inv_du;     // guide bins over ln g
   double R_star, L_star;
@@ -97,6 +101,14 @@ struct TraceArgs {
 constexpr int TAIL_STATE_BYTES = 512;
 constexpr int TAIL_CAP = 8192;
 
+// Per-context outcome counters that no single call can report itself: kernels
+// of a batched pass (or a graph) run long after the host call returned.
+struct DevHealth {
+  unsigned int hydro_cold;     // shells the last hydrostatic step left unchanged
+  unsigned int pda_fails;      // batched PDA solves that hit a cap since the batch began
+  unsigned long long capped;   // packets capped at max_events, summed over batched passes
+};
+
 }  // namespace mcrt
 
 struct mcrt_ctx {
@@ -111,6 +123,7 @@ struct mcrt_ctx {
   double* d_T = nullptr;        // current temperature
   double* d_T_prev = nullptr;   // temperature of the previous pass (MRW coefficients)
   uint8_t* d_region = nullptr;
+  mcrt::DevHealth* d_health = nullptr;
   unsigned long long* d_next = nullptr;
   void* d_tail = nullptr;             // hand-off buffer of long packets (TAIL_CAP states + count)
   void* d_blob = nullptr;       // model + tables

@@ -23,8 +23,10 @@
 // Picard sweeps on D(T) wrap the solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "mcrt_internal.h"
@@ -63,17 +65,28 @@ __global__ void update_T_kernel(DevModel M, const double* E, double* T, int nc) 
   T[c] = T_from_g(M.G, M.Tn, M.n_T, E[c] * M.inv4pim[c]);
 }
 
-// Vertical hydrostatic equilibrium (Sect. 3.4, eq. balance), one thread per
+// Vertical hydrostatic equilibrium (Sect. 2.5, eq. balance), one thread per
 // radial shell at its mid radius r, through the cell centres (z = r mu,
 // R = r sqrt(1 - mu^2)): ln(rho T) falls by A times the trapezoidal integral
 // of z / (R^3 T) between consecutive centres, A = mu_mol m_p G M / k, T
 // floored at T_floor.  The shell keeps its mass; the cell masses'
-// 1 / (4 pi m) follow.
+// 1 / (4 pi m) follow.  A shell with an optically thick dust cell (width >= 1
+// at its most opaque wavelength) at T <= 0 (no absorption there, so no
+// temperature) is left as it is and counted in *cold: a zero temperature
+// would collapse its scale height.  Cold cells transparent at every
+// wavelength hold next to no mass and are floored like any other.
 __global__ void hydro_kernel(DevModel M, const double* T, double* rho, double* inv4pim, double A,
-                             double T_floor) {
+                             double T_floor, unsigned int* cold) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M.n_r) return;
   const int n_mu = M.n_mu;
+  for (int j = 0; j < n_mu; ++j) {
+    const int c = i * n_mu + j;
+    if (rho[c] > 0.0 && !(T[c] > 0.0) && rho[c] * M.chi_max * M.cell_len[c] >= 1.0) {
+      atomicAdd(cold, 1u);
+      return;
+    }
+  }
   const double PI_ = 3.14159265358979323846;
   const double a = M.r_edges[i], b = M.r_edges[i + 1];
   const double dr3 = b * b * b - a * a * a;
@@ -141,17 +154,55 @@ __device__ inline bool in_grid(int i, int j, int n_r, int n_mu) {
   return i >= 0 && i < n_r && j >= 0 && j < n_mu;
 }
 
-__global__ void pda_region_kernel(DevModel M, const uint8_t* mask, const uint32_t* visits,
-                                  int thr, PdaArrays P) {
+// A neighbour outside the region gives the Monte Carlo solve its boundary
+// value (Sect. 2.2.1) when it holds dust and a temperature: a cell in which no
+// packet was absorbed has none, and its face carries no flux.
+__device__ inline bool gives_bc(const DevModel& M, const uint8_t* region, const double* T_mc,
+                                int cb) {
+  return M.rho[cb] > 0.0 && region[cb] != 1 && T_mc[cb] > 0.0;
+}
+
+// Optical width of cell c at its most opaque wavelength.
+__device__ inline double optical_width(const DevModel& M, int c) {
+  return M.rho[c] * M.chi_max * M.cell_len[c];
+}
+
+// The cells whose Monte Carlo temperature is not trusted (Sect. 3.1): a
+// caller mask, else fewer than thr packet entries, or (sigma > 0) a photon
+// noise 1 / (4 sqrt(N)) of the temperature above sigma, N the cell's
+// absorptions plus MRW deposits (no event: no temperature), in a cell of
+// optical width >= 1 (diffusion holds only in opaque matter; a nearly empty
+// cell absorbs few packets because it is transparent, not shielded).
+// Dust-free cells never join.
+struct RegionRule {
+  const uint8_t* mask;
+  const uint32_t* visits;
+  const uint32_t* n_abs;
+  const uint32_t* n_mrw;
+  int thr;
+  double sigma;
+};
+
+__device__ inline bool in_region(const DevModel& M, const RegionRule& R, int c) {
+  if (!(M.rho[c] > 0.0)) return false;
+  if (R.mask) return R.mask[c] != 0;
+  if (R.thr > 0 && R.visits[c] < (uint32_t)R.thr) return true;
+  if (R.sigma > 0.0 && optical_width(M, c) >= 1.0) {
+    const double N = (double)R.n_abs[c] + (double)R.n_mrw[c];
+    if (N == 0.0 || 1.0 / (4.0 * sqrt(N)) > R.sigma) return true;
+  }
+  return false;
+}
+
+__global__ void pda_region_kernel(DevModel M, RegionRule R, PdaArrays P) {
   int nc = M.n_r * M.n_mu;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  bool in = M.rho[c] > 0.0 && (mask ? mask[c] != 0 : visits[c] < (uint32_t)thr);
-  P.region[c] = in ? 1 : 0;
+  P.region[c] = in_region(M, R, c) ? 1 : 0;
 }
 
-// touch = region cell with a dust-bearing non-region neighbour
-__global__ void pda_touch_kernel(DevModel M, PdaArrays P) {
+// touch = region cell with a neighbour that gives a boundary value
+__global__ void pda_touch_kernel(DevModel M, const double* T_mc, PdaArrays P) {
   int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
@@ -163,7 +214,7 @@ __global__ void pda_touch_kernel(DevModel M, PdaArrays P) {
       int ib = i + di[q], jb = j + dj[q];
       if (!in_grid(ib, jb, n_r, n_mu)) continue;
       int cb = ib * n_mu + jb;
-      if (M.rho[cb] > 0.0 && P.region[cb] != 1) t = 1;
+      if (gives_bc(M, P.region, T_mc, cb)) t = 1;
     }
     atomicAdd(&P.sc->n_region, 1);
   }
@@ -240,7 +291,7 @@ __global__ void pda_floor_kernel(DevModel M, const double* T_mc, PdaArrays P) {
     int ib = i + di[q], jb = j + dj[q];
     if (!in_grid(ib, jb, n_r, n_mu)) continue;
     int cb = ib * n_mu + jb;
-    if (M.rho[cb] > 0.0 && P.region[cb] != 1) m = fmin(m, T_mc[cb]);
+    if (gives_bc(M, P.region, T_mc, cb)) m = fmin(m, T_mc[cb]);
   }
   if (m < INFINITY) atomicMin(&P.sc->floor_bits, (unsigned long long)__double_as_longlong(m));
 }
@@ -308,6 +359,7 @@ __global__ void pda_assemble_kernel(DevModel M, PdaGeom g, PdaArrays P) {
     if (!in_grid(ib, jb, n_r, n_mu)) continue;
     int cb = ib * n_mu + jb;
     if (!(M.rho[cb] > 0.0)) continue;
+    if (P.region[cb] != 1 && !(P.Tbc[cb] > 0.0)) continue;  // no boundary value
     double Rb = Rcell(M, g, P.Tw, cb);
     double A, dist;
     if (q < 2) {
@@ -495,9 +547,7 @@ struct PdaWgArgs {
   DevModel M;
   PdaArrays P;
   PdaGeom g;
-  const uint8_t* mask;      // nullable: visits rule
-  const uint32_t* visits;
-  int thr;
+  RegionRule rule;
   const double* T_mc;       // Monte Carlo temperature (Dirichlet data, initial guess)
   double* T_out;            // region cells overwritten
   uint8_t* reg_out;
@@ -507,6 +557,7 @@ struct PdaWgArgs {
   double cg_tol2;
   int precond;              // 0 diagonal, 1 theta lines
   mcrt_pda_stats* stats;    // device, nullable
+  unsigned int* fails;      // nullable: counts solves that hit a cap (batched passes)
 };
 
 template <bool MAX>
@@ -686,8 +737,7 @@ __device__ int wg_cg(const PdaArrays& P, int n_r, int n_mu, int precond, const d
   return it;
 }
 
-__global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
-  const PdaWgArgs& a = args[blockIdx.x];
+__device__ void pda_wg_body(const PdaWgArgs& a) {
   const DevModel& M = a.M;
   const PdaArrays& P = a.P;
   const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
@@ -695,10 +745,7 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
   __shared__ int changed;
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
   // region and Dirichlet contact
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    bool in = M.rho[c] > 0.0 && (a.mask ? a.mask[c] != 0 : a.visits[c] < (uint32_t)a.thr);
-    P.region[c] = in ? 1 : 0;
-  }
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) P.region[c] = in_region(M, a.rule, c) ? 1 : 0;
   __syncthreads();
   double n_reg = 0.0;
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -709,7 +756,7 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
         int ib = i + di[q], jb = j + dj[q];
         if (!in_grid(ib, jb, n_r, n_mu)) continue;
         int cb = ib * n_mu + jb;
-        if (M.rho[cb] > 0.0 && P.region[cb] != 1) t = 1;
+        if (gives_bc(M, P.region, a.T_mc, cb)) t = 1;
       }
       n_reg += 1.0;
     }
@@ -733,7 +780,7 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
       int ib = i + di[q], jb = j + dj[q];
       if (!in_grid(ib, jb, n_r, n_mu)) continue;
       int cb = ib * n_mu + jb;
-      if (M.rho[cb] > 0.0 && P.region[cb] != 1) mflo = fmax(mflo, -a.T_mc[cb]);
+      if (gives_bc(M, P.region, a.T_mc, cb)) mflo = fmax(mflo, -a.T_mc[cb]);
     }
   }
   double fl = -wg_reduce<true>(mflo, red);
@@ -745,9 +792,12 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
   }
   __syncthreads();
   const int n_solve = (int)(n_reg - n_iso + 0.5);
-  int sweeps = 0, iters_total = 0, iters_last = 0;
-  double change = 0.0, resid = 0.0;
+  int sweeps = 0, iters_total = 0, iters_last = 0, conv = 0;
+  double change = 0.0, resid = 0.0, prev = INFINITY;
   if (n_solve > 0) {
+    // Picard sweeps stop when the largest relative change falls below tol, or
+    // stalls below sqrt(tol) (the rounding floor of the linear solve)
+    const double stall = sqrt(a.tol);
     for (sweeps = 1; sweeps <= a.max_sweeps; ++sweeps) {
       // assemble with D from the current temperature
       for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -764,6 +814,7 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
           if (!in_grid(ib, jb, n_r, n_mu)) continue;
           int cb = ib * n_mu + jb;
           if (!(M.rho[cb] > 0.0)) continue;
+          if (P.region[cb] != 1 && !(P.Tbc[cb] > 0.0)) continue;  // no boundary value
           double Rb = Rcell(M, a.g, P.Tw, cb);
           double A, dist;
           if (q < 2) {
@@ -803,14 +854,22 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
         P.Tw[c] = Tn;
       }
       change = wg_reduce<true>(ch, red);
-      if (change < a.tol) break;
+      if (change < a.tol || (change < stall && change >= prev)) {
+        conv = 1;
+        break;
+      }
+      prev = change;
     }
     if (sweeps > a.max_sweeps) sweeps = a.max_sweeps;
+  } else {
+    conv = 1;
   }
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     if (P.region[c] == 1) a.T_out[c] = P.Tw[c];
     a.reg_out[c] = P.region[c];
   }
+  if (threadIdx.x == 0 && a.fails && (iters_last >= a.cg_max_iter || !conv))
+    atomicAdd(a.fails, 1u);
   if (threadIdx.x == 0 && a.stats) {
     mcrt_pda_stats s;
     s.sweeps = sweeps;
@@ -820,9 +879,17 @@ __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
     s.n_isolated = (int)(n_iso + 0.5);
     s.last_change = change;
     s.last_residual = resid;
+    s.converged = conv;
     *a.stats = s;
   }
 }
+
+// One workgroup per disk, arguments in device memory (batched passes and
+// graph capture).
+__global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
+  pda_wg_body(args[blockIdx.x]);
+}
+
 
 }  // namespace
 
@@ -840,8 +907,13 @@ int launch_update_T(mcrt_ctx* ctx, hipStream_t s) {
 
 int launch_hydrostatic(mcrt_ctx* ctx, double A, double T_floor, hipStream_t s) {
   const int n_r = ctx->n_r;
+  if (launch_zero(&ctx->d_health->hydro_cold, 4, s) != MCRT_OK) {
+    set_error(ctx, "hydrostatic: clearing the cold-shell count failed");
+    return MCRT_E_HIP;
+  }
   hipLaunchKernelGGL(hydro_kernel, dim3((n_r + 63) / 64), dim3(64), 0, s, ctx->m, ctx->d_T,
-                     (double*)ctx->m.rho, (double*)ctx->m.inv4pim, A, T_floor);
+                     (double*)ctx->m.rho, (double*)ctx->m.inv4pim, A, T_floor,
+                     &ctx->d_health->hydro_cold);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(ctx, std::string("hydrostatic launch: ") + hipGetErrorString(e));
@@ -859,6 +931,25 @@ int launch_zero(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
 }
 
+namespace {
+// Geometry of the finite volumes: cell-centre radii and angles, and the areas
+// of the faces r_{i+1} (over the cell's mu range) and mu_{j+1} (over its r
+// range), both hemispheres.  Every PDA solve takes it from this kernel, so
+// all solvers see the same numbers.
+__global__ void pda_geom_kernel(DevModel M, double* rc, double* thc, double* Ar, double* Amu) {
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    const int i = c / n_mu, j = c - i * n_mu;
+    const double a = M.r_edges[i], b = M.r_edges[i + 1];
+    const double m0 = M.mu_edges[j], m1 = M.mu_edges[j + 1];
+    if (j == 0) rc[i] = 0.5 * (a + b);
+    if (i == 0) thc[j] = 0.5 * (acos(m0) + acos(m1));
+    Ar[c] = 2.0 * PI * b * b * 2.0 * (m1 - m0);
+    Amu[c] = PI * (b * b - a * a) * 2.0 * sqrt(fmax(0.0, 1.0 - m1 * m1));
+  }
+}
+}  // namespace
+
 // Geometry arrays of the PDA live at the start of the PDA scratch blob.
 static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
   const int nc = ctx->n_cells, n_r = ctx->n_r, n_mu = ctx->n_mu;
@@ -872,30 +963,22 @@ static int pda_alloc(mcrt_ctx* ctx, PdaArrays& P, PdaGeom& g) {
       return MCRT_E_OOM;
     }
     ctx->pda_bytes = bytes;
-    // geometry (host FP64, uploaded once)
-    std::vector<double> rc(n_r), thc(n_mu), Ar(nc), Amu(nc);
-    std::vector<double> re(n_r + 1), me(n_mu + 1);
-    hipMemcpy(re.data(), ctx->m.r_edges, (n_r + 1) * sizeof(double), hipMemcpyDeviceToHost);
-    hipMemcpy(me.data(), ctx->m.mu_edges, (n_mu + 1) * sizeof(double), hipMemcpyDeviceToHost);
-    for (int i = 0; i < n_r; ++i) rc[i] = 0.5 * (re[i] + re[i + 1]);
-    for (int j = 0; j < n_mu; ++j) thc[j] = 0.5 * (std::acos(me[j]) + std::acos(me[j + 1]));
-    for (int i = 0; i < n_r; ++i)
-      for (int j = 0; j < n_mu; ++j) {
-        double rf = re[i + 1];
-        Ar[i * n_mu + j] = 2.0 * PI * rf * rf * 2.0 * (me[j + 1] - me[j]);
-        double mf = me[j + 1];
-        double a = re[i], b = re[i + 1];
-        Amu[i * n_mu + j] = PI * (b * b - a * a) * 2.0 * std::sqrt(std::fmax(0.0, 1.0 - mf * mf));
-      }
+    // geometry, once per context (before any stream work that reads it)
     char* q = (char*)ctx->d_pda_blob;
     q += align256(sizeof(PdaScalars)) + 2 * align256(nc) + 13 * align256(nd);
-    hipMemcpy(q, rc.data(), n_r * sizeof(double), hipMemcpyHostToDevice);
+    double* rc = (double*)q;
     q += align256(n_r * sizeof(double));
-    hipMemcpy(q, thc.data(), n_mu * sizeof(double), hipMemcpyHostToDevice);
+    double* thc = (double*)q;
     q += align256(n_mu * sizeof(double));
-    hipMemcpy(q, Ar.data(), nd, hipMemcpyHostToDevice);
+    double* Ar = (double*)q;
     q += align256(nd);
-    hipMemcpy(q, Amu.data(), nd, hipMemcpyHostToDevice);
+    double* Amu = (double*)q;
+    const unsigned nb = (unsigned)std::min<size_t>(((size_t)nc + 255) / 256, 1024);
+    hipLaunchKernelGGL(pda_geom_kernel, dim3(nb), dim3(256), 0, 0, ctx->m, rc, thc, Ar, Amu);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      set_error(ctx, "PDA geometry failed");
+      return MCRT_E_HIP;
+    }
   }
   char* q = (char*)ctx->d_pda_blob;
   P.sc = (PdaScalars*)q;
@@ -932,15 +1015,25 @@ static void pda_wg_slots(mcrt_ctx* ctx, PdaWgArgs** args, mcrt_pda_stats** stats
   *stats = (mcrt_pda_stats*)(q + align256(sizeof(PdaWgArgs)));
 }
 
+static RegionRule region_rule(const mcrt_ctx* ctx, const uint8_t* mask) {
+  RegionRule R;
+  R.mask = mask;
+  R.visits = ctx->t.visits;
+  R.n_abs = ctx->t.n_abs;
+  R.n_mrw = ctx->t.n_mrw;
+  R.thr = ctx->opt.pda_visits;
+  R.sigma = ctx->opt.pda_sigma;
+  return R;
+}
+
 static int pda_solve_wg(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s,
                         const PdaArrays& P, const PdaGeom& g) {
   PdaWgArgs h;
   h.M = ctx->m;
   h.P = P;
   h.g = g;
-  h.mask = mask;
-  h.visits = ctx->t.visits;
-  h.thr = ctx->opt.pda_visits;
+  h.rule = region_rule(ctx, mask);
+  h.fails = nullptr;
   h.T_mc = ctx->d_T;
   h.T_out = ctx->d_T;
   h.reg_out = ctx->d_region;
@@ -971,9 +1064,7 @@ static int pda_solve_wg(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, 
     return MCRT_E_HIP;
   }
   if (st) *st = out;
-  if (out.cg_iters_last >= ctx->opt.cg_max_iter ||
-      (out.n_region > 0 && !(out.last_change < ctx->opt.pda_tol)))
-    return MCRT_E_NOT_CONVERGED;
+  if (out.cg_iters_last >= ctx->opt.cg_max_iter || !out.converged) return MCRT_E_NOT_CONVERGED;
   return out.n_isolated > 0 ? MCRT_E_SINGULAR_REGION : MCRT_OK;
 }
 
@@ -989,9 +1080,8 @@ int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_
   const dim3 grid((nc + BS - 1) / BS), blk(BS);
   const DevModel& M = ctx->m;
   hipLaunchKernelGGL(pda_reset_scalars_kernel, dim3(1), dim3(64), 0, s, P.sc, 1);
-  hipLaunchKernelGGL(pda_region_kernel, grid, blk, 0, s, M, mask, ctx->t.visits,
-                     ctx->opt.pda_visits, P);
-  hipLaunchKernelGGL(pda_touch_kernel, grid, blk, 0, s, M, P);
+  hipLaunchKernelGGL(pda_region_kernel, grid, blk, 0, s, M, region_rule(ctx, mask), P);
+  hipLaunchKernelGGL(pda_touch_kernel, grid, blk, 0, s, M, ctx->d_T, P);
   hipLaunchKernelGGL(pda_components_kernel, dim3(1), dim3(256), 0, s, M, P);
   hipLaunchKernelGGL(pda_floor_kernel, grid, blk, 0, s, M, ctx->d_T, P);
   hipLaunchKernelGGL(pda_init_T_kernel, grid, blk, 0, s, M, ctx->d_T, P);
@@ -1004,11 +1094,14 @@ int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_
   mcrt_pda_stats out{};
   out.n_region = h.n_region - h.n_isolated;
   out.n_isolated = h.n_isolated;
+  out.converged = 1;
   int status = MCRT_OK;
   if (out.n_region > 0) {
     const double tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
     const int chunk = 16;
     int sweep;
+    double prev = INFINITY;
+    out.converged = 0;
     for (sweep = 1; sweep <= ctx->opt.pda_max_sweeps; ++sweep) {
       hipLaunchKernelGGL(pda_assemble_kernel, grid, blk, 0, s, M, g, P);
       hipLaunchKernelGGL(pda_x_from_T_kernel, grid, blk, 0, s, nc, P);
@@ -1045,9 +1138,13 @@ int pda_solve(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_
       std::memcpy(&change, &bits, sizeof(change));
       out.last_change = change;
       out.sweeps = sweep;
-      if (change < ctx->opt.pda_tol) break;
+      if (change < ctx->opt.pda_tol || (change < std::sqrt(ctx->opt.pda_tol) && change >= prev)) {
+        out.converged = 1;
+        break;
+      }
+      prev = change;
     }
-    if (sweep > ctx->opt.pda_max_sweeps && status == MCRT_OK) status = MCRT_E_NOT_CONVERGED;
+    if (!out.converged && status == MCRT_OK) status = MCRT_E_NOT_CONVERGED;
   }
   hipLaunchKernelGGL(pda_writeback_kernel, grid, blk, 0, s, nc, P, ctx->d_T, ctx->d_region);
   if (hipGetLastError() != hipSuccess) {
@@ -1200,6 +1297,7 @@ __global__ void __launch_bounds__(WG) pda_linear_kernel(const PdaLinArgs* args) 
     s.n_region = (int)n1;
     s.n_isolated = (int)n2;
     s.last_residual = resid;
+    s.converged = 1;  // one linear solve, no Picard sweeps
     *a.stats = s;
   }
 }
@@ -1261,6 +1359,7 @@ __global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args)
     s.cg_iters_total = it;
     s.cg_iters_last = it;
     s.last_residual = resid;
+    s.converged = 1;  // one linear solve, no Picard sweeps
     *a.stats = s;
   }
 }
@@ -1371,9 +1470,8 @@ int pda_batch_fill(mcrt_ctx** ctxs, int n, void* host) {
     h.M = ctx->m;
     h.P = P;
     h.g = g;
-    h.mask = nullptr;
-    h.visits = ctx->t.visits;
-    h.thr = ctx->opt.pda_visits;
+    h.rule = region_rule(ctx, nullptr);
+    h.fails = &ctx->d_health->pda_fails;
     h.T_mc = ctx->d_T;
     h.T_out = ctx->d_T;
     h.reg_out = ctx->d_region;

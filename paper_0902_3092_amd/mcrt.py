@@ -20,13 +20,13 @@ _lib = None
 OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
-    GET_TABLES, GET_RHO = range(10)
+    GET_TABLES, GET_RHO, GET_HYDRO_COLD = range(11)
 COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch", "handed"]
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
            "mcrt_get_size", "mcrt_set_T", "mcrt_hydrostatic", "mcrt_strerror", "mcrt_last_error",
-           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint"]
+           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_batch_pda"]
 
 
 class McrtError(RuntimeError):
@@ -60,14 +60,15 @@ class Options(C.Structure):
                 ("mrw_coef_T", C.c_int32), ("block_size", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("pda_solver", C.c_int32),
                 ("pda_precond", C.c_int32), ("wave_events", C.c_int64),
-                ("g_asym", C.c_double), ("hydro_M_star", C.c_double), ("hydro_mu", C.c_double)]
+                ("g_asym", C.c_double), ("hydro_M_star", C.c_double), ("hydro_mu", C.c_double),
+                ("pda_sigma", C.c_double)]
 
 
 class PdaStats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("cg_iters_total", C.c_int32),
                 ("cg_iters_last", C.c_int32), ("n_region", C.c_int32),
                 ("n_isolated", C.c_int32), ("last_change", C.c_double),
-                ("last_residual", C.c_double)]
+                ("last_residual", C.c_double), ("converged", C.c_int32)]
 
 
 REC_DTYPE = np.dtype([("fate", np.int32), ("k", np.int32), ("n_cross", np.int64),
@@ -109,6 +110,7 @@ def lib():
         L.mcrt_batch_run.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp, vp]
         L.mcrt_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mcrt_pda_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.mcrt_batch_pda.argtypes = [vp, C.c_int, vp, vp]
         _lib = L
     return _lib
 
@@ -144,7 +146,8 @@ class Context:
                  pda_max_sweeps: int = 50, pda_tol: float = 1e-8, cg_max_iter: int = 20000,
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
                  blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None,
-                 g_asym: float = 0.0, hydro_M_star: float = 0.0, hydro_mu: float = 2.3):
+                 g_asym: float = 0.0, hydro_M_star: float = 0.0, hydro_mu: float = 2.3,
+                 pda_sigma: float = 0.0):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()
@@ -160,6 +163,7 @@ class Context:
         o.wave_events = wave_events
         o.g_asym = g_asym
         o.hydro_M_star, o.hydro_mu = hydro_M_star, hydro_mu
+        o.pda_sigma = pda_sigma
         self.options = o
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
@@ -177,6 +181,10 @@ class Context:
         self.n_r, self.n_mu, self.n_lambda = g.n_r, g.n_mu, d.n_lambda
         self.n_cells = self.n_r * self.n_mu
         self.n_inc = n_inc
+        # count of calls that replace what mcrt_pda_adjoint differentiates:
+        # each mcrt_pda_linear starts a new generation, and any other call
+        # that reuses the PDA scratch or the density ends it
+        self._lin_gen = 0
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -217,6 +225,7 @@ class Context:
         return out
 
     def pda_solve(self, mask=None, stream=None) -> dict:
+        self._lin_gen += 1
         st = PdaStats()
         rc = lib().mcrt_pda_solve(self.handle, _ptr(mask), C.byref(st), _stream(stream))
         _check(rc, "mcrt_pda_solve", allow=(E_SINGULAR_REGION,))
@@ -247,7 +256,8 @@ class Context:
         dt = {GET_E_ABS: torch.float64, GET_VISITS: torch.int32, GET_N_ABS: torch.int32,
               GET_N_MRW: torch.int32, GET_T: torch.float64, GET_REGION: torch.uint8,
               GET_COUNTERS: torch.int64, GET_E_STAR: torch.float64,
-              GET_TABLES: torch.float64, GET_RHO: torch.float64}[what]
+              GET_TABLES: torch.float64, GET_RHO: torch.float64,
+              GET_HYDRO_COLD: torch.int32}[what]
         return buf.view(dt)
 
     def counters(self) -> dict:
@@ -274,6 +284,7 @@ class Context:
         current T (replaces the context's); returns a copy [n_cells]."""
         import torch
         rho = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        self._lin_gen += 1
         _check(lib().mcrt_hydrostatic(self.handle, float(M_star), float(mu_mol), _ptr(rho),
                                       _stream(stream)), "mcrt_hydrostatic")
         return rho
@@ -283,6 +294,7 @@ class Context:
         import torch
         T_out = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
         st = PdaStats()
+        self._lin_gen += 1
         rc = lib().mcrt_pda_linear(self.handle, _ptr(mask), _ptr(rho), _ptr(kscale), _ptr(T_D),
                                    _ptr(T_bc), _ptr(T_out), C.byref(st), _stream(stream))
         _check(rc, "mcrt_pda_linear")
@@ -299,16 +311,38 @@ class Context:
         return g_r, g_s
 
 
-def batch_run(contexts, n_packets, seeds, n_iter: int = 5, use_graph: bool = True,
-              stream=None):
-    """mcrt_batch_run over Context objects; returns the per-disk PDA statistics
-    of the last pass."""
+def batch_run_rc(contexts, n_packets, seeds, n_iter: int = 5, use_graph: bool = True,
+                 stream=None, allow=(E_NOT_CONVERGED, E_STUCK)):
+    """mcrt_batch_run over Context objects; returns (the per-disk PDA statistics
+    of the last pass, the return code).  Codes outside `allow` raise."""
     n = len(contexts)
     handles = (C.c_void_p * n)(*[c.handle.value for c in contexts])
     npk = (C.c_uint64 * n)(*[int(x) for x in n_packets])
     sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
     stats = (PdaStats * n)()
+    for c in contexts:
+        c._lin_gen += 1      # the batch overwrites what a linear PDA solve kept
     rc = lib().mcrt_batch_run(handles, n, npk, sd, n_iter, int(use_graph), stats,
                               _stream(stream))
-    _check(rc, "mcrt_batch_run")
-    return [{f: getattr(s, f) for f, _ in PdaStats._fields_} for s in stats]
+    _check(rc, "mcrt_batch_run", allow=allow)
+    return [{f: getattr(s, f) for f, _ in PdaStats._fields_} for s in stats], rc
+
+
+def batch_run(contexts, n_packets, seeds, n_iter: int = 5, use_graph: bool = True,
+              stream=None):
+    """mcrt_batch_run over Context objects; returns the per-disk PDA statistics
+    of the last pass.  Raises on any code but MCRT_OK."""
+    return batch_run_rc(contexts, n_packets, seeds, n_iter, use_graph, stream, allow=())[0]
+
+
+def batch_pda(contexts, stream=None, allow=(E_SINGULAR_REGION,)):
+    """mcrt_batch_pda: the PDA of every context in one launch; returns (the
+    per-disk statistics, the return code).  Codes outside `allow` raise."""
+    n = len(contexts)
+    handles = (C.c_void_p * n)(*[c.handle.value for c in contexts])
+    stats = (PdaStats * n)()
+    for c in contexts:
+        c._lin_gen += 1
+    rc = lib().mcrt_batch_pda(handles, n, stats, _stream(stream))
+    _check(rc, "mcrt_batch_pda", allow=allow)
+    return [{f: getattr(s, f) for f, _ in PdaStats._fields_} for s in stats], rc

@@ -1,0 +1,149 @@
+"""The PDA region with the photon-noise test of Sect. 3.1 (pda_sigma) and the
+hydrostatic step's cold-shell guard, on the GPU against the oracle.
+
+Both sides make their own tallies from the same frozen-temperature packets
+(identical draws, so identical integer tallies), apply their own region rule,
+and solve the PDA on it: the regions agree exactly, the temperatures to the
+CG tolerance.  The hydrostatic step takes the same synthetic temperature field
+with cold cells on both sides."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0902_3092_amd import workloads as W
+
+sys.path.insert(0, os.path.dirname(__file__))
+from frozen_runs import agreeing_runs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+M_STAR = 2.5 * W.M_SUN
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mcrt(torch_cuda):
+    from paper_0902_3092_amd import mcrt as M
+    M.lib()
+    return M
+
+
+@pytest.mark.parametrize("solver", [1, 2])
+@pytest.mark.parametrize("visits,sigma", [(100, 0.05), (30, 0.05), (0, 0.05), (100, 0.0)])
+def test_region_rule_and_pda_match_oracle(mcrt, oracle_mod, torch_cuda, solver, visits, sigma):
+    torch = torch_cuda
+    d = W.make_disk("r", M_dust_msun=1e-2, n_r=30, n_mu=24, n_lambda=30)
+    rc = 0.5 * (d.r_edges[:-1] + d.r_edges[1:]) / W.AU
+    mc = 0.5 * (d.mu_edges[:-1] + d.mu_edges[1:])
+    Tf = np.ascontiguousarray((350.0 * rc[:, None] ** -0.5 * (1 + 0.4 * mc[None, :])).reshape(-1))
+    kw = dict(mrw=True, gamma=3.0, n_int_min=20)
+    n, seed = 6000, 33
+    ora = oracle_mod.Oracle(d)
+    ctx, st, agree = agreeing_runs(
+        mcrt, lambda: mcrt.Context(d, pda_visits=visits, pda_sigma=sigma, pda_solver=solver,
+                                   **kw), ora, n, seed, Tf, torch, **kw)
+    assert agree >= 0.995
+    for what, key in ((mcrt.GET_VISITS, "visits"), (mcrt.GET_N_ABS, "n_abs"),
+                      (mcrt.GET_N_MRW, "n_mrw")):
+        assert np.array_equal(ctx.get(what).cpu().numpy().view(np.uint32), st[key]), key
+    # the temperature field of the solve: the frozen one, zero where nothing
+    # was absorbed (as a run's own inversion leaves such cells)
+    T_mc = np.where(st["n_abs"] + st["n_mrw"] > 0, Tf, 0.0)
+    ctx.set_T(torch.from_numpy(T_mc).cuda())
+    res = ctx.pda_solve()
+    reg_o = ora.pda_region(st["visits"], st["n_abs"], st["n_mrw"], visits_min=visits,
+                           sigma_max=sigma)
+    T_o, reg_out, _, _ = ora.pda(T_mc, reg_o)
+    reg_g = ctx.get(mcrt.GET_REGION).cpu().numpy()
+    assert np.array_equal(reg_g, reg_out)
+    chi = (d.mass_frac[:, None] * (d.kappa_abs + d.kappa_sca)).sum(0).max()
+    rcm = 0.5 * (d.r_edges[:-1] + d.r_edges[1:])
+    th = np.arccos(d.mu_edges)
+    wt = rcm[:, None] * (th[:-1] - th[1:])[None, :]
+    wt[:, 0] *= 2
+    width = (d.rho.reshape(d.n_r, d.n_mu) * chi *
+             np.minimum(np.diff(d.r_edges)[:, None], wt)).reshape(-1)
+    cold = (d.rho > 0) & (T_mc <= 0) & (width >= 1.0)
+    if sigma > 0:
+        # every opaque dust cell without an absorption joins (solved or isolated)
+        assert np.all(reg_g[cold] != 0)
+        assert cold.sum() > 0
+    assert res["n_region"] == int((reg_out == 1).sum()) > 0
+    T_g = ctx.get(mcrt.GET_T).cpu().numpy()
+    assert np.allclose(T_g, T_o, rtol=1e-7, atol=0)
+
+
+def test_hydrostatic_cold_shells_match_oracle(mcrt, oracle_mod, torch_cuda):
+    """A temperature field with zero-temperature dust cells: the shells of the
+    optically thick ones keep the density (not collapsed), the count is
+    reported, a transparent cold cell is floored, and every shell matches the
+    oracle's integration."""
+    torch = torch_cuda
+    d = W.small_disk(M_dust_msun=1e-1, n_r=12, n_mu=10, n_lambda=16)
+    rng = np.random.default_rng(8)
+    T = rng.uniform(30.0, 600.0, d.n_cells).reshape(d.n_r, d.n_mu)
+    T[4, 0] = 0.0          # a midplane cell with no absorption (optical width ~66)
+    T[7, 3] = 0.0          # optical width ~21
+    T[2, 9] = 0.0          # transparent: floored
+    T = T.reshape(-1)
+    ctx = mcrt.Context(d)
+    ctx.set_T(torch.from_numpy(T).cuda())
+    rho_g = ctx.hydrostatic(M_STAR, 2.3).cpu().numpy()
+    cold = int(ctx.get(mcrt.GET_HYDRO_COLD).cpu().numpy()[0])
+    ora = oracle_mod.Oracle(d)
+    rho_o, cold_o = ora.hydrostatic(T, M_STAR, 2.3, return_cold=True)
+    assert cold == cold_o == 2
+    assert np.allclose(rho_g, rho_o, rtol=1e-10, atol=0)
+    r0 = d.rho.reshape(d.n_r, -1)
+    rg = rho_g.reshape(d.n_r, -1)
+    assert np.array_equal(rg[4], r0[4]) and np.array_equal(rg[7], r0[7])
+    assert not np.array_equal(rg[2], r0[2])
+    # with the cold cells warmed the shells are solved and nothing is cold
+    T2 = T.copy()
+    T2[T2 == 0.0] = 50.0
+    ctx2 = mcrt.Context(d)
+    ctx2.set_T(torch.from_numpy(T2).cuda())
+    ctx2.hydrostatic(M_STAR, 2.3)
+    assert int(ctx2.get(mcrt.GET_HYDRO_COLD).cpu().numpy()[0]) == 0
+
+
+def test_sigma_rule_leaves_no_cold_cell_for_the_hydrostatic_step(mcrt, torch_cuda):
+    """A run with the photon-noise test on: after the PDA no dust cell that the
+    region could reach is left at T = 0, so the hydrostatic step balances
+    every shell (the paper's use of the PDA before the vertical structure,
+    Sect. 3.4 Case 3)."""
+    torch = torch_cuda
+    d, o = W.config("mrw_pda")
+    ctx = mcrt.Context(d, precision="fp32", mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                       pda_visits=o.pda_visits, pda_sigma=0.05, n_T=o.n_T)
+    ctx.reset()
+    ctx.trace(200000, 12)
+    T0 = ctx.update_T().cpu().numpy()
+    st = ctx.pda_solve()
+    torch.cuda.synchronize()
+    T = ctx.get(mcrt.GET_T).cpu().numpy()
+    reg = ctx.get(mcrt.GET_REGION).cpu().numpy()
+    chi = (d.mass_frac[:, None] * (d.kappa_abs + d.kappa_sca)).sum(0).max()
+    rcm = 0.5 * (d.r_edges[:-1] + d.r_edges[1:])
+    th = np.arccos(d.mu_edges)
+    wt = rcm[:, None] * (th[:-1] - th[1:])[None, :]
+    wt[:, 0] *= 2
+    thick = ((d.rho.reshape(d.n_r, d.n_mu) * chi *
+              np.minimum(np.diff(d.r_edges)[:, None], wt)).reshape(-1) >= 1.0)
+    dusty = d.rho > 0
+    assert ((T0 <= 0) & dusty & thick).sum() > 0    # the run left opaque cold cells
+    assert np.all(T[dusty & thick & (reg != 2)] > 0)
+    ctx.hydrostatic(2.5 * W.M_SUN, 2.3)
+    cold = int(ctx.get(mcrt.GET_HYDRO_COLD).cpu().numpy()[0])
+    iso_rows = len(set(np.nonzero((reg == 2) & dusty & thick & (T <= 0))[0] // d.n_mu))
+    assert cold == iso_rows
+    assert st["n_region"] > 0

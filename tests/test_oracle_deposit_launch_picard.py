@@ -104,7 +104,7 @@ def test_mrw_on_off_in_mrw_cells(oracle_mod):
     absorbed energy there comes from MRW deposits; the absorbed energy per
     cell must still match the explicit walk within the photon noise plus 5 %
     for the MRW's own bias (the paper finds its temperature errors of a few
-    percent, Sect. 4) -- a deposit off by a factor two would move it by
+    percent, Sect. 3.2) -- a deposit off by a factor two would move it by
     30-65 %."""
     d, _ = _gray_model(oracle_mod, rho=1.0)
     chi = d.kappa_abs[0, 0] + d.kappa_sca[0, 0]

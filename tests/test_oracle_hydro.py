@@ -1,4 +1,4 @@
-"""Pins of the oracle's vertical hydrostatic equilibrium (Sect. 3.4, eq.
+"""Pins of the oracle's vertical hydrostatic equilibrium (Sect. 2.5, eq.
 balance): an isothermal shell against the closed form of the integral of
 z / R^3 along it (with second-order convergence of the trapezoidal rule), a
 shell without gravity (rho T constant), and the mass of every shell kept."""
@@ -71,16 +71,19 @@ def test_shell_mass_kept(oracle_mod):
 
 
 def test_cold_shell_keeps_its_density(oracle_mod):
-    """A dust-bearing cell with no temperature (T = 0: nothing was absorbed
-    there) cannot be balanced: a zero temperature would collapse the scale
-    height, which the paper avoids by filling such cells with the PDA first
-    (Sect. 4, vertical-structure Case 3).  Its shell keeps the input density
-    and is counted; the other shells are solved as usual."""
-    d = W.small_disk(M_dust_msun=1e-3, n_r=12, n_mu=10, n_lambda=16)
+    """An optically thick dust cell with no temperature (T = 0: nothing was
+    absorbed there) cannot be balanced: a zero temperature would collapse the
+    scale height, which the paper avoids by filling such cells with the PDA
+    first (Sect. 3.4, vertical-structure Case 3).  Its shell keeps the input
+    density and is counted; the other shells are solved as usual.  A cold cell
+    transparent at every wavelength (optical width < 1) holds next to no mass
+    and is floored instead."""
+    d = W.small_disk(M_dust_msun=1e-1, n_r=12, n_mu=10, n_lambda=16)
     ora = oracle_mod.Oracle(d, n_T=16)
     T = np.random.default_rng(3).uniform(20.0, 500.0, ora.n_cells).reshape(d.n_r, -1)
-    T[4, 0] = 0.0          # a cold midplane cell
-    T[7, 5] = 0.0
+    T[4, 0] = 0.0          # a cold midplane cell (optical width ~66)
+    T[7, 3] = 0.0          # optical width ~21
+    T[2, 9] = 0.0          # transparent near the pole: floored, not counted
     rho, n_cold = ora.hydrostatic(T.reshape(-1), M_STAR, 2.3, return_cold=True)
     assert n_cold == 2
     rho = rho.reshape(d.n_r, -1)
@@ -90,6 +93,6 @@ def test_cold_shell_keeps_its_density(oracle_mod):
     assert not np.allclose(rho[warm], rho0[warm], rtol=1e-3, atol=0)
     # the warm shells match a run where the cold shells are given temperatures
     T2 = T.copy()
-    T2[4, 0], T2[7, 5] = 100.0, 100.0
+    T2[4, 0], T2[7, 3] = 100.0, 100.0
     rho2 = ora.hydrostatic(T2.reshape(-1), M_STAR, 2.3).reshape(d.n_r, -1)
     assert np.array_equal(rho[warm], rho2[warm])

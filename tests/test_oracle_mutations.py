@@ -27,8 +27,8 @@ MUTANTS = {
     "launch_bin_shift": ("    while (k < nl - 1 && !(t->star_cdf[k] > xs)) ++k;",
                          "    while (k < nl - 1 && !(t->star_cdf[k + 1] > xs)) ++k;"),
     # Picard keeps D at the Monte Carlo temperature
-    "picard_frozen_D": ("    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, u);",
-                        "    rc = pda_solve_once(m, t, &g, region_out, T_mc, T_mc, NULL, u);"),
+    "picard_frozen_D": ("    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, 1, u);",
+                        "    rc = pda_solve_once(m, t, &g, region_out, T_mc, T_mc, NULL, 1, u);"),
 }
 
 PIN = {

@@ -312,13 +312,16 @@ def test_philox_known_answer_vectors(oracle_mod):
 
 
 def test_pda_region_rule_boundaries(oracle_mod):
-    """The PDA region of Sect. 4: fewer than the minimum number of packet
+    """The PDA region of Sect. 3.1: fewer than the minimum number of packet
     entries, or a temperature photon noise 1/(4 sqrt(N)) above 5 %.  The
     boundaries worked out by hand: 1/(4 sqrt(25)) = 0.05 exactly (not above),
     1/(4 sqrt(24)) = 0.051 (above); N counts absorptions plus MRW deposits;
-    N = 0 has no temperature at all; dust-free cells never join."""
+    N = 0 has no temperature at all; dust-free cells never join, nor does a
+    cell transparent at every wavelength through the noise test (cell 8:
+    density 1e-40, optical width ~1e-25)."""
     d = W.small_disk(n_r=2, n_mu=6)
-    rho = np.full(12, 1e-15)
+    rho = np.full(12, 1e-9)       # optical widths >= 1e4
+    rho[8] = 1e-40
     rho[11] = 0.0
     ora = oracle_mod.Oracle(d, rho=rho)
     visits = np.array([99, 100, 500, 500, 500, 500, 500, 500, 500, 500, 500, 0])
@@ -329,7 +332,12 @@ def test_pda_region_rule_boundaries(oracle_mod):
     assert got.tolist() == [1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0]
     # both branches: 5 % (N < 25)
     got = ora.pda_region(visits, n_abs, n_mrw, visits_min=100, sigma_max=0.05)
-    assert got.tolist() == [1, 0, 0, 1, 1, 0, 0, 0, 1, 1, 0, 0]
+    assert got.tolist() == [1, 0, 0, 1, 1, 0, 0, 0, 0, 1, 0, 0]
     # the paper's own run: fewer than 30 entries, or above 5 %
     got = ora.pda_region(visits, n_abs, n_mrw, visits_min=30, sigma_max=0.05)
-    assert got.tolist() == [0, 0, 0, 1, 1, 0, 0, 0, 1, 1, 0, 0]
+    assert got.tolist() == [0, 0, 0, 1, 1, 0, 0, 0, 0, 1, 0, 0]
+    # the transparent cell still joins through the visit count
+    v2 = visits.copy()
+    v2[8] = 10
+    got = ora.pda_region(v2, n_abs, n_mrw, visits_min=30, sigma_max=0.05)
+    assert got[8] == 1
