@@ -120,7 +120,10 @@ def lib():
         L.ora_mrw_escape_s.restype = dbl
         L.ora_mrw_survival.argtypes = [dbl]
         L.ora_mrw_survival.restype = dbl
-        L.ora_run.argtypes = [vp, vp, vp, u64, u64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, i64]
+        L.ora_run.argtypes = [vp, vp, vp, u64, u64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, i64,
+                              vp]
+        L.ora_conv_stat.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
+        L.ora_conv_stat.restype = None
         L.ora_cell_volumes.argtypes = [vp, vp]
         L.ora_update_T.argtypes = [vp, vp, vp, vp]
         L.ora_pda.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, dbl, vp, vp, vp]
@@ -242,7 +245,8 @@ class Oracle:
             state = dict(E_abs=np.zeros(nc), visits=np.zeros(nc, np.uint32),
                          n_abs=np.zeros(nc, np.uint32), n_mrw=np.zeros(nc, np.uint32),
                          sed=np.zeros((nl, n_inc)),
-                         E_star=np.zeros(1), counters=np.zeros(N_COUNTERS, np.int64))
+                         E_star=np.zeros(1), counters=np.zeros(N_COUNTERS, np.int64),
+                         E_half=np.zeros(nc))
         fz = None
         if frozen_T is not None:
             fz = np.ascontiguousarray(frozen_T, dtype=np.float64)
@@ -255,10 +259,23 @@ class Oracle:
         lib().ora_run(C.byref(self.model), C.byref(self.tables), C.byref(opts), n_packets,
                       n_total, seed, offset, _p(state["E_abs"]), _p(state["visits"]),
                       _p(state["n_abs"]), _p(state["n_mrw"]), _p(state["sed"]), _p(state["E_star"]),
-                      _p(state["counters"]), _p(recs), n_recs)
+                      _p(state["counters"]), _p(recs), n_recs, _p(state["E_half"]))
         state["recs"] = recs[:n_recs]
         state["eps"] = self.L_star / n_total
         return state
+
+    def conv_stat(self, state, T_prev, s2_prev, n_min: int = 100):
+        """Convergence statistic of a pass (its tallies in `state`) against
+        the previous pass's T_prev and s2_prev, which are updated in place
+        (start with zeros and -1 for the first pass).  Returns (R, rms
+        relative change, rms noise, cells)."""
+        out = np.zeros(4)
+        assert T_prev.dtype == np.float64 and s2_prev.dtype == np.float64
+        lib().ora_conv_stat(C.byref(self.model), C.byref(self.tables), _p(state["E_abs"]),
+                            _p(state["E_half"]), _p(np.ascontiguousarray(state["visits"],
+                                                                         dtype=np.uint32)),
+                            int(n_min), _p(T_prev), _p(s2_prev), _p(out))
+        return float(out[0]), float(out[1]), float(out[2]), int(out[3])
 
     def counters(self, state) -> dict:
         return dict(zip(COUNTER_NAMES, (int(v) for v in state["counters"])))

@@ -634,6 +634,61 @@ int ora_hydrostatic(const ora_model* m, const double* T, double M_star, double m
   return n_cold;
 }
 
+/* Convergence statistic of the vertical-structure loop (Sect. 2.5: the mean
+ * change of the temperature between two consecutive passes against its
+ * photon noise; converged below 3).  The noise comes from the pass itself:
+ * its odd- and even-numbered packets are two independent half-size runs, so
+ * with E_a = 2 E_half and E_b = 2 (E - E_half) the absorbed energy's
+ * variance is ~ (E_a - E_b)^2 / 4 = (2 E_half - E)^2: whatever carries the
+ * energy (single absorptions or MRW deposits of any size), where 1 / N_abs
+ * would count absorptions as independent though one packet makes many.  The
+ * relative variance of T follows with the local slope of the inversion,
+ * dlnT/dlnE (a central difference of T(E) over E (1 +- 1e-4)):
+ *   s2 = (dlnT/dlnE)^2 ((2 E_half - E) / E)^2.
+ * Dusty cells entered by >= n_min packets with E > 0 are eligible; over the cells
+ * eligible in this pass and the previous one (s2_prev >= 0),
+ *   R = sqrt(sum x^2 / sum (s2 + s2_prev)),  x = (T - T_prev) / T.
+ * T_prev and s2_prev [n_cells] hold the previous pass (s2_prev < 0: not
+ * eligible) and are replaced by this pass's values.  out: R (0 when nothing
+ * is compared), the RMS of x, the RMS noise sqrt(mean(s2 + s2_prev)), the
+ * cells compared. */
+void ora_conv_stat(const ora_model* m, const ora_tables* t, const double* E_abs,
+                   const double* E_half, const uint32_t* visits, int n_min, double* T_prev,
+                   double* s2_prev, double out[4]) {
+  const int nc = m->n_r * m->n_mu;
+  const double h = 1e-4;
+  double* V = (double*)malloc(sizeof(double) * nc);
+  ora_cell_volumes(m, V);
+  double sx = 0.0, ss = 0.0;
+  long long cells = 0;
+  for (int c = 0; c < nc; ++c) {
+    const double mass = m->rho[c] * V[c];
+    const double E = E_abs[c];
+    const double T = ora_T_of_E(m, t, E, mass);
+    double s2 = -1.0;
+    if ((long long)visits[c] >= n_min && mass > 0.0 && E > 0.0 && T > 0.0) {
+      const double Tp = ora_T_of_E(m, t, E * (1.0 + h), mass);
+      const double Tm = ora_T_of_E(m, t, E * (1.0 - h), mass);
+      const double slope = log(Tp / Tm) / (2.0 * h);
+      const double rel = (2.0 * E_half[c] - E) / E;
+      s2 = slope * slope * rel * rel;
+      if (s2_prev[c] >= 0.0 && T_prev[c] > 0.0) {
+        const double x = (T - T_prev[c]) / T;
+        sx += x * x;
+        ss += s2 + s2_prev[c];
+        ++cells;
+      }
+    }
+    T_prev[c] = T;
+    s2_prev[c] = s2;
+  }
+  free(V);
+  out[0] = ss > 0.0 ? sqrt(sx / ss) : 0.0;
+  out[1] = cells ? sqrt(sx / (double)cells) : 0.0;
+  out[2] = cells ? sqrt(ss / (double)cells) : 0.0;
+  out[3] = (double)cells;
+}
+
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {
   int nc = m->n_r * m->n_mu;
   double* V = (double*)malloc(sizeof(double) * nc);
@@ -649,7 +704,7 @@ void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, 
 int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t n_packets,
             uint64_t n_total, uint64_t seed, uint64_t offset, double* E_abs, uint32_t* visits,
             uint32_t* n_abs, uint32_t* n_mrw_cell, double* sed, double* E_star,
-            long long* counters, ora_packet_rec* recs, int64_t n_recs) {
+            long long* counters, ora_packet_rec* recs, int64_t n_recs, double* E_half) {
   const int nl = m->n_lambda, nmu = m->n_mu, nr = m->n_r;
   const int nc = nr * nmu;
   const double eps = t->L_star / (double)n_total;
@@ -759,6 +814,7 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
         n_abs[c]++;
         double E_old = E_abs[c];
         E_abs[c] = E_old + eps;
+        if (E_half && (pid & 1)) E_half[c] += eps;
         double xb = rng_next(&rng);
         if (o->frozen_T) {
           k = reemit_bin(t, nl, -1.0, o->frozen_T[c], xb);
@@ -789,6 +845,7 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
           for (int a = 0; a < 3; ++a) p[a] += R0 * nrm[a];
           double E_old = E_abs[c];
           E_abs[c] = E_old + dE;
+          if (E_half && (pid & 1)) E_half[c] += dE;
           double xb = rng_next(&rng);
           if (o->frozen_T) {
             k = reemit_bin(t, nl, -1.0, o->frozen_T[c], xb);

@@ -98,7 +98,17 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o,
             uint64_t n_packets, uint64_t n_total, uint64_t seed, uint64_t offset,
             double* E_abs, uint32_t* visits, uint32_t* n_abs, uint32_t* n_mrw_cell,
             double* sed, double* E_star, long long* counters, ora_packet_rec* recs,
-            int64_t n_recs);
+            int64_t n_recs, double* E_half);
+/* E_half (nullable): absorbed energy of the odd-numbered packets alone. */
+
+/* Convergence statistic of the vertical-structure loop from one pass's
+ * tallies (E_half: the odd-numbered packets' share; visits: packets entering
+ * each cell, >= n_min to take part) against the previous pass's T_prev and
+ * relative noise s2_prev (in/out, s2_prev < 0: cell not eligible).  out: R,
+ * RMS relative change, RMS noise, cells compared. */
+void ora_conv_stat(const ora_model* m, const ora_tables* t, const double* E_abs,
+                   const double* E_half, const uint32_t* visits, int n_min, double* T_prev,
+                   double* s2_prev, double out[4]);
 
 void ora_cell_volumes(const ora_model* m, double* V);
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T);

@@ -10,6 +10,7 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
 import test_oracle_deposit_launch_picard as P  # noqa: E402
+import test_oracle_convergence as CV  # noqa: E402
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "mcrt_oracle.c")
 
@@ -29,6 +30,15 @@ MUTANTS = {
     # Picard keeps D at the Monte Carlo temperature
     "picard_frozen_D": ("    rc = pda_solve_once(m, t, &g, region_out, T_out, T_mc, NULL, 1, u);",
                         "    rc = pda_solve_once(m, t, &g, region_out, T_mc, T_mc, NULL, 1, u);"),
+    # the split tally takes the even-numbered packets
+    "half_tally_even": ("        if (E_half && (pid & 1)) E_half[c] += eps;",
+                        "        if (E_half && !(pid & 1)) E_half[c] += eps;"),
+    # the spread of the halves loses its factor 2
+    "conv_half_spread": ("      const double rel = (2.0 * E_half[c] - E) / E;",
+                         "      const double rel = (E_half[c] - E) / E;"),
+    # the slope of the inversion enters unsquared
+    "conv_slope_unsquared": ("      s2 = slope * slope * rel * rel;",
+                             "      s2 = slope * rel * rel;"),
 }
 
 PIN = {
@@ -37,7 +47,16 @@ PIN = {
     "deposit_D_times_3": lambda o: P.test_mrw_deposit_vs_explicit_walk(o, 10.0, 20000),
     "launch_bin_shift": lambda o: P.test_launch_spectrum_is_stellar(o),
     "picard_frozen_D": lambda o: P.test_pda_picard_on_temperature_dependent_D(o),
+    "half_tally_even": lambda o: CV.test_odd_tally_is_the_odd_packets_alone(o),
+    "conv_half_spread": lambda o: CV.test_split_noise_against_run_to_run_spread(o, _passes()),
+    "conv_slope_unsquared": lambda o: CV.test_split_noise_against_run_to_run_spread(o, _passes()),
 }
+
+
+def _passes():
+    from multiprocessing import get_context
+    with get_context("fork").Pool(8) as pool:
+        return pool.map(CV._pass, [(k, 100000) for k in range(16)])
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
