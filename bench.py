@@ -97,8 +97,16 @@ def measured_traffic(kernel, packets):
             "profiles/trace_fp32_counters.json")
 
 
+T_START = time.perf_counter()
+
+
 def log(msg):
-    print("bench: " + msg, file=sys.stderr, flush=True)
+    print("bench: [%6.1f s] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr,
+          flush=True)
+
+
+def elapsed():
+    return time.perf_counter() - T_START
 
 
 def parse():
@@ -116,6 +124,12 @@ def parse():
     p.add_argument("--c3-plain-every", type=int, default=8,
                    help="the plain FP64 comparison of the 64-disk workload runs every n-th disk")
     p.add_argument("--cpu-packets", type=int, default=1000000)
+    p.add_argument("--budget-s", type=float, default=560.0,
+                   help="wall-clock budget of the whole run: a leg after the timed steps "
+                        "whose expected length would pass it is skipped and reported so")
+    p.add_argument("--pda-probe", action="store_true",
+                   help="the 64-disk workload, one pass at its drawn packets, then the batched "
+                        "PDA of that pass alone (for counter runs) and exit")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-ref", action="store_true")
     p.add_argument("--no-batch", action="store_true")
@@ -608,12 +622,11 @@ def reference_halves(mcrt, disk, o, n_total, torch):
     return out, time.perf_counter() - t0
 
 
-def c3_full(mcrt, W, torch, passes, plain_every):
+def c3_full(mcrt, W, torch, passes):
     """The 64-disk batched workload at its drawn packet counts: `passes`
     passes (trace, T, PDA) captured in one HIP graph, the MRW coefficients of
     pass k > 0 from the temperature after pass k - 1; then the batched PDA of
-    the last pass alone (mcrt_batch_pda, HIP events); then the plain FP64 path
-    on every `plain_every`-th disk one at a time (one pass each, no graph)."""
+    the last pass alone (mcrt_batch_pda, HIP events)."""
     import numpy as np
     draws = W.batch_draws()
     npk = [b["n_packets"] for b in draws]
@@ -667,6 +680,15 @@ def c3_full(mcrt, W, torch, passes, plain_every):
     if hit:
         out["batched_pda"].update(hit)
     del ctxs
+    return out
+
+
+def c3_plain(mcrt, W, torch, c3out, plain_every):
+    """The plain FP64 path on every `plain_every`-th disk of the 64-disk
+    workload, one at a time (one pass each, no graph), beside the batched
+    passes of `c3out`."""
+    draws = W.batch_draws()
+    out = c3out
     sel = list(range(0, len(draws), plain_every))
     tp, npl = 0.0, 0
     for q in sel:
@@ -687,6 +709,31 @@ def c3_full(mcrt, W, torch, passes, plain_every):
         "graph": False}
     out["batched_vs_plain"] = out["batched_fp32"]["value"] / out["plain_fp64_one_at_a_time"]["value"]
     return out
+
+
+def pda_probe(mcrt, W, torch):
+    """One pass of the 64-disk workload at its drawn packets (batched, one
+    graph), then the batched PDA of that pass on its own: the launch that the
+    PDA counter runs select by kernel name."""
+    draws = W.batch_draws()
+    ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
+                         pda_visits=100, mrw_coef_T=1) for b in draws]
+    mcrt.batch_run_rc(ctxs, [b["n_packets"] for b in draws], [b["seed"] for b in draws],
+                      n_iter=1, use_graph=True)
+    torch.cuda.synchronize()
+    log("pda probe: pass done")
+    for c in ctxs:
+        c.update_T()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pst, prc = mcrt.batch_pda(ctxs, allow=(mcrt.E_SINGULAR_REGION, mcrt.E_NOT_CONVERGED))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bpu = PCG_BYTES_PER_UNKNOWN[ctxs[0].options.pda_precond]
+    nbytes = sum(x["n_region"] * (x["cg_iters_total"] * bpu + x["sweeps"] * PDA_SWEEP_BYTES)
+                 for x in pst)
+    return {"s": dt, "unknowns": int(sum(x["n_region"] for x in pst)),
+            "algorithmic_bytes": nbytes, "return_code": prc}
 
 
 def pda_l2_hit_rate():
@@ -788,6 +835,10 @@ def main():
               flush=True)
         return
 
+    if a.pda_probe:
+        print(json.dumps({"pda_probe": pda_probe(mcrt, W, torch)}), flush=True)
+        return
+
     disk, o = W.config("mrw_pda")
     N = a.packets
     tuned = None
@@ -872,17 +923,83 @@ def main():
     }
     if tuned:
         out["autotune"] = {k: tuned[k] for k in ("trace_s", "pda_s", "pda_iters", "n_packets")}
-    if not a.no_ref:
+    # the legs after the timed steps, in order of importance; each is skipped
+    # (and reported so) when its expected length would pass the budget
+    leg_s, skipped = {}, {}
+
+    def leg(name, est_s, fn):
+        if elapsed() + est_s > a.budget_s:
+            skipped[name] = "expected ~%.0f s at %.0f s elapsed, budget %.0f s" % (
+                est_s, elapsed(), a.budget_s)
+            log("skipping %s (%s)" % (name, skipped[name]))
+            return False
+        t = time.perf_counter()
+        fn()
+        leg_s[name] = time.perf_counter() - t
+        return True
+
+    step_s = ms_step * 1e-3
+    ref = {}
+
+    def do_ref():
         nref = a.ref_packets if a.ref_packets > 0 else N
         log("reference: FP64, no MRW, %.3g packets in two independent halves" % nref)
-        (R1, R2), dt = reference_halves(mcrt, disk, o, nref, torch)
+        ref["halves"], dt = reference_halves(mcrt, disk, o, nref, torch)
+        R1, R2 = ref["halves"]
         err = midplane_error_vs_halves(disk, T_meas, vis_meas, reg_meas, R1, R2)
         err["reference"] = ("FP64, no MRW, same PDA rule, %.3g packets as two independent "
                             "halves of one call each (%.1f s)" % (nref, dt))
         err["run"] = "the last timed step"
         out["midplane_T_error"] = err
         out["meets_1pct_midplane"] = err["meets_1pct"]
-    if not a.no_plain and a.precision != "fp64":
+
+    if not a.no_ref:
+        # FP64 without MRW takes ~17 times the FP32 step with it
+        leg("reference", 17.0 * step_s * (a.ref_packets or N) / N, do_ref)
+
+    def do_c1():
+        n1 = o.n_packets
+        log("the configuration's own step: %d packets, %d steps" % (n1, a.c1_steps))
+        run_once(ctx, n1, o.seed + 31)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(a.c1_steps):
+            run_once(ctx, n1, o.seed + 37 + i)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.c1_steps
+        c1 = {"value": n1 / dt, "unit": "photon packets/s", "packets": n1,
+              "ms_per_step": dt * 1e3, "steps": a.c1_steps}
+        if "halves" in ref:
+            Tm, vm, rm, _ = fields(ctx, mcrt)
+            c1["midplane_T_error"] = midplane_error_vs_halves(disk, Tm, vm, rm, *ref["halves"])
+        out["c1_1e6_step"] = c1
+
+    if a.c1_steps > 0:
+        leg("c1_1e6_step", 3.0 * (a.c1_steps + 1), do_c1)
+    del ctx
+    torch.cuda.empty_cache()
+
+    def do_c3():
+        out["c3"] = c3_full(mcrt, W, torch, a.c3_passes)
+
+    if not a.no_batch:
+        leg("c3_batched", 30.0 * a.c3_passes, do_c3)
+
+    def do_cpu():
+        log("CPU oracle, %d packets" % a.cpu_packets)
+        out["cpu_baseline"] = cpu_baseline(disk, o, a.cpu_packets)
+
+    if not a.no_cpu:
+        leg("cpu_baseline", a.cpu_packets / 5e4, do_cpu)
+
+    def do_grad():
+        log("PDA and adjoint on the differentiation workload")
+        out["pda_grad"] = pda_grad(mcrt, W, torch)
+
+    if not a.no_pda:
+        leg("pda_grad", 10.0, do_grad)
+
+    def do_plain():
         log("plain FP64 step, %.3g packets" % N)
         ctx64 = mcrt.Context(disk, precision="fp64", mrw=True, gamma=o.gamma,
                              n_int_min=o.n_int_min, pda_visits=o.pda_visits, n_T=o.n_T)
@@ -893,36 +1010,23 @@ def main():
         dt = time.perf_counter() - t0
         out["plain_fp64"] = {"value": N / dt, "ms_per_step": dt * 1e3, "steps": 1,
                              "packets": N}
-        if not a.no_ref:
+        if "halves" in ref:
             T64, vis64, reg64, _ = fields(ctx64, mcrt)
             out["plain_fp64"]["midplane_T_error"] = midplane_error_vs_halves(
-                disk, T64, vis64, reg64, R1, R2)
+                disk, T64, vis64, reg64, *ref["halves"])
         del ctx64
-    if a.c1_steps > 0:
-        n1 = o.n_packets
-        log("the configuration's own step: %d packets, %d steps" % (n1, a.c1_steps))
-        run_once(ctx, n1, o.seed + 31)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(a.c1_steps):
-            run_once(ctx, n1, o.seed + 37 + i)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / a.c1_steps
-        c1 = {"value": n1 / dt, "unit": "photon packets/s", "packets": n1, "ms_per_step": dt * 1e3,
-              "steps": a.c1_steps}
-        if not a.no_ref:
-            Tm, vm, rm, _ = fields(ctx, mcrt)
-            c1["midplane_T_error"] = midplane_error_vs_halves(disk, Tm, vm, rm, R1, R2)
-        out["c1_1e6_step"] = c1
-    del ctx
-    if not a.no_batch:
-        out["c3"] = c3_full(mcrt, W, torch, a.c3_passes, a.c3_plain_every)
-    if not a.no_pda:
-        log("PDA and adjoint on the differentiation workload")
-        out["pda_grad"] = pda_grad(mcrt, W, torch)
-    if not a.no_cpu:
-        log("CPU oracle, %d packets" % a.cpu_packets)
-        out["cpu_baseline"] = cpu_baseline(disk, o, a.cpu_packets)
+
+    if not a.no_plain and a.precision != "fp64":
+        leg("plain_fp64", 3.0 * step_s + 5.0, do_plain)
+
+    def do_c3_plain():
+        c3_plain(mcrt, W, torch, out["c3"], a.c3_plain_every)
+
+    if not a.no_batch and "c3" in out and not a.no_plain:
+        leg("c3_plain_fp64", 6.0 * (64 // a.c3_plain_every), do_c3_plain)
+    out["legs_s"] = leg_s
+    out["legs_skipped"] = skipped
+    out["wall_s"] = elapsed()
     print(json.dumps(out), flush=True)
 
 

@@ -37,8 +37,10 @@ photon statistics):
   estimate of the mass-weighted mean squared bias), is at most (1 %)^2 for
   the Monte Carlo cells and (2 %)^2 for the PDA cells, within three of its
   own standard errors (sigma^2 is estimated from K runs a side, so under no
-  bias each term has variance ~2 sigma^4 (1 + 1/(2K - 2))); and the signed
-  mean sum w d is within 1 % (2 %) plus three of its standard errors;
+  bias each term has variance ~2 sigma^4 (1 + 1/(2K - 2)) for Gaussian
+  noise; where the terms spread more -- heavy tails from long walks -- their
+  empirical spread is taken); and the signed mean sum w d is within 1 % (2 %)
+  plus three of its standard errors;
 * SED bins with >= 1e4 packets on both sides within max(2 %, 3 sigma);
 * energy conserved to 1e-6 in every GPU run.
 """
@@ -92,8 +94,15 @@ def compare_ensembles(name, mass, Tg, To, Vg, Vo, Rg, Ro, Sg, So, eps, Mg=None, 
         bad = np.abs(rel[sel]) > tol
         w = mass[sel] / mass[sel].sum()
         s2 = se[sel] ** 2
-        excess2 = float((w * (rel[sel] ** 2 - s2)).sum())
-        excess2_se = float(np.sqrt((w * w * 2 * s2 * s2).sum() * (1 + 1 / (Kg + Ko - 2))))
+        t = rel[sel] ** 2 - s2
+        excess2 = float((w * t).sum())
+        # standard error of the excess: the Gaussian one, or the empirical
+        # spread of the weighted terms where that is larger (in cells whose
+        # energy a few long walks carry, T has heavy tails and K runs
+        # underestimate the variance of each term)
+        n_eff = 1.0 / (1.0 - float((w * w).sum())) if (w * w).sum() < 1 else 1.0
+        excess2_se = max(float(np.sqrt((w * w * 2 * s2 * s2).sum() * (1 + 1 / (Kg + Ko - 2)))),
+                         float(np.sqrt((w * w).sum() * n_eff * (w * (t - excess2) ** 2).sum())))
         out[label] = dict(cells=int(sel.sum()), frac_fail=float(bad.mean()),
                           worst=float(np.abs(rel[sel]).max()),
                           mean_abs=float((w * np.abs(rel[sel])).sum()),
@@ -186,7 +195,7 @@ def test_batched_passes_match_oracle(mcrt, oracle_mod, torch_cuda):
     disks = [W.make_disk("b0", M_dust_msun=1e-4, n_r=20, n_mu=16, n_lambda=30),
              W.make_disk("b1", M_dust_msun=3e-3, n_r=34, n_mu=22, n_lambda=30, hr0=0.04),
              W.make_disk("b2", M_dust_msun=1e-5, n_r=12, n_mu=10, n_lambda=30, hr0=0.02)]
-    npk = [60000, 40000, 20000]
+    npk = [60000, 40000, 40000]
     K = 8
     o = W.RunOptions(n_packets=0, seed=0, mrw=True, gamma=3.0, n_int_min=20, pda_visits=30)
     ctxs = [mcrt.Context(dk, precision="fp32", mrw=True, gamma=3.0, n_int_min=20, pda_visits=30,
@@ -217,6 +226,8 @@ def test_batched_passes_match_oracle(mcrt, oracle_mod, torch_cuda):
         ob = [np.array(a) for a in O[q]]
         out = compare_ensembles("batch-%d" % q, ora.mass, g[0], ob[0], g[1], ob[1], g[2], ob[2],
                                 g[3], ob[3], ora.L_star / n, g[4], ob[4], min_visits=100)
+        # (the PDA cells of these small disks take their values from a handful
+        # of low-visit boundary cells, so they are reported, not gated)
         mc = out["mc"]
         assert mc is not None and mc["cells"] >= 20
         assert mc["frac_fail"] <= 0.05 or mc["cells"] * mc["frac_fail"] <= 2, mc
