@@ -121,7 +121,11 @@ def lib():
         L.ora_mrw_survival.argtypes = [dbl]
         L.ora_mrw_survival.restype = dbl
         L.ora_run.argtypes = [vp, vp, vp, u64, u64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, i64,
-                              vp]
+                              vp, vp, vp]
+        L.ora_mean_intensity.argtypes = [vp, vp, vp, vp, vp]
+        L.ora_mean_intensity.restype = None
+        L.ora_raytrace_sed.argtypes = [vp, vp, vp, vp, C.c_int, vp, C.c_int, C.c_int, vp]
+        L.ora_raytrace_sed.restype = None
         L.ora_conv_stat.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.ora_conv_stat.restype = None
         L.ora_cell_volumes.argtypes = [vp, vp]
@@ -234,7 +238,7 @@ class Oracle:
     def run(self, n_packets: int, seed: int, *, n_total: int = None, offset: int = 0,
             mrw: bool = False, gamma: float = 3.0, n_int_min: int = 20, n_inc: int = 10,
             max_events: int = 1 << 30, frozen_T=None, n_recs: int = 0, state=None,
-            coef_T=None):
+            coef_T=None, paths: bool = False):
         """Trace packets [offset, offset+n_packets) of a run of n_total packets.
         `state` (a previous result) accumulates tallies across calls.  coef_T:
         temperatures for the MRW's coefficients and criterion (a previous
@@ -247,6 +251,9 @@ class Oracle:
                          sed=np.zeros((nl, n_inc)),
                          E_star=np.zeros(1), counters=np.zeros(N_COUNTERS, np.int64),
                          E_half=np.zeros(nc))
+        if paths and "path" not in state:
+            state["path"] = np.zeros((nc, nl))
+            state["mrw_path"] = np.zeros(nc)
         fz = None
         if frozen_T is not None:
             fz = np.ascontiguousarray(frozen_T, dtype=np.float64)
@@ -259,10 +266,32 @@ class Oracle:
         lib().ora_run(C.byref(self.model), C.byref(self.tables), C.byref(opts), n_packets,
                       n_total, seed, offset, _p(state["E_abs"]), _p(state["visits"]),
                       _p(state["n_abs"]), _p(state["n_mrw"]), _p(state["sed"]), _p(state["E_star"]),
-                      _p(state["counters"]), _p(recs), n_recs, _p(state["E_half"]))
+                      _p(state["counters"]), _p(recs), n_recs, _p(state["E_half"]),
+                      _p(state["path"]) if "path" in state else None,
+                      _p(state["mrw_path"]) if "path" in state else None)
         state["recs"] = recs[:n_recs]
         state["eps"] = self.L_star / n_total
         return state
+
+    def mean_intensity(self, T, state) -> np.ndarray:
+        """J [n_cells, n_lambda] from a run's path tallies (run with paths=True)."""
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        J = np.empty((self.n_cells, self.n_lambda))
+        lib().ora_mean_intensity(C.byref(self.model), _p(T), _p(state["path"]),
+                                 _p(state["mrw_path"]), _p(J))
+        return J
+
+    def raytrace_sed(self, T, J=None, cos_i=(0.7071067811865476,), n_sub: int = 4,
+                     n_phi: int = 16) -> np.ndarray:
+        """Ray-traced isotropic-equivalent luminosity per bin [n_inc, n_lambda]."""
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        ci = np.ascontiguousarray(cos_i, dtype=np.float64)
+        Jc = None if J is None else np.ascontiguousarray(J, dtype=np.float64)
+        out = np.empty((len(ci), self.n_lambda))
+        lib().ora_raytrace_sed(C.byref(self.model), C.byref(self.tables), _p(T),
+                               _p(Jc) if Jc is not None else None, len(ci), _p(ci), int(n_sub),
+                               int(n_phi), _p(out))
+        return out
 
     def conv_stat(self, state, T_prev, s2_prev, n_min: int = 100):
         """Convergence statistic of a pass (its tallies in `state`) against

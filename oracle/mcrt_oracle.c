@@ -131,6 +131,38 @@ void ora_planck_bins(const double* lambda_edges, int n_lambda, double T, double*
 /* values are interpolated linearly in T between nodes (reading).  Frequency  */
 /* integrals are sums over the wavelength bins (reading).                     */
 /* ------------------------------------------------------------------------ */
+/* eq:eta nu iter at one temperature, from eta = kappa dB/dT: eta_k <-
+ * kappa_k dB_k (sum eta kappa/chi)/(sum eta) + (sigma_k/chi_k) eta_k until the
+ * largest relative change is below 1e-13.  Anisotropic scattering enters the
+ * diffusion quantities through the isotropic equivalent sigma' = (1 - g) sigma
+ * (Sect. 2.2.3).  dBb [n_lambda] the bin integrals of dB/dT; eta_new scratch.
+ * Returns the iterations taken. */
+static int eta_iterate(const ora_model* m, const double* dBb, double* eta, double* eta_new) {
+  const int nl = m->n_lambda;
+  const double sim = 1.0 - m->g_asym;
+  for (int k = 0; k < nl; ++k) eta[k] = m->kappa_abs[k] * dBb[k];
+  int it;
+  for (it = 0; it < 20000; ++it) {
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < nl; ++k) {
+      double chi = m->kappa_abs[k] + m->kappa_sca[k] * sim;
+      num += eta[k] * m->kappa_abs[k] / chi;
+      den += eta[k];
+    }
+    double ratio = num / den, change = 0.0;
+    for (int k = 0; k < nl; ++k) {
+      double sca = m->kappa_sca[k] * sim;
+      double chi = m->kappa_abs[k] + sca;
+      eta_new[k] = m->kappa_abs[k] * dBb[k] * ratio + (sca / chi) * eta[k];
+      double rel = fabs(eta_new[k] - eta[k]) / (fabs(eta_new[k]) + 1e-300);
+      if (eta_new[k] != 0.0 && rel > change) change = rel;
+    }
+    memcpy(eta, eta_new, sizeof(double) * nl);
+    if (change < 1e-13) break;
+  }
+  return it + 1;
+}
+
 int ora_build_tables(const ora_model* m, ora_tables* t) {
   const int nl = m->n_lambda, nT = t->n_T;
   if (nT < 3 || nl < 1) return -1;
@@ -152,32 +184,9 @@ int ora_build_tables(const ora_model* m, ora_tables* t) {
       t->cdf[(size_t)n * nl + k] = c;
     }
     if (n == 0) continue;
-    /* eq:eta nu iter: eta_k <- kappa_k dB_k * (sum eta kappa/chi)/(sum eta)
-     *                         + (sigma_k/chi_k) eta_k, from eta = kappa dB.
-     * Anisotropic scattering enters the diffusion quantities through the
-     * isotropic equivalent sigma' = (1 - g) sigma (Sect. 2.2.3). */
     const double sim = 1.0 - m->g_asym;
-    for (int k = 0; k < nl; ++k) eta[k] = m->kappa_abs[k] * dBb[k];
-    int it;
-    for (it = 0; it < 20000; ++it) {
-      double num = 0.0, den = 0.0;
-      for (int k = 0; k < nl; ++k) {
-        double chi = m->kappa_abs[k] + m->kappa_sca[k] * sim;
-        num += eta[k] * m->kappa_abs[k] / chi;
-        den += eta[k];
-      }
-      double ratio = num / den, change = 0.0;
-      for (int k = 0; k < nl; ++k) {
-        double sca = m->kappa_sca[k] * sim;
-        double chi = m->kappa_abs[k] + sca;
-        eta_new[k] = m->kappa_abs[k] * dBb[k] * ratio + (sca / chi) * eta[k];
-        double rel = fabs(eta_new[k] - eta[k]) / (fabs(eta_new[k]) + 1e-300);
-        if (eta_new[k] != 0.0 && rel > change) change = rel;
-      }
-      memcpy(eta, eta_new, sizeof(double) * nl);
-      if (change < 1e-13) break;
-    }
-    if (it + 1 > t->eta_iters_max) t->eta_iters_max = it + 1;
+    int its = eta_iterate(m, dBb, eta, eta_new);
+    if (its > t->eta_iters_max) t->eta_iters_max = its;
     /* eq:avd, eq:avd2 (per unit rho), eq:diffusion coeff, kappa-bar */
     double s_eta = 0.0, s_d = 0.0, s_d2 = 0.0, s_kc = 0.0, s_ic = 0.0;
     for (int k = 0; k < nl; ++k) {
@@ -689,6 +698,173 @@ void ora_conv_stat(const ora_model* m, const ora_tables* t, const double* E_abs,
   out[3] = (double)cells;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Observables by integration of the source function (Sect. 2.3, Sect. 3.3)  */
+/* ------------------------------------------------------------------------ */
+
+/* Mean intensity per cell and bin (erg s^-1 cm^-2 sr^-1, integrated over the
+ * bin) from a run's path-length tallies: J_k = (path_k + w_k mrw_path) /
+ * (4 pi V).  Explicit flights add eps * length at their bin; an MRW step adds
+ * eps * c t to the cell, spread over the bins as the walk's photons spend
+ * their path: weights eta_k / chi_k normalised (the weighting that defines
+ * kappa-bar, so sum_k w_k kappa_k = kappa-bar), eta at the cell's T. */
+void ora_mean_intensity(const ora_model* m, const double* T, const double* path,
+                        const double* mrw_path, double* J) {
+  const int nl = m->n_lambda, nc = m->n_r * m->n_mu;
+  double* V = (double*)malloc(sizeof(double) * nc);
+  double* Bb = (double*)malloc(sizeof(double) * nl);
+  double* dBb = (double*)malloc(sizeof(double) * nl);
+  double* eta = (double*)malloc(sizeof(double) * nl);
+  double* tmp = (double*)malloc(sizeof(double) * nl);
+  ora_cell_volumes(m, V);
+  const double sim = 1.0 - m->g_asym;
+  for (int c = 0; c < nc; ++c) {
+    const double iv = V[c] > 0.0 ? 1.0 / (4.0 * PI * V[c]) : 0.0;
+    for (int k = 0; k < nl; ++k) J[(size_t)c * nl + k] = path[(size_t)c * nl + k] * iv;
+    if (mrw_path && mrw_path[c] > 0.0 && T[c] > 0.0) {
+      ora_planck_bins(m->lambda_edges, nl, T[c], Bb, dBb);
+      eta_iterate(m, dBb, eta, tmp);
+      double sw = 0.0;
+      for (int k = 0; k < nl; ++k) sw += eta[k] / (m->kappa_abs[k] + m->kappa_sca[k] * sim);
+      for (int k = 0; k < nl; ++k)
+        J[(size_t)c * nl + k] +=
+            mrw_path[c] * iv * eta[k] / (m->kappa_abs[k] + m->kappa_sca[k] * sim) / sw;
+    }
+  }
+  free(V); free(Bb); free(dBb); free(eta); free(tmp);
+}
+
+/* Crossings of the ray x(s) = b + s n (b perpendicular to n, |n| = 1) with the
+ * grid's faces inside r_out: spheres r_e (|x|^2 = |b|^2 + s^2) and cones
+ * |z| = mu_e |x| (e = 1 .. n_mu-1).  Returns their count in s_out (unsorted). */
+static int ray_crossings(const ora_model* m, const double b[3], const double n[3], double* s_out) {
+  const int nr = m->n_r, nmu = m->n_mu;
+  const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  const double ro = m->r_edges[nr];
+  const double S = sqrt(fmax(ro * ro - bb, 0.0));
+  int q = 0;
+  for (int e = 0; e <= nr; ++e) {
+    double d2 = m->r_edges[e] * m->r_edges[e] - bb;
+    if (d2 > 0.0) {
+      s_out[q++] = -sqrt(d2);
+      s_out[q++] = sqrt(d2);
+    }
+  }
+  for (int e = 1; e < nmu; ++e) {
+    /* (b_z + s n_z)^2 = mu^2 (|b|^2 + s^2) */
+    const double mu2 = m->mu_edges[e] * m->mu_edges[e];
+    const double A = n[2] * n[2] - mu2, B = b[2] * n[2], C = b[2] * b[2] - mu2 * bb;
+    if (A == 0.0) {
+      if (B != 0.0) {
+        double r = -C / (2.0 * B);
+        if (fabs(r) < S) s_out[q++] = r;
+      }
+      continue;
+    }
+    double disc = B * B - A * C;
+    if (disc <= 0.0) continue;
+    double sq = sqrt(disc);
+    double r1 = (-B - sq) / A, r2 = (-B + sq) / A;
+    if (fabs(r1) < S) s_out[q++] = r1;
+    if (fabs(r2) < S) s_out[q++] = r2;
+  }
+  return q;
+}
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* Isotropic-equivalent luminosity per bin seen from the directions of
+ * cos(inclination) cos_i[q] (erg/s per bin: 4 pi D^2 times the flux at
+ * distance D), from the formal solution of the transfer equation along
+ * parallel rays towards the observer, dI/ds = rho chi (S - I), with the
+ * source function of isotropic scattering
+ *   S_k = (kappa_abs,k Bbar_k(T) + kappa_sca,k J_k) / chi_k
+ * per cell (J nullable: no scattering source), constant over each cell
+ * segment: I <- I e^(-dtau) + S (1 - e^(-dtau)) from the far side to the
+ * near one.  Rays: the image plane around the star in rings -- the hole
+ * [0, r_0] and every radial cell [r_i, r_{i+1}] cut into n_sub equal rings
+ * -- and n_phi azimuths phi = (p + 1/2) pi / n_phi on one side of the plane
+ * through the line of sight and the pole, each standing also for its mirror
+ * image; a ray at the ring's mid radius carries the area
+ * pi (b_hi^2 - b_lo^2) / n_phi.  The star adds its luminosity per bin (the
+ * spectrum the packets are launched with) times e^(-tau) along the line of
+ * sight from its centre.  out [n_inc][n_lambda]. */
+void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, const double* J,
+                      int n_inc, const double* cos_i, int n_sub, int n_phi, double* out) {
+  const int nl = m->n_lambda, nr = m->n_r, nmu = m->n_mu, nc = nr * nmu;
+  double* S = (double*)malloc(sizeof(double) * (size_t)nc * nl);
+  double* Bb = (double*)malloc(sizeof(double) * nl);
+  double* dBb = (double*)malloc(sizeof(double) * nl);
+  double* I = (double*)malloc(sizeof(double) * nl);
+  double* cr = (double*)malloc(sizeof(double) * (2 * (nr + 1) + 2 * nmu + 2));
+  for (int c = 0; c < nc; ++c) {
+    ora_planck_bins(m->lambda_edges, nl, T[c] > 0.0 ? T[c] : 0.0, Bb, dBb);
+    for (int k = 0; k < nl; ++k) {
+      const double chi = m->kappa_abs[k] + m->kappa_sca[k];
+      const double sca = J ? m->kappa_sca[k] * J[(size_t)c * nl + k] : 0.0;
+      S[(size_t)c * nl + k] = (m->kappa_abs[k] * Bb[k] + sca) / chi;
+    }
+  }
+  for (int q = 0; q < n_inc; ++q) {
+    const double ci = cos_i[q], si = sqrt(fmax(0.0, 1.0 - ci * ci));
+    const double n[3] = {si, 0.0, ci};      /* towards the observer */
+    const double e1[3] = {ci, 0.0, -si};    /* image plane */
+    const double e2[3] = {0.0, 1.0, 0.0};
+    double* L = out + (size_t)q * nl;
+    for (int k = 0; k < nl; ++k) L[k] = 0.0;
+    for (int ring = 0; ring < (nr + 1) * n_sub; ++ring) {
+      const int cell = ring / n_sub, part = ring % n_sub;
+      const double lo = cell == 0 ? 0.0 : m->r_edges[cell - 1];
+      const double hi = m->r_edges[cell];
+      const double b_lo = lo + (hi - lo) * part / n_sub;
+      const double b_hi = lo + (hi - lo) * (part + 1) / n_sub;
+      const double bm = 0.5 * (b_lo + b_hi);
+      const double area = PI * (b_hi * b_hi - b_lo * b_lo) / n_phi;
+      for (int ph = 0; ph < n_phi; ++ph) {
+        const double phi = (ph + 0.5) * PI / n_phi;
+        double b[3];
+        for (int a = 0; a < 3; ++a) b[a] = bm * (cos(phi) * e1[a] + sin(phi) * e2[a]);
+        int nx = ray_crossings(m, b, n, cr);
+        qsort(cr, nx, sizeof(double), cmp_double);
+        for (int k = 0; k < nl; ++k) I[k] = 0.0;
+        for (int g = 0; g + 1 < nx; ++g) {
+          const double len = cr[g + 1] - cr[g];
+          if (!(len > 0.0)) continue;
+          const double sm = 0.5 * (cr[g] + cr[g + 1]);
+          const int64_t c = ora_locate(m, b[0] + sm * n[0], b[1] + sm * n[1], b[2] + sm * n[2]);
+          if (c < 0 || m->rho[c] <= 0.0) continue;
+          for (int k = 0; k < nl; ++k) {
+            const double dtau = m->rho[c] * (m->kappa_abs[k] + m->kappa_sca[k]) * len;
+            const double at = exp(-dtau);
+            I[k] = I[k] * at + S[(size_t)c * nl + k] * (1.0 - at);
+          }
+        }
+        for (int k = 0; k < nl; ++k) L[k] += 4.0 * PI * I[k] * area;
+      }
+    }
+    /* the star, through the cells along the line of sight from its centre */
+    const double zero[3] = {0.0, 0.0, 0.0};
+    int nx = ray_crossings(m, zero, n, cr);
+    qsort(cr, nx, sizeof(double), cmp_double);
+    for (int k = 0; k < nl; ++k) {
+      double tau = 0.0;
+      for (int g = 0; g + 1 < nx; ++g) {
+        const double len = cr[g + 1] - cr[g];
+        const double sm = 0.5 * (cr[g] + cr[g + 1]);
+        if (!(len > 0.0) || sm <= 0.0) continue;
+        const int64_t c = ora_locate(m, sm * n[0], sm * n[1], sm * n[2]);
+        if (c >= 0) tau += m->rho[c] * (m->kappa_abs[k] + m->kappa_sca[k]) * len;
+      }
+      const double share = t->star_cdf[k] - (k ? t->star_cdf[k - 1] : 0.0);
+      L[k] += t->L_star * share * exp(-tau);
+    }
+  }
+  free(S); free(Bb); free(dBb); free(I); free(cr);
+}
+
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {
   int nc = m->n_r * m->n_mu;
   double* V = (double*)malloc(sizeof(double) * nc);
@@ -704,7 +880,8 @@ void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, 
 int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t n_packets,
             uint64_t n_total, uint64_t seed, uint64_t offset, double* E_abs, uint32_t* visits,
             uint32_t* n_abs, uint32_t* n_mrw_cell, double* sed, double* E_star,
-            long long* counters, ora_packet_rec* recs, int64_t n_recs, double* E_half) {
+            long long* counters, ora_packet_rec* recs, int64_t n_recs, double* E_half,
+            double* path, double* mrw_path) {
   const int nl = m->n_lambda, nmu = m->n_mu, nr = m->n_r;
   const int nc = nr * nmu;
   const double eps = t->L_star / (double)n_total;
@@ -778,6 +955,7 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
       double tau_b = alpha * sb;
       if (tau_b <= tau) {
         /* reach the face: move, spend optical depth, step the index */
+        if (path) path[(size_t)c * nl + k] += eps * sb;
         for (int a = 0; a < 3; ++a) p[a] += sb * d[a];
         tau -= tau_b;
         ++n_cross;
@@ -804,6 +982,7 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
       }
       /* interaction inside the cell */
       double sint = tau / alpha;
+      if (path) path[(size_t)c * nl + k] += eps * sint;
       for (int a = 0; a < 3; ++a) p[a] += sint * d[a];
       double omega = m->kappa_sca[k] / chi;
       if (rng_next(&rng) < omega) {
@@ -840,6 +1019,8 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o, uint64_t
           double R0 = dmin * (1.0 - 1e-6);
           double s = ora_mrw_escape_s(rng_next(&rng));
           double dE = eps * ora_mrw_deposit(m, t, c, Tc, R0, s);
+          /* the walk's path, c t = s R0^2 / D */
+          if (mrw_path) mrw_path[c] += eps * s * R0 * R0 * m->rho[c] / t_interp(t, t->Drho, Tc);
           double nrm[3];
           iso_dir(&rng, nrm);
           for (int a = 0; a < 3; ++a) p[a] += R0 * nrm[a];

@@ -98,8 +98,24 @@ int ora_run(const ora_model* m, const ora_tables* t, const ora_opts* o,
             uint64_t n_packets, uint64_t n_total, uint64_t seed, uint64_t offset,
             double* E_abs, uint32_t* visits, uint32_t* n_abs, uint32_t* n_mrw_cell,
             double* sed, double* E_star, long long* counters, ora_packet_rec* recs,
-            int64_t n_recs, double* E_half);
-/* E_half (nullable): absorbed energy of the odd-numbered packets alone. */
+            int64_t n_recs, double* E_half, double* path, double* mrw_path);
+/* E_half (nullable): absorbed energy of the odd-numbered packets alone.
+ * path (nullable) [n_cells][n_lambda]: eps times the length of every explicit
+ * flight, by cell and bin; mrw_path (nullable) [n_cells]: eps times the path
+ * c t of every MRW step. */
+
+/* Mean intensity J [n_cells][n_lambda] (bin-integrated, erg/s/cm^2/sr) from
+ * the path tallies; the MRW path is spread over the bins with the weights
+ * eta/chi at T. */
+void ora_mean_intensity(const ora_model* m, const double* T, const double* path,
+                        const double* mrw_path, double* J);
+
+/* Isotropic-equivalent luminosity per bin [n_inc][n_lambda] seen at
+ * cos(inclination) cos_i, by ray tracing the source function of T and J
+ * (nullable) on rings of n_sub per radial cell and n_phi azimuths, plus the
+ * attenuated star. */
+void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, const double* J,
+                      int n_inc, const double* cos_i, int n_sub, int n_phi, double* out);
 
 /* Convergence statistic of the vertical-structure loop from one pass's
  * tallies (E_half: the odd-numbered packets' share; visits: packets entering

@@ -11,6 +11,7 @@ import pytest
 sys.path.insert(0, os.path.dirname(__file__))
 import test_oracle_deposit_launch_picard as P  # noqa: E402
 import test_oracle_convergence as CV  # noqa: E402
+import test_oracle_raytrace as RT  # noqa: E402
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "mcrt_oracle.c")
 
@@ -39,6 +40,17 @@ MUTANTS = {
     # the slope of the inversion enters unsquared
     "conv_slope_unsquared": ("      s2 = slope * slope * rel * rel;",
                              "      s2 = slope * rel * rel;"),
+    # the formal solution forgets to attenuate what lies behind
+    "ray_no_attenuation": ("            I[k] = I[k] * at + S[(size_t)c * nl + k] * (1.0 - at);",
+                           "            I[k] = I[k] + S[(size_t)c * nl + k] * (1.0 - at);"),
+    # a ray stands for one azimuth only, not also its mirror image
+    "ray_area_halved": ("      const double area = PI * (b_hi * b_hi - b_lo * b_lo) / n_phi;",
+                        "      const double area = PI * (b_hi * b_hi - b_lo * b_lo) / (2 * n_phi);"),
+    "ray_area_halved_thick": ("      const double area = PI * (b_hi * b_hi - b_lo * b_lo) / n_phi;",
+                              "      const double area = PI * (b_hi * b_hi - b_lo * b_lo) / (2 * n_phi);"),
+    # the mean intensity loses its 4 pi
+    "mean_intensity_no_4pi": ("    const double iv = V[c] > 0.0 ? 1.0 / (4.0 * PI * V[c]) : 0.0;",
+                              "    const double iv = V[c] > 0.0 ? 1.0 / V[c] : 0.0;"),
 }
 
 PIN = {
@@ -50,6 +62,10 @@ PIN = {
     "half_tally_even": lambda o: CV.test_odd_tally_is_the_odd_packets_alone(o),
     "conv_half_spread": lambda o: CV.test_split_noise_against_run_to_run_spread(o, _passes()),
     "conv_slope_unsquared": lambda o: CV.test_split_noise_against_run_to_run_spread(o, _passes()),
+    "ray_no_attenuation": lambda o: RT.test_thick_isothermal_shell(o),
+    "ray_area_halved": lambda o: RT.test_thin_isothermal_shell(o),
+    "ray_area_halved_thick": lambda o: RT.test_thick_isothermal_shell(o),
+    "mean_intensity_no_4pi": lambda o: RT.test_mean_intensity_follows_the_dilution_law(o),
 }
 
 
