@@ -22,6 +22,11 @@ Printed: one JSON line with
 * the 64-disk batched workload at its drawn packet counts, five passes in one
   HIP graph, beside the plain FP64 path one disk at a time on a sample of the
   disks; the batched PDA of the last pass alone, in GB/s;
+* the vertical-structure loop with the hydrostatic step run to convergence
+  on the device (passes and the statistic of each);
+* the ray-traced SED (source function of the Monte Carlo T and mean
+  intensity) with and without the MRW at 1e6 packets, and the ray tracer's
+  time;
 * the PDA and its adjoint on the 200 x 120 differentiation workload;
 * the CPU oracle on a bounded sample of the step on this host.
 Stage lines go to stderr.
@@ -127,10 +132,18 @@ def parse():
     p.add_argument("--budget-s", type=float, default=560.0,
                    help="wall-clock budget of the whole run: a leg after the timed steps "
                         "whose expected length would pass it is skipped and reported so")
+    p.add_argument("--tune-out", default="",
+                   help="time the autotuner's candidates on the step at --packets, write "
+                        "the choice to this file and exit")
+    p.add_argument("--sed-study", type=int, default=0,
+                   help="the MRW's effect on the ray-traced SED at this many packets per run "
+                        "and exit")
     p.add_argument("--pda-probe", action="store_true",
                    help="the 64-disk workload, one pass at its drawn packets, then the batched "
                         "PDA of that pass alone (for counter runs) and exit")
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-hydro", action="store_true")
+    p.add_argument("--no-sed", action="store_true")
     p.add_argument("--no-ref", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-pda", action="store_true")
@@ -499,6 +512,75 @@ def hydro(mcrt, W, torch, n_iter):
     return out
 
 
+def vertical_structure(mcrt, W, torch, max_iter):
+    """The vertical-structure loop run to convergence on the device
+    (mcrt_batch_converge): the step's disk with the hydrostatic step
+    (M_star 2.5 Msun, mu 2.3), 1e6 packets per pass, one HIP graph per pass,
+    stopped when the statistic R (the change of T against its photon noise
+    from the split tallies, Sect. 2.5) is below 3."""
+    d, o = W.config("mrw_pda")
+    ctx = mcrt.Context(d, precision="fp32", mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                       pda_visits=o.pda_visits, n_T=o.n_T, hydro_M_star=2.5 * W.M_SUN,
+                       hydro_mu=2.3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rec, rc = mcrt.batch_converge([ctx], [o.n_packets], [o.seed], max_iter=max_iter)
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t0
+    r = rec[0]
+    return {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins, 1e6 packets per pass, MRW "
+                        "gamma=3, PDA < 100 visits; hydrostatic step M_star 2.5 Msun, mu 2.3",
+            "passes": r["passes"], "converged_pass": r["converged_pass"],
+            "R_per_pass": [round(x, 3) for x in r["R"]], "threshold": 3.0,
+            "dT_rms_last": r["dT_rms"], "noise_rms_last": r["noise_rms"],
+            "cells_compared": r["cells"], "return_code": rc, "s": s,
+            "packets_per_s": r["passes"] * o.n_packets / s}
+
+
+def sed_study(mcrt, W, torch, n_packets, cos_i=(0.7071067811865476, 0.2588190451025208,
+                                                  0.9659258262890683)):
+    """The effect of the MRW on the ray-traced SED (Sect. 3.3): the step's
+    disk traced with the MRW (FP32, gamma = 3) and without it (FP64, the
+    reference), n_packets each with the path-length tallies; the SED of each
+    from its Monte Carlo T (before the PDA) and its mean intensity, at 45
+    degrees and two more inclinations; the relative difference per bin.  Also
+    the ray tracer's time."""
+    import numpy as np
+    d, o = W.config("mrw_pda")
+    out = {"workload": "disk 1e-2 Msun, 100 r x 60 theta, 100 bins, %.3g packets each, "
+                       "MRW gamma=3 (FP32) against no MRW (FP64)" % n_packets,
+           "cos_i": list(cos_i)}
+    seds = {}
+    for name, kw in (("mrw", dict(precision="fp32", mrw=True)),
+                     ("reference", dict(precision="fp64", mrw=False))):
+        ctx = mcrt.Context(d, gamma=o.gamma, n_int_min=o.n_int_min, pda_visits=o.pda_visits,
+                           n_T=o.n_T, j_tally=1, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.reset()
+        ctx.trace(n_packets, o.seed + 5150)
+        T = ctx.update_T()
+        J = ctx.mean_intensity(T)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L = ctx.raytrace_sed(T, J, cos_i=list(cos_i), n_sub=4, n_phi=32)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        seds[name] = L.cpu().numpy()
+        out[name + "_trace_s"] = t1 - t0
+        out[name + "_raytrace_ms"] = (t2 - t1) * 1e3
+        log("sed study: %s done (%.1f s trace, %.1f ms ray tracing)" % (name, t1 - t0,
+                                                                      (t2 - t1) * 1e3))
+        del ctx
+    a, b = seds["mrw"], seds["reference"]
+    rel = a / np.where(b > 0, b, 1) - 1
+    keep = b > 1e-6 * b.max(axis=1, keepdims=True)   # bins that carry light
+    out["max_abs_rel_diff"] = [float(np.abs(rel[q][keep[q]]).max()) for q in range(len(cos_i))]
+    out["mean_abs_rel_diff"] = [float(np.abs(rel[q][keep[q]]).mean()) for q in range(len(cos_i))]
+    out["rays"] = len(cos_i) * (d.n_r + 1) * 4 * 32
+    return out
+
+
 def hydro_batched(mcrt, W, torch, n_iter):
     """The same loop as one mcrt_batch_run call: n_iter passes of trace (1e6
     packets) -> T -> PDA -> hydrostatic equilibrium captured in one HIP graph
@@ -838,26 +920,42 @@ def main():
     if a.pda_probe:
         print(json.dumps({"pda_probe": pda_probe(mcrt, W, torch)}), flush=True)
         return
+    if a.sed_study > 0:
+        print(json.dumps({"sed_study": sed_study(mcrt, W, torch, a.sed_study)}), flush=True)
+        return
 
     disk, o = W.config("mrw_pda")
     N = a.packets
-    tuned = None
+    from paper_0902_3092_amd import autotune
+    phys = dict(precision=a.precision, mrw=True, gamma=o.gamma, n_int_min=o.n_int_min,
+                pda_visits=o.pda_visits, n_T=o.n_T)
+    if a.tune_out:
+        # measure the choices for this step and write them where the package
+        # keeps them (the caller copies the file into the package)
+        log("autotune: timing candidates at %.3g packets" % N)
+        e = autotune.tune(disk, n_packets=N, seeds=(11,), path=a.tune_out, log=log, **phys)
+        print(json.dumps({"autotune": e}), flush=True)
+        return
     if a.autotune:
-        from paper_0902_3092_amd import autotune
         log("autotune: timing candidates")
-        tuned = autotune.tune(disk, n_packets=200000, precision=a.precision, mrw=True,
-                              gamma=o.gamma, n_int_min=o.n_int_min, pda_visits=o.pda_visits,
-                              n_T=o.n_T, log=log)
-    ctx = mcrt.Context(disk, precision=a.precision, mrw=True, gamma=o.gamma,
-                       n_int_min=o.n_int_min, pda_visits=o.pda_visits, n_T=o.n_T,
-                       **(tuned["options"] if tuned else {}))
+        tuned = autotune.tune(disk, n_packets=N, seeds=(11,), log=log, **phys)
+        tuned_src = "measured in this run"
+    else:
+        tuned = autotune.lookup(disk, N, **phys)
+        tuned_src = ("the package's cache (%s), measured on an MI355X"
+                     % os.path.basename(autotune.PACKAGED_CACHE))
+    t_opts = autotune.options_for(disk, N, **phys) if tuned and not a.autotune else (
+        {k: v for k, v in tuned["options"].items() if k not in autotune.NON_OPTIONS}
+        if tuned else {})
+    n_calls = int(tuned["options"].get("calls_per_pass", 1)) if tuned else 1
+    ctx = mcrt.Context(disk, **phys, **t_opts)
     stream = torch.cuda.current_stream()
 
     def step(i, ev=None):
         ctx.reset()
         if ev is not None:
             ev[0].record(stream)
-        ctx.trace(N, o.seed + 1000 * i)
+        autotune.trace_pass(ctx, N, o.seed + 1000 * i, n_calls)
         if ev is not None:
             ev[1].record(stream)
         ctx.update_T()
@@ -918,11 +1016,16 @@ def main():
                      "kernel_ms": float(np.mean(trace_ms)),
                      "flops_per_launch": flops},
         "events_per_step": c,
-        "options": (tuned["options"] if tuned else "library defaults"),
+        "options": (dict(t_opts, calls_per_pass=n_calls) if tuned else "library defaults"),
         "pda": {k: pda[k] for k in ("sweeps", "cg_iters_total", "n_region")},
     }
     if tuned:
-        out["autotune"] = {k: tuned[k] for k in ("trace_s", "pda_s", "pda_iters", "n_packets")}
+        out["autotune"] = {"source": tuned_src, "choice": tuned["options"],
+                           **{k: tuned[k] for k in ("shape_s", "trace_s", "calls_s", "pda_s",
+                                                    "pda_iters", "n_packets", "when")
+                              if k in tuned}}
+    else:
+        out["autotune"] = {"source": "no cached choice for this step: library defaults"}
     # the legs after the timed steps, in order of importance; each is skipped
     # (and reported so) when its expected length would pass the budget
     leg_s, skipped = {}, {}
@@ -991,6 +1094,20 @@ def main():
 
     if not a.no_cpu:
         leg("cpu_baseline", a.cpu_packets / 5e4, do_cpu)
+
+    def do_vertical():
+        log("vertical-structure loop to convergence")
+        out["vertical_structure"] = vertical_structure(mcrt, W, torch, 10)
+
+    if not a.no_hydro:
+        leg("vertical_structure", 40.0, do_vertical)
+
+    def do_sed():
+        log("ray-traced SED, MRW against no MRW, 1e6 packets")
+        out["sed_study_1e6"] = sed_study(mcrt, W, torch, o.n_packets)
+
+    if not a.no_sed:
+        leg("sed_study_1e6", 40.0, do_sed)
 
     def do_grad():
         log("PDA and adjoint on the differentiation workload")

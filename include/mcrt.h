@@ -102,8 +102,13 @@ typedef struct {
                             context holds when a trace starts, once mcrt_update_T
                             or mcrt_set_T has run (the previous pass's, PDA
                             included) (0) */
-  int32_t block_size;    /* trace workgroup size, 0 = library choice */
-  int32_t blocks_per_cu; /* trace workgroups per compute unit, 0 = library choice */
+  int32_t block_size;    /* trace workgroup size: 0 or 512 (one workgroup per compute
+                            unit, tables and emission CDF in up to 155 KB of LDS), or
+                            256 with FP32 tracking (LDS capped at half of that, so two
+                            share a compute unit; the CDF then stays in L2); batched
+                            runs use 512 (0) */
+  int32_t blocks_per_cu; /* trace workgroups launched per compute unit (0: as many as
+                            fit at once); more than fit wait for a free slot (0) */
   int32_t pda_solver;    /* 0 auto, 1 grid-wide CG kernels, 2 one workgroup per disk (0) */
   int32_t pda_precond;   /* CG preconditioner of the one-workgroup solver: 0 Jacobi (the
                             diagonal), 1 block Jacobi on the theta lines of each radius
@@ -132,6 +137,15 @@ typedef struct {
                             the cell, so every such cell without an absorption (T = 0)
                             joins (the second test of Sect. 3.1; the paper uses 0.05;
                             transparent cells are not diffusive); 0: visits rule only (0) */
+  int32_t conv_split;    /* 1: mcrt_trace also tallies the absorbed energy of the
+                            odd-numbered packets apart (MCRT_GET_E_HALF), from which
+                            mcrt_convergence takes the photon noise (0).  The converging
+                            batch loop keeps that tally whatever this says. */
+  int32_t j_tally;       /* 1: the context holds path-length tallies (eps times every
+                            explicit flight length by cell and bin, and eps times the
+                            path c t of every MRW step by cell) that mcrt_trace and
+                            batched passes fill, for mcrt_mean_intensity (0: none;
+                            costs 8 (n_lambda + 1) bytes per cell) */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
@@ -259,6 +273,12 @@ int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_d
                                kappa-bar [n_T], star cdf [n_lambda], L_star [1] */
 #define MCRT_GET_HYDRO_COLD 10 /* uint32 [1]: shells the last hydrostatic step left
                                   unchanged (an opaque dust cell at T <= 0) */
+#define MCRT_GET_E_HALF 11  /* double [n_cells], erg/s absorbed from the odd-numbered
+                               packets alone (kept with conv_split, or by
+                               mcrt_batch_converge) */
+#define MCRT_GET_PATH 12    /* double [n_cells][n_lambda], eps times the explicit flight
+                               lengths (j_tally; else MCRT_E_ARG) */
+#define MCRT_GET_MRW_PATH 13 /* double [n_cells], eps times the MRW steps' c t (j_tally) */
 
 /* Copy a context array into caller device memory (async, device to device):
  * the Monte Carlo tallies of Sect. 2.1 (absorbed energy, visits, absorption
@@ -319,6 +339,93 @@ int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_de
 int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
                    const uint64_t* seeds, int n_iter, int use_graph, mcrt_pda_stats* stats,
                    hipStream_t stream);
+
+/* Convergence statistic of the vertical-structure loop (Sect. 2.5: the mean
+ * change of the temperature structure between two consecutive passes,
+ * against the error that the Monte Carlo statistics give it; converged below
+ * 3 sigma), from the context's current tallies (a pass traced with
+ * conv_split = 1) and the values the previous call stored in the context.
+ * Per dusty cell entered by >= n_min packets with E > 0: T = T(E) (the
+ * inversion of mcrt_update_T); the odd- and even-numbered packets are two
+ * independent half-size runs, so the relative variance of E is
+ * ((2 E_half - E) / E)^2, and that of T is (dlnT/dlnE)^2 times it, the slope
+ * a central difference of T(E) over E (1 +- 1e-4).  Over the cells eligible
+ * in this pass and the previous one,
+ *   R = sqrt(sum x^2 / sum (s2 + s2_prev)),  x = (T - T_prev) / T.
+ * first != 0: no previous pass (nothing compared, R = 0).  Stores this pass's
+ * T and s2 for the next call.  out_host (nullable) [4] double: R, the RMS of
+ * x, the RMS noise sqrt(mean(s2 + s2_prev)), the cells compared; when given,
+ * the call waits for the stream.  Errors: MCRT_E_ARG for a null context or
+ * n_min < 1. */
+int mcrt_convergence(mcrt_ctx* ctx, int32_t n_min, int32_t first, double* out_host,
+                     hipStream_t stream);
+
+/* Mean intensity of the radiation field per cell and bin (Sect. 2.3: the
+ * source function the observables integrate), from the path-length tallies
+ * of the traces since the last reset (j_tally = 1, else MCRT_E_ARG):
+ *   J_k = (P_k + w_k P_mrw) / (4 pi V),
+ * P_k the explicit flights' eps * length at bin k, P_mrw the MRW steps'
+ * eps * c t, spread over the bins as a walk spends its path: w_k = eta_k /
+ * chi_k normalised, the weighting that defines kappa-bar (Sect. 2.2.3), which
+ * at the fixed point of eq. eta nu iter is dB_k/dT over its sum, at the
+ * cell's temperature T_dev [n_cells] (nullable: the context's T).  J_dev
+ * [n_cells][n_lambda] double, erg s^-1 cm^-2 sr^-1 integrated over the bin.
+ * Asynchronous.  Errors: MCRT_E_ARG for a null context or J_dev, or no
+ * path tallies. */
+int mcrt_mean_intensity(mcrt_ctx* ctx, const double* T_dev, double* J_dev, hipStream_t stream);
+
+/* Spectral energy distribution by integration of the source function
+ * (Sect. 2.3; the paper takes T before the PDA, Sect. 3.3): the
+ * isotropic-equivalent luminosity per bin (4 pi D^2 times the flux at
+ * distance D, erg/s per bin) seen at n_inc inclinations cos_i_host[q]
+ * (cosine of the angle to the pole, host, in [0, 1]), from the formal solution
+ * dI/ds = rho chi (S - I) along parallel rays, with the isotropic-scattering
+ * source function S_k = (kappa_abs,k Bbar_k(T) + kappa_sca,k J_k) / chi_k
+ * constant in each cell, I <- I e^(-dtau) + S (1 - e^(-dtau)) from the far
+ * side to the near one.  Rays: the image plane in rings -- the central hole
+ * [0, r_0] and each radial cell [r_i, r_i+1] cut into n_sub equal rings --
+ * and n_phi azimuths phi = (p + 1/2) pi / n_phi on one side of the plane of
+ * the line of sight and the pole, each standing also for its mirror image,
+ * a ray at the ring's mid radius carrying the area pi (b_hi^2 - b_lo^2) /
+ * n_phi.  The star adds its luminosity in the bin (the launch spectrum)
+ * times e^(-tau) along the line of sight from its centre.  T_dev [n_cells]
+ * (nullable: the context's T); J_dev [n_cells][n_lambda] (nullable: no
+ * scattering source).  L_dev [n_inc][n_lambda] double, overwritten.  The
+ * context keeps a source-function buffer of 8 n_cells n_lambda bytes after
+ * its first call.  Asynchronous.  Errors: MCRT_E_ARG for a null context or
+ * L_dev, n_inc outside [1, 64], n_sub < 1, n_phi < 1, a cos_i outside
+ * [0, 1], more than 512 bins, or g_asym != 0 (the source function here
+ * scatters isotropically); MCRT_E_OOM. */
+int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
+                      const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* L_dev,
+                      hipStream_t stream);
+
+/* Outcome of mcrt_batch_converge for one disk. */
+typedef struct {
+  int32_t passes;          /* passes run */
+  int32_t converged_pass;  /* first pass (0-based) whose R fell below the threshold, -1 */
+  double R_last;           /* the statistic of the last pass (0 after a single pass) */
+  double dT_rms;           /* its RMS relative change of T */
+  double noise_rms;        /* its RMS photon noise of that change */
+  int32_t cells;           /* cells it compared */
+} mcrt_conv_stats;
+
+/* The vertical-structure loop run to convergence (Sect. 2.5): the passes of
+ * mcrt_batch_run (pass k with seeds[d] + (k << 32), one HIP graph per pass
+ * when use_graph != 0), each followed on the device by mcrt_convergence for
+ * every disk (n_min packets per cell; the split tally is kept for the call),
+ * until every disk's statistic R has fallen below `threshold` (the paper's
+ * 3) or max_iter passes have run; at least 2 passes.  Disks that converge
+ * before the others keep iterating with them.  conv (host, nullable)
+ * [n_disks]; R_hist (host, nullable) [n_disks][max_iter] receives each pass's
+ * R (0 for pass 0, -1 for passes not run); stats as for mcrt_batch_run.
+ * Returns as mcrt_batch_run, or MCRT_E_NOT_CONVERGED when some disk did not
+ * converge within max_iter passes (its conv entry says which).  Errors:
+ * MCRT_E_ARG as for mcrt_batch_run, or max_iter < 2, threshold <= 0. */
+int mcrt_batch_converge(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
+                        const uint64_t* seeds, int max_iter, int32_t n_min, double threshold,
+                        int use_graph, mcrt_pda_stats* stats, mcrt_conv_stats* conv,
+                        double* R_hist, hipStream_t stream);
 
 /* The PDA step of mcrt_batch_run alone (Sect. 2.2.1, eq. T diffusion; the
  * region rule of each context, Sect. 3.1): every context's region solved from

@@ -1,18 +1,27 @@
 """Pick launch and solver options for a disk by timing them on the GPU, and
 cache the choice per problem shape.
 
-Knobs (all are `mcrt_options` fields, so a tuned context is an ordinary one):
+Knobs (`mcrt_options` fields, so a tuned context is an ordinary one, and
+the packets per trace call, which the caller applies):
+  * Trace launch shape: `block_size` and `blocks_per_cu` -- 512-thread
+    workgroups, one per compute unit with the emission CDF in LDS (the
+    default), or 256-thread ones, two per compute unit with the CDF in L2, or
+    one.  FP32 tracking only (the FP64 kernels are built for 512).
+  * Trace hand-off: `wave_events`, the event count after which a packet still
+    going once all packets are handed out moves to the whole-wavefront launch.
+  * Packets per `mcrt_trace` call: a pass of n packets as 1, 2 or 4 calls
+    (same packets, by offset); each call pays the tail of its longest walk,
+    so one call is expected to win -- the tuner measures it.
   * PDA: `pda_solver` (1 grid-wide CG kernels, 2 one workgroup) and, for the
     one-workgroup solver, `pda_precond` (0 point Jacobi, 1 theta-line blocks).
     Timed on the region and Monte Carlo temperature of a real pass, restored
     before every solve, so every candidate solves the same system.
-  * Trace: `wave_events`, the event count after which a packet still going
-    once all packets are handed out moves to the whole-wavefront launch.
-    Timed as whole passes on the same seeds, so the candidates trace the same
-    packets.
+The trace candidates are timed as whole passes on the same seeds, so they
+trace the same packets; each stage keeps the winner of the one before.
 
-Nothing here runs implicitly: `options_for` only reads the cache, and
-`tune` is called by the user (or `bench.py --autotune`).
+Nothing here runs implicitly: `options_for` only reads a cache, and `tune`
+is called by the user (or `bench.py --autotune`).  `PACKAGED_CACHE` holds
+choices measured on an MI355X, which `options_for` falls back to.
 """
 import json
 import math
@@ -25,6 +34,9 @@ import numpy as np
 CACHE_ENV = "MCRT_AUTOTUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_0902_3092_amd",
                              "autotune.json")
+PACKAGED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
+# what a choice holds beyond the mcrt_options fields
+NON_OPTIONS = ("calls_per_pass",)
 # physics options that must be equal between the tuned and the timed contexts
 PHYSICS = ("precision", "mrw", "gamma", "n_int_min", "n_T", "pda_visits")
 
@@ -67,10 +79,34 @@ def store(key: str, entry: dict, path: Optional[str] = None) -> None:
     os.replace(tmp, p)
 
 
+def lookup(disk, n_packets: int, path: Optional[str] = None, **phys) -> Optional[dict]:
+    """The cached entry for this shape (the user's cache, else the packaged
+    one), or None."""
+    key = shape_key(disk, n_packets, **phys)
+    e = load(path).get(key)
+    if e is None and path is None:
+        e = load(PACKAGED_CACHE).get(key)
+    return e
+
+
 def options_for(disk, n_packets: int, path: Optional[str] = None, **phys) -> dict:
-    """The cached options for this shape, or {} (library defaults)."""
-    e = load(path).get(shape_key(disk, n_packets, **phys))
-    return dict(e["options"]) if e else {}
+    """The cached mcrt_options fields for this shape, or {} (library
+    defaults)."""
+    e = lookup(disk, n_packets, path, **phys)
+    return {k: v for k, v in e["options"].items() if k not in NON_OPTIONS} if e else {}
+
+
+def calls_per_pass(disk, n_packets: int, path: Optional[str] = None, **phys) -> int:
+    """The cached number of trace calls per pass for this shape (1 if none)."""
+    e = lookup(disk, n_packets, path, **phys)
+    return int(e["options"].get("calls_per_pass", 1)) if e else 1
+
+
+def trace_pass(ctx, n_packets: int, seed: int, calls: int = 1, stream=None):
+    """One pass of n packets as `calls` trace calls (packets by offset)."""
+    per = -(-n_packets // calls)
+    for off in range(0, n_packets, per):
+        ctx.trace(min(per, n_packets - off), seed, n_total=n_packets, offset=off, stream=stream)
 
 
 def pick(timings: Dict[str, float], ok: Dict[str, bool], default: str,
@@ -91,10 +127,13 @@ def _label(opts: dict) -> str:
 
 
 def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
-         wave_events: Sequence[int] = (512, 2048, 8192), pda_repeats: int = 3,
+         wave_events: Sequence[int] = (512, 2048, 8192),
+         shapes: Sequence[tuple] = ((512, 0), (256, 0), (256, 1)),
+         calls: Sequence[int] = (1, 2, 4), pda_repeats: int = 3,
          path: Optional[str] = None, save: bool = True, log=None, **phys) -> dict:
     """Time the candidates on this disk and return (and cache) the choice:
-    {"key", "options", "trace_s", "pda_s", "pda_iters"}."""
+    {"key", "options", "shape_s", "trace_s", "calls_s", "pda_s", "pda_iters"}.
+    shapes: (block_size, blocks_per_cu) pairs, tried with FP32 tracking."""
     import torch
     from . import mcrt as M
 
@@ -104,28 +143,45 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
     phys.setdefault("mrw", True)
     key = shape_key(disk, n_packets, **phys)
 
-    # trace: whole passes on the same seeds
-    trace_s, trace_ok = {}, {}
-    for we in wave_events:
-        ctx = M.Context(disk, wave_events=int(we), **phys)
+    def passes(opts, n_calls=1):
+        """(seconds over the seeds, every packet traced and none capped)"""
+        ctx = M.Context(disk, **phys, **opts)
         t = 0.0
         for s in seeds:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ctx.reset()
-            ctx.trace(n_packets, int(s))
+            trace_pass(ctx, n_packets, int(s), n_calls)
             ctx.update_T()
             torch.cuda.synchronize()
             t += time.perf_counter() - t0
         c = ctx.counters()
-        trace_s[str(we)] = t
-        trace_ok[str(we)] = c["capped"] == 0 and c["launch"] == n_packets
-        say("autotune: wave_events=%d: %.3f s" % (we, t))
         del ctx
+        return t, c["capped"] == 0 and c["launch"] == n_packets
+
+    # launch shape (FP32 only), then the hand-off threshold, then calls per pass
+    shape_s, shape_ok = {}, {}
+    if phys["precision"] != "fp32":
+        shapes = ((512, 0),)
+    for bs, per_cu in shapes:
+        lab = "%d/%d" % (bs, per_cu)
+        shape_s[lab], shape_ok[lab] = passes(dict(block_size=bs, blocks_per_cu=per_cu))
+        say("autotune: block_size/blocks_per_cu %s: %.3f s" % (lab, shape_s[lab]))
+    bs_best, cu_best = (int(x) for x in pick(shape_s, shape_ok, "512/0").split("/"))
+    shape = dict(block_size=bs_best, blocks_per_cu=cu_best)
+    trace_s, trace_ok = {}, {}
+    for we in wave_events:
+        trace_s[str(we)], trace_ok[str(we)] = passes(dict(wave_events=int(we), **shape))
+        say("autotune: wave_events=%d: %.3f s" % (we, trace_s[str(we)]))
     we_best = int(pick(trace_s, trace_ok, str(2048 if 2048 in wave_events else wave_events[0])))
+    calls_s, calls_ok = {}, {}
+    for k in calls:
+        calls_s[str(k)], calls_ok[str(k)] = passes(dict(wave_events=we_best, **shape), int(k))
+        say("autotune: %d trace call(s) per pass: %.3f s" % (k, calls_s[str(k)]))
+    calls_best = int(pick(calls_s, calls_ok, "1"))
 
     # PDA: the region and MC temperature of one pass, the same system for all
-    base = M.Context(disk, wave_events=we_best, **phys)
+    base = M.Context(disk, wave_events=we_best, **shape, **phys)
     base.reset()
     base.trace(n_packets, int(seeds[0]))
     base.update_T()
@@ -139,7 +195,7 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
         cands += [dict(pda_solver=2, pda_precond=0), dict(pda_solver=2, pda_precond=1)]
     pda_s, pda_ok, pda_it = {}, {}, {}
     for cand in cands:
-        ctx = M.Context(disk, wave_events=we_best, **phys, **cand)
+        ctx = M.Context(disk, wave_events=we_best, **shape, **phys, **cand)
         best = float("inf")
         st = None
         for _ in range(pda_repeats):
@@ -163,9 +219,11 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
     default_pda = _label(dict(pda_solver=2, pda_precond=1)) if n_cells <= 65536 else \
         _label(cands[0])
     pda_best = pick(pda_s, pda_ok, default_pda)
-    opts = {"wave_events": we_best}
+    opts = {"wave_events": we_best, "calls_per_pass": calls_best}
+    opts.update(shape)
     opts.update({k: int(v) for k, v in (kv.split("=") for kv in pda_best.split(","))})
-    entry = {"key": key, "options": opts, "trace_s": trace_s, "pda_s": pda_s,
+    entry = {"key": key, "options": opts, "shape_s": shape_s, "trace_s": trace_s,
+             "calls_s": calls_s, "pda_s": pda_s,
              "pda_iters": pda_it, "n_packets": n_packets, "seeds": list(seeds),
              "device": torch.cuda.get_device_name(0),
              "when": time.strftime("%Y-%m-%dT%H:%M:%S")}

@@ -12,7 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmcrt.so")
-SOURCES = ["mcrt_api.hip", "trace_fp64.hip", "trace_fp32.hip", "pda.hip", "batch.hip"]
+SOURCES = ["mcrt_api.hip", "trace_fp64.hip", "trace_fp32.hip", "pda.hip", "batch.hip",
+           "observe.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,

@@ -25,11 +25,9 @@ int fail_batch(int code, const std::string& msg) {
 __global__ void add_capped_kernel(const unsigned long long* counters, mcrt::DevHealth* h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) h->capped += counters[mcrt::C_CAPPED];
 }
-}  // namespace
 
-extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
-                              const uint64_t* seeds, int n_iter, int use_graph,
-                              mcrt_pda_stats* stats, hipStream_t s) {
+int check_batch(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets, const uint64_t* seeds,
+                int n_iter) {
   if (!ctxs || n_disks < 1 || !n_packets || !seeds || n_iter < 1)
     return fail_batch(MCRT_E_ARG, "bad batch arguments");
   for (int d = 0; d < n_disks; ++d) {
@@ -40,6 +38,28 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
       return fail_batch(MCRT_E_ARG, "batched runs scatter isotropically (g_asym = 0)");
     if (ctxs[d]->device != ctxs[0]->device) return fail_batch(MCRT_E_ARG, "contexts on one device");
   }
+  return MCRT_OK;
+}
+
+// Clear the outcome counters of a batch; the batch overwrites the PDA
+// scratch (and, with the hydrostatic step, the density) that a linear PDA
+// solve left for its adjoint.
+int begin_batch(mcrt_ctx** ctxs, int n_disks, hipStream_t s) {
+  for (int d = 0; d < n_disks; ++d) {
+    ctxs[d]->lin_ready = false;
+    if (mcrt::launch_zero(ctxs[d]->d_health, sizeof(mcrt::DevHealth), s) != MCRT_OK)
+      return fail_batch(MCRT_E_HIP, "clearing the batch counters failed");
+  }
+  return MCRT_OK;
+}
+
+// Passes it0 .. it0 + n_iter - 1 of a batch (pass k traces with seed
+// seeds[d] + (k << 32)), queued on s -- captured in one HIP graph when
+// use_graph -- and waited for.  conv_n_min > 0: each pass also keeps the
+// split tally and ends its Monte Carlo part with the convergence statistic
+// (the first pass of the batch, k = 0, only stores its values).
+int run_passes(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets, const uint64_t* seeds,
+               int it0, int n_iter, bool use_graph, int conv_n_min, hipStream_t s) {
   mcrt_ctx* c0 = ctxs[0];
   // launch shape: LDS for the largest disk, workgroups shared by packets
   size_t lds = 0;
@@ -73,17 +93,19 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
   // arguments for every pass, uploaded before any work is queued
   const size_t targs = sizeof(mcrt::TraceArgs);
   std::vector<mcrt::TraceArgs> ta((size_t)n_iter * n_disks);
-  for (int it = 0; it < n_iter; ++it)
+  for (int q = 0; q < n_iter; ++q)
     for (int d = 0; d < n_disks; ++d) {
+      const int it = it0 + q;
       mcrt_ctx* c = ctxs[d];
       mcrt::TraceArgs a = mcrt::make_trace_args(c, n_packets[d], n_packets[d],
                                                 seeds[d] + ((uint64_t)it << 32), 0, nullptr,
                                                 nullptr, 0);
+      if (conv_n_min > 0) a.t.E_half = c->d_E_half;
       // passes after the first may take the MRW coefficients from the
       // previous pass's (PDA-corrected) temperature
       a.T_coef = (c->opt.mrw_coef_T == 1 && (it > 0 || c->have_T_prev)) ? c->d_T_prev : nullptr;
       a.vis_lds = mcrt::trace_fp32_lds(c->m, cdf_lds) + (size_t)4 * c->n_cells <= lds;
-      ta[(size_t)it * n_disks + d] = a;
+      ta[(size_t)q * n_disks + d] = a;
     }
   const size_t pda_bytes = mcrt::pda_wg_args_size() * n_disks;
   std::vector<char> pda_host(pda_bytes);
@@ -121,25 +143,22 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
     return fail_batch(MCRT_E_HIP, "batch argument upload");
   }
   mcrt::prepare_trace_fp32_batch(lds, cdf_lds);
-  // outcome counters of this batch; the batch overwrites the PDA scratch (and,
-  // with the hydrostatic step, the density) that a linear PDA solve left for
-  // its adjoint
-  for (int d = 0; d < n_disks; ++d) {
-    ctxs[d]->lin_ready = false;
-    if (mcrt::launch_zero(ctxs[d]->d_health, sizeof(mcrt::DevHealth), s) != MCRT_OK) {
-      (void)hipFree(blob);
-      return fail_batch(MCRT_E_HIP, "clearing the batch counters failed");
-    }
-  }
   // the passes
   auto enqueue = [&](hipStream_t s) -> int {
-    for (int it = 0; it < n_iter; ++it) {
+    for (int qi = 0; qi < n_iter; ++qi) {
+      const int it = it0 + qi;
       for (int d = 0; d < n_disks; ++d) {
         mcrt_ctx* c = ctxs[d];
-        size_t tally = (size_t)((char*)c->d_next - (char*)c->t.E_abs) + 8;  // tallies + counter
+        // tallies, split tally and work counter
+        size_t tally = (size_t)((char*)c->d_next - (char*)c->t.E_abs) + 8;
         int r = mcrt::launch_zero(c->t.E_abs, tally, s);
         if (r) return r;
-        const mcrt::TraceArgs& a = ta[(size_t)it * n_disks + d];
+        if (c->t.path) {
+          r = mcrt::launch_zero(c->d_paths, (size_t)((char*)(c->t.mrw_path + c->n_cells) -
+                                                     (char*)c->d_paths), s);
+          if (r) return r;
+        }
+        const mcrt::TraceArgs& a = ta[(size_t)qi * n_disks + d];
         if (a.tail_count) {
           r = mcrt::launch_zero(a.tail_count, 8, s);  // and tail_next
           if (r) return r;
@@ -151,8 +170,8 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
       }
       int r = mcrt::launch_zero(d_live, 16, s);  // the live count and its wavefronts
       if (r) return r;
-      r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)it * n_disks, d_bd, n_disks,
-                                            (int)block_disk.size(), lds, cdf_lds, s);
+      r = mcrt::launch_trace_fp32_batch(d_ta + (size_t)qi * n_disks, d_bd, n_disks,
+                                        (int)block_disk.size(), lds, cdf_lds, s);
       if (r) return r;
       for (int d = 0; d < n_disks; ++d) {
         hipLaunchKernelGGL(add_capped_kernel, dim3(1), dim3(64), 0, s, ctxs[d]->t.counters,
@@ -162,6 +181,10 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
       for (int d = 0; d < n_disks; ++d) {
         r = mcrt::launch_update_T(ctxs[d], s);
         if (r) return r;
+        if (conv_n_min > 0) {
+          r = mcrt::launch_convergence(ctxs[d], conv_n_min, it == 0 ? 1 : 0, s);
+          if (r) return r;
+        }
       }
       r = mcrt::pda_batch_launch(d_pda, n_disks, s);
       if (r) return r;
@@ -207,43 +230,105 @@ extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_pa
     status = enqueue(s);
     if (hipStreamSynchronize(s) != hipSuccess && status == MCRT_OK) status = MCRT_E_HIP;
   }
-  if (status == MCRT_OK && stats) {
-    for (int d = 0; d < n_disks; ++d)
-      if (hipMemcpy(&stats[d], mcrt::pda_stats_slot(ctxs[d]), sizeof(mcrt_pda_stats),
-                    hipMemcpyDeviceToHost) != hipSuccess)
-        status = MCRT_E_HIP;
-  }
   if (status == MCRT_OK)
     for (int d = 0; d < n_disks; ++d)
       if (ctxs[d]->opt.mrw_coef_T == 1) ctxs[d]->have_T_prev = true;
-  // the outcome of every pass: a PDA solve that hit its iteration cap, or
-  // packets that hit the event cap, in any pass of any disk
-  if (status == MCRT_OK) {
-    unsigned long long fails = 0, capped = 0;
-    int first_fail = -1, first_capped = -1;
-    for (int d = 0; d < n_disks && status == MCRT_OK; ++d) {
-      mcrt::DevHealth h{};
-      if (hipMemcpy(&h, ctxs[d]->d_health, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
-        status = MCRT_E_HIP;
-        break;
-      }
-      if (h.pda_fails && first_fail < 0) first_fail = d;
-      if (h.capped && first_capped < 0) first_capped = d;
-      fails += h.pda_fails;
-      capped += h.capped;
-    }
-    if (status == MCRT_OK && fails) {
-      status = fail_batch(MCRT_E_NOT_CONVERGED,
-                          std::to_string(fails) + " PDA solve(s) hit an iteration cap (first: disk " +
-                              std::to_string(first_fail) + ")");
-    } else if (status == MCRT_OK && capped) {
-      status = fail_batch(MCRT_E_STUCK, std::to_string(capped) +
-                                            " packet(s) hit the event cap (first: disk " +
-                                            std::to_string(first_capped) + ")");
-    }
-  }
   (void)hipFree(blob);
   return status;
+}
+
+// The PDA statistics of the last pass, then the outcome of every pass: a PDA
+// solve that hit its iteration cap, or packets that hit the event cap, in
+// any pass of any disk.
+int end_batch(mcrt_ctx** ctxs, int n_disks, mcrt_pda_stats* stats) {
+  if (stats) {
+    for (int d = 0; d < n_disks; ++d)
+      if (hipMemcpy(&stats[d], mcrt::pda_stats_slot(ctxs[d]), sizeof(mcrt_pda_stats),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return fail_batch(MCRT_E_HIP, "reading the PDA statistics failed");
+  }
+  unsigned long long fails = 0, capped = 0;
+  int first_fail = -1, first_capped = -1;
+  for (int d = 0; d < n_disks; ++d) {
+    mcrt::DevHealth h{};
+    if (hipMemcpy(&h, ctxs[d]->d_health, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail_batch(MCRT_E_HIP, "reading the batch counters failed");
+    if (h.pda_fails && first_fail < 0) first_fail = d;
+    if (h.capped && first_capped < 0) first_capped = d;
+    fails += h.pda_fails;
+    capped += h.capped;
+  }
+  if (fails)
+    return fail_batch(MCRT_E_NOT_CONVERGED,
+                      std::to_string(fails) + " PDA solve(s) hit an iteration cap (first: disk " +
+                          std::to_string(first_fail) + ")");
+  if (capped)
+    return fail_batch(MCRT_E_STUCK, std::to_string(capped) +
+                                        " packet(s) hit the event cap (first: disk " +
+                                        std::to_string(first_capped) + ")");
+  return MCRT_OK;
+}
+}  // namespace
+
+extern "C" int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
+                              const uint64_t* seeds, int n_iter, int use_graph,
+                              mcrt_pda_stats* stats, hipStream_t s) {
+  int rc = check_batch(ctxs, n_disks, n_packets, seeds, n_iter);
+  if (rc) return rc;
+  rc = begin_batch(ctxs, n_disks, s);
+  if (rc) return rc;
+  rc = run_passes(ctxs, n_disks, n_packets, seeds, 0, n_iter, use_graph != 0, 0, s);
+  if (rc) return rc;
+  return end_batch(ctxs, n_disks, stats);
+}
+
+extern "C" int mcrt_batch_converge(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
+                                   const uint64_t* seeds, int max_iter, int32_t n_min,
+                                   double threshold, int use_graph, mcrt_pda_stats* stats,
+                                   mcrt_conv_stats* conv, double* R_hist, hipStream_t s) {
+  int rc = check_batch(ctxs, n_disks, n_packets, seeds, max_iter);
+  if (rc) return rc;
+  if (max_iter < 2 || n_min < 1 || !(threshold > 0.0))
+    return fail_batch(MCRT_E_ARG, "max_iter >= 2, n_min >= 1 and threshold > 0 needed");
+  rc = begin_batch(ctxs, n_disks, s);
+  if (rc) return rc;
+  std::vector<mcrt_conv_stats> cs(n_disks);
+  for (auto& c : cs) c = mcrt_conv_stats{0, -1, 0.0, 0.0, 0.0, 0};
+  if (R_hist)
+    for (size_t k = 0; k < (size_t)n_disks * max_iter; ++k) R_hist[k] = -1.0;
+  std::vector<double> res(4);
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    rc = run_passes(ctxs, n_disks, n_packets, seeds, it, 1, use_graph != 0, n_min, s);
+    if (rc) return rc;
+    bool all = true;
+    for (int d = 0; d < n_disks; ++d) {
+      if (hipMemcpy(res.data(), mcrt::conv_result(ctxs[d]), 4 * sizeof(double),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return fail_batch(MCRT_E_HIP, "reading the convergence statistic failed");
+      mcrt_conv_stats& c = cs[d];
+      c.passes = it + 1;
+      c.R_last = res[0];
+      c.dT_rms = res[1];
+      c.noise_rms = res[2];
+      c.cells = (int32_t)res[3];
+      if (R_hist) R_hist[(size_t)d * max_iter + it] = res[0];
+      if (it > 0 && c.converged_pass < 0 && c.cells > 0 && res[0] < threshold)
+        c.converged_pass = it;
+      all = all && c.converged_pass >= 0;
+    }
+    if (all) break;
+  }
+  if (conv)
+    for (int d = 0; d < n_disks; ++d) conv[d] = cs[d];
+  rc = end_batch(ctxs, n_disks, stats);
+  if (rc) return rc;
+  for (int d = 0; d < n_disks; ++d)
+    if (cs[d].converged_pass < 0)
+      return fail_batch(MCRT_E_NOT_CONVERGED,
+                        "disk " + std::to_string(d) + " did not converge in " +
+                            std::to_string(max_iter) + " passes");
+  return MCRT_OK;
 }
 
 // The PDA step of a batched pass alone: every context's region (its rule on

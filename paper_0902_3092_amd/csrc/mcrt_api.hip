@@ -167,6 +167,7 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
   TraceArgs a{};
   a.m = ctx->m;
   a.t = ctx->t;
+  if (!ctx->opt.conv_split) a.t.E_half = nullptr;
   a.eps = ctx->L_star / (double)n_total;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
@@ -237,6 +238,8 @@ void mcrt_default_options(mcrt_options* o) {
   o->hydro_M_star = 0.0;
   o->hydro_mu = 2.3;
   o->pda_sigma = 0.0;
+  o->conv_split = 0;
+  o->j_tally = 0;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -265,8 +268,11 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
       opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0 ||
       !(opt->g_asym > -1.0 && opt->g_asym < 1.0) || !(opt->hydro_M_star >= 0.0) ||
-      !(opt->hydro_mu > 0.0) || !(opt->pda_sigma >= 0.0))
+      !(opt->hydro_mu > 0.0) || !(opt->pda_sigma >= 0.0) || opt->blocks_per_cu < 0)
     return fail(nullptr, MCRT_E_ARG, "bad options");
+  if (!(opt->block_size == 0 || opt->block_size == 512 ||
+        (opt->block_size == 256 && opt->precision == MCRT_FP32)))
+    return fail(nullptr, MCRT_E_ARG, "block_size: 0 or 512, or 256 with FP32 tracking");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)
     if (!(rho[c] >= 0.0) || !std::isfinite(rho[c])) return fail(nullptr, MCRT_E_ARG, "rho must be finite and >= 0");
@@ -454,6 +460,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       {inv_dT.data(), nT * sizeof(double), (void**)&M.inv_dT},
       {g_slope.data(), nT * sizeof(double), (void**)&M.g_slope},
       {cell_len.data(), nc * sizeof(double), (void**)&M.cell_len},
+      {dust->lambda_edges, (nl + 1) * sizeof(double), (void**)&M.lam},
+      {pl.a, sizeof(pl.a), (void**)&M.planck_a},
   };
   size_t total = 0;
   for (auto& p : parts) total += al(p.bytes);
@@ -477,7 +485,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   // tallies + state
   size_t nd = nc * sizeof(double), nu = nc * sizeof(uint32_t);
   size_t tb = al(nd) + 3 * al(nu) + al((size_t)nl * opt->n_inc * sizeof(double)) + al(8) +
-              al(mcrt::N_COUNTERS * 8) + al(8) + 2 * al(nd) + al(nc) + al(sizeof(mcrt::DevHealth));
+              al(mcrt::N_COUNTERS * 8) + al(nd) + al(8) + 2 * al(nd) + al(nc) +
+              al(sizeof(mcrt::DevHealth)) + 2 * al(nd) + al(8 * sizeof(double));
   if (hipMalloc(&ctx->d_tally_blob, tb) != hipSuccess) {
     mcrt_destroy(ctx);
     return fail(nullptr, MCRT_E_OOM, "device allocation of the tallies failed");
@@ -490,14 +499,30 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
   ctx->t.sed = (double*)q; q += al((size_t)nl * opt->n_inc * sizeof(double));
   ctx->t.E_star = (double*)q; q += al(8);
   ctx->t.counters = (unsigned long long*)q; q += al(mcrt::N_COUNTERS * 8);
+  ctx->d_E_half = (double*)q; q += al(nd);   // inside the span that clearing covers
+  ctx->t.E_half = ctx->d_E_half;
   ctx->d_next = (unsigned long long*)q; q += al(8);
   ctx->d_T = (double*)q; q += al(nd);
   ctx->d_T_prev = (double*)q; q += al(nd);
   ctx->d_region = (uint8_t*)q; q += al(nc);
-  ctx->d_health = (mcrt::DevHealth*)q;
+  ctx->d_health = (mcrt::DevHealth*)q; q += al(sizeof(mcrt::DevHealth));
+  ctx->d_conv = (double*)q;
   if (hipMalloc(&ctx->d_tail, (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES + 256) != hipSuccess) {
     mcrt_destroy(ctx);
     return fail(nullptr, MCRT_E_OOM, "device allocation of the hand-off buffer failed");
+  }
+  if (opt->j_tally) {
+    const size_t pb = al((size_t)nc * nl * sizeof(double)) + al(nd);
+    if (hipMalloc(&ctx->d_paths, pb) != hipSuccess) {
+      mcrt_destroy(ctx);
+      return fail(nullptr, MCRT_E_OOM, "device allocation of the path tallies failed");
+    }
+    ctx->t.path = (double*)ctx->d_paths;
+    ctx->t.mrw_path = (double*)((char*)ctx->d_paths + al((size_t)nc * nl * sizeof(double)));
+    if (hipMemset(ctx->d_paths, 0, pb) != hipSuccess) {
+      mcrt_destroy(ctx);
+      return fail(nullptr, MCRT_E_HIP, "clearing the path tallies failed");
+    }
   }
   if (hipMemset(ctx->d_tally_blob, 0, tb) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     mcrt_destroy(ctx);
@@ -514,6 +539,8 @@ void mcrt_destroy(mcrt_ctx* ctx) {
   if (ctx->d_pda_blob) hipFree(ctx->d_pda_blob);
   if (ctx->d_lin_args) hipFree(ctx->d_lin_args);
   if (ctx->d_tail) hipFree(ctx->d_tail);
+  if (ctx->d_paths) hipFree(ctx->d_paths);
+  if (ctx->d_src) hipFree(ctx->d_src);
   delete ctx;
 }
 
@@ -521,7 +548,11 @@ int mcrt_reset(mcrt_ctx* ctx, hipStream_t stream) {
   if (!ctx) return fail(nullptr, MCRT_E_ARG, "null context");
   // tallies are contiguous from E_abs up to (excluding) the work counter
   size_t bytes = (size_t)((char*)ctx->d_next - (char*)ctx->t.E_abs);
-  return mcrt::launch_zero(ctx->t.E_abs, bytes, stream);
+  int rc = mcrt::launch_zero(ctx->t.E_abs, bytes, stream);
+  if (!rc && ctx->t.path)
+    rc = mcrt::launch_zero(ctx->d_paths, (size_t)((char*)(ctx->t.mrw_path + ctx->n_cells) -
+                                                  (char*)ctx->d_paths), stream);
+  return rc;
 }
 
 int mcrt_trace(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
@@ -612,6 +643,9 @@ int64_t mcrt_get_size(mcrt_ctx* ctx, int what) {
     case MCRT_GET_TABLES: return (nT + nT * nl + nT + nT + nl + 1) * 8;
     case MCRT_GET_RHO: return nc * 8;
     case MCRT_GET_HYDRO_COLD: return 4;
+    case MCRT_GET_E_HALF: return nc * 8;
+    case MCRT_GET_PATH: return ctx->t.path ? nc * nl * 8 : -1;
+    case MCRT_GET_MRW_PATH: return ctx->t.path ? nc * 8 : -1;
     default: return -1;
   }
 }
@@ -629,6 +663,9 @@ int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream) {
     case MCRT_GET_COUNTERS: src = ctx->t.counters; break;
     case MCRT_GET_RHO: src = ctx->m.rho; break;
     case MCRT_GET_HYDRO_COLD: src = &ctx->d_health->hydro_cold; break;
+    case MCRT_GET_E_HALF: src = ctx->d_E_half; break;
+    case MCRT_GET_PATH: src = ctx->t.path; break;
+    case MCRT_GET_MRW_PATH: src = ctx->t.mrw_path; break;
     case MCRT_GET_E_STAR: src = ctx->t.E_star; break;
     case MCRT_GET_TABLES: {
       int64_t nT = ctx->opt.n_T, nl = ctx->n_lambda;
@@ -649,6 +686,7 @@ int mcrt_get(mcrt_ctx* ctx, int what, void* dst_dev, hipStream_t stream) {
     }
     default: return fail(ctx, MCRT_E_ARG, "unknown quantity");
   }
+  if (!src) return fail(ctx, MCRT_E_ARG, "this context does not keep that quantity");
   HIPCHK(ctx, hipMemcpyAsync(dst_dev, src, (size_t)mcrt_get_size(ctx, what),
                              hipMemcpyDeviceToDevice, stream));
   return MCRT_OK;
@@ -666,6 +704,48 @@ int mcrt_hydrostatic(mcrt_ctx* ctx, double M_star, double mu_mol, double* rho_de
     HIPCHK(ctx, hipMemcpyAsync(rho_dev, ctx->m.rho, ctx->n_cells * sizeof(double),
                                hipMemcpyDeviceToDevice, stream));
   return MCRT_OK;
+}
+
+int mcrt_convergence(mcrt_ctx* ctx, int32_t n_min, int32_t first, double* out_host,
+                     hipStream_t stream) {
+  if (!ctx) return fail(nullptr, MCRT_E_ARG, "null context");
+  if (n_min < 1) return fail(ctx, MCRT_E_ARG, "n_min must be >= 1");
+  int rc = mcrt::launch_convergence(ctx, n_min, first ? 1 : 0, stream);
+  if (rc) return fail(ctx, rc, "convergence statistic launch failed");
+  if (out_host) {
+    HIPCHK(ctx, hipMemcpyAsync(out_host, mcrt::conv_result(ctx), 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
+  }
+  return MCRT_OK;
+}
+
+int mcrt_mean_intensity(mcrt_ctx* ctx, const double* T_dev, double* J_dev, hipStream_t stream) {
+  if (!ctx || !J_dev) return fail(ctx, MCRT_E_ARG, "null argument");
+  if (!ctx->t.path) return fail(ctx, MCRT_E_ARG, "the context keeps no path tallies (j_tally)");
+  int rc = mcrt::launch_mean_intensity(ctx, T_dev ? T_dev : ctx->d_T, J_dev, stream);
+  return rc ? fail(ctx, rc, "mean intensity launch failed") : MCRT_OK;
+}
+
+int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
+                      const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* L_dev,
+                      hipStream_t stream) {
+  if (!ctx || !L_dev || !cos_i_host) return fail(ctx, MCRT_E_ARG, "null argument");
+  if (n_inc < 1 || n_sub < 1 || n_phi < 1) return fail(ctx, MCRT_E_ARG, "n_inc, n_sub, n_phi >= 1");
+  for (int q = 0; q < n_inc; ++q)
+    if (!(cos_i_host[q] >= 0.0 && cos_i_host[q] <= 1.0))
+      return fail(ctx, MCRT_E_ARG, "cos_i must lie in [0, 1]");
+  if (ctx->opt.g_asym != 0.0)
+    return fail(ctx, MCRT_E_ARG, "the ray tracer's source function scatters isotropically");
+  if (!ctx->d_src &&
+      hipMalloc((void**)&ctx->d_src, (size_t)ctx->n_cells * ctx->n_lambda * sizeof(double)) !=
+          hipSuccess) {
+    ctx->d_src = nullptr;
+    return fail(ctx, MCRT_E_OOM, "source-function buffer");
+  }
+  int rc = mcrt::launch_raytrace(ctx, T_dev ? T_dev : ctx->d_T, J_dev, n_inc, cos_i_host, n_sub,
+                                 n_phi, L_dev, stream);
+  return rc ? fail(ctx, rc, "ray tracing launch failed") : MCRT_OK;
 }
 
 int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream) {

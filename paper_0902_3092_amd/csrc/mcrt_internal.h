@@ -50,6 +50,8 @@ struct DevModel {
                            // the midplane row spanning both hemispheres)
   double chi_max;          // largest extinction per mass over the bins: a cell's optical
                            // width at its most opaque wavelength is (rho chi_max) cell_len
+  const double* lam;       // [n_lambda+1] wavelength bin edges, cm
+  const double* planck_a;  // [64] series coefficients of t / (e^t - 1)
   double lnT_lo, inv_dlnT; // T nodes 1..n_T-1 = T_lo exp((n-1) dlnT)
   double lnG0, inv_du;     // guide bins over ln g
   double R_star, L_star;
@@ -66,6 +68,9 @@ struct DevTally {
   double* sed;                 // [n_lambda][n_inc]
   double* E_star;              // [1]
   unsigned long long* counters;// [N_COUNTERS]
+  double* E_half;              // [n_cells] the odd-numbered packets' share (null: not kept)
+  double* path;                // [n_cells][n_lambda] eps * flight length (null: not kept)
+  double* mrw_path;            // [n_cells] eps * c t of the MRW steps (with path)
 };
 
 struct TraceArgs {
@@ -124,6 +129,10 @@ struct mcrt_ctx {
   double* d_T_prev = nullptr;   // temperature of the previous pass (MRW coefficients)
   uint8_t* d_region = nullptr;
   mcrt::DevHealth* d_health = nullptr;
+  double* d_E_half = nullptr;   // split tally (inside the cleared tally span)
+  double* d_conv = nullptr;     // convergence state: T [n_cells], s2 [n_cells], sums [8]
+  void* d_paths = nullptr;      // path tallies (j_tally): path [n_cells][n_lambda], mrw [n_cells]
+  double* d_src = nullptr;      // source function of the ray tracer [n_cells][n_lambda]
   unsigned long long* d_next = nullptr;
   void* d_tail = nullptr;             // hand-off buffer of long packets (TAIL_CAP states + count)
   void* d_blob = nullptr;       // model + tables
@@ -158,6 +167,14 @@ int pda_batch_fill(mcrt_ctx** ctxs, int n, void* host);
 int pda_batch_launch(const void* d_args, int n, hipStream_t s);
 mcrt_pda_stats* pda_stats_slot(mcrt_ctx* ctx);
 int launch_copy(double* dst, const double* src, size_t n, hipStream_t s);
+// convergence statistic of the context's tallies against its stored pass;
+// the result (R, rms change, rms noise, cells) lands in conv_result(ctx)
+int launch_convergence(mcrt_ctx* ctx, int n_min, int first, hipStream_t s);
+const double* conv_result(const mcrt_ctx* ctx);
+// observables: J from the path tallies; the SED by ray tracing
+int launch_mean_intensity(mcrt_ctx* ctx, const double* T, double* J, hipStream_t s);
+int launch_raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
+                    const double* cos_i_host, int n_sub, int n_phi, double* L, hipStream_t s);
 size_t trace_fp32_lds(const DevModel& M, bool with_cdf);
 size_t trace_fp32_lds_cap();
 int trace_fp32_blocks_per_cu(size_t lds, bool cdf_lds);

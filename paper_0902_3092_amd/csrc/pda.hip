@@ -65,6 +65,69 @@ __global__ void update_T_kernel(DevModel M, const double* E, double* T, int nc) 
   T[c] = T_from_g(M.G, M.Tn, M.n_T, E[c] * M.inv4pim[c]);
 }
 
+// Convergence statistic of the vertical-structure loop (Sect. 2.5): per
+// dusty cell entered by >= n_min packets, T from its tally and the relative
+// variance of T from the spread of the odd and even packets' halves,
+//   s2 = (dlnT/dlnE)^2 ((2 E_half - E) / E)^2,
+// the slope a central difference of the inversion over E (1 +- 1e-4); the
+// squared relative change against the stored pass and the two variances are
+// summed over the cells eligible in both.  The stored T and s2 are replaced.
+// sums: [0] sum x^2, [1] sum (s2 + s2_prev), [2] cells (cleared before).
+__global__ void conv_kernel(DevModel M, const double* __restrict__ E,
+                            const double* __restrict__ E_half, const uint32_t* __restrict__ vis,
+                            int n_min, int first, double* T_prev, double* s2_prev, double* sums,
+                            int nc) {
+  __shared__ double red[3][BS];
+  double sx = 0.0, ss = 0.0, n = 0.0;
+  for (int c = blockIdx.x * BS + threadIdx.x; c < nc; c += gridDim.x * BS) {
+    const double im = M.inv4pim[c];
+    const double e = E[c];
+    const double g = e * im;
+    const double T = T_from_g(M.G, M.Tn, M.n_T, g);
+    double s2 = -1.0;
+    if (vis[c] >= (uint32_t)n_min && im > 0.0 && e > 0.0 && T > 0.0) {
+      const double h = 1e-4;
+      const double Tp = T_from_g(M.G, M.Tn, M.n_T, g * (1.0 + h));
+      const double Tm = T_from_g(M.G, M.Tn, M.n_T, g * (1.0 - h));
+      const double slope = log(Tp / Tm) / (2.0 * h);
+      const double rel = (2.0 * E_half[c] - e) / e;
+      s2 = slope * slope * rel * rel;
+      const double sp = s2_prev[c], Tq = T_prev[c];
+      if (!first && sp >= 0.0 && Tq > 0.0) {
+        const double x = (T - Tq) / T;
+        sx += x * x;
+        ss += s2 + sp;
+        n += 1.0;
+      }
+    }
+    T_prev[c] = T;
+    s2_prev[c] = s2;
+  }
+  red[0][threadIdx.x] = sx;
+  red[1][threadIdx.x] = ss;
+  red[2][threadIdx.x] = n;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q)
+      if (red[q][0] != 0.0) unsafeAtomicAdd(&sums[q], red[q][0]);
+}
+
+// out: R = sqrt(sum x^2 / sum noise^2) (0 when nothing was compared), the
+// RMS change, the RMS noise, the cells.
+__global__ void conv_finish_kernel(const double* sums, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double n = sums[2];
+  out[0] = sums[1] > 0.0 ? sqrt(sums[0] / sums[1]) : 0.0;
+  out[1] = n > 0.0 ? sqrt(sums[0] / n) : 0.0;
+  out[2] = n > 0.0 ? sqrt(sums[1] / n) : 0.0;
+  out[3] = n;
+}
+
 // Vertical hydrostatic equilibrium (Sect. 2.5, eq. balance), one thread per
 // radial shell at its mid radius r, through the cell centres (z = r mu,
 // R = r sqrt(1 - mu^2)): ln(rho T) falls by A times the trapezoidal integral
@@ -921,6 +984,25 @@ int launch_hydrostatic(mcrt_ctx* ctx, double A, double T_floor, hipStream_t s) {
   }
   return MCRT_OK;
 }
+
+// The convergence state of a context: T [n_cells], s2 [n_cells], then the
+// sums [4] and the result [4].
+int launch_convergence(mcrt_ctx* ctx, int n_min, int first, hipStream_t s) {
+  const int nc = ctx->n_cells;
+  double* T_prev = ctx->d_conv;
+  double* s2_prev = T_prev + nc;
+  double* sums = s2_prev + nc;
+  int r = launch_zero(sums, 4 * sizeof(double), s);
+  if (r) return r;
+  unsigned nb = (unsigned)((nc + BS - 1) / BS);
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(conv_kernel, dim3(nb), dim3(BS), 0, s, ctx->m, ctx->t.E_abs, ctx->d_E_half,
+                     ctx->t.visits, n_min, first, T_prev, s2_prev, sums, nc);
+  hipLaunchKernelGGL(conv_finish_kernel, dim3(1), dim3(64), 0, s, sums, sums + 4);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
+
+const double* conv_result(const mcrt_ctx* ctx) { return ctx->d_conv + 2 * (size_t)ctx->n_cells + 4; }
 
 int launch_zero(void* p, size_t bytes, hipStream_t s) {
   size_t words = bytes / 4;

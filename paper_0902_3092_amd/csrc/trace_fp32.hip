@@ -452,6 +452,8 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
   auto deposit = [&](int c, double dE) -> double {  // returns the tally before
     double E_old = 0.0;
     if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    // the odd-numbered packets' share, kept apart for the noise estimate
+    if (issuer && A.t.E_half && (rng.pid & 1)) unsafeAtomicAdd(&A.t.E_half[c], dE);
     if (WAVE) E_old = wave_bcast0(E_old);
     return E_old;
   };
@@ -544,6 +546,8 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
     if (!inside && tau_b <= P.tau) {
       P.d_safe = 0.0f;
       P.dm_up = INFINITY;
+      // path-length tally of the mean intensity (when kept)
+      if (issuer && A.t.path) unsafeAtomicAdd(&A.t.path[(size_t)c * nl + P.k], A.eps * (double)sb);
       if (issuer && P.cell_abs) atomicAdd(&A.t.n_abs[c], P.cell_abs);
       if (issuer && P.cell_mrw) atomicAdd(&A.t.n_mrw[c], P.cell_mrw);
       P.cell_abs = P.cell_mrw = 0;
@@ -594,6 +598,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       // a packet with no optical depth left (its flight is 0) and inf
       // otherwise (bounded by the face it cannot reach)
       const float sint = P.tau > 0.0f ? fminf(fdiv(P.tau, alpha), inside ? P.d_safe : sb) : 0.0f;
+      if (issuer && A.t.path) unsafeAtomicAdd(&A.t.path[(size_t)c * nl + P.k], A.eps * (double)sint);
       P.q[0] += sint * P.d[0]; P.q[1] += sint * P.d[1]; P.q[2] += sint * P.d[2];
       P.d_safe -= sint;
       P.dm_up += 1.00001f * sint;
@@ -670,6 +675,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
           const int ns = P.mrw_seg;
           const double kbar = L.tv.kbar[ns] + P.mrw_f * (L.tv.kbar[ns + 1] - L.tv.kbar[ns]);
           double dE = A.eps * P.rho * kbar * ell;
+          if (issuer && A.t.path) unsafeAtomicAdd(&A.t.mrw_path[c], A.eps * ell);
           double E_old = deposit(c, dE);
           float nv[3];
           iso32(rng, nv);
@@ -963,16 +969,16 @@ __device__ __forceinline__ void trace_fp32_body(const TraceArgs& A) {
   }
 }
 
-template <bool CDF_LDS, bool HG>
-__global__ void __launch_bounds__(BS32) trace_fp32_kernel(TraceArgs A) {
+template <bool CDF_LDS, bool HG, int BS>
+__global__ void __launch_bounds__(BS) trace_fp32_kernel(TraceArgs A) {
   trace_fp32_body<CDF_LDS, HG>(A);
 }
 
 // The packets handed over by the trace launch, one wavefront each; this
-// workgroup is number `rank` of those serving the disk.
-template <bool CDF_LDS, bool HG>
+// workgroup (of BS threads) is number `rank` of those serving the disk.
+template <bool CDF_LDS, bool HG, int BS = BS32>
 __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigned rank) {
-  const unsigned wpb = BS32 / 64;
+  const unsigned wpb = BS / 64;
   if (!A.tail) return;  // traced without hand-off
   const unsigned count = min(*A.tail_count, (unsigned)A.tail_cap);
   if (rank * wpb >= count) return;  // the whole workgroup
@@ -1009,9 +1015,9 @@ __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigne
   }
 }
 
-template <bool CDF_LDS, bool HG>
-__global__ void __launch_bounds__(BS32) trace_fp32_tail_kernel(TraceArgs A) {
-  trace_fp32_tail_body<CDF_LDS, HG>(A, blockIdx.x);
+template <bool CDF_LDS, bool HG, int BS>
+__global__ void __launch_bounds__(BS) trace_fp32_tail_kernel(TraceArgs A) {
+  trace_fp32_tail_body<CDF_LDS, HG, BS>(A, blockIdx.x);
 }
 
 // Many disks in one launch: workgroup b works on disk block_disk[b] for the
@@ -1060,10 +1066,10 @@ __global__ void __launch_bounds__(BS32)
   }
 }
 
-template <bool CDF_LDS, bool HG>
+template <bool CDF_LDS, bool HG, int BS>
 int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
-  auto kern = trace_fp32_kernel<CDF_LDS, HG>;
-  auto tail = trace_fp32_tail_kernel<CDF_LDS, HG>;
+  auto kern = trace_fp32_kernel<CDF_LDS, HG, BS>;
+  auto tail = trace_fp32_tail_kernel<CDF_LDS, HG, BS>;
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -1071,24 +1077,24 @@ int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
                               (int)lds);
   }
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, BS32, lds) != hipSuccess || occ < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, BS, lds) != hipSuccess || occ < 1)
     occ = 1;
   int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : occ;
   long long nb = (long long)ctx->n_cu * per_cu;
-  long long need = ((long long)a.n_packets + BS32 - 1) / BS32;
+  long long need = ((long long)a.n_packets + BS - 1) / BS;
   if (nb > need) nb = need < 1 ? 1 : need;
   // the hand-off launch: enough workgroups for every slot, one workgroup
   // per compute unit at a time; packets are handed off once no more are
   // left than it has wavefronts
   long long tb = (long long)ctx->n_cu * per_cu;
-  const long long slots = ((long long)a.tail_cap + BS32 / 64 - 1) / (BS32 / 64);
+  const long long slots = ((long long)a.tail_cap + BS / 64 - 1) / (BS / 64);
   if (tb > slots) tb = slots;
   TraceArgs b = a;
-  b.live_handoff = (unsigned)(tb * (BS32 / 64));
+  b.live_handoff = (unsigned)(tb * (BS / 64));
   // a launch with no more packets than that needs no count
-  b.n_waves = a.n_packets <= b.live_handoff ? 0u : (unsigned)(nb * (BS32 / 64));
-  hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS32), lds, s, b);
-  if (a.tail) hipLaunchKernelGGL(tail, dim3((unsigned)tb), dim3(BS32), lds, s, b);
+  b.n_waves = a.n_packets <= b.live_handoff ? 0u : (unsigned)(nb * (BS / 64));
+  hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS), lds, s, b);
+  if (a.tail) hipLaunchKernelGGL(tail, dim3((unsigned)tb), dim3(BS), lds, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(ctx, std::string("trace launch: ") + hipGetErrorString(e));
@@ -1099,25 +1105,33 @@ int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
 
 }  // namespace
 
-// LDS: the tables (with the emission CDF when it fits), then the visit
-// histogram when that fits too.
-int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
+template <int BS>
+int launch_trace_fp32_bs(mcrt_ctx* ctx, const TraceArgs& a, size_t cap, hipStream_t s) {
   const DevModel& M = ctx->m;
-  const size_t cap = 155 * 1024;
   const size_t vis = (size_t)4 * M.n_r * M.n_mu;
   TraceArgs b = a;
   size_t with = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, true);
   if (with <= cap) {
     b.vis_lds = with + vis <= cap;
     const size_t lds = b.vis_lds ? with + vis : with;
-    return a.g_asym != 0.0 ? launch32<true, true>(ctx, b, lds, s)
-                           : launch32<true, false>(ctx, b, lds, s);
+    return a.g_asym != 0.0 ? launch32<true, true, BS>(ctx, b, lds, s)
+                           : launch32<true, false, BS>(ctx, b, lds, s);
   }
   size_t without = lds32_bytes(M.n_r, M.n_mu, M.n_T, M.n_lambda, false);
   b.vis_lds = without + vis <= cap;
   const size_t lds = b.vis_lds ? without + vis : without;
-  return a.g_asym != 0.0 ? launch32<false, true>(ctx, b, lds, s)
-                         : launch32<false, false>(ctx, b, lds, s);
+  return a.g_asym != 0.0 ? launch32<false, true, BS>(ctx, b, lds, s)
+                         : launch32<false, false, BS>(ctx, b, lds, s);
+}
+
+// LDS: the tables (with the emission CDF when it fits), then the visit
+// histogram when that fits too.  512-thread workgroups (the default) take up
+// to 155 KB, one per compute unit; 256-thread ones up to half of it, so that
+// two share a compute unit (the CDF then usually stays in L2).
+int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
+  const int bs = ctx->opt.block_size;
+  if (bs == 256) return launch_trace_fp32_bs<256>(ctx, a, (size_t)155 * 1024 / 2, s);
+  return launch_trace_fp32_bs<512>(ctx, a, (size_t)155 * 1024, s);
 }
 
 size_t trace_fp32_lds(const DevModel& M, bool with_cdf) {

@@ -312,6 +312,8 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
   auto deposit = [&](int c, double dE) -> double {
     double E_old = 0.0;
     if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    // the odd-numbered packets' share, kept apart for the noise estimate
+    if (issuer && A.t.E_half && (rng.pid & 1)) unsafeAtomicAdd(&A.t.E_half[c], dE);
     if (WAVE) E_old = bcd0(E_old);
     return E_old;
   };
@@ -380,6 +382,8 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
       tau_b = alpha * sb;
     }
     if (!inside && tau_b <= P.tau) {
+      // path-length tally of the mean intensity (when kept)
+      if (issuer && A.t.path) unsafeAtomicAdd(&A.t.path[(size_t)c * M.n_lambda + P.k], A.eps * sb);
       if (issuer && P.cell_abs) atomicAdd(&A.t.n_abs[c], P.cell_abs);
       if (issuer && P.cell_mrw) atomicAdd(&A.t.n_mrw[c], P.cell_mrw);
       P.cell_abs = P.cell_mrw = 0;
@@ -422,6 +426,7 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
     } else {
       // interaction in the cell
       double sint = P.tau / alpha;
+      if (issuer && A.t.path) unsafeAtomicAdd(&A.t.path[(size_t)c * M.n_lambda + P.k], A.eps * sint);
       P.p[0] += sint * P.d[0]; P.p[1] += sint * P.d[1]; P.p[2] += sint * P.d[2];
       P.d_safe -= sint;
       P.dm_up += 1.000001 * sint;
@@ -493,6 +498,7 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
           const int ns = P.mrw_seg;
           const double kbar = L.tv.kbar[ns] + P.mrw_f * (L.tv.kbar[ns + 1] - L.tv.kbar[ns]);
           double dE = A.eps * P.rho * kbar * ell;
+          if (issuer && A.t.path) unsafeAtomicAdd(&A.t.mrw_path[c], A.eps * ell);
           double E_old = deposit(c, dE);
           double nrm[3];
           iso64(rng, nrm);

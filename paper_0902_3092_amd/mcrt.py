@@ -20,13 +20,14 @@ _lib = None
 OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
-    GET_TABLES, GET_RHO, GET_HYDRO_COLD = range(11)
+    GET_TABLES, GET_RHO, GET_HYDRO_COLD, GET_E_HALF, GET_PATH, GET_MRW_PATH = range(14)
 COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch", "handed"]
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
            "mcrt_get_size", "mcrt_set_T", "mcrt_hydrostatic", "mcrt_strerror", "mcrt_last_error",
-           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_batch_pda"]
+           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_batch_pda",
+           "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity", "mcrt_raytrace_sed"]
 
 
 class McrtError(RuntimeError):
@@ -61,7 +62,12 @@ class Options(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("pda_solver", C.c_int32),
                 ("pda_precond", C.c_int32), ("wave_events", C.c_int64),
                 ("g_asym", C.c_double), ("hydro_M_star", C.c_double), ("hydro_mu", C.c_double),
-                ("pda_sigma", C.c_double)]
+                ("pda_sigma", C.c_double), ("conv_split", C.c_int32), ("j_tally", C.c_int32)]
+
+
+class ConvStats(C.Structure):
+    _fields_ = [("passes", C.c_int32), ("converged_pass", C.c_int32), ("R_last", C.c_double),
+                ("dT_rms", C.c_double), ("noise_rms", C.c_double), ("cells", C.c_int32)]
 
 
 class PdaStats(C.Structure):
@@ -111,6 +117,11 @@ def lib():
         L.mcrt_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mcrt_pda_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.mcrt_batch_pda.argtypes = [vp, C.c_int, vp, vp]
+        L.mcrt_convergence.argtypes = [vp, i32, i32, vp, vp]
+        L.mcrt_mean_intensity.argtypes = [vp, vp, vp, vp]
+        L.mcrt_raytrace_sed.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
+        L.mcrt_batch_converge.argtypes = [vp, C.c_int, vp, vp, C.c_int, i32, C.c_double, C.c_int,
+                                          vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -147,7 +158,7 @@ class Context:
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
                  blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None,
                  g_asym: float = 0.0, hydro_M_star: float = 0.0, hydro_mu: float = 2.3,
-                 pda_sigma: float = 0.0):
+                 pda_sigma: float = 0.0, conv_split: int = 0, j_tally: int = 0):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()
@@ -164,6 +175,8 @@ class Context:
         o.g_asym = g_asym
         o.hydro_M_star, o.hydro_mu = hydro_M_star, hydro_mu
         o.pda_sigma = pda_sigma
+        o.conv_split = int(conv_split)
+        o.j_tally = int(j_tally)
         self.options = o
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
@@ -251,13 +264,16 @@ class Context:
     def get(self, what: int, stream=None):
         import torch
         nbytes = lib().mcrt_get_size(self.handle, what)
+        if nbytes < 0:
+            raise McrtError(E_ARG, "mcrt_get_size")
         buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         _check(lib().mcrt_get(self.handle, what, _ptr(buf), _stream(stream)), "mcrt_get")
         dt = {GET_E_ABS: torch.float64, GET_VISITS: torch.int32, GET_N_ABS: torch.int32,
               GET_N_MRW: torch.int32, GET_T: torch.float64, GET_REGION: torch.uint8,
               GET_COUNTERS: torch.int64, GET_E_STAR: torch.float64,
               GET_TABLES: torch.float64, GET_RHO: torch.float64,
-              GET_HYDRO_COLD: torch.int32}[what]
+              GET_HYDRO_COLD: torch.int32, GET_E_HALF: torch.float64, GET_PATH: torch.float64,
+              GET_MRW_PATH: torch.float64}[what]
         return buf.view(dt)
 
     def counters(self) -> dict:
@@ -275,6 +291,33 @@ class Context:
         out["cdf"] = out["cdf"].reshape(nT, nl)
         out["L_star"] = float(out["L_star"][0])
         return out
+
+    def convergence(self, n_min: int = 100, first: bool = False, stream=None):
+        """mcrt_convergence on the current tallies: (R, rms change, rms noise,
+        cells)."""
+        out = (C.c_double * 4)()
+        _check(lib().mcrt_convergence(self.handle, int(n_min), int(first), out, _stream(stream)),
+               "mcrt_convergence")
+        return float(out[0]), float(out[1]), float(out[2]), int(out[3])
+
+    def mean_intensity(self, T=None, stream=None):
+        """mcrt_mean_intensity: J [n_cells, n_lambda] from the path tallies."""
+        import torch
+        J = torch.empty((self.n_cells, self.n_lambda), dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_mean_intensity(self.handle, _ptr(T), _ptr(J), _stream(stream)),
+               "mcrt_mean_intensity")
+        return J
+
+    def raytrace_sed(self, T=None, J=None, cos_i=(0.7071067811865476,), n_sub: int = 4,
+                     n_phi: int = 16, stream=None):
+        """mcrt_raytrace_sed: isotropic-equivalent luminosity per bin
+        [n_inc, n_lambda] at the inclinations cos_i."""
+        import torch
+        ci = (C.c_double * len(cos_i))(*[float(x) for x in cos_i])
+        L = torch.empty((len(cos_i), self.n_lambda), dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_raytrace_sed(self.handle, _ptr(T), _ptr(J), len(cos_i), ci, int(n_sub),
+                                       int(n_phi), _ptr(L), _stream(stream)), "mcrt_raytrace_sed")
+        return L
 
     def set_T(self, T, stream=None):
         _check(lib().mcrt_set_T(self.handle, _ptr(T), _stream(stream)), "mcrt_set_T")
@@ -333,6 +376,34 @@ def batch_run(contexts, n_packets, seeds, n_iter: int = 5, use_graph: bool = Tru
     """mcrt_batch_run over Context objects; returns the per-disk PDA statistics
     of the last pass.  Raises on any code but MCRT_OK."""
     return batch_run_rc(contexts, n_packets, seeds, n_iter, use_graph, stream, allow=())[0]
+
+
+def batch_converge(contexts, n_packets, seeds, max_iter: int = 10, n_min: int = 100,
+                   threshold: float = 3.0, use_graph: bool = True, stream=None,
+                   allow=(E_NOT_CONVERGED,)):
+    """mcrt_batch_converge over Context objects: passes until every disk's
+    convergence statistic is below `threshold`.  Returns (PDA statistics of
+    the last pass, per-disk convergence records with the R of every pass, the
+    return code).  Codes outside `allow` raise."""
+    n = len(contexts)
+    handles = (C.c_void_p * n)(*[c.handle.value for c in contexts])
+    npk = (C.c_uint64 * n)(*[int(x) for x in n_packets])
+    sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    stats = (PdaStats * n)()
+    conv = (ConvStats * n)()
+    hist = (C.c_double * (n * max_iter))()
+    for c in contexts:
+        c._lin_gen += 1
+    rc = lib().mcrt_batch_converge(handles, n, npk, sd, int(max_iter), int(n_min),
+                                   float(threshold), int(use_graph), stats, conv, hist,
+                                   _stream(stream))
+    _check(rc, "mcrt_batch_converge", allow=allow)
+    recs = []
+    for d in range(n):
+        r = {f: getattr(conv[d], f) for f, _ in ConvStats._fields_}
+        r["R"] = [hist[d * max_iter + k] for k in range(r["passes"])]
+        recs.append(r)
+    return [{f: getattr(s_, f) for f, _ in PdaStats._fields_} for s_ in stats], recs, rc
 
 
 def batch_pda(contexts, stream=None, allow=(E_SINGULAR_REGION,)):

@@ -32,18 +32,19 @@ def runs_of(mask):
     return out
 
 
-def agreeing_runs(mcrt, make_ctx, ora, n, seed, T_frozen, torch, **kw):
+def agreeing_runs(mcrt, make_ctx, ora, n, seed, T_frozen, torch, ctx=None, **kw):
     """Trace packets [0, n) frozen at T_frozen on a fresh context from
     make_ctx() and on the oracle, then again only the agreeing ranges on
-    another fresh context and on the oracle.  Returns (ctx, oracle state,
-    fraction of packets that agreed)."""
+    another fresh context (or on `ctx`, its tallies cleared) and on the
+    oracle.  Returns (ctx, oracle state, fraction of packets that agreed)."""
     Tg = torch.from_numpy(np.ascontiguousarray(T_frozen)).cuda()
     probe = make_ctx()
     g = mcrt.Context.records_numpy(probe.trace(n, seed, frozen_T=Tg, n_recs=n))
     o = ora.run(n, seed, frozen_T=T_frozen, n_recs=n, **kw)["recs"]
     same = same_records(g, o)
     del probe
-    ctx = make_ctx()
+    if ctx is None:
+        ctx = make_ctx()
     ctx.reset()
     st = None
     for a, b in runs_of(same):
