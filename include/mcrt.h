@@ -221,6 +221,22 @@ typedef struct {
 int mcrt_pda_solve(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats,
                    hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * mcrt_pda_solve by its one-workgroup solver (pda_solver = 2), with its work
+ * arrays in a fixed device array of the library -- about 4.5 MB on each
+ * device the library runs on, held until the process ends -- where
+ * mcrt_pda_solve allocates them on first use.  Grids of at most
+ * MCRT_NOALLOC_MAX_CELLS cells (else MCRT_E_ARG, nothing launched); the
+ * context's device must be current (else MCRT_E_ARG).  Every call on a device
+ * shares that array, so calls that overlap in time on one device race.  A
+ * linear solve kept for mcrt_pda_adjoint stays intact.  Same region, result,
+ * statistics and return codes as mcrt_pda_solve with pda_solver = 2; waits for
+ * the stream. */
+#define MCRT_NOALLOC_MAX_CELLS 32768
+int mcrt_pda_solve_noalloc(mcrt_ctx* ctx, const uint8_t* mask_dev, mcrt_pda_stats* stats,
+                           hipStream_t stream);
+
 /* Linear PDA for differentiation: eq. T diffusion on the cells with
  * mask_dev[c] = 1 (parts without a Dirichlet neighbour are left out and
  * flagged 2 in MCRT_GET_REGION) with the diffusion coefficient frozen at a

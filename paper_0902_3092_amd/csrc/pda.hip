@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -948,11 +949,12 @@ __device__ void pda_wg_body(const PdaWgArgs& a) {
 }
 
 // One workgroup per disk, arguments in device memory (batched passes and
-// graph capture).
+// graph capture); or one disk with its arguments passed by value.
 __global__ void __launch_bounds__(WG) pda_wg_kernel(const PdaWgArgs* args) {
   pda_wg_body(args[blockIdx.x]);
 }
 
+__global__ void __launch_bounds__(WG) pda_wg_kernel_val(PdaWgArgs a) { pda_wg_body(a); }
 
 }  // namespace
 
@@ -1599,3 +1601,127 @@ int launch_copy(double* dst, const double* src, size_t n, hipStream_t s) {
 }
 
 }  // namespace mcrt
+
+// ------------------------------------------------------------------------
+// The PDA solve without allocation, for callers that cannot allocate device
+// memory.  Its work arrays live in one file-scope device array: the region
+// and contact flags, the thirteen FP64 work vectors of the single-workgroup
+// solver, the cell-centre geometry and the statistics slot, for up to
+// MCRT_NOALLOC_MAX_CELLS cells.  Each device holds its own copy; its address
+// is looked up once per device.  Calls on one device share it, so calls that
+// overlap in time on one device race.
+// ------------------------------------------------------------------------
+namespace {
+constexpr size_t NA_CELLS = MCRT_NOALLOC_MAX_CELLS;
+constexpr size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+// flags 2 x u8, 13 work vectors, geometry (rc [n_r], thc [n_mu], Ar, Amu: each
+// at most NA_CELLS doubles), statistics
+constexpr size_t NA_BYTES = 2 * al256(NA_CELLS) + 13 * al256(NA_CELLS * 8) +
+                            4 * al256(NA_CELLS * 8) + al256(sizeof(mcrt_pda_stats));
+
+__device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+std::mutex na_mutex;
+void* na_ptr[64] = {};
+
+// address of this device's scratch array (looked up once per device, with the
+// device current)
+int na_scratch(int device, void** out) {
+  if (device < 0 || device >= 64) return MCRT_E_ARG;
+  std::lock_guard<std::mutex> lk(na_mutex);
+  if (!na_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MCRT_E_HIP;
+    na_ptr[device] = p;
+  }
+  *out = na_ptr[device];
+  return MCRT_OK;
+}
+
+}  // namespace
+
+extern "C" int mcrt_pda_solve_noalloc(mcrt_ctx* ctx, const uint8_t* mask_dev,
+                                      mcrt_pda_stats* stats, hipStream_t stream) {
+  using namespace mcrt;
+  if (!ctx) {
+    set_error(nullptr, "null context");
+    return MCRT_E_ARG;
+  }
+  if ((size_t)ctx->n_cells > NA_CELLS) {
+    set_error(ctx, "mcrt_pda_solve_noalloc: " + std::to_string(ctx->n_cells) +
+                       " cells exceed its fixed scratch of " + std::to_string(NA_CELLS));
+    return MCRT_E_ARG;
+  }
+  if (!mask_dev && ctx->opt.pda_visits <= 0 && !(ctx->opt.pda_sigma > 0.0)) {
+    set_error(ctx, "no PDA mask, pda_visits <= 0 and pda_sigma = 0");
+    return MCRT_E_ARG;
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+    set_error(ctx, "mcrt_pda_solve_noalloc: the context's device is not the current device");
+    return MCRT_E_ARG;
+  }
+  void* base = nullptr;
+  int rc = na_scratch(ctx->device, &base);
+  if (rc) {
+    set_error(ctx, "mcrt_pda_solve_noalloc: scratch address lookup failed");
+    return rc;
+  }
+  const size_t nc = (size_t)ctx->n_cells;
+  char* q = (char*)base;
+  PdaWgArgs h;
+  h.M = ctx->m;
+  PdaArrays& P = h.P;
+  P.sc = nullptr;  // scalars of the grid-wide solver: unused here
+  P.region = (uint8_t*)q;
+  q += al256(nc);
+  P.touch = (uint8_t*)q;
+  q += al256(nc);
+  double** arr[13] = {&P.Tw, &P.Tbc, &P.diag, &P.aE, &P.aN, &P.b, &P.x, &P.r, &P.p0, &P.p1, &P.q,
+                      &P.z, &P.lm};
+  for (auto a : arr) {
+    *a = (double*)q;
+    q += al256(nc * 8);
+  }
+  double* rc_ = (double*)q;
+  q += al256(nc * 8);
+  double* thc = (double*)q;
+  q += al256(nc * 8);
+  double* Ar = (double*)q;
+  q += al256(nc * 8);
+  double* Amu = (double*)q;
+  q += al256(nc * 8);
+  mcrt_pda_stats* d_stats = (mcrt_pda_stats*)q;
+  h.g.rc = rc_;
+  h.g.thc = thc;
+  h.g.Ar = Ar;
+  h.g.Amu = Amu;
+  h.g.kscale = nullptr;
+  h.rule = region_rule(ctx, mask_dev);
+  h.T_mc = ctx->d_T;
+  h.T_out = ctx->d_T;
+  h.reg_out = ctx->d_region;
+  h.max_sweeps = ctx->opt.pda_max_sweeps;
+  h.tol = ctx->opt.pda_tol;
+  h.cg_max_iter = ctx->opt.cg_max_iter;
+  h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  h.precond = ctx->opt.pda_precond;
+  h.stats = d_stats;
+  h.fails = nullptr;
+  const unsigned nb = (unsigned)std::min<size_t>((nc + 255) / 256, 1024);
+  hipLaunchKernelGGL(pda_geom_kernel, dim3(nb), dim3(256), 0, stream, ctx->m, rc_, thc, Ar, Amu);
+  hipLaunchKernelGGL(pda_wg_kernel_val, dim3(1), dim3(WG), 0, stream, h);
+  if (hipGetLastError() != hipSuccess) {
+    set_error(ctx, "mcrt_pda_solve_noalloc: launch failed");
+    return MCRT_E_HIP;
+  }
+  mcrt_pda_stats out{};
+  if (hipMemcpyAsync(&out, d_stats, sizeof(out), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    set_error(ctx, "mcrt_pda_solve_noalloc: solve failed");
+    return MCRT_E_HIP;
+  }
+  if (stats) *stats = out;
+  if (out.cg_iters_last >= ctx->opt.cg_max_iter || !out.converged) return MCRT_E_NOT_CONVERGED;
+  return out.n_isolated > 0 ? MCRT_E_SINGULAR_REGION : MCRT_OK;
+}

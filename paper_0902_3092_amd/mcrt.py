@@ -26,8 +26,9 @@ COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "la
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
            "mcrt_get_size", "mcrt_set_T", "mcrt_hydrostatic", "mcrt_strerror", "mcrt_last_error",
-           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_batch_pda",
-           "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity", "mcrt_raytrace_sed"]
+           "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_pda_solve_noalloc",
+           "mcrt_batch_pda", "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity",
+           "mcrt_raytrace_sed"]
 
 
 class McrtError(RuntimeError):
@@ -116,6 +117,7 @@ def lib():
         L.mcrt_batch_run.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp, vp]
         L.mcrt_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mcrt_pda_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.mcrt_pda_solve_noalloc.argtypes = [vp, vp, vp, vp]
         L.mcrt_batch_pda.argtypes = [vp, C.c_int, vp, vp]
         L.mcrt_convergence.argtypes = [vp, i32, i32, vp, vp]
         L.mcrt_mean_intensity.argtypes = [vp, vp, vp, vp]
@@ -242,6 +244,16 @@ class Context:
         st = PdaStats()
         rc = lib().mcrt_pda_solve(self.handle, _ptr(mask), C.byref(st), _stream(stream))
         _check(rc, "mcrt_pda_solve", allow=(E_SINGULAR_REGION,))
+        out = {f: getattr(st, f) for f, _ in PdaStats._fields_}
+        out["rc"] = rc
+        return out
+
+    def pda_solve_noalloc(self, mask=None, stream=None) -> dict:
+        """mcrt_pda_solve_noalloc: the one-workgroup PDA solve with the
+        library's fixed scratch (no device allocation)."""
+        st = PdaStats()
+        rc = lib().mcrt_pda_solve_noalloc(self.handle, _ptr(mask), C.byref(st), _stream(stream))
+        _check(rc, "mcrt_pda_solve_noalloc", allow=(E_SINGULAR_REGION,))
         out = {f: getattr(st, f) for f, _ in PdaStats._fields_}
         out["rc"] = rc
         return out
