@@ -129,7 +129,7 @@ def parse():
     p.add_argument("--c3-plain-every", type=int, default=8,
                    help="the plain FP64 comparison of the 64-disk workload runs every n-th disk")
     p.add_argument("--cpu-packets", type=int, default=1000000)
-    p.add_argument("--budget-s", type=float, default=560.0,
+    p.add_argument("--budget-s", type=float, default=540.0,
                    help="wall-clock budget of the whole run: a leg after the timed steps "
                         "whose expected length would pass it is skipped and reported so")
     p.add_argument("--tune-out", default="",
@@ -933,7 +933,8 @@ def main():
         # measure the choices for this step and write them where the package
         # keeps them (the caller copies the file into the package)
         log("autotune: timing candidates at %.3g packets" % N)
-        e = autotune.tune(disk, n_packets=N, seeds=(11,), path=a.tune_out, log=log, **phys)
+        e = autotune.tune(disk, n_packets=N, seeds=(11, 12, 13), path=a.tune_out, log=log,
+                          **phys)
         print(json.dumps({"autotune": e}), flush=True)
         return
     if a.autotune:

@@ -104,9 +104,10 @@ typedef struct {
                             included) (0) */
   int32_t block_size;    /* trace workgroup size: 0 or 512 (one workgroup per compute
                             unit, tables and emission CDF in up to 155 KB of LDS), or
-                            256 with FP32 tracking (LDS capped at half of that, so two
-                            share a compute unit; the CDF then stays in L2); batched
-                            runs use 512 (0) */
+                            with FP32 tracking 768 (the same LDS, 3 wavefronts per SIMD
+                            instead of 2, registers capped at 168 with some spilled) or
+                            256 (LDS capped at half, so two share a compute unit; the
+                            CDF then stays in L2); batched runs use 512 (0) */
   int32_t blocks_per_cu; /* trace workgroups launched per compute unit (0: as many as
                             fit at once); more than fit wait for a free slot (0) */
   int32_t pda_solver;    /* 0 auto, 1 grid-wide CG kernels, 2 one workgroup per disk (0) */

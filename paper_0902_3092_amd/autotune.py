@@ -5,8 +5,9 @@ Knobs (`mcrt_options` fields, so a tuned context is an ordinary one, and
 the packets per trace call, which the caller applies):
   * Trace launch shape: `block_size` and `blocks_per_cu` -- 512-thread
     workgroups, one per compute unit with the emission CDF in LDS (the
-    default), or 256-thread ones, two per compute unit with the CDF in L2, or
-    one.  FP32 tracking only (the FP64 kernels are built for 512).
+    default); 768-thread ones (3 wavefronts per SIMD, fewer registers); or
+    256-thread ones, two per compute unit with the CDF in L2, or one.  FP32
+    tracking only (the FP64 kernels are built for 512).
   * Trace hand-off: `wave_events`, the event count after which a packet still
     going once all packets are handed out moves to the whole-wavefront launch.
   * Packets per `mcrt_trace` call: a pass of n packets as 1, 2 or 4 calls
@@ -128,7 +129,7 @@ def _label(opts: dict) -> str:
 
 def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
          wave_events: Sequence[int] = (512, 2048, 8192),
-         shapes: Sequence[tuple] = ((512, 0), (256, 0), (256, 1)),
+         shapes: Sequence[tuple] = ((512, 0), (768, 0), (256, 0), (256, 1)),
          calls: Sequence[int] = (1, 2, 4), pda_repeats: int = 3,
          path: Optional[str] = None, save: bool = True, log=None, **phys) -> dict:
     """Time the candidates on this disk and return (and cache) the choice:
@@ -144,9 +145,12 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
     key = shape_key(disk, n_packets, **phys)
 
     def passes(opts, n_calls=1):
-        """(seconds over the seeds, every packet traced and none capped)"""
+        """(median seconds of a pass over the seeds, every packet traced and
+        none capped).  A pass lasts as long as its longest walk, which the
+        running temperature makes differ from run to run even on one seed, so
+        the median of several is taken."""
         ctx = M.Context(disk, **phys, **opts)
-        t = 0.0
+        ts = []
         for s in seeds:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -154,10 +158,10 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
             trace_pass(ctx, n_packets, int(s), n_calls)
             ctx.update_T()
             torch.cuda.synchronize()
-            t += time.perf_counter() - t0
+            ts.append(time.perf_counter() - t0)
         c = ctx.counters()
         del ctx
-        return t, c["capped"] == 0 and c["launch"] == n_packets
+        return float(np.median(ts)), c["capped"] == 0 and c["launch"] == n_packets
 
     # launch shape (FP32 only), then the hand-off threshold, then calls per pass
     shape_s, shape_ok = {}, {}

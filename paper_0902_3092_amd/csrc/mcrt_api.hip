@@ -271,8 +271,8 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       !(opt->hydro_mu > 0.0) || !(opt->pda_sigma >= 0.0) || opt->blocks_per_cu < 0)
     return fail(nullptr, MCRT_E_ARG, "bad options");
   if (!(opt->block_size == 0 || opt->block_size == 512 ||
-        (opt->block_size == 256 && opt->precision == MCRT_FP32)))
-    return fail(nullptr, MCRT_E_ARG, "block_size: 0 or 512, or 256 with FP32 tracking");
+        ((opt->block_size == 256 || opt->block_size == 768) && opt->precision == MCRT_FP32)))
+    return fail(nullptr, MCRT_E_ARG, "block_size: 0 or 512, or 256 or 768 with FP32 tracking");
   const int nc = n_r * n_mu;
   for (int c = 0; c < nc; ++c)
     if (!(rho[c] >= 0.0) || !std::isfinite(rho[c])) return fail(nullptr, MCRT_E_ARG, "rho must be finite and >= 0");

@@ -88,8 +88,12 @@ __global__ void mean_intensity_kernel(DevModel M, const double* __restrict__ T,
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const int nl = M.n_lambda;
-  // 1 / (4 pi V) = rho / (4 pi m)
-  const double iv = M.rho[c] > 0.0 ? M.inv4pim[c] * M.rho[c] : 0.0;
+  // 1 / (4 pi V) from the cell's geometry (packets cross empty cells too)
+  const int i = c / M.n_mu, j = c % M.n_mu;
+  const double ra = M.r_edges[i], rb = M.r_edges[i + 1];
+  const double V = 4.0 * KPI / 3.0 * (rb * rb * rb - ra * ra * ra) *
+                   (M.mu_edges[j + 1] - M.mu_edges[j]);
+  const double iv = 1.0 / (4.0 * KPI * V);
   const double pm = mrw_path[c];
   const double Tc = T[c];
   double sum_dB = 0.0;

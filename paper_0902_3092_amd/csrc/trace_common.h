@@ -257,6 +257,46 @@ __device__ __forceinline__ int mu_row(const double* mu2, int n_mu, double r2, do
   return lo;
 }
 
+// Value of lane l (a wave-uniform index) of a per-lane double.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((unsigned long long)x >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Tally add returning the value before it, aggregated over the wavefront:
+// the active lanes whose cell is the first active lane's cell (packets that
+// absorb in one cell at the same step -- the hot cells of the inner rim) make
+// one atomic for their sum, and each takes the interval after its
+// predecessors' in lane order, as if they had added one after another; the
+// other lanes add on their own.  Call with the lanes that deposit active.
+__device__ __forceinline__ double tally_add_grouped(double* tally, int c, double v) {
+  const unsigned long long act = __ballot(true);
+  const int first = __ffsll((long long)act) - 1;
+  const int c0 = __builtin_amdgcn_readlane(c, first);
+  const unsigned long long grp = __ballot(c == c0);
+  if (__popcll(grp) == 1) return unsafeAtomicAdd(&tally[c], v);
+  const int lane = __lane_id();
+  double pre = 0.0, tot = 0.0;
+  for (unsigned long long m = grp; m; m &= m - 1) {
+    const int l = __ffsll((long long)m) - 1;
+    const double x = readlane_f64(v, l);
+    pre += l < lane ? x : 0.0;
+    tot += x;
+  }
+  double old;
+  if (c == c0) {
+    double b = 0.0;
+    if (lane == first) b = unsafeAtomicAdd(&tally[c0], tot);
+    old = readlane_f64(b, first) + pre;
+  } else {
+    old = unsafeAtomicAdd(&tally[c], v);
+  }
+  return old;
+}
+
 // Wavefront sums of per-lane counters, one atomic per counter per wavefront.
 __device__ __forceinline__ void flush_counters(unsigned long long* dst, const uint32_t* v, int n) {
   for (int q = 0; q < n; ++q) {

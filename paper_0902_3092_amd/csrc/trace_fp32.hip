@@ -451,7 +451,11 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
   };
   auto deposit = [&](int c, double dE) -> double {  // returns the tally before
     double E_old = 0.0;
-    if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    if (WAVE) {
+      if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    } else {
+      E_old = tally_add_grouped(A.t.E_abs, c, dE);
+    }
     // the odd-numbered packets' share, kept apart for the noise estimate
     if (issuer && A.t.E_half && (rng.pid & 1)) unsafeAtomicAdd(&A.t.E_half[c], dE);
     if (WAVE) E_old = wave_bcast0(E_old);
@@ -1126,11 +1130,15 @@ int launch_trace_fp32_bs(mcrt_ctx* ctx, const TraceArgs& a, size_t cap, hipStrea
 
 // LDS: the tables (with the emission CDF when it fits), then the visit
 // histogram when that fits too.  512-thread workgroups (the default) take up
-// to 155 KB, one per compute unit; 256-thread ones up to half of it, so that
-// two share a compute unit (the CDF then usually stays in L2).
+// to 155 KB, one per compute unit: 8 wavefronts, the ~215 registers of the
+// kernel allowing 2 per SIMD.  768-thread ones share the same LDS among 12
+// wavefronts, 3 per SIMD, which caps the registers at 168 (the compiler
+// spills ~130 bytes per lane).  256-thread ones take up to half of the LDS,
+// so that two share a compute unit (the CDF then usually stays in L2).
 int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s) {
   const int bs = ctx->opt.block_size;
   if (bs == 256) return launch_trace_fp32_bs<256>(ctx, a, (size_t)155 * 1024 / 2, s);
+  if (bs == 768) return launch_trace_fp32_bs<768>(ctx, a, (size_t)155 * 1024, s);
   return launch_trace_fp32_bs<512>(ctx, a, (size_t)155 * 1024, s);
 }
 

@@ -311,7 +311,11 @@ __device__ __forceinline__ int event64(Pk64& P, RNG& rng, const TraceArgs& A, co
   };
   auto deposit = [&](int c, double dE) -> double {
     double E_old = 0.0;
-    if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    if (WAVE) {
+      if (issuer) E_old = unsafeAtomicAdd(&A.t.E_abs[c], dE);
+    } else {
+      E_old = tally_add_grouped(A.t.E_abs, c, dE);
+    }
     // the odd-numbered packets' share, kept apart for the noise estimate
     if (issuer && A.t.E_half && (rng.pid & 1)) unsafeAtomicAdd(&A.t.E_half[c], dE);
     if (WAVE) E_old = bcd0(E_old);

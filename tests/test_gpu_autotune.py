@@ -33,10 +33,10 @@ def test_autotune_small_disk(mcrt, torch_cuda, tmp_path):
     e = A.tune(d, n_packets=20000, seeds=(3,), wave_events=(512, 2048), pda_repeats=1,
                path=p, **phys)
     assert set(e["trace_s"]) == {"512", "2048"}
-    assert set(e["shape_s"]) == {"512/0", "256/0", "256/1"}
+    assert set(e["shape_s"]) == {"512/0", "768/0", "256/0", "256/1"}
     assert set(e["calls_s"]) == {"1", "2", "4"}
     o = e["options"]
-    assert o["wave_events"] in (512, 2048) and o["block_size"] in (256, 512)
+    assert o["wave_events"] in (512, 2048) and o["block_size"] in (256, 512, 768)
     assert o["calls_per_pass"] in (1, 2, 4) and o["pda_solver"] in (1, 2)
     opts = A.options_for(d, 20000, path=p, **phys)
     assert "calls_per_pass" not in opts and opts["block_size"] == o["block_size"]
@@ -50,7 +50,7 @@ def test_autotune_small_disk(mcrt, torch_cuda, tmp_path):
     assert c["launch"] == 20000 and c["escaped"] + c["star"] == 20000
 
 
-@pytest.mark.parametrize("shape", [(256, 0), (256, 1), (512, 2)])
+@pytest.mark.parametrize("shape", [(256, 0), (256, 1), (512, 2), (768, 0)])
 def test_launch_shapes_trace_the_same_packets(mcrt, torch_cuda, shape):
     """Frozen temperature: every launch shape traces each packet to the same
     events, so the integer tallies agree exactly with the default shape's and

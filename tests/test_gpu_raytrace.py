@@ -58,9 +58,24 @@ def test_mean_intensity_matches_oracle(mcrt, oracle_mod, torch_cuda):
     ctx, st, agree = agreeing_runs(mcrt, make, ora, 20000, 71, Tf, torch, paths=True, **kw)
     assert agree >= 0.999
     assert st["mrw_path"].sum() > 0
+    # the tallies themselves, then the mean intensity they give
+    Pg = ctx.get(mcrt.GET_PATH).cpu().numpy().reshape(st["path"].shape)
+    Mg = ctx.get(mcrt.GET_MRW_PATH).cpu().numpy()
+    for name, g, w in (("path", Pg, st["path"]), ("mrw_path", Mg, st["mrw_path"])):
+        bad = ~np.isclose(g, w, rtol=rtol, atol=1e-12 * w.max())
+        if bad.any():
+            idx = np.argsort(-np.abs(g - w).reshape(-1) / (np.abs(w).reshape(-1) + 1e-300))[:5]
+            print(name, "differs at", [(int(i), float(g.reshape(-1)[i]), float(w.reshape(-1)[i]))
+                                       for i in idx])
+        assert not bad.any(), name
     Jg = ctx.mean_intensity(torch.from_numpy(Tf).cuda()).cpu().numpy()
     Jo = ora.mean_intensity(Tf, st)
-    assert np.allclose(Jg, Jo, rtol=rtol, atol=1e-12 * Jo.max())
+    bad = ~np.isclose(Jg, Jo, rtol=rtol, atol=1e-12 * Jo.max())
+    if bad.any():
+        i = np.argwhere(bad)[:5]
+        print("J differs at (cell, bin, gpu, oracle, mrw path):",
+              [(int(c), int(k), float(Jg[c, k]), float(Jo[c, k]), float(Mg[c])) for c, k in i])
+    assert not bad.any()
     # the MRW cells' share is there on both sides
     m = st["n_mrw"] > 0
     assert m.sum() > 50 and Jo[m].sum() > 0
