@@ -983,6 +983,17 @@ def main():
     ms_step = (t1 - t0) * 1e3 / a.steps
     trace_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     T_meas, vis_meas, reg_meas, nabs_meas = fields(ctx, mcrt)
+
+    def sigma_rule_fields():
+        """The same tallies with the PDA region of both tests of Sect. 3.1:
+        fewer than 100 visits, or photon noise above 5 % (or no absorption) in
+        an opaque cell."""
+        ctx.update_T()
+        st_s = ctx.pda_solve(ctx.region_mask(o.pda_visits, 0.05))
+        f = fields(ctx, mcrt)
+        return f, st_s
+
+    (T_sig, vis_sig, reg_sig, _), pda_sig = sigma_rule_fields()
     c = counters[-1]
     flops = sum(FLOPS_PER_EVENT[k] * c[k] for k in FLOPS_PER_EVENT)
     traffic, traffic_src = (measured_traffic(TRACE32_KERNELS, N) if a.precision == "fp32"
@@ -1054,8 +1065,14 @@ def main():
         err["reference"] = ("FP64, no MRW, same PDA rule, %.3g packets as two independent "
                             "halves of one call each (%.1f s)" % (nref, dt))
         err["run"] = "the last timed step"
+        err["pda_rule"] = "visits < 100 (the step's rule)"
         out["midplane_T_error"] = err
         out["meets_1pct_midplane"] = err["meets_1pct"]
+        err_s = midplane_error_vs_halves(disk, T_sig, vis_sig, reg_sig, R1, R2)
+        err_s["pda_rule"] = ("visits < 100, or noise 1/(4 sqrt N) > 5 % or no absorption in an "
+                             "opaque cell (Sect. 3.1), on the same tallies")
+        err_s["pda_region_cells"] = pda_sig["n_region"]
+        out["midplane_T_error_sigma_rule"] = err_s
 
     if not a.no_ref:
         # FP64 without MRW takes ~17 times the FP32 step with it
@@ -1076,6 +1093,10 @@ def main():
         if "halves" in ref:
             Tm, vm, rm, _ = fields(ctx, mcrt)
             c1["midplane_T_error"] = midplane_error_vs_halves(disk, Tm, vm, rm, *ref["halves"])
+            (Ts, vs, rs, _), st_s = sigma_rule_fields()
+            c1["midplane_T_error_sigma_rule"] = midplane_error_vs_halves(disk, Ts, vs, rs,
+                                                                         *ref["halves"])
+            c1["midplane_T_error_sigma_rule"]["pda_region_cells"] = st_s["n_region"]
         out["c1_1e6_step"] = c1
 
     if a.c1_steps > 0:

@@ -377,6 +377,18 @@ int mcrt_batch_run(mcrt_ctx** ctxs, int n_disks, const uint64_t* n_packets,
 int mcrt_convergence(mcrt_ctx* ctx, int32_t n_min, int32_t first, double* out_host,
                      hipStream_t stream);
 
+/* The PDA region rule of Sect. 3.1 evaluated on the context's current
+ * tallies with the given parameters, whatever the context's own options say:
+ * mask_dev[c] = 1 for dusty cells entered by fewer than visits_min packets
+ * (visits_min <= 0: no visits test), or, with sigma_max > 0, opaque cells
+ * (optical width >= 1, as for pda_sigma) whose temperature noise
+ * 1 / (4 sqrt(N)) exceeds sigma_max or that absorbed nothing; else 0.  Pass
+ * the mask to mcrt_pda_solve to solve a region of another rule on the same
+ * tallies.  mask_dev [n_cells] uint8.  Asynchronous.  Errors: MCRT_E_ARG for
+ * a null argument or sigma_max < 0. */
+int mcrt_region_mask(mcrt_ctx* ctx, int32_t visits_min, double sigma_max, uint8_t* mask_dev,
+                     hipStream_t stream);
+
 /* Mean intensity of the radiation field per cell and bin (Sect. 2.3: the
  * source function the observables integrate), from the path-length tallies
  * of the traces since the last reset (j_tally = 1, else MCRT_E_ARG):

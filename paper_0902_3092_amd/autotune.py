@@ -197,6 +197,8 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
     cands = [dict(pda_solver=1, pda_precond=0)]
     if n_cells <= 65536:
         cands += [dict(pda_solver=2, pda_precond=0), dict(pda_solver=2, pda_precond=1)]
+    if int(mask.sum().item()) == 0:
+        cands = []   # no region at this packet count: nothing to time, library defaults
     pda_s, pda_ok, pda_it = {}, {}, {}
     for cand in cands:
         ctx = M.Context(disk, wave_events=we_best, **shape, **phys, **cand)
@@ -220,12 +222,13 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
         pda_it[lab] = int(st["cg_iters_total"]) if st is not None else -1
         say("autotune: %s: %.4f s, %d CG iterations" % (lab, best, pda_it[lab]))
         del ctx
-    default_pda = _label(dict(pda_solver=2, pda_precond=1)) if n_cells <= 65536 else \
-        _label(cands[0])
-    pda_best = pick(pda_s, pda_ok, default_pda)
     opts = {"wave_events": we_best, "calls_per_pass": calls_best}
     opts.update(shape)
-    opts.update({k: int(v) for k, v in (kv.split("=") for kv in pda_best.split(","))})
+    if cands:
+        default_pda = _label(dict(pda_solver=2, pda_precond=1)) if n_cells <= 65536 else \
+            _label(cands[0])
+        pda_best = pick(pda_s, pda_ok, default_pda)
+        opts.update({k: int(v) for k, v in (kv.split("=") for kv in pda_best.split(","))})
     entry = {"key": key, "options": opts, "shape_s": shape_s, "trace_s": trace_s,
              "calls_s": calls_s, "pda_s": pda_s,
              "pda_iters": pda_it, "n_packets": n_packets, "seeds": list(seeds),

@@ -720,6 +720,14 @@ int mcrt_convergence(mcrt_ctx* ctx, int32_t n_min, int32_t first, double* out_ho
   return MCRT_OK;
 }
 
+int mcrt_region_mask(mcrt_ctx* ctx, int32_t visits_min, double sigma_max, uint8_t* mask_dev,
+                     hipStream_t stream) {
+  if (!ctx || !mask_dev) return fail(ctx, MCRT_E_ARG, "null argument");
+  if (!(sigma_max >= 0.0)) return fail(ctx, MCRT_E_ARG, "sigma_max must be >= 0");
+  int rc = mcrt::launch_region_mask(ctx, visits_min, sigma_max, mask_dev, stream);
+  return rc ? fail(ctx, rc, "region mask launch failed") : MCRT_OK;
+}
+
 int mcrt_mean_intensity(mcrt_ctx* ctx, const double* T_dev, double* J_dev, hipStream_t stream) {
   if (!ctx || !J_dev) return fail(ctx, MCRT_E_ARG, "null argument");
   if (!ctx->t.path) return fail(ctx, MCRT_E_ARG, "the context keeps no path tallies (j_tally)");

@@ -171,6 +171,8 @@ int launch_copy(double* dst, const double* src, size_t n, hipStream_t s);
 // the result (R, rms change, rms noise, cells) lands in conv_result(ctx)
 int launch_convergence(mcrt_ctx* ctx, int n_min, int first, hipStream_t s);
 const double* conv_result(const mcrt_ctx* ctx);
+// the PDA region rule with the given parameters, into a mask
+int launch_region_mask(mcrt_ctx* ctx, int visits_min, double sigma, uint8_t* out, hipStream_t s);
 // observables: J from the path tallies; the SED by ray tracing
 int launch_mean_intensity(mcrt_ctx* ctx, const double* T, double* J, hipStream_t s);
 int launch_raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,

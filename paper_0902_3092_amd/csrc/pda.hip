@@ -265,6 +265,12 @@ __global__ void pda_region_kernel(DevModel M, RegionRule R, PdaArrays P) {
   P.region[c] = in_region(M, R, c) ? 1 : 0;
 }
 
+// The rule alone, into a caller mask (mcrt_region_mask).
+__global__ void region_mask_kernel(DevModel M, RegionRule R, uint8_t* out, int nc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) out[c] = in_region(M, R, c) ? 1 : 0;
+}
+
 // touch = region cell with a neighbour that gives a boundary value
 __global__ void pda_touch_kernel(DevModel M, const double* T_mc, PdaArrays P) {
   int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
@@ -1108,6 +1114,16 @@ static RegionRule region_rule(const mcrt_ctx* ctx, const uint8_t* mask) {
   R.thr = ctx->opt.pda_visits;
   R.sigma = ctx->opt.pda_sigma;
   return R;
+}
+
+int launch_region_mask(mcrt_ctx* ctx, int visits_min, double sigma, uint8_t* out, hipStream_t s) {
+  RegionRule R = region_rule(ctx, nullptr);
+  R.thr = visits_min;
+  R.sigma = sigma;
+  const int nc = ctx->n_cells;
+  hipLaunchKernelGGL(region_mask_kernel, dim3((nc + BS - 1) / BS), dim3(BS), 0, s, ctx->m, R, out,
+                     nc);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
 }
 
 static int pda_solve_wg(mcrt_ctx* ctx, const uint8_t* mask, mcrt_pda_stats* st, hipStream_t s,

@@ -28,7 +28,7 @@ EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "
            "mcrt_get_size", "mcrt_set_T", "mcrt_hydrostatic", "mcrt_strerror", "mcrt_last_error",
            "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_pda_solve_noalloc",
            "mcrt_batch_pda", "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity",
-           "mcrt_raytrace_sed"]
+           "mcrt_raytrace_sed", "mcrt_region_mask"]
 
 
 class McrtError(RuntimeError):
@@ -121,6 +121,7 @@ def lib():
         L.mcrt_batch_pda.argtypes = [vp, C.c_int, vp, vp]
         L.mcrt_convergence.argtypes = [vp, i32, i32, vp, vp]
         L.mcrt_mean_intensity.argtypes = [vp, vp, vp, vp]
+        L.mcrt_region_mask.argtypes = [vp, i32, C.c_double, vp, vp]
         L.mcrt_raytrace_sed.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
         L.mcrt_batch_converge.argtypes = [vp, C.c_int, vp, vp, C.c_int, i32, C.c_double, C.c_int,
                                           vp, vp, vp, vp]
@@ -311,6 +312,15 @@ class Context:
         _check(lib().mcrt_convergence(self.handle, int(n_min), int(first), out, _stream(stream)),
                "mcrt_convergence")
         return float(out[0]), float(out[1]), float(out[2]), int(out[3])
+
+    def region_mask(self, visits_min: int = 100, sigma_max: float = 0.0, stream=None):
+        """mcrt_region_mask: the PDA region rule with these parameters on the
+        current tallies, as a uint8 mask [n_cells]."""
+        import torch
+        m = torch.empty(self.n_cells, dtype=torch.uint8, device="cuda")
+        _check(lib().mcrt_region_mask(self.handle, int(visits_min), float(sigma_max), _ptr(m),
+                                      _stream(stream)), "mcrt_region_mask")
+        return m
 
     def mean_intensity(self, T=None, stream=None):
         """mcrt_mean_intensity: J [n_cells, n_lambda] from the path tallies."""

@@ -65,6 +65,8 @@ def test_region_rule_and_pda_match_oracle(mcrt, oracle_mod, torch_cuda, solver, 
     T_o, reg_out, _, _ = ora.pda(T_mc, reg_o)
     reg_g = ctx.get(mcrt.GET_REGION).cpu().numpy()
     assert np.array_equal(reg_g, reg_out)
+    # the rule alone (mcrt_region_mask) marks the oracle's candidate cells
+    assert np.array_equal(ctx.region_mask(visits, sigma).cpu().numpy(), reg_o)
     chi = (d.mass_frac[:, None] * (d.kappa_abs + d.kappa_sca)).sum(0).max()
     rcm = 0.5 * (d.r_edges[:-1] + d.r_edges[1:])
     th = np.arccos(d.mu_edges)
