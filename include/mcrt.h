@@ -133,7 +133,7 @@ typedef struct {
   double hydro_mu;       /* mean molecular weight of that step (2.3) */
   double pda_sigma;      /* > 0: the PDA region also takes the opaque cells (optical width
                             >= 1 at the most opaque wavelength, rho chi_max times the
-                            cell's smallest width) whose temperature photon noise
+                            cell's largest width) whose temperature photon noise
                             1 / (4 sqrt(N)) exceeds this, N = absorptions + MRW deposits in
                             the cell, so every such cell without an absorption (T = 0)
                             joins (the second test of Sect. 3.1; the paper uses 0.05;

@@ -557,9 +557,12 @@ void ora_cell_volumes(const ora_model* m, double* V) {
 }
 
 /* Optical width of cell c at its most opaque wavelength: rho chi_max l with
- * l the cell's smallest width -- radial r_{i+1} - r_i, or polar r_c times its
+ * l the cell's largest width -- radial r_{i+1} - r_i, or polar r_c times its
  * angular width (the midplane row spans both hemispheres: twice its half
- * width).  Below 1 the cell is transparent at every wavelength. */
+ * width).  Below 1 the cell is transparent at every wavelength along every
+ * direction.  (The thin midplane row is opaque along its radial width while
+ * its height is a sliver, so the largest width, not the smallest, says
+ * whether it is diffusive.) */
 static double cell_optical_width(const ora_model* m, int c) {
   int i = c / m->n_mu, j = c % m->n_mu;
   double chi = 0.0;
@@ -570,7 +573,7 @@ static double cell_optical_width(const ora_model* m, int c) {
   double rc = 0.5 * (m->r_edges[i] + m->r_edges[i + 1]);
   double wr = m->r_edges[i + 1] - m->r_edges[i];
   double wt = rc * (acos(m->mu_edges[j]) - acos(m->mu_edges[j + 1])) * (j == 0 ? 2.0 : 1.0);
-  return m->rho[c] * chi * (wr < wt ? wr : wt);
+  return m->rho[c] * chi * (wr > wt ? wr : wt);
 }
 
 /* Vertical hydrostatic equilibrium (Sect. 2.5, eq. balance): dP/dz =

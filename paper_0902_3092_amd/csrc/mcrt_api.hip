@@ -408,7 +408,7 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       const double rc = 0.5 * (a + b), wr = b - a;
       const double wt = rc * (std::acos(grid->mu_edges[j]) - std::acos(grid->mu_edges[j + 1])) *
                         (j == 0 ? 2.0 : 1.0);
-      cell_len[i * n_mu + j] = wr < wt ? wr : wt;
+      cell_len[i * n_mu + j] = wr > wt ? wr : wt;
     }
   }
   double chi_max = 0.0;

@@ -46,7 +46,7 @@ struct DevModel {
   const int* g_guide;      // [N_GUIDE] largest n with G[n] <= exp(lnG0 + b / inv_du)
   const double* inv_dT;    // [n_T] 1 / (T[n+1] - T[n])  (last entry unused)
   const double* g_slope;   // [n_T] (T[n+1] - T[n]) / (G[n+1] - G[n])
-  const double* cell_len;  // [n_cells] smallest width of the cell (radial, or polar with
+  const double* cell_len;  // [n_cells] largest width of the cell (radial, or polar with
                            // the midplane row spanning both hemispheres)
   double chi_max;          // largest extinction per mass over the bins: a cell's optical
                            // width at its most opaque wavelength is (rho chi_max) cell_len

@@ -73,7 +73,7 @@ def test_region_rule_and_pda_match_oracle(mcrt, oracle_mod, torch_cuda, solver, 
     wt = rcm[:, None] * (th[:-1] - th[1:])[None, :]
     wt[:, 0] *= 2
     width = (d.rho.reshape(d.n_r, d.n_mu) * chi *
-             np.minimum(np.diff(d.r_edges)[:, None], wt)).reshape(-1)
+             np.maximum(np.diff(d.r_edges)[:, None], wt)).reshape(-1)
     cold = (d.rho > 0) & (T_mc <= 0) & (width >= 1.0)
     if sigma > 0:
         # every opaque dust cell without an absorption joins (solved or isolated)
@@ -140,7 +140,7 @@ def test_sigma_rule_leaves_no_cold_cell_for_the_hydrostatic_step(mcrt, torch_cud
     wt = rcm[:, None] * (th[:-1] - th[1:])[None, :]
     wt[:, 0] *= 2
     thick = ((d.rho.reshape(d.n_r, d.n_mu) * chi *
-              np.minimum(np.diff(d.r_edges)[:, None], wt)).reshape(-1) >= 1.0)
+              np.maximum(np.diff(d.r_edges)[:, None], wt)).reshape(-1) >= 1.0)
     dusty = d.rho > 0
     assert ((T0 <= 0) & dusty & thick).sum() > 0    # the run left opaque cold cells
     assert np.all(T[dusty & thick & (reg != 2)] > 0)
