@@ -187,6 +187,11 @@ def parse():
                         "alone, per lane and in whole-wavefront mode, and exit")
     p.add_argument("--source-hash", action="store_true",
                    help="print the hash of the FP32 trace kernel sources and exit")
+    p.add_argument("--handoff-live", type=int, default=-1,
+                   help="override the hand-off live count of the timed step (0: the hand-off "
+                        "launch's wavefronts)")
+    p.add_argument("--runahead", type=int, default=-1,
+                   help="override wave_runahead of the timed step (0 or 1)")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="only copy this many MiB device to device once (a plain copy kernel of "
                         "known size, to scale the HBM byte counters) and exit")
@@ -337,7 +342,8 @@ def tail_probe(mcrt, W, torch):
     """Latency of one long random walk: on the step's disk with a frozen
     power-law temperature field (so a packet's events do not depend on the
     others), find the longest of 3e5 packets, then trace it alone, once per
-    lane (wave_events = 0) and once in whole-wavefront mode."""
+    lane (wave_events = 0) and in whole-wavefront mode, FP32 both one event
+    at a time and with runs of interactions traced lane-parallel."""
     import numpy as np
     d, o = W.config("mrw_pda")
     rc = 0.5 * (d.r_edges[:-1] + d.r_edges[1:]) / W.AU
@@ -351,10 +357,12 @@ def tail_probe(mcrt, W, torch):
         recs = mcrt.Context.records_numpy(ctx.trace(n, 7, n_total=1000000, frozen_T=Tf, n_recs=n))
         ev = recs["n_cross"] + recs["n_scat"] + recs["n_abs"] + recs["n_mrw"]
         pid = int(np.argmax(ev))
-        modes = (("per_lane", 0), ("whole_wave", 32))
+        modes = (("per_lane", 0, 0), ("whole_wave", 32, 0))
+        if prec == "fp32":
+            modes += (("whole_wave_runahead", 32, 1),)
         res = {"pid": pid}
-        for name, we in modes:
-            c1 = mcrt.Context(d, wave_events=we, **kw)
+        for name, we, ra in modes:
+            c1 = mcrt.Context(d, wave_events=we, wave_runahead=ra, **kw)
             c1.trace(1, 7, n_total=1000000, offset=pid, frozen_T=Tf)   # warm-up
             c1.reset()
             torch.cuda.synchronize()
@@ -949,6 +957,11 @@ def main():
         {k: v for k, v in tuned["options"].items() if k not in autotune.NON_OPTIONS}
         if tuned else {})
     n_calls = int(tuned["options"].get("calls_per_pass", 1)) if tuned else 1
+    t_opts = dict(t_opts)
+    if a.handoff_live >= 0:
+        t_opts["handoff_live"] = a.handoff_live
+    if a.runahead >= 0:
+        t_opts["wave_runahead"] = a.runahead
     ctx = mcrt.Context(disk, **phys, **t_opts)
     stream = torch.cuda.current_stream()
 
@@ -1033,7 +1046,7 @@ def main():
     }
     if tuned:
         out["autotune"] = {"source": tuned_src, "choice": tuned["options"],
-                           **{k: tuned[k] for k in ("shape_s", "trace_s", "calls_s", "pda_s",
+                           **{k: tuned[k] for k in ("shape_s", "trace_s", "handoff_s", "calls_s", "pda_s",
                                                     "pda_iters", "n_packets", "when")
                               if k in tuned}}
     else:

@@ -147,6 +147,17 @@ typedef struct {
                             path c t of every MRW step by cell) that mcrt_trace and
                             batched passes fill, for mcrt_mean_intensity (0: none;
                             costs 8 (n_lambda + 1) bytes per cell) */
+  int32_t wave_runahead; /* 1: with FP32 tracking, the whole-wavefront launch traces each
+                            run of interactions inside a cell lane-parallel: the draws,
+                            kinds, reemission bins and positions of up to 64 interactions,
+                            the first face crossing or MRW start among them, and one
+                            compare-and-swap of the cell's tally for the run's deposits;
+                            the same events as one at a time from the same tally.  Not
+                            with g_asym != 0 or j_tally.  0: one event at a time (0) */
+  int32_t handoff_live;  /* a single-disk trace hands packets off once at most this many
+                            are live; the hand-off launch's wavefronts then take them one
+                            after another (0: as many as it has wavefronts; at most 8192,
+                            the hand-off buffer) (0) */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);
@@ -281,9 +292,10 @@ int mcrt_locate(mcrt_ctx* ctx, const double* xyz_dev, int64_t n, int32_t* cell_d
 #define MCRT_GET_N_MRW 3    /* uint32 [n_cells], MRW steps */
 #define MCRT_GET_T 4        /* double [n_cells], K */
 #define MCRT_GET_REGION 5   /* uint8 [n_cells]: 1 PDA-solved, 2 isolated, 0 outside */
-#define MCRT_GET_COUNTERS 6 /* uint64 [9]: escaped, star, capped, crossings,
+#define MCRT_GET_COUNTERS 6 /* uint64 [10]: escaped, star, capped, crossings,
                                scatterings, absorptions, MRW steps, launches, packets
-                               handed off to the whole-wavefront launch */
+                               handed off to the whole-wavefront launch, interactions
+                               of those traced lane-parallel (wave_runahead) */
 #define MCRT_GET_E_STAR 7   /* double [1], erg/s absorbed by the star */
 #define MCRT_GET_RHO 9      /* double [n_cells], the context's current dust density */
 #define MCRT_GET_TABLES 8   /* double: T nodes [n_T], cdf [n_T][n_lambda], D*rho [n_T],

@@ -130,11 +130,14 @@ def _label(opts: dict) -> str:
 def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
          wave_events: Sequence[int] = (512, 2048, 8192),
          shapes: Sequence[tuple] = ((512, 0), (768, 0), (256, 0), (256, 1)),
-         calls: Sequence[int] = (1, 2, 4), pda_repeats: int = 3,
+         calls: Sequence[int] = (1, 2, 4), handoff: Sequence[int] = (0, 4096, 8192),
+         pda_repeats: int = 3,
          path: Optional[str] = None, save: bool = True, log=None, **phys) -> dict:
     """Time the candidates on this disk and return (and cache) the choice:
-    {"key", "options", "shape_s", "trace_s", "calls_s", "pda_s", "pda_iters"}.
-    shapes: (block_size, blocks_per_cu) pairs, tried with FP32 tracking."""
+    {"key", "options", "shape_s", "trace_s", "handoff_s", "calls_s", "pda_s",
+    "pda_iters"}.  shapes: (block_size, blocks_per_cu) pairs, tried with FP32
+    tracking; handoff: live counts at which hand-offs begin (0: the hand-off
+    launch's wavefronts)."""
     import torch
     from . import mcrt as M
 
@@ -178,6 +181,13 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
         trace_s[str(we)], trace_ok[str(we)] = passes(dict(wave_events=int(we), **shape))
         say("autotune: wave_events=%d: %.3f s" % (we, trace_s[str(we)]))
     we_best = int(pick(trace_s, trace_ok, str(2048 if 2048 in wave_events else wave_events[0])))
+    handoff_s, handoff_ok = {}, {}
+    for hl in handoff:
+        handoff_s[str(hl)], handoff_ok[str(hl)] = passes(dict(wave_events=we_best,
+                                                              handoff_live=int(hl), **shape))
+        say("autotune: handoff_live=%d: %.3f s" % (hl, handoff_s[str(hl)]))
+    hl_best = int(pick(handoff_s, handoff_ok, str(handoff[0]))) if handoff else 0
+    shape = dict(shape, handoff_live=hl_best)
     calls_s, calls_ok = {}, {}
     for k in calls:
         calls_s[str(k)], calls_ok[str(k)] = passes(dict(wave_events=we_best, **shape), int(k))
@@ -230,7 +240,7 @@ def tune(disk, *, n_packets: int = 200000, seeds: Sequence[int] = (11, 12),
         pda_best = pick(pda_s, pda_ok, default_pda)
         opts.update({k: int(v) for k, v in (kv.split("=") for kv in pda_best.split(","))})
     entry = {"key": key, "options": opts, "shape_s": shape_s, "trace_s": trace_s,
-             "calls_s": calls_s, "pda_s": pda_s,
+             "handoff_s": handoff_s, "calls_s": calls_s, "pda_s": pda_s,
              "pda_iters": pda_it, "n_packets": n_packets, "seeds": list(seeds),
              "device": torch.cuda.get_device_name(0),
              "when": time.strftime("%Y-%m-%dT%H:%M:%S")}

@@ -184,11 +184,13 @@ TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, u
   a.n_recs = n_recs;
   a.wave_events = ctx->opt.wave_events;
   a.g_asym = ctx->opt.g_asym;
+  a.runahead = ctx->opt.wave_runahead != 0 && ctx->opt.g_asym == 0.0 && a.t.path == nullptr;
   if (ctx->opt.wave_events > 0 && ctx->d_tail) {
     a.tail = ctx->d_tail;
     a.tail_count = (unsigned int*)((char*)ctx->d_tail + (size_t)mcrt::TAIL_CAP * mcrt::TAIL_STATE_BYTES);
     a.tail_next = a.tail_count + 1;
     a.tail_cap = mcrt::TAIL_CAP;
+    a.live_handoff = (unsigned)ctx->opt.handoff_live;  // 0: the launch's wavefronts
     // after the two counters: the live count (8-byte aligned) and the
     // wavefronts counted into it; the launch sets n_waves and live_handoff
     a.live = (long long*)(a.tail_count + 2);
@@ -240,6 +242,8 @@ void mcrt_default_options(mcrt_options* o) {
   o->pda_sigma = 0.0;
   o->conv_split = 0;
   o->j_tally = 0;
+  o->wave_runahead = 0;
+  o->handoff_live = 0;
 }
 
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
@@ -268,7 +272,9 @@ int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
       (opt->precision != MCRT_FP64 && opt->precision != MCRT_FP32) || opt->pda_solver < 0 ||
       opt->pda_solver > 2 || opt->pda_precond < 0 || opt->pda_precond > 1 || opt->wave_events < 0 ||
       !(opt->g_asym > -1.0 && opt->g_asym < 1.0) || !(opt->hydro_M_star >= 0.0) ||
-      !(opt->hydro_mu > 0.0) || !(opt->pda_sigma >= 0.0) || opt->blocks_per_cu < 0)
+      !(opt->hydro_mu > 0.0) || !(opt->pda_sigma >= 0.0) || opt->blocks_per_cu < 0 ||
+      opt->wave_runahead < 0 || opt->wave_runahead > 1 || opt->handoff_live < 0 ||
+      opt->handoff_live > mcrt::TAIL_CAP)
     return fail(nullptr, MCRT_E_ARG, "bad options");
   if (!(opt->block_size == 0 || opt->block_size == 512 ||
         ((opt->block_size == 256 || opt->block_size == 768) && opt->precision == MCRT_FP32)))

@@ -13,7 +13,7 @@ namespace mcrt {
 
 // Counters, in the order of MCRT_GET_COUNTERS.
 enum { C_ESCAPED = 0, C_STAR, C_CAPPED, C_CROSS, C_SCAT, C_ABS, C_MRW, C_LAUNCH, C_HANDED,
-       N_COUNTERS };
+       C_RUN, N_COUNTERS };
 
 // Nodes of the MRW escape-time table: s as a function of v = ln(-ln P0).
 constexpr int MRW_TAB_N = 512;
@@ -100,8 +100,9 @@ struct TraceArgs {
   // all n_waves wavefronts are counted and *live <= live_handoff
   long long* live;
   unsigned int* waves_in;
-  unsigned int n_waves, live_handoff;
+  unsigned int n_waves, live_handoff;  // live_handoff from the options: 0 = the launch's waves
   double g_asym;               // Henyey-Greenstein asymmetry parameter (0: isotropic)
+  int runahead;                // FP32 whole-wavefront mode: runs of interactions lane-parallel
 };
 constexpr int TAIL_STATE_BYTES = 512;
 constexpr int TAIL_CAP = 8192;

@@ -251,6 +251,10 @@ __device__ __forceinline__ void iso32(Rng32& r, float d[3]) {
 }
 __device__ __forceinline__ float tau32(Rng32& r) { return tau_of(r.next()); }
 __device__ __forceinline__ void ensure_draws(Rng32&, int) {}
+// a scattering leaves the interaction's reemission word unused, so that
+// every interaction takes five words (albedo, bin, two of direction, optical
+// depth) and interaction j of a run in a cell starts 5 j words on
+__device__ __forceinline__ void skip_draw(Rng32& r) { (void)r.next(); }
 // the two draws of a scattering: the first raw (the scattering angle), the
 // second as the sine and cosine of its azimuth
 __device__ __forceinline__ void scat_draws(Rng32& r, float& u1, float& sn, float& cs) {
@@ -390,6 +394,15 @@ struct WaveRng {
     }
   }
   __device__ __forceinline__ int take() { return pos++; }
+  // skip n words (a run of interactions traced lane-parallel)
+  __device__ __forceinline__ void advance(int n) {
+    pos += n;
+    if (pos + 8 > 64) {
+      blk0 += (uint32_t)(pos >> 2);
+      pos &= 3;
+      fill();
+    }
+  }
   __device__ __forceinline__ float next() { return at(u, take()); }
   __device__ __forceinline__ float next_tau() { return at(tau, take()); }
   __device__ __forceinline__ void next_iso(float d[3]) {
@@ -414,6 +427,7 @@ struct WaveRng {
 __device__ __forceinline__ void iso32(WaveRng& r, float d[3]) { r.next_iso(d); }
 __device__ __forceinline__ float tau32(WaveRng& r) { return r.next_tau(); }
 __device__ __forceinline__ void ensure_draws(WaveRng& r, int n) { r.ensure(n); }
+__device__ __forceinline__ void skip_draw(WaveRng& r) { (void)r.take(); }
 __device__ __forceinline__ void scat_draws(WaveRng& r, float& u1, float& sn, float& cs) {
   r.next_scat(u1, sn, cs);
 }
@@ -610,6 +624,7 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
       ensure_draws(rng, 6);  // albedo, bin, direction, optical depth
       if (rng.next() < P.omega) {
         ++P.pc_scat;
+        skip_draw(rng);
         if constexpr (HG) {
           float u1, sn, cs;
           scat_draws(rng, u1, sn, cs);
@@ -699,6 +714,274 @@ __device__ __forceinline__ int event32(Pk& P, RNG& rng, const TraceArgs& A, cons
     }
   }
   return fate;
+}
+
+// ------------------------------------------------------------ run-ahead
+// A run of interactions inside one cell, traced lane-parallel by the
+// wavefront that follows a packet (whole-wavefront mode, isotropic
+// scattering).  Interaction j of the run takes the five stream words
+// w0 + 5 j .. w0 + 5 j + 4 (albedo, reemission bin, direction cosine,
+// azimuth, next optical depth), so lane j draws its own without knowing the
+// kinds of the interactions before it.  Then:
+//  * kinds and bins, in order.  From the bin of a flight, the next
+//    absorption is the first later interaction whose albedo draw is not
+//    below the albedo at that bin (one ballot); its bin is the reemission
+//    search for the k-th deposit of the run (Sect. 2.1), between the
+//    temperatures of the tallies E + k eps and E + (k + 1) eps, which the
+//    lanes invert at once;
+//  * positions, flight by flight in the order and with the FP32 operations
+//    of one event at a time, a chunk of flights at a time;
+//  * per lane, what ends a run: the flight reaches a face (tau >= alpha s_b),
+//    or the MRW criterion holds after the interaction (Sect. 2.2.2, eq.
+//    criterion, after n_int_min interactions in the cell); the first such
+//    interaction, and everything after it, is left to event32;
+//  * the deposits before it, committed by one compare-and-swap of the cell's
+//    tally from the E the run started from to E + k eps (added one deposit at
+//    a time, as the atomics would).  If another packet deposited in between,
+//    the run is redone from the tally found.
+// These are the tests event32 makes, without the conservative shortcuts it
+// takes on them (the safe distance d_safe and the bound dm_up), so a packet
+// follows the same events either way.  Per event, the returned atomic, the
+// face distances and most of the draw handling leave the serial chain.
+constexpr int RUN_KMAX = 12;  // deposits of one run
+constexpr int RUN_CHUNK = 8;  // flights per chunk of the position chain
+
+struct RunDraws {
+  float a, xb, tn;   // albedo, bin, optical depth of the next flight
+  float dx, dy, dz;  // direction after the interaction
+};
+
+__device__ __forceinline__ uint32_t pick4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                          int i) {
+  return i == 0 ? x0 : i == 1 ? x1 : i == 2 ? x2 : x3;
+}
+
+// The five words from stream word w (two consecutive Philox blocks), through
+// the same functions of a draw as Rng32 and WaveRng.
+__device__ __forceinline__ RunDraws run_draws(uint64_t pid, uint32_t k0, uint32_t k1, uint64_t w) {
+  const uint32_t b = (uint32_t)(w >> 2);
+  const int o = (int)(w & 3u);
+  uint32_t c0 = (uint32_t)pid, c1 = (uint32_t)(pid >> 32), c2 = b, c3 = 0u;
+  philox4x32_10(c0, c1, c2, c3, k0, k1);
+  uint32_t e0 = (uint32_t)pid, e1 = (uint32_t)(pid >> 32), e2 = b + 1u, e3 = 0u;
+  philox4x32_10(e0, e1, e2, e3, k0, k1);
+  uint32_t wd[5];
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int i = o + t;
+    wd[t] = i < 4 ? pick4(c0, c1, c2, c3, i) : pick4(e0, e1, e2, e3, i - 4);
+  }
+  RunDraws R;
+  R.a = Rng32::unit(wd[0]);
+  R.xb = Rng32::unit(wd[1]);
+  const float u1 = Rng32::unit(wd[2]);
+  float sn, cs;
+  iso_phi(Rng32::unit(wd[3]), sn, cs);
+  const float st = iso_st(u1);
+  R.dx = st * cs;
+  R.dy = st * sn;
+  R.dz = iso_mu(u1);
+  R.tn = tau_of(Rng32::unit(wd[4]));
+  return R;
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Interactions committed (0: the next event is left to event32).  Needs
+// P.i >= 0 and isotropic scattering; all lanes hold the same P.
+__device__ __forceinline__ int run_ahead32(Pk& P, WaveRng& wr, const TraceArgs& A, const Lds32& L,
+                                        const double* fixT, int lane) {
+  const DevModel& M = A.m;
+  const int n_mu = M.n_mu, nl = M.n_lambda;
+  const int c = P.i * n_mu + P.j;
+  const long long room = A.max_events - P.events;
+  if (room <= 0) return 0;
+  const int J = room < 64 ? (int)room : 64;
+  const bool frozen = A.frozen_T != nullptr;
+  const RunDraws R = run_draws(wr.pid, wr.k0, wr.k1, wr.draws() + 5ull * (uint64_t)lane);
+  // flight `lane`: its optical depth and direction (flight 0 is the pending one)
+  float tau_f = __shfl_up(R.tn, 1), fx = __shfl_up(R.dx, 1), fy = __shfl_up(R.dy, 1),
+        fz = __shfl_up(R.dz, 1);
+  if (lane == 0) {
+    tau_f = P.tau;
+    fx = P.d[0];
+    fy = P.d[1];
+    fz = P.d[2];
+  }
+  Reemit<float> Rf{};
+  if (frozen) Rf = reemit_setup<float>(L.tv, L.cdf, -1.0, P.Tfix);
+  // the cell's tally as this packet last saw it, else as it is now
+  double Eg = P.E_seen;
+  bool loaded = false;
+  if (!frozen && !(Eg >= 0.0)) {
+    double e = 0.0;
+    if (lane == 0)
+      e = __hip_atomic_load(&A.t.E_abs[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Eg = wave_bcast0(e);
+    loaded = true;
+  }
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    // lane k: the tally after k deposits of the run and its temperature
+    double Ek = 0.0, Tk = 0.0;
+    int nk = 0;
+    if (!frozen) {
+      double e = Eg;
+      for (int k = 0; k <= RUN_KMAX; ++k) {
+        if (lane == k) Ek = e;
+        e = e + A.eps;
+      }
+      Tk = T_of_g_seg_near(L.tv, Ek * P.im, P.seg_seen, nk);
+    }
+    // kinds and bins
+    int lam = P.k, pos = 0, k = 0, Jc = J, lam_after = 0;
+    unsigned long long absm = 0ull;
+    for (;;) {
+      const float om = L.omega[lam];
+      const unsigned long long m = __ballot(lane >= pos && lane < Jc && !(R.a < om));
+      if (m == 0ull) break;
+      const int j = __ffsll((long long)m) - 1;
+      if (k == RUN_KMAX) {
+        Jc = j;
+        break;
+      }
+      const float xb = readlane_f32(R.xb, j);
+      int b;
+      if (frozen) {
+        b = reemit_search_wave<float>(Rf, nl, xb);
+      } else {
+        const double To = readlane_f64(Tk, k), Tn = readlane_f64(Tk, k + 1);
+        const int no = __builtin_amdgcn_readlane(nk, k), nn = __builtin_amdgcn_readlane(nk, k + 1);
+        b = reemit_search_wave<float>(reemit_setup<float>(L.tv, L.cdf, To, Tn, nn, no), nl, xb);
+      }
+      if (lane == k) lam_after = b;
+      absm |= 1ull << j;
+      ++k;
+      lam = b;
+      pos = j + 1;
+    }
+    // flight `lane`: bin, extinction, length, and the MRW limit after its interaction
+    const int kj = __popcll(absm & ((1ull << lane) - 1ull));
+    const int lam_src = __shfl(lam_after, kj > 0 ? kj - 1 : 0);
+    const int lam_j = kj > 0 ? lam_src : P.k;
+    const float alpha_j = (float)P.rho * L.chi[lam_j];
+    const float sint_j = tau_f > 0.0f ? fdiv(tau_f, alpha_j) : 0.0f;
+    float lim_j = 0.0f;
+    if (A.mrw) {
+      const int kk = kj + (int)((absm >> lane) & 1ull);
+      const double T_kk = __shfl(Tk, kk);
+      const int n_kk = __shfl(nk, kk);
+      double T_here;
+      int n_here;
+      if (fixT) {
+        // the segment as event32 finds it: the one of the tally's inversion
+        // when the fixed T happens to equal the T last seen
+        T_here = P.Tfix;
+        const double Ts = (!frozen && kk > 0) ? T_kk : P.T_seen;
+        const int ns = (!frozen && kk > 0) ? n_kk : P.seg_seen;
+        n_here = T_here == Ts ? ns : t_segment(L.tv, T_here);
+      } else {
+        T_here = T_kk;
+        n_here = n_kk;
+      }
+      const double f = (T_here - L.tv.Tn[n_here]) * L.tv.inv_dT[n_here];
+      const double Drho = L.tv.Drho[n_here] + f * (L.tv.Drho[n_here + 1] - L.tv.Drho[n_here]);
+      lim_j = (float)Drho * P.lim_scale;
+    }
+    // positions in chunks, then the tests of the chunk's flights
+    float q0 = P.q[0], q1 = P.q[1], q2 = P.q[2];
+    float qa[3] = {0.0f, 0.0f, 0.0f}, qb[3] = {0.0f, 0.0f, 0.0f};
+    int n = Jc;
+    for (int j0 = 0; j0 < Jc; j0 += RUN_CHUNK) {
+      const int j1 = j0 + RUN_CHUNK < Jc ? j0 + RUN_CHUNK : Jc;
+      for (int j = j0; j < j1; ++j) {
+        const float s = readlane_f32(sint_j, j);
+        const float ex = readlane_f32(fx, j), ey = readlane_f32(fy, j), ez = readlane_f32(fz, j);
+        if (lane == j) {
+          qa[0] = q0;
+          qa[1] = q1;
+          qa[2] = q2;
+        }
+        q0 += s * ex;
+        q1 += s * ey;
+        q2 += s * ez;
+        if (lane == j) {
+          qb[0] = q0;
+          qb[1] = q1;
+          qb[2] = q2;
+        }
+      }
+      const bool mine = lane >= j0 && lane < j1;
+      const float dd[3] = {fx, fy, fz};
+      int face;
+      const float sb = boundary32(P.an, L, n_mu, P.i, P.j, qa, dd, face);
+      const bool cross = alpha_j * sb <= tau_f;
+      const bool clip = !cross && sint_j > sb;
+      bool mrw = false;
+      if (A.mrw && P.n_int + lane + 1 >= A.n_int_min)
+        mrw = min_boundary32(P.an, L, n_mu, P.i, P.j, qb) > lim_j;
+      const unsigned long long bm = __ballot(mine && (cross || clip || mrw));
+      if (bm) {
+        n = __ffsll((long long)bm) - 1;
+        break;
+      }
+    }
+    if (n == 0) return 0;
+    const unsigned long long cm = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    const int kst = __popcll(absm & cm);
+    if (kst > 0) {
+      if (frozen) {
+        if (lane == 0)
+          for (int t = 0; t < kst; ++t) unsafeAtomicAdd(&A.t.E_abs[c], A.eps);
+      } else {
+        const double En = readlane_f64(Ek, kst);
+        unsigned long long old = 0ull;
+        const unsigned long long want = (unsigned long long)__double_as_longlong(Eg);
+        if (lane == 0)
+          old = atomicCAS((unsigned long long*)&A.t.E_abs[c], want,
+                          (unsigned long long)__double_as_longlong(En));
+        old = (unsigned long long)__double_as_longlong(
+            wave_bcast0(__longlong_as_double((long long)old)));
+        if (old != want) {  // another packet deposited: redo from its tally
+          Eg = __longlong_as_double((long long)old);
+          loaded = true;
+          continue;
+        }
+      }
+      // the odd-numbered packets' share, one deposit at a time
+      if (lane == 0 && A.t.E_half && (wr.pid & 1))
+        for (int t = 0; t < kst; ++t) unsafeAtomicAdd(&A.t.E_half[c], A.eps);
+    }
+    // the state after interaction n - 1
+    const int last = n - 1;
+    P.q[0] = readlane_f32(qb[0], last);
+    P.q[1] = readlane_f32(qb[1], last);
+    P.q[2] = readlane_f32(qb[2], last);
+    P.d[0] = readlane_f32(R.dx, last);
+    P.d[1] = readlane_f32(R.dy, last);
+    P.d[2] = readlane_f32(R.dz, last);
+    P.tau = readlane_f32(R.tn, last);
+    if (kst > 0) P.k = __builtin_amdgcn_readlane(lam_after, kst - 1);
+    P.alpha = (float)P.rho * L.chi[P.k];
+    P.omega = L.omega[P.k];
+    P.n_int += n;
+    P.events += n;
+    P.pc_scat += (uint32_t)(n - kst);
+    P.pc_abs += (uint32_t)kst;
+    P.cell_abs += (uint32_t)kst;
+    if (!frozen && (kst > 0 || loaded)) {
+      P.E_seen = readlane_f64(Ek, kst);
+      P.T_seen = readlane_f64(Tk, kst);
+      P.seg_seen = __builtin_amdgcn_readlane(nk, kst);
+      P.Tc = P.T_seen;
+    }
+    P.d_safe = 0.0f;
+    P.dm_up = INFINITY;
+    wr.advance(5 * n);
+    return n;
+  }
+  return 0;  // the tally kept changing under the run: one event at a time
 }
 
 // End of a packet: remaining per-cell counts, counters, the star's tally and
@@ -1005,6 +1288,12 @@ __device__ __forceinline__ void trace_fp32_tail_body(const TraceArgs& A, unsigne
     const uint64_t pid = ts.pid;
     int f;
     do {
+      if constexpr (!HG) {
+        if (A.runahead && S.i >= 0 && S.alpha > 0.0f) {
+          const int n = run_ahead32(S, wr, A, L, fixT, lane);
+          if (lane == 0) tot[C_RUN] += (uint32_t)n;
+        }
+      }
       f = event32<true, HG>(S, wr, A, L, fixT, lane);
     } while (f == 0);
     finish32<true>(S, wr, f, pid, A, tot, lane);
@@ -1094,7 +1383,9 @@ int launch32(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   const long long slots = ((long long)a.tail_cap + BS / 64 - 1) / (BS / 64);
   if (tb > slots) tb = slots;
   TraceArgs b = a;
-  b.live_handoff = (unsigned)(tb * (BS / 64));
+  // (or the count asked for: more than it has wavefronts queue for them)
+  b.live_handoff = a.live_handoff > 0 ? min((unsigned)a.live_handoff, (unsigned)a.tail_cap)
+                                      : (unsigned)(tb * (BS / 64));
   // a launch with no more packets than that needs no count
   b.n_waves = a.n_packets <= b.live_handoff ? 0u : (unsigned)(nb * (BS / 64));
   hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS), lds, s, b);

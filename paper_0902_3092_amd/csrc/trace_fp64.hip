@@ -878,7 +878,9 @@ int launch_mode(mcrt_ctx* ctx, const TraceArgs& a, size_t lds, hipStream_t s) {
   const long long slots = ((long long)a.tail_cap + BS64 / 64 - 1) / (BS64 / 64);
   if (tb > slots) tb = slots;
   TraceArgs b = a;
-  b.live_handoff = (unsigned)(tb * (BS64 / 64));
+  // (or the count asked for: more than it has wavefronts queue for them)
+  b.live_handoff = a.live_handoff > 0 ? min((unsigned)a.live_handoff, (unsigned)a.tail_cap)
+                                      : (unsigned)(tb * (BS64 / 64));
   // a launch with no more packets than that needs no count
   b.n_waves = a.n_packets <= b.live_handoff ? 0u : (unsigned)(nb * (BS64 / 64));
   hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BS64), lds, s, b);

@@ -21,7 +21,8 @@ OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2
 FP64, FP32 = 0, 1
 GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
     GET_TABLES, GET_RHO, GET_HYDRO_COLD, GET_E_HALF, GET_PATH, GET_MRW_PATH = range(14)
-COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch", "handed"]
+COUNTER_NAMES = ["escaped", "star", "capped", "cross", "scat", "abs", "mrw", "launch", "handed",
+                 "in_runs"]
 
 EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "mcrt_trace",
            "mcrt_update_T", "mcrt_pda_solve", "mcrt_sed", "mcrt_locate", "mcrt_get",
@@ -63,7 +64,8 @@ class Options(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("pda_solver", C.c_int32),
                 ("pda_precond", C.c_int32), ("wave_events", C.c_int64),
                 ("g_asym", C.c_double), ("hydro_M_star", C.c_double), ("hydro_mu", C.c_double),
-                ("pda_sigma", C.c_double), ("conv_split", C.c_int32), ("j_tally", C.c_int32)]
+                ("pda_sigma", C.c_double), ("conv_split", C.c_int32), ("j_tally", C.c_int32),
+                ("wave_runahead", C.c_int32), ("handoff_live", C.c_int32)]
 
 
 class ConvStats(C.Structure):
@@ -161,7 +163,8 @@ class Context:
                  cg_tol: float = 1e-12, mrw_coef_T: int = 0, block_size: int = 0,
                  blocks_per_cu: int = 0, pda_solver: int = 0, pda_precond: int = 1, wave_events: int = 2048, rho=None,
                  g_asym: float = 0.0, hydro_M_star: float = 0.0, hydro_mu: float = 2.3,
-                 pda_sigma: float = 0.0, conv_split: int = 0, j_tally: int = 0):
+                 pda_sigma: float = 0.0, conv_split: int = 0, j_tally: int = 0,
+                 wave_runahead: int = 0, handoff_live: int = 0):
         import torch  # noqa: F401  (the device context)
         L = lib()
         o = default_options()
@@ -180,6 +183,8 @@ class Context:
         o.pda_sigma = pda_sigma
         o.conv_split = int(conv_split)
         o.j_tally = int(j_tally)
+        o.wave_runahead = int(wave_runahead)
+        o.handoff_live = int(handoff_live)
         self.options = o
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self._keep = [f64(disk.r_edges), f64(disk.mu_edges), f64(disk.lambda_edges),
