@@ -342,7 +342,7 @@ def test_mrw_coefficients_from_current_T(mcrt, torch_cuda, precision):
     d = W.small_disk(M_dust_msun=1e-1, n_r=14, n_mu=10, n_lambda=24)
     kw = dict(precision=precision, mrw=True, gamma=2.0, n_int_min=5, mrw_coef_T=1,
               wave_events=0)
-    n = 40
+    n = 150
 
     def sequence(ctx):
         ctx.reset()
