@@ -133,6 +133,9 @@ def lib():
         L.ora_pda.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, dbl, vp, vp, vp]
         L.ora_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ora_pda_grad_direct.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
+        L.ora_pda_nl.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, vp, vp, vp]
+        L.ora_pda_nl_grad_direct.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, vp, vp,
+                                             C.c_int, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -395,3 +398,45 @@ def _pda_grad_direct(self, T_D, T_bc, region, dJdT, cells, kscale=None):
 
 
 Oracle.pda_grad_direct = _pda_grad_direct
+
+
+def _pda_nonlinear(self, T_bc, region, kscale=None, max_sweeps: int = 200, tol: float = 1e-13):
+    """Nonlinear PDA for differentiation: Picard to the fixed point from T_bc
+    (D from the current T), Dirichlet T_bc outside the region.  Returns
+    (T, sweeps, last relative change)."""
+    T_bc = np.ascontiguousarray(T_bc, dtype=np.float64)
+    reg = np.ascontiguousarray(region, dtype=np.uint8)
+    ks = None if kscale is None else np.ascontiguousarray(kscale, dtype=np.float64)
+    T_out = np.empty(self.n_cells)
+    sweeps = C.c_int(0)
+    change = C.c_double(0.0)
+    rc = lib().ora_pda_nl(C.byref(self.model), C.byref(self.tables), _p(T_bc),
+                          _p(ks) if ks is not None else None, _p(reg), max_sweeps, tol,
+                          _p(T_out), C.byref(sweeps), C.byref(change))
+    if rc != 0:
+        raise RuntimeError("oracle PDA: matrix not positive definite")
+    return T_out, sweeps.value, change.value
+
+
+def _pda_nl_grad_direct(self, T_bc, region, dJdT, cells, kscale=None, max_sweeps: int = 200,
+                        tol: float = 1e-13):
+    """dJ/dlog rho and dJ/ds of the nonlinear PDA for the listed cells, by the
+    direct method on its Jacobian.  Returns (T, g_logrho, g_kscale)."""
+    T_bc = np.ascontiguousarray(T_bc, dtype=np.float64)
+    reg = np.ascontiguousarray(region, dtype=np.uint8)
+    g = np.ascontiguousarray(dJdT, dtype=np.float64)
+    cl = np.ascontiguousarray(cells, dtype=np.int32)
+    ks = None if kscale is None else np.ascontiguousarray(kscale, dtype=np.float64)
+    T_out = np.empty(self.n_cells)
+    gr = np.empty(len(cl))
+    gs = np.empty(len(cl))
+    rc = lib().ora_pda_nl_grad_direct(C.byref(self.model), C.byref(self.tables), _p(T_bc),
+                                      _p(ks) if ks is not None else None, _p(reg), max_sweeps,
+                                      tol, _p(g), _p(cl), len(cl), _p(T_out), _p(gr), _p(gs))
+    if rc != 0:
+        raise RuntimeError("oracle nonlinear PDA: solve failed")
+    return T_out, gr, gs
+
+
+Oracle.pda_nonlinear = _pda_nonlinear
+Oracle.pda_nl_grad_direct = _pda_nl_grad_direct

@@ -1471,3 +1471,189 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
   pda_geom_free(&g);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Nonlinear PDA for differentiation (Sect. 2.2.1, eq. T diffusion, with the */
+/* diffusion coefficient D(T) of Sect. 2.2.3): Picard sweeps of the linear   */
+/* solve, D from the current T, until the fixed point; Dirichlet T_bc on the */
+/* other cells.  At the fixed point the residual of every region cell,       */
+/*   r_c(u, p) = sum_f a_f(R_c, R_b) (u_c - u_b),  R = rho s / (D rho)(T),   */
+/* a_f = (A_f / dist_f) 2 / (R_c + R_b), u = T^4, vanishes; so by the        */
+/* implicit function theorem J du/dp = -dr/dp with the Jacobian J = dr/du,   */
+/* which, beside the conductances, holds their dependence on u through       */
+/* R(T(u)): da_f/du_x = -a_f / (R_c + R_b) dR_x/du_x for x = c, b, and       */
+/* dR/du = -R (D rho)'(T) / (D rho)(T) T / (4 u) with (D rho)' the slope of  */
+/* the tabulated segment.  J is not symmetric.                              */
+/* ------------------------------------------------------------------------ */
+int ora_pda_nl(const ora_model* m, const ora_tables* t, const double* T_bc,
+               const double* kscale, const uint8_t* region_in, int max_sweeps, double tol,
+               double* T_out, int* n_sweeps, double* last_change) {
+  int n = m->n_r * m->n_mu;
+  pda_geom g;
+  pda_geom_init(m, &g);
+  uint8_t* reg = (uint8_t*)malloc(n);
+  for (int c = 0; c < n; ++c) reg[c] = (region_in[c] && m->rho[c] > 0.0) ? 1 : 0;
+  pda_components(m, NULL, reg);
+  double* u = (double*)malloc(sizeof(double) * n);
+  for (int c = 0; c < n; ++c) T_out[c] = T_bc[c];
+  int sweeps = 0, rc = 0;
+  double change = 0.0, prev = INFINITY;
+  for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
+    rc = pda_solve_once(m, t, &g, reg, T_out, T_bc, kscale, 0, u);
+    if (rc) break;
+    change = 0.0;
+    for (int c = 0; c < n; ++c) {
+      if (reg[c] != 1) continue;
+      double Tn = pow(fmax(u[c], 0.0), 0.25);
+      double ch = fabs(Tn - T_out[c]) / fmax(Tn, 1e-300);
+      if (ch > change) change = ch;
+      T_out[c] = Tn;
+    }
+    if (change < tol || (change < sqrt(tol) && change >= prev)) break;
+    prev = change;
+  }
+  if (sweeps > max_sweeps) sweeps = max_sweeps;
+  if (n_sweeps) *n_sweeps = sweeps;
+  if (last_change) *last_change = change;
+  free(u);
+  free(reg);
+  pda_geom_free(&g);
+  return rc;
+}
+
+/* banded LU without pivoting of a (2 bw + 1)-diagonal matrix in place,
+ * band[c][q] = A[c][c - bw + q], q = 0 .. 2 bw; then solves for x */
+static int band_lu_factor(int n, int bw, double* band) {
+  const int W = 2 * bw + 1;
+  for (int k = 0; k < n; ++k) {
+    double piv = band[(size_t)k * W + bw];
+    if (!(fabs(piv) > 0.0)) return -1;
+    int rmax = k + bw < n - 1 ? k + bw : n - 1;
+    for (int r = k + 1; r <= rmax; ++r) {
+      double* lr = &band[(size_t)r * W + (k - r + bw)];
+      if (*lr == 0.0) continue;
+      double l = *lr / piv;
+      *lr = l;
+      int cmax = k + bw < n - 1 ? k + bw : n - 1;
+      for (int col = k + 1; col <= cmax; ++col)
+        band[(size_t)r * W + (col - r + bw)] -= l * band[(size_t)k * W + (col - k + bw)];
+    }
+  }
+  return 0;
+}
+
+static void band_lu_solve(int n, int bw, const double* band, double* x) {
+  const int W = 2 * bw + 1;
+  for (int r = 0; r < n; ++r) {
+    int k0 = r - bw < 0 ? 0 : r - bw;
+    double s = x[r];
+    for (int k = k0; k < r; ++k) s -= band[(size_t)r * W + (k - r + bw)] * x[k];
+    x[r] = s;
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    int k1 = r + bw > n - 1 ? n - 1 : r + bw;
+    double s = x[r];
+    for (int k = r + 1; k <= k1; ++k) s -= band[(size_t)r * W + (k - r + bw)] * x[k];
+    x[r] = s / band[(size_t)r * W + bw];
+  }
+}
+
+/* slope of a tabulated quantity on the segment holding T (the derivative
+ * of t_interp's linear interpolation) */
+static double t_slope(const ora_tables* t, const double* tab, double T) {
+  int n;
+  double f;
+  t_segment(t, T, &n, &f);
+  return (tab[n + 1] - tab[n]) / (t->T[n + 1] - t->T[n]);
+}
+
+int ora_pda_nl_grad_direct(const ora_model* m, const ora_tables* t, const double* T_bc,
+                           const double* kscale, const uint8_t* region_in, int max_sweeps,
+                           double tol, const double* dJdT, const int* cells, int n_req,
+                           double* T_out, double* g_logrho, double* g_kscale) {
+  int nr = m->n_r, nmu = m->n_mu, n = nr * nmu, bw = nmu, W = 2 * bw + 1;
+  int rc = ora_pda_nl(m, t, T_bc, kscale, region_in, max_sweeps, tol, T_out, NULL, NULL);
+  if (rc) return rc;
+  pda_geom g;
+  pda_geom_init(m, &g);
+  uint8_t* reg = (uint8_t*)malloc(n);
+  for (int c = 0; c < n; ++c) reg[c] = (region_in[c] && m->rho[c] > 0.0) ? 1 : 0;
+  pda_components(m, NULL, reg);
+  double* R = (double*)malloc(sizeof(double) * n);
+  double* ks = (double*)malloc(sizeof(double) * n);
+  double* u = (double*)malloc(sizeof(double) * n);
+  double* dRdu = (double*)malloc(sizeof(double) * n);
+  for (int c = 0; c < n; ++c) {
+    ks[c] = kscale ? kscale[c] : 1.0;
+    double T = T_out[c];
+    double Drho = t_interp(t, t->Drho, T);
+    R[c] = m->rho[c] > 0.0 ? m->rho[c] * ks[c] / Drho : 0.0;
+    u[c] = pow(T, 4.0);
+    dRdu[c] = 0.0;
+    if (reg[c] == 1 && u[c] > 0.0 && m->rho[c] > 0.0)
+      dRdu[c] = -R[c] * t_slope(t, t->Drho, T) / Drho * T / (4.0 * u[c]);
+  }
+  /* the Jacobian, band storage; the rows of the Dirichlet cells are the
+   * identity (their u does not move) */
+  double* band = (double*)calloc((size_t)n * W, sizeof(double));
+  for (int c = 0; c < n; ++c) {
+    if (reg[c] != 1) {
+      band[(size_t)c * W + bw] = 1.0;
+      continue;
+    }
+    int i = c / nmu, j = c % nmu;
+    int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    for (int q = 0; q < 4; ++q) {
+      int ib = nb[q][0], jb = nb[q][1];
+      if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+      int cb = ib * nmu + jb;
+      if (!(m->rho[cb] > 0.0)) continue;
+      double a = face_cond(&g, i, j, ib, jb, R[c], R[cb]);
+      double dadR = -a / (R[c] + R[cb]);
+      band[(size_t)c * W + bw] += a + dadR * dRdu[c] * (u[c] - u[cb]);
+      if (reg[cb] == 1)
+        band[(size_t)c * W + (cb - c + bw)] += -a + dadR * dRdu[cb] * (u[c] - u[cb]);
+    }
+  }
+  rc = band_lu_factor(n, bw, band);
+  double* w = (double*)malloc(sizeof(double) * n);
+  for (int r = 0; rc == 0 && r < n_req; ++r) {
+    int c = cells[r];
+    g_logrho[r] = 0.0;
+    if (g_kscale) g_kscale[r] = 0.0;
+    if (!(m->rho[c] > 0.0)) continue;
+    for (int k = 0; k < n; ++k) w[k] = 0.0;
+    int i = c / nmu, j = c % nmu;
+    int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    int any = 0;
+    for (int q = 0; q < 4; ++q) {
+      int ib = nb[q][0], jb = nb[q][1];
+      if (ib < 0 || ib >= nr || jb < 0 || jb >= nmu) continue;
+      int cb = ib * nmu + jb;
+      if (!(m->rho[cb] > 0.0)) continue;
+      if (reg[c] != 1 && reg[cb] != 1) continue;
+      /* dr/dlog rho_c through R_c = rho_c s_c / (D rho)(T_c) */
+      double a = face_cond(&g, i, j, ib, jb, R[c], R[cb]);
+      double da = -a / (R[c] + R[cb]) * R[c];
+      if (reg[c] == 1) w[c] -= da * (u[c] - u[cb]);
+      if (reg[cb] == 1) w[cb] -= da * (u[cb] - u[c]);
+      any = 1;
+    }
+    if (!any) continue;
+    band_lu_solve(n, bw, band, w);
+    double s = 0.0;
+    for (int k = 0; k < n; ++k)
+      if (reg[k] == 1 && u[k] > 0.0) s += dJdT[k] * (T_out[k] / (4.0 * u[k])) * w[k];
+    g_logrho[r] = s;
+    if (g_kscale) g_kscale[r] = s / ks[c];
+  }
+  free(w);
+  free(band);
+  free(dRdu);
+  free(u);
+  free(ks);
+  free(R);
+  free(reg);
+  pda_geom_free(&g);
+  return rc;
+}

@@ -150,6 +150,21 @@ int ora_pda_grad_direct(const ora_model* m, const ora_tables* t, const double* T
                         const double* dJdT, const int* cells, int n_req, double* g_logrho,
                         double* g_kscale);
 
+/* Nonlinear PDA for differentiation: Picard sweeps of the linear solve (D
+ * from the current T) to the fixed point, Dirichlet T_bc on the other cells,
+ * starting from T_bc; the stop rule of ora_pda.  T_out [n_cells]. */
+int ora_pda_nl(const ora_model* m, const ora_tables* t, const double* T_bc,
+               const double* kscale, const uint8_t* region, int max_sweeps, double tol,
+               double* T_out, int* n_sweeps, double* last_change);
+
+/* Gradient of J(T) of the nonlinear PDA above w.r.t. log rho and s of the
+ * listed cells, by the direct method on its Jacobian (non-symmetric, with
+ * the conductances' dependence on T): T_out [n_cells], outputs [n_req]. */
+int ora_pda_nl_grad_direct(const ora_model* m, const ora_tables* t, const double* T_bc,
+                           const double* kscale, const uint8_t* region, int max_sweeps,
+                           double tol, const double* dJdT, const int* cells, int n_req,
+                           double* T_out, double* g_logrho, double* g_kscale);
+
 /* Vertical hydrostatic equilibrium of each radial shell for the cell
  * temperatures T [n_cells] (floored at T_floor), star mass M_star (g) and mean
  * molecular weight mu_mol; each shell keeps the mass of m->rho.  rho_out

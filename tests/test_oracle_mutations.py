@@ -12,6 +12,7 @@ sys.path.insert(0, os.path.dirname(__file__))
 import test_oracle_deposit_launch_picard as P  # noqa: E402
 import test_oracle_convergence as CV  # noqa: E402
 import test_oracle_raytrace as RT  # noqa: E402
+import test_oracle_pda_nl as NL  # noqa: E402
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "mcrt_oracle.c")
 
@@ -51,6 +52,14 @@ MUTANTS = {
     # the mean intensity loses its 4 pi
     "mean_intensity_no_4pi": ("    const double iv = V[c] > 0.0 ? 1.0 / (4.0 * PI * V[c]) : 0.0;",
                               "    const double iv = V[c] > 0.0 ? 1.0 / V[c] : 0.0;"),
+    # the nonlinear Jacobian drops the dependence of D on T (the linear operator)
+    "nl_jacobian_without_dDdT": (
+        "      dRdu[c] = -R[c] * t_slope(t, t->Drho, T) / Drho * T / (4.0 * u[c]);",
+        "      dRdu[c] = 0.0;"),
+    # the resistance grows where D rho grows
+    "nl_dRdu_sign": (
+        "      dRdu[c] = -R[c] * t_slope(t, t->Drho, T) / Drho * T / (4.0 * u[c]);",
+        "      dRdu[c] = R[c] * t_slope(t, t->Drho, T) / Drho * T / (4.0 * u[c]);"),
 }
 
 PIN = {
@@ -66,6 +75,10 @@ PIN = {
     "ray_area_halved": lambda o: RT.test_thin_isothermal_shell(o),
     "ray_area_halved_thick": lambda o: RT.test_thick_isothermal_shell(o),
     "mean_intensity_no_4pi": lambda o: RT.test_mean_intensity_follows_the_dilution_law(o),
+    "nl_jacobian_without_dDdT":
+        lambda o: NL.test_nonlinear_gradient_matches_finite_differences(o, "logrho", True),
+    "nl_dRdu_sign":
+        lambda o: NL.test_nonlinear_gradient_matches_finite_differences(o, "logrho", False),
 }
 
 
