@@ -54,6 +54,14 @@ if ROOT not in sys.path:
 FLOPS_PER_EVENT = {"cross": 62, "scat": 25, "abs": 90, "mrw": 270, "launch": 40}
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
 HBM_PEAK = 8.0e12
+# BiCGSTAB on the transposed Jacobian, bytes per unknown and iteration (FP64):
+# two operator products, each reading the diagonal, four couplings and the
+# vector at the cell and its four neighbours and writing the product (11
+# words, 88 B); the updates p, y (read r, p, v, diagonal; write p, y), s, z
+# (read r, v, diagonal; write s, z), lambda, r (read lambda, y, z, s, t;
+# write lambda, r) and the dot products' extra reads of rh (2): 6 + 5 + 7 + 2
+# = 20 words.
+BICGSTAB_BYTES_PER_UNKNOWN = 2 * 88 + 20 * 8
 # PCG bytes per unknown and iteration (FP64).  Jacobi: the operator product
 # reads diag, two couplings and p and writes q (40 B); the update reads x, r,
 # p, q and diag and writes x, r and p (64 B).  Theta-line preconditioner: the
@@ -864,12 +872,30 @@ def pda_grad(mcrt, W, torch):
     bpu = PCG_BYTES_PER_UNKNOWN[ctx.options.pda_precond]
     nbytes = st["cg_iters_total"] * st["n_region"] * bpu
     gbs = nbytes / (t1 - t0)
+    # the nonlinear PDA (D follows T) and the adjoint of its Jacobian
+    ctx.pda_nonlinear(m_t, Tbc_t, kscale=ks_t)                 # warm-up
+    ctx.pda_nonlinear_adjoint(w_t)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    _, nst = ctx.pda_nonlinear(m_t, Tbc_t, kscale=ks_t)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    _, _, ast = ctx.pda_nonlinear_adjoint(w_t, stats=True)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    nl_bytes = ast["cg_iters_total"] * nst["n_region"] * BICGSTAB_BYTES_PER_UNKNOWN
     return {"workload": "200 r x 120 theta, 1e-1 Msun, region tau_R > 10",
             "preconditioner": "theta lines" if ctx.options.pda_precond else "Jacobi",
             "n_region": st["n_region"], "cg_iters": st["cg_iters_total"],
             "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
             "pcg_bytes_per_unknown_iter": bpu,
-            "achieved_GBps": gbs / 1e9, "frac_hbm_peak": gbs / HBM_PEAK}
+            "achieved_GBps": gbs / 1e9, "frac_hbm_peak": gbs / HBM_PEAK,
+            "nonlinear": {"forward_ms": (t4 - t3) * 1e3, "picard_sweeps": nst["sweeps"],
+                          "cg_iters_total": nst["cg_iters_total"],
+                          "adjoint_ms": (t5 - t4) * 1e3,
+                          "bicgstab_iters": ast["cg_iters_total"],
+                          "bicgstab_bytes_per_unknown_iter": BICGSTAB_BYTES_PER_UNKNOWN,
+                          "adjoint_GBps": nl_bytes / (t5 - t4) / 1e9}}
 
 
 def main():

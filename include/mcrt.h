@@ -271,6 +271,38 @@ int mcrt_pda_linear(mcrt_ctx* ctx, const uint8_t* mask_dev, const double* rho_de
 int mcrt_pda_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev,
                      double* g_kscale_dev, hipStream_t stream);
 
+/* Nonlinear PDA for differentiation: eq. T diffusion (Sect. 2.2.1) with the
+ * diffusion coefficient of the temperature itself, D_c = (D rho)(T_c) /
+ * (rho_c s_c) (Sect. 2.2.3), solved by Picard sweeps of the linear solve of
+ * mcrt_pda_linear -- D from the T of the previous sweep, the first from
+ * T_bc -- until the largest relative change of T falls below pda_tol (or
+ * stalls below its square root).  Arguments as mcrt_pda_linear without T_D;
+ * T_bc [n_cells] gives the Dirichlet values outside the region and the
+ * starting T inside; T_out_dev [n_cells] receives T.  stats (nullable, host):
+ * sweeps, CG iterations in all, region size, last change, converged.  The
+ * last sweep's linear solve is kept for mcrt_pda_nonlinear_adjoint (and is
+ * what mcrt_pda_adjoint would differentiate).  MCRT_E_NOT_CONVERGED if the
+ * sweeps or a CG solve hit their caps (T_out holds the last sweep).  Waits
+ * for the stream. */
+int mcrt_pda_nonlinear(mcrt_ctx* ctx, const uint8_t* mask_dev, const double* rho_dev,
+                       const double* kscale_dev, const double* T_bc_dev, double* T_out_dev,
+                       mcrt_pda_stats* stats, hipStream_t stream);
+
+/* Adjoint of the last mcrt_pda_nonlinear: dJ/d(log rho_c) into g_logrho_dev
+ * and (nullable) dJ/ds_c into g_kscale_dev, [n_cells] each, given dJ/dT
+ * [n_cells] for an objective J of its output.  At the fixed point the
+ * residual of the finite-volume system vanishes, so the adjoint solves
+ * J^T lambda = dJ/du with the Jacobian J = dr/du of u = T^4, which holds the
+ * conductances' dependence on T through D(T) (not symmetric: BiCGSTAB with a
+ * diagonal preconditioner, to cg_tol, at most cg_max_iter iterations), and
+ * the gradient is -lambda . dr/dp as in mcrt_pda_adjoint.  stats (nullable):
+ * iterations and relative residual.  MCRT_E_ARG without a preceding
+ * mcrt_pda_nonlinear on this context (or after any call that reused its
+ * scratch), MCRT_E_NOT_CONVERGED at the iteration cap.  Waits for the
+ * stream. */
+int mcrt_pda_nonlinear_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev,
+                               double* g_kscale_dev, mcrt_pda_stats* stats, hipStream_t stream);
+
 /* The spectral energy distribution from the escaping packets (Sect. 3.3
  * studies it at fixed inclination): escaped luminosity per wavelength bin and
  * |cos i| bin of the packet's direction, sed_dev [n_lambda][n_inc] double,

@@ -544,6 +544,7 @@ void mcrt_destroy(mcrt_ctx* ctx) {
   if (ctx->d_tally_blob) hipFree(ctx->d_tally_blob);
   if (ctx->d_pda_blob) hipFree(ctx->d_pda_blob);
   if (ctx->d_lin_args) hipFree(ctx->d_lin_args);
+  if (ctx->d_nl) hipFree(ctx->d_nl);
   if (ctx->d_tail) hipFree(ctx->d_tail);
   if (ctx->d_paths) hipFree(ctx->d_paths);
   if (ctx->d_src) hipFree(ctx->d_src);
@@ -617,6 +618,22 @@ int mcrt_pda_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev
                      double* g_kscale_dev, hipStream_t stream) {
   if (!ctx || !dJdT_dev || !g_logrho_dev) return fail(ctx, MCRT_E_ARG, "mcrt_pda_adjoint: null argument");
   return mcrt::pda_adjoint(ctx, dJdT_dev, g_logrho_dev, g_kscale_dev, nullptr, stream);
+}
+
+int mcrt_pda_nonlinear(mcrt_ctx* ctx, const uint8_t* mask_dev, const double* rho_dev,
+                       const double* kscale_dev, const double* T_bc_dev, double* T_out_dev,
+                       mcrt_pda_stats* stats, hipStream_t stream) {
+  if (!ctx || !mask_dev || !T_bc_dev || !T_out_dev)
+    return fail(ctx, MCRT_E_ARG, "mcrt_pda_nonlinear: null argument");
+  return mcrt::pda_nonlinear(ctx, mask_dev, rho_dev, kscale_dev, T_bc_dev, T_out_dev, stats,
+                             stream);
+}
+
+int mcrt_pda_nonlinear_adjoint(mcrt_ctx* ctx, const double* dJdT_dev, double* g_logrho_dev,
+                               double* g_kscale_dev, mcrt_pda_stats* stats, hipStream_t stream) {
+  if (!ctx || !dJdT_dev || !g_logrho_dev)
+    return fail(ctx, MCRT_E_ARG, "mcrt_pda_nonlinear_adjoint: null argument");
+  return mcrt::pda_nl_adjoint(ctx, dJdT_dev, g_logrho_dev, g_kscale_dev, stats, stream);
 }
 
 int mcrt_sed(mcrt_ctx* ctx, double* sed_dev, hipStream_t stream) {

@@ -144,6 +144,8 @@ struct mcrt_ctx {
   void* d_lin_args = nullptr;        // argument slot of the linear PDA / adjoint
   const double* lin_rho = nullptr;   // density of the last linear forward
   bool lin_ready = false;
+  bool nl_ready = false;               // the kept linear solve ends a nonlinear forward
+  void* d_nl = nullptr;                // nonlinear PDA adjoint scratch
   // host copies
   std::string err;
 };
@@ -162,6 +164,10 @@ int pda_linear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const doub
                hipStream_t s);
 int pda_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_kscale,
                 mcrt_pda_stats* st, hipStream_t s);
+int pda_nonlinear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const double* kscale,
+                  const double* T_bc, double* T_out, mcrt_pda_stats* st, hipStream_t s);
+int pda_nl_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_kscale,
+                   mcrt_pda_stats* st, hipStream_t s);
 // batches
 size_t pda_wg_args_size();
 int pda_batch_fill(mcrt_ctx** ctxs, int n, void* host);

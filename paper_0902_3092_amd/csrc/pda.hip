@@ -1290,6 +1290,7 @@ struct PdaLinArgs {
   const double* dJdT;
   double* g_logrho;
   double* g_kscale;
+  double* nl;              // nonlinear adjoint: NL_ARRAYS work arrays of n_cells doubles
 };
 
 // face conductance from the two resistances, and its derivative by R_a
@@ -1402,6 +1403,42 @@ __global__ void __launch_bounds__(WG) pda_linear_kernel(const PdaLinArgs* args) 
   }
 }
 
+// dJ/d(log rho_c) and dJ/ds_c from the adjoint lambda: -lambda . dr/dp
+// through the resistances R = rho s / (D rho)(T) of the kept solve.
+__device__ void grad_from_lambda(const PdaLinArgs& a, const PdaArrays& P, const double* lam) {
+  const DevModel& M = a.M;
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double dJdR = 0.0;
+    if (a.rho[c] > 0.0) {
+      const int i = c / n_mu, j = c - i * n_mu;
+      const bool rc_ = P.region[c] == 1;
+      double uc = rc_ ? P.x[c] : P.Tbc[c] * P.Tbc[c] * P.Tbc[c] * P.Tbc[c];
+      for (int q = 0; q < 4; ++q) {
+        int ib = i + di[q], jb = j + dj[q];
+        if (!in_grid(ib, jb, n_r, n_mu)) continue;
+        int cb = ib * n_mu + jb;
+        if (!(a.rho[cb] > 0.0)) continue;
+        const bool rb = P.region[cb] == 1;
+        if (!rc_ && !rb) continue;
+        double ub = rb ? P.x[cb] : P.Tbc[cb] * P.Tbc[cb] * P.Tbc[cb] * P.Tbc[cb];
+        double lam_dr;  // lambda . dr/da_f
+        if (rc_ && rb) lam_dr = (lam[c] - lam[cb]) * (uc - ub);
+        else if (rc_) lam_dr = lam[c] * (uc - ub);
+        else lam_dr = lam[cb] * (ub - uc);
+        double dA;
+        (void)lin_cond(a, i, j, ib, jb, P.p1[c], P.p1[cb], &dA);
+        dJdR -= lam_dr * dA;
+      }
+    }
+    // dR/dlog rho = R, dR/ds = R/s
+    const double R = P.p1[c];
+    a.g_logrho[c] = R * dJdR;
+    if (a.g_kscale) a.g_kscale[c] = R / P.b[c] * dJdR;
+  }
+}
+
 // Adjoint of the linear solve above (same workgroup arrays).
 __global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args) {
   const PdaLinArgs& a = *args;
@@ -1424,35 +1461,7 @@ __global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args)
   double resid;
   int it = wg_cg(P, n_r, n_mu, a.precond, a.g_logrho, P.Tw, a.cg_max_iter, a.cg_tol2, red, &resid);
   __syncthreads();
-  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    double dJdR = 0.0;
-    if (a.rho[c] > 0.0) {
-      const int i = c / n_mu, j = c - i * n_mu;
-      const bool rc_ = P.region[c] == 1;
-      double uc = rc_ ? P.x[c] : P.Tbc[c] * P.Tbc[c] * P.Tbc[c] * P.Tbc[c];
-      for (int q = 0; q < 4; ++q) {
-        int ib = i + di[q], jb = j + dj[q];
-        if (!in_grid(ib, jb, n_r, n_mu)) continue;
-        int cb = ib * n_mu + jb;
-        if (!(a.rho[cb] > 0.0)) continue;
-        const bool rb = P.region[cb] == 1;
-        if (!rc_ && !rb) continue;
-        double ub = rb ? P.x[cb] : P.Tbc[cb] * P.Tbc[cb] * P.Tbc[cb] * P.Tbc[cb];
-        double lam_dr;  // lambda . dr/da_f
-        if (rc_ && rb) lam_dr = (P.Tw[c] - P.Tw[cb]) * (uc - ub);
-        else if (rc_) lam_dr = P.Tw[c] * (uc - ub);
-        else lam_dr = P.Tw[cb] * (ub - uc);
-        double dA;
-        (void)lin_cond(a, i, j, ib, jb, P.p1[c], P.p1[cb], &dA);
-        dJdR -= lam_dr * dA;
-      }
-    }
-    // dR/dlog rho = R, dR/ds = R/s
-    const double R = P.p1[c];
-    a.g_logrho[c] = R * dJdR;
-    if (a.g_kscale) a.g_kscale[c] = R / P.b[c] * dJdR;
-  }
+  grad_from_lambda(a, P, P.Tw);
   if (threadIdx.x == 0 && a.stats) {
     mcrt_pda_stats s{};
     s.sweeps = 1;
@@ -1464,11 +1473,200 @@ __global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args)
   }
 }
 
+// Adjoint of the nonlinear PDA (Picard to its fixed point, D = D(T)).  At the
+// fixed point the residual r_c = sum_f a_f (u_c - u_b) of every region cell
+// vanishes; its Jacobian J = dr/du holds, beside the conductances, their
+// dependence on u through R(T(u)):
+//   J_cc = sum_f [a_f + da_f/dR_c dR_c/du_c (u_c - u_b)],
+//   J_cb = -a_f + da_f/dR_b dR_b/du_b (u_c - u_b)       (b in the region),
+// da_f/dR = -a_f / (R_c + R_b), dR/du = -R (D rho)'(T) / (D rho)(T) T / (4 u),
+// (D rho)' the slope of the table segment.  J is not symmetric: the adjoint
+// J^T lambda = dJ/du is solved by BiCGSTAB with the diagonal as
+// preconditioner, then the gradient is that of the linear adjoint with this
+// lambda.  Work arrays (of the nl scratch): lambda, r, rh, p, v, s, t, y, z,
+// the diagonal, and per cell b the four couplings J_cb from its neighbours.
+constexpr int NL_ARRAYS = 14;
+
+__global__ void __launch_bounds__(WG) pda_nl_adjoint_kernel(const PdaLinArgs* args) {
+  const PdaLinArgs& a = *args;
+  const DevModel& M = a.M;
+  const PdaArrays& P = a.P;
+  const int n_r = M.n_r, n_mu = M.n_mu, nc = n_r * n_mu;
+  __shared__ double red[WG / 64];
+  double* const lam = a.nl;
+  double* const r = lam + nc;
+  double* const rh = r + nc;
+  double* const p = rh + nc;
+  double* const v = p + nc;
+  double* const sv = v + nc;
+  double* const t = sv + nc;
+  double* const y = t + nc;
+  double* const z = y + nc;
+  double* const jd = z + nc;
+  double* const in0 = jd + nc;  // in0 .. in3: J_cb from the neighbour in direction q
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  auto u_of = [&](int c) -> double {
+    if (P.region[c] == 1) return P.x[c];
+    const double tb = P.Tbc[c], t2 = tb * tb;
+    return t2 * t2;
+  };
+  auto dRdu_of = [&](int c) -> double {  // region cells
+    const double u = P.x[c];
+    if (!(u > 0.0) || !(a.rho[c] > 0.0)) return 0.0;
+    const double T = sqrt(sqrt(u));
+    const int n = seg_of_g(M.Tn, M.n_T, T);
+    const double f = (T - M.Tn[n]) / (M.Tn[n + 1] - M.Tn[n]);
+    const double Drho = M.Drho[n] + f * (M.Drho[n + 1] - M.Drho[n]);
+    const double slope = (M.Drho[n + 1] - M.Drho[n]) / (M.Tn[n + 1] - M.Tn[n]);
+    return -P.p1[c] * slope / Drho * T / (4.0 * u);
+  };
+  // the transposed operator's coefficients
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double d = 1.0, cq[4] = {0.0, 0.0, 0.0, 0.0};
+    if (P.region[c] == 1) {
+      const int i = c / n_mu, j = c - i * n_mu;
+      const double uc = P.x[c], dRc = dRdu_of(c);
+      d = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int ib = i + di[q], jb = j + dj[q];
+        if (!in_grid(ib, jb, n_r, n_mu)) continue;
+        const int cb = ib * n_mu + jb;
+        if (!(a.rho[cb] > 0.0)) continue;
+        const double af = lin_cond(a, i, j, ib, jb, P.p1[c], P.p1[cb], nullptr);
+        const double dadR = -af / (P.p1[c] + P.p1[cb]);
+        const double ub = u_of(cb);
+        d += af + dadR * dRc * (uc - ub);
+        // row cb's coupling to column c, J_{cb,c} (cb in the region)
+        if (P.region[cb] == 1) cq[q] = -af + dadR * dRc * (ub - uc);
+      }
+    }
+    jd[c] = d;
+    for (int q = 0; q < 4; ++q) in0[(size_t)q * nc + c] = cq[q];
+  }
+  __syncthreads();
+  auto applyT = [&](const double* x, int c) -> double {  // (J^T x)_c, c in the region
+    const int i = c / n_mu, j = c - i * n_mu;
+    double acc = jd[c] * x[c];
+    for (int q = 0; q < 4; ++q) {
+      const int ib = i + di[q], jb = j + dj[q];
+      if (!in_grid(ib, jb, n_r, n_mu)) continue;
+      const int cb = ib * n_mu + jb;
+      if (P.region[cb] == 1) acc += in0[(size_t)q * nc + c] * x[cb];
+    }
+    return acc;
+  };
+  // right-hand side dJ/du, and BiCGSTAB from lambda = 0
+  double bb = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double g = 0.0;
+    if (P.region[c] == 1) {
+      const double u = P.x[c];
+      g = u > 0.0 ? a.dJdT[c] * sqrt(sqrt(u)) / (4.0 * u) : 0.0;
+    }
+    lam[c] = 0.0;
+    r[c] = g;
+    rh[c] = g;
+    p[c] = 0.0;
+    v[c] = 0.0;
+    bb += g * g;
+  }
+  bb = wg_reduce<false>(bb, red);
+  double rho_old = 1.0, alpha = 1.0, omega = 1.0, rr = bb;
+  int it = 0;
+  while (bb > 0.0 && rr > a.cg_tol2 * bb && it < a.cg_max_iter) {
+    double rho = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x)
+      if (P.region[c] == 1) rho += rh[c] * r[c];
+    rho = wg_reduce<false>(rho, red);
+    if (rho == 0.0) break;  // breakdown: stop with the iterate reached
+    const double beta = (rho / rho_old) * (alpha / omega);
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      p[c] = r[c] + beta * (p[c] - omega * v[c]);
+      y[c] = p[c] / jd[c];
+    }
+    __syncthreads();
+    double rv = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      v[c] = applyT(y, c);
+      rv += rh[c] * v[c];
+    }
+    rv = wg_reduce<false>(rv, red);
+    alpha = rv != 0.0 ? rho / rv : 0.0;
+    double ss = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      sv[c] = r[c] - alpha * v[c];
+      z[c] = sv[c] / jd[c];
+      ss += sv[c] * sv[c];
+    }
+    ss = wg_reduce<false>(ss, red);
+    ++it;
+    if (ss <= a.cg_tol2 * bb) {
+      for (int c = threadIdx.x; c < nc; c += blockDim.x)
+        if (P.region[c] == 1) lam[c] += alpha * y[c];
+      rr = ss;
+      break;
+    }
+    double ts = 0.0, tt = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      t[c] = applyT(z, c);
+      ts += t[c] * sv[c];
+      tt += t[c] * t[c];
+    }
+    ts = wg_reduce<false>(ts, red);
+    tt = wg_reduce<false>(tt, red);
+    omega = tt > 0.0 ? ts / tt : 0.0;
+    double rn = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      if (P.region[c] != 1) continue;
+      lam[c] += alpha * y[c] + omega * z[c];
+      r[c] = sv[c] - omega * t[c];
+      rn += r[c] * r[c];
+    }
+    rr = wg_reduce<false>(rn, red);
+    rho_old = rho;
+    if (omega == 0.0) break;
+  }
+  __syncthreads();
+  grad_from_lambda(a, P, lam);
+  if (threadIdx.x == 0 && a.stats) {
+    mcrt_pda_stats s{};
+    s.sweeps = 1;
+    s.cg_iters_total = it;
+    s.cg_iters_last = it;
+    s.last_residual = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    s.converged = (bb == 0.0 || rr <= a.cg_tol2 * bb) ? 1 : 0;
+    *a.stats = s;
+  }
+}
+
+// Largest relative change of T over the region cells, into *out (as the
+// bits of a non-negative double, so an integer maximum orders them).
+__global__ void nl_change_kernel(const double* T_new, const double* T_old, const uint8_t* region,
+                                 int nc, unsigned long long* out) {
+  double m = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    if (region[c] != 1) continue;
+    const double ch = fabs(T_new[c] - T_old[c]) / fmax(T_new[c], 1e-300);
+    m = fmax(m, ch);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void nl_zero_kernel(unsigned long long* out) {
+  if (threadIdx.x == 0) *out = 0ull;
+}
+
 }  // namespace
 
 // The argument slot of the single-workgroup solve doubles as the slot of the
 // linear/adjoint pair (both are synchronous).
-static int pda_lin_call(mcrt_ctx* ctx, const PdaLinArgs& h, bool adjoint, mcrt_pda_stats* st,
+// kind: 0 the linear solve, 1 its adjoint, 2 the adjoint of the nonlinear solve
+static int pda_lin_call(mcrt_ctx* ctx, const PdaLinArgs& h, int kind, mcrt_pda_stats* st,
                         hipStream_t s) {
   static_assert(sizeof(PdaLinArgs) <= 4096, "argument slot");
   PdaWgArgs* d_args;
@@ -1481,7 +1679,10 @@ static int pda_lin_call(mcrt_ctx* ctx, const PdaLinArgs& h, bool adjoint, mcrt_p
     set_error(ctx, "PDA argument upload failed");
     return MCRT_E_HIP;
   }
-  if (adjoint)
+  if (kind == 2)
+    hipLaunchKernelGGL(pda_nl_adjoint_kernel, dim3(1), dim3(WG), 0, s,
+                       (const PdaLinArgs*)ctx->d_lin_args);
+  else if (kind == 1)
     hipLaunchKernelGGL(pda_adjoint_kernel, dim3(1), dim3(WG), 0, s,
                        (const PdaLinArgs*)ctx->d_lin_args);
   else
@@ -1525,7 +1726,8 @@ int pda_linear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const doub
   h.precond = ctx->opt.pda_precond;
   ctx->lin_rho = h.rho;
   ctx->lin_ready = true;
-  return pda_lin_call(ctx, h, false, st, s);
+  ctx->nl_ready = false;
+  return pda_lin_call(ctx, h, 0, st, s);
 }
 
 int pda_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_kscale,
@@ -1549,7 +1751,100 @@ int pda_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_k
   h.cg_max_iter = ctx->opt.cg_max_iter;
   h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
   h.precond = ctx->opt.pda_precond;
-  return pda_lin_call(ctx, h, true, st, s);
+  return pda_lin_call(ctx, h, 1, st, s);
+}
+
+// The nonlinear PDA for differentiation: Picard sweeps of the linear solve,
+// D from the T of the previous sweep (the first from T_bc), until the
+// largest relative change of T falls below pda_tol or stalls below its
+// square root (the rule of mcrt_pda_solve).  The last sweep's linear solve
+// stays for the adjoint.
+static int nl_scratch(mcrt_ctx* ctx) {
+  if (ctx->d_nl) return MCRT_OK;
+  const size_t bytes = (size_t)(NL_ARRAYS + 1) * ctx->n_cells * sizeof(double) + 256;
+  if (hipMalloc(&ctx->d_nl, bytes) != hipSuccess) {
+    ctx->d_nl = nullptr;
+    set_error(ctx, "nonlinear PDA scratch allocation failed");
+    return MCRT_E_OOM;
+  }
+  return MCRT_OK;
+}
+
+int pda_nonlinear(mcrt_ctx* ctx, const uint8_t* mask, const double* rho, const double* kscale,
+                  const double* T_bc, double* T_out, mcrt_pda_stats* st, hipStream_t s) {
+  int rc = nl_scratch(ctx);
+  if (rc) return rc;
+  const int nc = ctx->n_cells;
+  double* T_cur = (double*)ctx->d_nl + (size_t)NL_ARRAYS * nc;
+  unsigned long long* d_change = (unsigned long long*)(T_cur + nc);
+  if (hipMemcpyAsync(T_cur, T_bc, (size_t)nc * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+      hipSuccess) {
+    set_error(ctx, "nonlinear PDA: copy failed");
+    return MCRT_E_HIP;
+  }
+  mcrt_pda_stats out{}, lst{};
+  int status = MCRT_OK;
+  double prev = INFINITY;
+  const unsigned nb = (unsigned)std::min<size_t>(((size_t)nc + 255) / 256, 1024);
+  for (int sweep = 1; sweep <= ctx->opt.pda_max_sweeps; ++sweep) {
+    rc = pda_linear(ctx, mask, rho, kscale, T_cur, T_bc, T_out, &lst, s);
+    if (rc != MCRT_OK && rc != MCRT_E_NOT_CONVERGED) return rc;
+    if (rc == MCRT_E_NOT_CONVERGED) status = rc;
+    out.cg_iters_total += lst.cg_iters_total;
+    out.cg_iters_last = lst.cg_iters_last;
+    out.last_residual = lst.last_residual;
+    out.n_region = lst.n_region;
+    out.n_isolated = lst.n_isolated;
+    out.sweeps = sweep;
+    hipLaunchKernelGGL(nl_zero_kernel, dim3(1), dim3(64), 0, s, d_change);
+    hipLaunchKernelGGL(nl_change_kernel, dim3(nb), dim3(256), 0, s, (const double*)T_out,
+                       (const double*)T_cur, (const uint8_t*)ctx->d_region, nc, d_change);
+    unsigned long long bits = 0;
+    if (hipMemcpyAsync(&bits, d_change, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(T_cur, T_out, (size_t)nc * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error(ctx, "nonlinear PDA sweep failed");
+      return MCRT_E_HIP;
+    }
+    double change;
+    std::memcpy(&change, &bits, sizeof(change));
+    out.last_change = change;
+    if (change < ctx->opt.pda_tol || (change < std::sqrt(ctx->opt.pda_tol) && change >= prev)) {
+      out.converged = 1;
+      break;
+    }
+    prev = change;
+  }
+  if (!out.converged && status == MCRT_OK) status = MCRT_E_NOT_CONVERGED;
+  ctx->nl_ready = true;  // after pda_linear, which clears it
+  if (st) *st = out;
+  return status;
+}
+
+int pda_nl_adjoint(mcrt_ctx* ctx, const double* dJdT, double* g_logrho, double* g_kscale,
+                   mcrt_pda_stats* st, hipStream_t s) {
+  if (!ctx->lin_ready || !ctx->nl_ready || !ctx->d_nl) {
+    set_error(ctx, "mcrt_pda_nonlinear_adjoint needs a preceding mcrt_pda_nonlinear");
+    return MCRT_E_ARG;
+  }
+  PdaArrays P;
+  PdaGeom g;
+  int rc = pda_alloc(ctx, P, g);
+  if (rc) return rc;
+  PdaLinArgs h{};
+  h.M = ctx->m;
+  h.P = P;
+  h.g = g;
+  h.rho = ctx->lin_rho;
+  h.dJdT = dJdT;
+  h.g_logrho = g_logrho;
+  h.g_kscale = g_kscale;
+  h.nl = (double*)ctx->d_nl;
+  h.cg_max_iter = ctx->opt.cg_max_iter;
+  h.cg_tol2 = ctx->opt.cg_tol * ctx->opt.cg_tol;
+  h.precond = ctx->opt.pda_precond;
+  return pda_lin_call(ctx, h, 2, st, s);
 }
 
 // ---------------------------------------------------------------- batches

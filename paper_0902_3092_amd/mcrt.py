@@ -29,7 +29,8 @@ EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "
            "mcrt_get_size", "mcrt_set_T", "mcrt_hydrostatic", "mcrt_strerror", "mcrt_last_error",
            "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_pda_solve_noalloc",
            "mcrt_batch_pda", "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity",
-           "mcrt_raytrace_sed", "mcrt_region_mask"]
+           "mcrt_raytrace_sed", "mcrt_region_mask", "mcrt_pda_nonlinear",
+           "mcrt_pda_nonlinear_adjoint"]
 
 
 class McrtError(RuntimeError):
@@ -119,6 +120,8 @@ def lib():
         L.mcrt_batch_run.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp, vp]
         L.mcrt_pda_linear.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mcrt_pda_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.mcrt_pda_nonlinear.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mcrt_pda_nonlinear_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mcrt_pda_solve_noalloc.argtypes = [vp, vp, vp, vp]
         L.mcrt_batch_pda.argtypes = [vp, C.c_int, vp, vp]
         L.mcrt_convergence.argtypes = [vp, i32, i32, vp, vp]
@@ -378,6 +381,33 @@ class Context:
         rc = lib().mcrt_pda_adjoint(self.handle, _ptr(dJdT.contiguous()), _ptr(g_r), _ptr(g_s),
                                     _stream(stream))
         _check(rc, "mcrt_pda_adjoint")
+        return g_r, g_s
+
+
+    def pda_nonlinear(self, mask, T_bc, rho=None, kscale=None, stream=None):
+        """mcrt_pda_nonlinear: Picard to the fixed point with D = D(T), from
+        T_bc; returns (T, stats)."""
+        import torch
+        T_out = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        st = PdaStats()
+        self._lin_gen += 1
+        rc = lib().mcrt_pda_nonlinear(self.handle, _ptr(mask), _ptr(rho), _ptr(kscale),
+                                      _ptr(T_bc), _ptr(T_out), C.byref(st), _stream(stream))
+        _check(rc, "mcrt_pda_nonlinear")
+        return T_out, {f: getattr(st, f) for f, _ in PdaStats._fields_}
+
+    def pda_nonlinear_adjoint(self, dJdT, stream=None, stats=False):
+        """mcrt_pda_nonlinear_adjoint of the last pda_nonlinear: (dJ/dlog rho,
+        dJ/ds), and its statistics with stats=True."""
+        import torch
+        g_r = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        g_s = torch.empty(self.n_cells, dtype=torch.float64, device="cuda")
+        st = PdaStats()
+        rc = lib().mcrt_pda_nonlinear_adjoint(self.handle, _ptr(dJdT.contiguous()), _ptr(g_r),
+                                              _ptr(g_s), C.byref(st), _stream(stream))
+        _check(rc, "mcrt_pda_nonlinear_adjoint")
+        if stats:
+            return g_r, g_s, {f: getattr(st, f) for f, _ in PdaStats._fields_}
         return g_r, g_s
 
 
