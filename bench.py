@@ -259,8 +259,7 @@ def c3(mcrt, W, torch, scale, iters, plain, split=False):
     draws = W.batch_draws()
     npk = [max(1000, int(round(b["n_packets"] * scale))) for b in draws]
     seeds = [b["seed"] for b in draws]
-    ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
-                         pda_visits=100, mrw_coef_T=1) for b in draws]
+    ctxs = batch_contexts(mcrt, W, draws)
     torch.cuda.synchronize()
     log("c3: %d disks, %d packets per pass, %d passes in %s" %
         (len(ctxs), sum(npk), iters, "one graph each" if split else "one graph"))
@@ -720,6 +719,28 @@ def reference_halves(mcrt, disk, o, n_total, torch):
     return out, time.perf_counter() - t0
 
 
+BATCH_PHYS = dict(precision="fp32", mrw=True, gamma=3.0, n_int_min=20, pda_visits=100)
+
+
+def batch_contexts(mcrt, W, draws):
+    """Contexts of the 64-disk workload, each with the autotuner's cached
+    choices for its shape where there are any (MRW coefficients from the
+    previous pass's T)."""
+    from paper_0902_3092_amd import autotune
+    out = []
+    for b in draws:
+        d = W.batch_disk(b)
+        out.append(mcrt.Context(d, mrw_coef_T=1, **BATCH_PHYS,
+                                **autotune.batch_options(d, b["n_packets"], **BATCH_PHYS)))
+    return out
+
+
+def batch_tuned_count(W, draws):
+    from paper_0902_3092_amd import autotune
+    return sum(1 for b in draws
+               if autotune.batch_options(W.batch_disk(b), b["n_packets"], **BATCH_PHYS))
+
+
 def c3_full(mcrt, W, torch, passes):
     """The 64-disk batched workload at its drawn packet counts: `passes`
     passes (trace, T, PDA) captured in one HIP graph, the MRW coefficients of
@@ -729,8 +750,7 @@ def c3_full(mcrt, W, torch, passes):
     draws = W.batch_draws()
     npk = [b["n_packets"] for b in draws]
     seeds = [b["seed"] for b in draws]
-    ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
-                         pda_visits=100, mrw_coef_T=1) for b in draws]
+    ctxs = batch_contexts(mcrt, W, draws)
     torch.cuda.synchronize()
     log("c3: %d disks, %.3g packets per pass, %d passes in one graph" %
         (len(ctxs), sum(npk), passes))
@@ -749,7 +769,8 @@ def c3_full(mcrt, W, torch, passes):
                             "capped_last_pass": int(sum(c["capped"] for c in cnt)),
                             "handed_off_last_pass": int(sum(c["handed"] for c in cnt)),
                             "cells": int(sum(c.n_cells for c in ctxs)),
-                            "pda_region_cells_last_pass": int(sum(x["n_region"] for x in st))}}
+                            "pda_region_cells_last_pass": int(sum(x["n_region"] for x in st)),
+                            "disks_with_tuned_options": batch_tuned_count(W, draws)}}
     # the PDA of the last pass again, alone: Monte Carlo T from the tallies,
     # then all disks' PDA in one launch
     for c in ctxs:
@@ -814,8 +835,7 @@ def pda_probe(mcrt, W, torch):
     graph), then the batched PDA of that pass on its own: the launch that the
     PDA counter runs select by kernel name."""
     draws = W.batch_draws()
-    ctxs = [mcrt.Context(W.batch_disk(b), precision="fp32", mrw=True, gamma=3.0, n_int_min=20,
-                         pda_visits=100, mrw_coef_T=1) for b in draws]
+    ctxs = batch_contexts(mcrt, W, draws)
     mcrt.batch_run_rc(ctxs, [b["n_packets"] for b in draws], [b["seed"] for b in draws],
                       n_iter=1, use_graph=True)
     torch.cuda.synchronize()

@@ -97,6 +97,17 @@ def options_for(disk, n_packets: int, path: Optional[str] = None, **phys) -> dic
     return {k: v for k, v in e["options"].items() if k not in NON_OPTIONS} if e else {}
 
 
+# what a batched pass takes from a disk's context: its hand-off threshold and
+# PDA solver (the batched trace has one launch shape for all disks)
+BATCH_KEYS = ("wave_events", "pda_solver", "pda_precond")
+
+
+def batch_options(disk, n_packets: int, path: Optional[str] = None, **phys) -> dict:
+    """The cached choices of this disk shape that a batched pass uses, or {}."""
+    return {k: v for k, v in options_for(disk, n_packets, path, **phys).items()
+            if k in BATCH_KEYS}
+
+
 def calls_per_pass(disk, n_packets: int, path: Optional[str] = None, **phys) -> int:
     """The cached number of trace calls per pass for this shape (1 if none)."""
     e = lookup(disk, n_packets, path, **phys)
