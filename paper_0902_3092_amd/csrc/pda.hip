@@ -1484,8 +1484,12 @@ __global__ void __launch_bounds__(WG) pda_adjoint_kernel(const PdaLinArgs* args)
 // J^T lambda = dJ/du is solved by BiCGSTAB with the diagonal as
 // preconditioner, then the gradient is that of the linear adjoint with this
 // lambda.  Work arrays (of the nl scratch): lambda, r, rh, p, v, s, t, y, z,
-// the diagonal, and per cell b the four couplings J_cb from its neighbours.
-constexpr int NL_ARRAYS = 14;
+// the diagonal, per cell b the four couplings J_cb from its neighbours, and
+// the factors of the theta-line preconditioner.  That preconditioner
+// (pda_precond = 1; else the diagonal) solves the tridiagonal block of J^T
+// along each radius exactly, as the linear solve's does for A: the couplings
+// across theta dominate where the cells are thin in theta.
+constexpr int NL_ARRAYS = 16;
 
 __global__ void __launch_bounds__(WG) pda_nl_adjoint_kernel(const PdaLinArgs* args) {
   const PdaLinArgs& a = *args;
@@ -1504,6 +1508,8 @@ __global__ void __launch_bounds__(WG) pda_nl_adjoint_kernel(const PdaLinArgs* ar
   double* const z = y + nc;
   double* const jd = z + nc;
   double* const in0 = jd + nc;  // in0 .. in3: J_cb from the neighbour in direction q
+  double* const cp = in0 + 4 * (size_t)nc;  // line factors: modified super-diagonal
+  double* const dinv = cp + nc;             // and reciprocal pivots
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
   auto u_of = [&](int c) -> double {
     if (P.region[c] == 1) return P.x[c];
@@ -1544,6 +1550,56 @@ __global__ void __launch_bounds__(WG) pda_nl_adjoint_kernel(const PdaLinArgs* ar
     for (int q = 0; q < 4; ++q) in0[(size_t)q * nc + c] = cq[q];
   }
   __syncthreads();
+  // theta-line factors (Thomas algorithm, no pivoting: the blocks are
+  // diagonally dominant); cells outside the region are identity rows
+  const bool lines = a.precond == 1;
+  if (lines) {
+    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+      double cprev = 0.0;
+      for (int j = 0; j < n_mu; ++j) {
+        const int c = i * n_mu + j;
+        if (P.region[c] != 1) {
+          cp[c] = 0.0;
+          dinv[c] = 1.0;
+          cprev = 0.0;
+          continue;
+        }
+        const double sub = j > 0 ? in0[2 * (size_t)nc + c] : 0.0;
+        const double sup = j + 1 < n_mu ? in0[3 * (size_t)nc + c] : 0.0;
+        const double den = jd[c] - sub * cprev;
+        dinv[c] = 1.0 / den;
+        cp[c] = sup * dinv[c];
+        cprev = cp[c];
+      }
+    }
+    __syncthreads();
+  }
+  // M^-1 x into out (all region cells; a barrier follows in the caller)
+  auto precond = [&](const double* x, double* out) {
+    if (!lines) {
+      for (int c = threadIdx.x; c < nc; c += blockDim.x)
+        if (P.region[c] == 1) out[c] = x[c] / jd[c];
+      return;
+    }
+    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+      double prev = 0.0;
+      for (int j = 0; j < n_mu; ++j) {
+        const int c = i * n_mu + j;
+        if (P.region[c] != 1) {
+          out[c] = 0.0;
+          prev = 0.0;
+          continue;
+        }
+        const double sub = j > 0 ? in0[2 * (size_t)nc + c] : 0.0;
+        prev = (x[c] - sub * prev) * dinv[c];
+        out[c] = prev;
+      }
+      for (int j = n_mu - 2; j >= 0; --j) {
+        const int c = i * n_mu + j;
+        if (P.region[c] == 1) out[c] -= cp[c] * out[c + 1];
+      }
+    }
+  };
   auto applyT = [&](const double* x, int c) -> double {  // (J^T x)_c, c in the region
     const int i = c / n_mu, j = c - i * n_mu;
     double acc = jd[c] * x[c];
@@ -1580,11 +1636,10 @@ __global__ void __launch_bounds__(WG) pda_nl_adjoint_kernel(const PdaLinArgs* ar
     rho = wg_reduce<false>(rho, red);
     if (rho == 0.0) break;  // breakdown: stop with the iterate reached
     const double beta = (rho / rho_old) * (alpha / omega);
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      if (P.region[c] != 1) continue;
-      p[c] = r[c] + beta * (p[c] - omega * v[c]);
-      y[c] = p[c] / jd[c];
-    }
+    for (int c = threadIdx.x; c < nc; c += blockDim.x)
+      if (P.region[c] == 1) p[c] = r[c] + beta * (p[c] - omega * v[c]);
+    __syncthreads();
+    precond(p, y);
     __syncthreads();
     double rv = 0.0;
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -1598,10 +1653,11 @@ __global__ void __launch_bounds__(WG) pda_nl_adjoint_kernel(const PdaLinArgs* ar
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
       if (P.region[c] != 1) continue;
       sv[c] = r[c] - alpha * v[c];
-      z[c] = sv[c] / jd[c];
       ss += sv[c] * sv[c];
     }
-    ss = wg_reduce<false>(ss, red);
+    ss = wg_reduce<false>(ss, red);   // (its barrier also orders sv for the sweep)
+    precond(sv, z);
+    __syncthreads();
     ++it;
     if (ss <= a.cg_tol2 * bb) {
       for (int c = threadIdx.x; c < nc; c += blockDim.x)
