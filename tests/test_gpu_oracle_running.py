@@ -27,11 +27,15 @@ The gates (Sect. 2.1 and 2.2 fix no tolerance; these restate the method's
 photon statistics):
 
 * per cell, eligible = at least 100 packet entries in every run, or in the PDA
-  region of every run: |mean T_gpu / mean T_ora - 1| <= max(1 %, 3 sigma) for
-  the Monte Carlo cells and max(2 %, 3 sigma) for the PDA cells, sigma the
-  standard error of the difference of the two ensemble means; with K runs a
-  side the 3-sigma test fails by chance for ~1 % of cells (Student t), so at
-  most 3 % may fail;
+  region of every run: |mean T_gpu / mean T_ora - 1| <= max(1 %, t sigma) for
+  the Monte Carlo cells and max(2 %, t sigma) for the PDA cells, sigma the
+  standard error of the difference of the two ensemble means and t the
+  Student quantile, at the Welch-Satterthwaite degrees of freedom of that
+  difference, of the two-sided Gaussian 3-sigma tail (0.27 %): sigma is
+  estimated from K runs a side, and a fixed factor 3 would fail by chance
+  for ~1 % of cells at K = 8 and more where one side's spread dominates;
+  neighbouring cells share packets, so chance failures come in clusters, and
+  at most 3 % may fail;
 * mass-weighted over those cells, the systematic part of the difference:
   the squared excess over the noise, sum w (d^2 - sigma^2) (an unbiased
   estimate of the mass-weighted mean squared bias), is at most (1 %)^2 for
@@ -48,10 +52,13 @@ import math
 
 import numpy as np
 import pytest
+from scipy.stats import t as student_t
 
 from paper_0902_3092_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+TAIL = math.erfc(3.0 / math.sqrt(2.0))     # two-sided Gaussian 3-sigma tail
 
 
 @pytest.fixture(scope="module")
@@ -83,14 +90,18 @@ def compare_ensembles(name, mass, Tg, To, Vg, Vo, Rg, Ro, Sg, So, eps, Mg=None, 
     mc = mc_all & ~mrw
     pda = (Rg.min(0) == 1) & (Ro.min(0) == 1) & (To.min(0) > 0)
     mg, mo = Tg.mean(0), To.mean(0)
-    se = np.sqrt(Tg.var(0, ddof=1) / Kg + To.var(0, ddof=1) / Ko) / np.where(mo > 0, mo, 1)
+    vg, vo = Tg.var(0, ddof=1) / Kg, To.var(0, ddof=1) / Ko
+    se = np.sqrt(vg + vo) / np.where(mo > 0, mo, 1)
+    den = vg * vg / (Kg - 1) + vo * vo / (Ko - 1)
+    dof = np.where(den > 0, (vg + vo) ** 2 / np.where(den > 0, den, 1), Kg + Ko - 2)
+    q = student_t.ppf(1.0 - 0.5 * TAIL, np.maximum(dof, 1.0))
     rel = np.where(mo > 0, mg / np.where(mo > 0, mo, 1) - 1, 0.0)
     out = {"name": name}
     for label, sel, floor in (("mc", mc, 0.01), ("pda", pda, 0.02), ("mrw", mc_all & mrw, 0.01)):
         if not sel.any():
             out[label] = None
             continue
-        tol = np.maximum(floor, 3 * se[sel])
+        tol = np.maximum(floor, q[sel] * se[sel])
         bad = np.abs(rel[sel]) > tol
         w = mass[sel] / mass[sel].sum()
         s2 = se[sel] ** 2
@@ -110,7 +121,10 @@ def compare_ensembles(name, mass, Tg, To, Vg, Vo, Rg, Ro, Sg, So, eps, Mg=None, 
                           excess=math.sqrt(max(excess2, 0.0)), excess2=excess2,
                           excess2_se=excess2_se,
                           signed=float((w * rel[sel]).sum()),
-                          signed_se=float(np.sqrt((w * w * s2).sum())))
+                          signed_se=float(np.sqrt((w * w * s2).sum())),
+                          failed=[(int(c), round(float(r), 4), round(float(e), 4), round(float(k), 1))
+                                  for c, r, e, k in zip(np.nonzero(sel)[0][bad], rel[sel][bad],
+                                                        se[sel][bad], dof[sel][bad])])
     sg, so = Sg.sum(0) / eps, So.sum(0) / eps       # packets per (bin, inclination)
     big = (sg >= 1e4) & (so >= 1e4)
     srel = sg[big] / so[big] - 1
