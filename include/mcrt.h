@@ -49,6 +49,7 @@ extern "C" {
 #define MCRT_E_SINGULAR_REGION (-6) /* a PDA region part has no Dirichlet neighbour (solved
                                        without it: informational) */
 
+#define MCRT_TAIL_CAP 8192          /* packets the hand-off buffer of a context holds */
 #define MCRT_FP64 0                 /* tracking, tallies and inversion in FP64 */
 #define MCRT_FP32 1                 /* packet geometry in FP32 cell-relative coordinates;
                                        tallies, inversion and PDA in FP64 */
@@ -156,8 +157,8 @@ typedef struct {
                             with g_asym != 0 or j_tally.  0: one event at a time (0) */
   int32_t handoff_live;  /* a single-disk trace hands packets off once at most this many
                             are live; the hand-off launch's wavefronts then take them one
-                            after another (0: as many as it has wavefronts; at most 8192,
-                            the hand-off buffer) (0) */
+                            after another (0: as many as it has wavefronts; at most
+                            MCRT_TAIL_CAP, the hand-off buffer) (0) */
 } mcrt_options;
 
 void mcrt_default_options(mcrt_options* opt);

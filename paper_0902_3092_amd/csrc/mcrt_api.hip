@@ -246,6 +246,8 @@ void mcrt_default_options(mcrt_options* o) {
   o->handoff_live = 0;
 }
 
+static_assert(mcrt::TAIL_CAP == MCRT_TAIL_CAP, "hand-off buffer size as declared");
+
 int mcrt_setup(mcrt_ctx** out, const mcrt_grid* grid, const mcrt_star* star,
                const mcrt_dust* dust, const double* rho, const mcrt_options* opt) {
   if (!out || !grid || !star || !dust || !rho || !opt) return fail(nullptr, MCRT_E_ARG, "null argument");

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmcrt.so")
 _lib = None
 
 OK, E_ARG, E_OOM, E_HIP, E_NOT_CONVERGED, E_STUCK, E_SINGULAR_REGION = 0, -1, -2, -3, -4, -5, -6
+TAIL_CAP = 8192   # packets the hand-off buffer holds (MCRT_TAIL_CAP)
 FP64, FP32 = 0, 1
 GET_E_ABS, GET_VISITS, GET_N_ABS, GET_N_MRW, GET_T, GET_REGION, GET_COUNTERS, GET_E_STAR, \
     GET_TABLES, GET_RHO, GET_HYDRO_COLD, GET_E_HALF, GET_PATH, GET_MRW_PATH = range(14)
