@@ -1,9 +1,9 @@
-"""Early hand-offs: with option handoff_live at the hand-off buffer's capacity,
-packets move to the whole-wavefront launch as soon as the launch's packets
-are all out, and more of them are saved than that launch has wavefronts, so
-they wait in a queue; once the buffer is full the rest stay in the per-lane
-launch.  Every saved packet must be taken exactly once, and each must follow
-the events it follows without hand-offs.
+"""Early hand-offs: a launch of no more packets than option handoff_live (here
+the hand-off buffer's capacity) hands packets to the whole-wavefront launch
+from its start, each once it has taken a few events.  More of them are saved
+than that launch has wavefronts, so they wait in a queue.  Every saved packet
+must be taken exactly once, and each must follow the events it follows
+without hand-offs.
 
 Frozen temperature, the thick test disk: the same packets traced with
 hand-offs off (per lane only) and with early hand-offs give the same records
@@ -46,20 +46,20 @@ def test_early_handoffs_queue_and_follow_the_same_events(mcrt, torch_cuda, preci
     torch = torch_cuda
     d = W.small_disk(M_dust_msun=1e-1, n_r=14, n_mu=10, n_lambda=24)
     Tf = torch.from_numpy(_frozen_field(d)).cuda()
-    n = 60000
+    n = mcrt.TAIL_CAP
     kw = dict(precision=precision, mrw=True, gamma=2.0, n_int_min=5)
     lanes = mcrt.Context(d, wave_events=0, **kw)
     lanes.reset()
     ref = mcrt.Context.records_numpy(lanes.trace(n, 41, frozen_T=Tf, n_recs=n))
-    early = mcrt.Context(d, wave_events=8, handoff_live=mcrt.TAIL_CAP, **kw)
+    early = mcrt.Context(d, wave_events=4, handoff_live=mcrt.TAIL_CAP, **kw)
     early.reset()
     got = mcrt.Context.records_numpy(early.trace(n, 41, frozen_T=Tf, n_recs=n))
     torch.cuda.synchronize()
     c = early.counters()
     print(precision, "handed", c["handed"])
     # more saved packets than the hand-off launch has wavefronts (2048 on a
-    # 256-CU device), so the launch took them from a queue, and a full buffer
-    assert c["handed"] == mcrt.TAIL_CAP
+    # 256-CU device), so the launch took them from a queue
+    assert 2048 < c["handed"] <= n
     assert lanes.counters()["handed"] == 0
     assert np.all(got["fate"] != 0)
     same = same_records(got, ref)
