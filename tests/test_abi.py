@@ -58,3 +58,22 @@ def test_options_struct_matches_header():
         typ, names = decl.split(None, 1)
         fields += [(n.strip(), typ) for n in names.split(",")]
     assert [f for f, _ in fields] == [f for f, _ in mcrt.Options._fields_]
+
+
+def test_header_constants_match_the_binding():
+    """Every #define of include/mcrt.h that the binding mirrors has the same
+    value there: error codes, precisions, what mcrt_get returns, and the
+    hand-off buffer size."""
+    from paper_0902_3092_amd import mcrt
+    text = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in
+            re.finditer(r"^#define MCRT_([A-Z0-9_]+)\s+\(?(-?\d+)\)?", text, flags=re.M)}
+    mirrored = 0
+    for name, value in defs.items():
+        if hasattr(mcrt, name):
+            assert getattr(mcrt, name) == value, name
+            mirrored += 1
+    for name in ("OK", "E_ARG", "E_STUCK", "E_SINGULAR_REGION", "FP32", "TAIL_CAP", "GET_E_ABS",
+                 "GET_RHO", "GET_TABLES", "GET_MRW_PATH"):
+        assert name in defs and hasattr(mcrt, name), name
+    assert mirrored >= 20
