@@ -200,6 +200,8 @@ def parse():
                         "launch's wavefronts)")
     p.add_argument("--runahead", type=int, default=-1,
                    help="override wave_runahead of the timed step (0 or 1)")
+    p.add_argument("--block-size", type=int, default=-1,
+                   help="override block_size of the timed step (0, 256, 512, 768)")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="only copy this many MiB device to device once (a plain copy kernel of "
                         "known size, to scale the HBM byte counters) and exit")
@@ -1008,6 +1010,8 @@ def main():
         t_opts["handoff_live"] = a.handoff_live
     if a.runahead >= 0:
         t_opts["wave_runahead"] = a.runahead
+    if a.block_size >= 0:
+        t_opts["block_size"] = a.block_size
     ctx = mcrt.Context(disk, **phys, **t_opts)
     stream = torch.cuda.current_stream()
 
