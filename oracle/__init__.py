@@ -126,6 +126,8 @@ def lib():
         L.ora_mean_intensity.restype = None
         L.ora_raytrace_sed.argtypes = [vp, vp, vp, vp, C.c_int, vp, C.c_int, C.c_int, vp]
         L.ora_raytrace_sed.restype = None
+        L.ora_raytrace_image.argtypes = [vp, vp, vp, vp, C.c_int, vp, C.c_int, C.c_int, vp]
+        L.ora_raytrace_image.restype = None
         L.ora_conv_stat.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.ora_conv_stat.restype = None
         L.ora_cell_volumes.argtypes = [vp, vp]
@@ -294,6 +296,19 @@ class Oracle:
         lib().ora_raytrace_sed(C.byref(self.model), C.byref(self.tables), _p(T),
                                _p(Jc) if Jc is not None else None, len(ci), _p(ci), int(n_sub),
                                int(n_phi), _p(out))
+        return out
+
+    def raytrace_image(self, T, J=None, cos_i=(0.7071067811865476,), n_sub: int = 4,
+                       n_phi: int = 16) -> np.ndarray:
+        """Intensity per ray and bin [n_inc, (n_r + 1) n_sub, n_phi, n_lambda]
+        of the ray set of raytrace_sed, without the star."""
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        ci = np.ascontiguousarray(cos_i, dtype=np.float64)
+        Jc = None if J is None else np.ascontiguousarray(J, dtype=np.float64)
+        out = np.empty((len(ci), (self.n_r + 1) * n_sub, n_phi, self.n_lambda))
+        lib().ora_raytrace_image(C.byref(self.model), C.byref(self.tables), _p(T),
+                                 _p(Jc) if Jc is not None else None, len(ci), _p(ci),
+                                 int(n_sub), int(n_phi), _p(out))
         return out
 
     def conv_stat(self, state, T_prev, s2_prev, n_min: int = 100):

@@ -795,8 +795,9 @@ static int cmp_double(const void* a, const void* b) {
  * pi (b_hi^2 - b_lo^2) / n_phi.  The star adds its luminosity per bin (the
  * spectrum the packets are launched with) times e^(-tau) along the line of
  * sight from its centre.  out [n_inc][n_lambda]. */
-void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, const double* J,
-                      int n_inc, const double* cos_i, int n_sub, int n_phi, double* out) {
+static void raytrace(const ora_model* m, const ora_tables* t, const double* T, const double* J,
+                     int n_inc, const double* cos_i, int n_sub, int n_phi, double* out,
+                     double* img) {
   const int nl = m->n_lambda, nr = m->n_r, nmu = m->n_mu, nc = nr * nmu;
   double* S = (double*)malloc(sizeof(double) * (size_t)nc * nl);
   double* Bb = (double*)malloc(sizeof(double) * nl);
@@ -816,8 +817,9 @@ void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, 
     const double n[3] = {si, 0.0, ci};      /* towards the observer */
     const double e1[3] = {ci, 0.0, -si};    /* image plane */
     const double e2[3] = {0.0, 1.0, 0.0};
-    double* L = out + (size_t)q * nl;
-    for (int k = 0; k < nl; ++k) L[k] = 0.0;
+    double* L = out ? out + (size_t)q * nl : NULL;
+    if (L)
+      for (int k = 0; k < nl; ++k) L[k] = 0.0;
     for (int ring = 0; ring < (nr + 1) * n_sub; ++ring) {
       const int cell = ring / n_sub, part = ring % n_sub;
       const double lo = cell == 0 ? 0.0 : m->r_edges[cell - 1];
@@ -845,9 +847,15 @@ void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, 
             I[k] = I[k] * at + S[(size_t)c * nl + k] * (1.0 - at);
           }
         }
-        for (int k = 0; k < nl; ++k) L[k] += 4.0 * PI * I[k] * area;
+        if (img) {
+          double* dst = img + (((size_t)q * (nr + 1) * n_sub + ring) * n_phi + ph) * nl;
+          for (int k = 0; k < nl; ++k) dst[k] = I[k];
+        }
+        if (L)
+          for (int k = 0; k < nl; ++k) L[k] += 4.0 * PI * I[k] * area;
       }
     }
+    if (!L) continue;
     /* the star, through the cells along the line of sight from its centre */
     const double zero[3] = {0.0, 0.0, 0.0};
     int nx = ray_crossings(m, zero, n, cr);
@@ -866,6 +874,20 @@ void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, 
     }
   }
   free(S); free(Bb); free(dBb); free(I); free(cr);
+}
+
+void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, const double* J,
+                      int n_inc, const double* cos_i, int n_sub, int n_phi, double* out) {
+  raytrace(m, t, T, J, n_inc, cos_i, n_sub, n_phi, out, NULL);
+}
+
+/* The image behind the same rays: the intensity each ray reaches the observer
+ * with (erg s^-1 cm^-2 sr^-1 per bin), without the star.
+ * img [n_inc][(n_r + 1) n_sub][n_phi][n_lambda]. */
+void ora_raytrace_image(const ora_model* m, const ora_tables* t, const double* T,
+                        const double* J, int n_inc, const double* cos_i, int n_sub, int n_phi,
+                        double* img) {
+  raytrace(m, t, T, J, n_inc, cos_i, n_sub, n_phi, NULL, img);
 }
 
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {

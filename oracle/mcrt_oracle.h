@@ -117,6 +117,13 @@ void ora_mean_intensity(const ora_model* m, const double* T, const double* path,
 void ora_raytrace_sed(const ora_model* m, const ora_tables* t, const double* T, const double* J,
                       int n_inc, const double* cos_i, int n_sub, int n_phi, double* out);
 
+/* The intensity per ray and bin of the same ray set, without the star
+ * (Sect. 3.3: images from the source function), img
+ * [n_inc][(n_r + 1) n_sub][n_phi][n_lambda]. */
+void ora_raytrace_image(const ora_model* m, const ora_tables* t, const double* T,
+                        const double* J, int n_inc, const double* cos_i, int n_sub, int n_phi,
+                        double* img);
+
 /* Convergence statistic of the vertical-structure loop from one pass's
  * tallies (E_half: the odd-numbered packets' share; visits: packets entering
  * each cell, >= n_min to take part) against the previous pass's T_prev and

@@ -13,6 +13,7 @@ import test_oracle_deposit_launch_picard as P  # noqa: E402
 import test_oracle_convergence as CV  # noqa: E402
 import test_oracle_raytrace as RT  # noqa: E402
 import test_oracle_pda_nl as NL  # noqa: E402
+import test_oracle_raytrace_image as IM  # noqa: E402
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "mcrt_oracle.c")
 
@@ -60,6 +61,13 @@ MUTANTS = {
     "nl_dRdu_sign": (
         "      dRdu[c] = -R[c] * t_slope(t, t->Drho, T) / Drho * T / (4.0 * u[c]);",
         "      dRdu[c] = R[c] * t_slope(t, t->Drho, T) / Drho * T / (4.0 * u[c]);"),
+    # the image stores the rays azimuth-major instead of ring-major
+    "image_layout_swapped": (
+        "          double* dst = img + (((size_t)q * (nr + 1) * n_sub + ring) * n_phi + ph) * nl;",
+        "          double* dst = img + (((size_t)q * n_phi + ph) * (nr + 1) * n_sub + ring) * nl;"),
+    # the image plane's first axis leaves out the tilt of the pole
+    "image_axis_untilted": ("    const double e1[3] = {ci, 0.0, -si};    /* image plane */",
+                            "    const double e1[3] = {0.0, 0.0, -1.0};    /* image plane */"),
 }
 
 PIN = {
@@ -79,6 +87,8 @@ PIN = {
         lambda o: NL.test_nonlinear_gradient_matches_finite_differences(o, "logrho", True),
     "nl_dRdu_sign":
         lambda o: NL.test_nonlinear_gradient_matches_finite_differences(o, "logrho", False),
+    "image_layout_swapped": lambda o: IM.test_isothermal_shell_image_is_the_chord_law(o),
+    "image_axis_untilted": lambda o: IM.test_pole_on_image_is_axisymmetric(o),
 }
 
 
