@@ -474,6 +474,23 @@ int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, i
                       const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* L_dev,
                       hipStream_t stream);
 
+/* Ray-traced images (Sect. 3.3: images among the observables from the source
+ * function, the Monte Carlo T before the PDA): the intensity with which each
+ * ray of mcrt_raytrace_sed's ray set reaches the observer, per bin
+ * (erg s^-1 cm^-2 sr^-1 integrated over the bin), without the star.  Same
+ * arguments, source function and formal solution as mcrt_raytrace_sed.
+ * I_dev [n_inc][(n_r + 1) n_sub][n_phi][n_lambda] double, overwritten: ray
+ * (q, ring, p) looks along cos(inclination) cos_i[q] at impact parameter b =
+ * the mid radius of ring `ring` (ring = c n_sub + part: c = 0 the hole
+ * [0, r_0], c >= 1 the radial cell [r_(c-1), r_c], cut into n_sub equal
+ * rings) and position angle phi = (p + 1/2) pi / n_phi from the projected
+ * pole, towards +y; the mirror image (-phi) has the same intensity.  Sum of
+ * 4 pi I pi (b_hi^2 - b_lo^2) / n_phi over the rays, plus the dimmed star, is
+ * mcrt_raytrace_sed.  Asynchronous.  Errors: as mcrt_raytrace_sed. */
+int mcrt_raytrace_image(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
+                        const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* I_dev,
+                        hipStream_t stream);
+
 /* Outcome of mcrt_batch_converge for one disk. */
 typedef struct {
   int32_t passes;          /* passes run */

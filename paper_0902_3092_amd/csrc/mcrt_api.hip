@@ -159,6 +159,9 @@ void set_error(mcrt_ctx* ctx, const std::string& msg) {
   g_last_error = msg;
 }
 int launch_trace_fp64(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
+int launch_raytrace_image(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
+                          const double* cos_i_host, int n_sub, int n_phi, double* img,
+                          hipStream_t s);
 int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
 
 TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
@@ -760,10 +763,12 @@ int mcrt_mean_intensity(mcrt_ctx* ctx, const double* T_dev, double* J_dev, hipSt
   return rc ? fail(ctx, rc, "mean intensity launch failed") : MCRT_OK;
 }
 
-int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
-                      const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* L_dev,
-                      hipStream_t stream) {
-  if (!ctx || !L_dev || !cos_i_host) return fail(ctx, MCRT_E_ARG, "null argument");
+namespace {
+// Checks shared by the ray-traced spectrum and image; allocates the
+// context's source-function buffer on first use.
+int raytrace_checks(mcrt_ctx* ctx, const double* out, const double* cos_i_host, int32_t n_inc,
+                    int32_t n_sub, int32_t n_phi) {
+  if (!ctx || !out || !cos_i_host) return fail(ctx, MCRT_E_ARG, "null argument");
   if (n_inc < 1 || n_sub < 1 || n_phi < 1) return fail(ctx, MCRT_E_ARG, "n_inc, n_sub, n_phi >= 1");
   for (int q = 0; q < n_inc; ++q)
     if (!(cos_i_host[q] >= 0.0 && cos_i_host[q] <= 1.0))
@@ -776,8 +781,27 @@ int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, i
     ctx->d_src = nullptr;
     return fail(ctx, MCRT_E_OOM, "source-function buffer");
   }
-  int rc = mcrt::launch_raytrace(ctx, T_dev ? T_dev : ctx->d_T, J_dev, n_inc, cos_i_host, n_sub,
-                                 n_phi, L_dev, stream);
+  return MCRT_OK;
+}
+}  // namespace
+
+int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
+                      const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* L_dev,
+                      hipStream_t stream) {
+  int rc = raytrace_checks(ctx, L_dev, cos_i_host, n_inc, n_sub, n_phi);
+  if (rc) return rc;
+  rc = mcrt::launch_raytrace(ctx, T_dev ? T_dev : ctx->d_T, J_dev, n_inc, cos_i_host, n_sub,
+                             n_phi, L_dev, stream);
+  return rc ? fail(ctx, rc, "ray tracing launch failed") : MCRT_OK;
+}
+
+int mcrt_raytrace_image(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
+                        const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* I_dev,
+                        hipStream_t stream) {
+  int rc = raytrace_checks(ctx, I_dev, cos_i_host, n_inc, n_sub, n_phi);
+  if (rc) return rc;
+  rc = mcrt::launch_raytrace_image(ctx, T_dev ? T_dev : ctx->d_T, J_dev, n_inc, cos_i_host,
+                                   n_sub, n_phi, I_dev, stream);
   return rc ? fail(ctx, rc, "ray tracing launch failed") : MCRT_OK;
 }
 

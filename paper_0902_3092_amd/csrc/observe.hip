@@ -136,10 +136,13 @@ struct RayGeom {
 
 // One wavefront per ray: ring (hole and radial cells, n_sub each), azimuth,
 // inclination from the ray index; traversal from the far side of the outer
-// sphere to the near one; each lane holds bins lane, lane + 64, ...
+// sphere to the near one; each lane holds bins lane, lane + 64, ...  The
+// ray's intensity goes into the spectrum L (4 pi I times its area), or, for
+// an image, to img[ray][bin].
 __global__ void __launch_bounds__(RAY_BS) ray_kernel(DevModel M, RayGeom G,
                                                      const double* __restrict__ S,
-                                                     double* __restrict__ L) {
+                                                     double* __restrict__ L,
+                                                     double* __restrict__ img) {
   const int lane = __lane_id();
   const long long ray = (long long)blockIdx.x * (RAY_BS / 64) + threadIdx.x / 64;
   const long long per_inc = (long long)G.n_rings * G.n_phi;
@@ -229,7 +232,9 @@ __global__ void __launch_bounds__(RAY_BS) ray_kernel(DevModel M, RayGeom G,
   }
   for (int m = 0; m < nq; ++m) {
     const int k = lane + 64 * m;
-    if (k < nl && I[m] != 0.0) unsafeAtomicAdd(&L[(size_t)q * nl + k], 4.0 * KPI * I[m] * area);
+    if (k >= nl) continue;
+    if (img) img[(size_t)ray * nl + k] = I[m];
+    else if (I[m] != 0.0) unsafeAtomicAdd(&L[(size_t)q * nl + k], 4.0 * KPI * I[m] * area);
   }
 }
 
@@ -259,8 +264,12 @@ int launch_mean_intensity(mcrt_ctx* ctx, const double* T, double* J, hipStream_t
   return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
 }
 
-int launch_raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
-                    const double* cos_i_host, int n_sub, int n_phi, double* L, hipStream_t s) {
+namespace {
+// The spectrum (L: per inclination and bin, with the star) or the image
+// (img: per ray and bin, without it) of the same rays.
+int raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
+             const double* cos_i_host, int n_sub, int n_phi, double* L, double* img,
+             hipStream_t s) {
   const DevModel& M = ctx->m;
   if (M.n_lambda > MAX_BINS) {
     set_error(ctx, "the ray tracer holds at most 512 bins");
@@ -273,8 +282,10 @@ int launch_raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
   const long long cells_bins = (long long)ctx->n_cells * M.n_lambda;
   hipLaunchKernelGGL(source_kernel, dim3((unsigned)((cells_bins + 255) / 256)), dim3(256), 0, s,
                      M, T, J, ctx->d_src, ctx->n_cells);
-  int rc = launch_zero(L, (size_t)n_inc * M.n_lambda * sizeof(double), s);
-  if (rc) return rc;
+  if (L) {
+    int rc = launch_zero(L, (size_t)n_inc * M.n_lambda * sizeof(double), s);
+    if (rc) return rc;
+  }
   RayGeom G{};
   G.n_inc = n_inc;
   G.n_rings = (M.n_r + 1) * n_sub;
@@ -283,9 +294,21 @@ int launch_raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
   for (int q = 0; q < n_inc; ++q) G.cos_i[q] = cos_i_host[q];
   const long long rays = (long long)n_inc * G.n_rings * n_phi;
   hipLaunchKernelGGL(ray_kernel, dim3((unsigned)((rays + 3) / 4)), dim3(RAY_BS), 0, s, M, G,
-                     ctx->d_src, L);
-  hipLaunchKernelGGL(star_kernel, dim3(n_inc), dim3(64), 0, s, M, G, L);
+                     ctx->d_src, img ? nullptr : L, img);
+  if (!img) hipLaunchKernelGGL(star_kernel, dim3(n_inc), dim3(64), 0, s, M, G, L);
   return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
+}  // namespace
+
+int launch_raytrace(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
+                    const double* cos_i_host, int n_sub, int n_phi, double* L, hipStream_t s) {
+  return raytrace(ctx, T, J, n_inc, cos_i_host, n_sub, n_phi, L, nullptr, s);
+}
+
+int launch_raytrace_image(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
+                          const double* cos_i_host, int n_sub, int n_phi, double* img,
+                          hipStream_t s) {
+  return raytrace(ctx, T, J, n_inc, cos_i_host, n_sub, n_phi, nullptr, img, s);
 }
 
 }  // namespace mcrt

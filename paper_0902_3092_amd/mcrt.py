@@ -31,7 +31,7 @@ EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "
            "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_pda_solve_noalloc",
            "mcrt_batch_pda", "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity",
            "mcrt_raytrace_sed", "mcrt_region_mask", "mcrt_pda_nonlinear",
-           "mcrt_pda_nonlinear_adjoint"]
+           "mcrt_pda_nonlinear_adjoint", "mcrt_raytrace_image"]
 
 
 class McrtError(RuntimeError):
@@ -129,6 +129,7 @@ def lib():
         L.mcrt_mean_intensity.argtypes = [vp, vp, vp, vp]
         L.mcrt_region_mask.argtypes = [vp, i32, C.c_double, vp, vp]
         L.mcrt_raytrace_sed.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
+        L.mcrt_raytrace_image.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
         L.mcrt_batch_converge.argtypes = [vp, C.c_int, vp, vp, C.c_int, i32, C.c_double, C.c_int,
                                           vp, vp, vp, vp]
         _lib = L
@@ -349,6 +350,20 @@ class Context:
         _check(lib().mcrt_raytrace_sed(self.handle, _ptr(T), _ptr(J), len(cos_i), ci, int(n_sub),
                                        int(n_phi), _ptr(L), _stream(stream)), "mcrt_raytrace_sed")
         return L
+
+    def raytrace_image(self, T=None, J=None, cos_i=(0.7071067811865476,), n_sub: int = 4,
+                       n_phi: int = 16, stream=None):
+        """mcrt_raytrace_image: the intensity per ray and bin
+        [n_inc, (n_r + 1) n_sub, n_phi, n_lambda] of raytrace_sed's rays,
+        without the star."""
+        import torch
+        ci = (C.c_double * len(cos_i))(*[float(x) for x in cos_i])
+        img = torch.empty((len(cos_i), (self.n_r + 1) * int(n_sub), int(n_phi), self.n_lambda),
+                          dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_raytrace_image(self.handle, _ptr(T), _ptr(J), len(cos_i), ci,
+                                         int(n_sub), int(n_phi), _ptr(img), _stream(stream)),
+               "mcrt_raytrace_image")
+        return img
 
     def set_T(self, T, stream=None):
         _check(lib().mcrt_set_T(self.handle, _ptr(T), _stream(stream)), "mcrt_set_T")

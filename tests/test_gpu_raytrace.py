@@ -6,7 +6,10 @@
   (MRW on, so the walk's path and its spectrum weights are covered);
 * the ray-traced SED from the same temperature and mean intensity, at three
   inclinations, ray for ray the same quadrature;
-* the optically thin isothermal shell against its closed form.
+* the optically thin isothermal shell against its closed form;
+* the ray-traced image (the intensity of every ray) of the same disk and of
+  the 1e-2 Msun workload's grid, ray for ray against the oracle, and summed
+  with the rays' areas against the ray-traced SED.
 """
 import math
 import os
@@ -176,3 +179,65 @@ def test_raytrace_thin_shell_closed_form(mcrt, oracle_mod, torch_cuda):
     for q in range(3):
         got = L[q] - star
         assert np.allclose(got[big], dust[big], rtol=2e-3, atol=0)
+
+
+def _ray_inputs(ora, d):
+    T = _field(d)
+    nodes = ora.T_nodes
+    idx = np.clip(np.searchsorted(nodes, T) - 1, 0, len(nodes) - 1)
+    kB = np.diff(np.concatenate([np.zeros((len(nodes), 1)), ora.cdf], axis=1), axis=1)
+    J = np.ascontiguousarray(0.3 * kB[idx] / d.kappa_abs[0][None, :])
+    return T, J
+
+
+def test_raytrace_image_matches_oracle(mcrt, oracle_mod, torch_cuda):
+    """The disk, temperature and scattering source of the SED test: every ray's
+    intensity at three inclinations against the oracle's, and the image summed
+    over its rays (4 pi I times the area each ray carries) plus the dimmed star
+    against the ray-traced SED of the same rays."""
+    torch = torch_cuda
+    d = W.make_disk("ray", M_dust_msun=1e-3, n_r=30, n_mu=20, n_lambda=30)
+    ora = oracle_mod.Oracle(d)
+    ctx = mcrt.Context(d)
+    T, J = _ray_inputs(ora, d)
+    ci = [0.05, 0.5, 0.95]
+    n_sub, n_phi = 2, 8
+    Io = ora.raytrace_image(T, J=J, cos_i=ci, n_sub=n_sub, n_phi=n_phi)
+    Tg, Jg = torch.from_numpy(T).cuda(), torch.from_numpy(J).cuda()
+    Ig = ctx.raytrace_image(Tg, Jg, cos_i=ci, n_sub=n_sub, n_phi=n_phi).cpu().numpy()
+    assert Ig.shape == Io.shape == (3, (d.n_r + 1) * n_sub, n_phi, d.n_lambda)
+    scale = np.abs(Io).max()
+    big = Io > 1e-12 * scale
+    assert big.mean() > 0.3
+    assert np.allclose(Ig[big], Io[big], rtol=1e-8, atol=0), np.max(np.abs(Ig[big] / Io[big] - 1))
+    assert np.all(np.abs(Ig[~big]) <= 1e-10 * scale)
+    # summed with the rays' areas: the SED without the star, which is at
+    # most the star's own luminosity per bin
+    from test_oracle_raytrace_image import ring_radii
+    _, area = ring_radii(d.r_edges, n_sub)
+    dust = 4 * math.pi * np.einsum("qrpk,r->qk", Ig, area / n_phi)
+    L = ctx.raytrace_sed(Tg, Jg, cos_i=ci, n_sub=n_sub, n_phi=n_phi).cpu().numpy()
+    share = np.diff(np.concatenate([[0.0], ctx.tables()["star_cdf"]]))
+    star = L - dust
+    assert np.all(star >= -1e-9 * L)
+    assert np.all(star <= ctx.tables()["L_star"] * share * (1 + 1e-9))
+
+
+def test_raytrace_image_full_grid(mcrt, oracle_mod, torch_cuda):
+    """The 1e-2 Msun workload's grid (100 x 60 cells, 100 bins) seen at 45
+    degrees, no scattering source: the image ray for ray against the oracle."""
+    torch = torch_cuda
+    d, _ = W.config("mrw_pda")
+    ora = oracle_mod.Oracle(d)
+    ctx = mcrt.Context(d)
+    T = _field(d)
+    ci, n_sub, n_phi = [0.7071067811865476], 2, 12
+    Io = ora.raytrace_image(T, cos_i=ci, n_sub=n_sub, n_phi=n_phi)
+    Ig = ctx.raytrace_image(torch.from_numpy(T).cuda(), cos_i=ci, n_sub=n_sub,
+                            n_phi=n_phi).cpu().numpy()
+    scale = np.abs(Io).max()
+    big = Io > 1e-12 * scale
+    assert big.mean() > 0.3
+    assert np.allclose(Ig[big], Io[big], rtol=1e-8, atol=0), np.max(np.abs(Ig[big] / Io[big] - 1))
+    assert np.all(np.abs(Ig[~big]) <= 1e-10 * scale)
+
