@@ -128,6 +128,9 @@ def lib():
         L.ora_raytrace_sed.restype = None
         L.ora_raytrace_image.argtypes = [vp, vp, vp, vp, C.c_int, vp, C.c_int, C.c_int, vp]
         L.ora_raytrace_image.restype = None
+        L.ora_visibility.argtypes = [vp, vp, vp, C.c_int, vp, C.c_int, C.c_int, C.c_int, vp,
+                                     C.c_double, vp]
+        L.ora_visibility.restype = None
         L.ora_conv_stat.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.ora_conv_stat.restype = None
         L.ora_cell_volumes.argtypes = [vp, vp]
@@ -309,6 +312,19 @@ class Oracle:
         lib().ora_raytrace_image(C.byref(self.model), C.byref(self.tables), _p(T),
                                  _p(Jc) if Jc is not None else None, len(ci), _p(ci),
                                  int(n_sub), int(n_phi), _p(out))
+        return out
+
+    def visibility(self, img, cos_i, n_sub: int, n_phi: int, baselines, distance: float):
+        """Visibility amplitudes [n_inc, n_base, n_lambda] of an image from
+        raytrace_image (same cos_i, n_sub, n_phi) with the dimmed star;
+        baselines [n_base, 2]: length (cm), position angle (rad)."""
+        img = np.ascontiguousarray(img, dtype=np.float64)
+        ci = np.ascontiguousarray(cos_i, dtype=np.float64)
+        bl = np.ascontiguousarray(baselines, dtype=np.float64).reshape(-1, 2)
+        assert img.shape == (len(ci), (self.n_r + 1) * n_sub, n_phi, self.n_lambda)
+        out = np.empty((len(ci), len(bl), self.n_lambda))
+        lib().ora_visibility(C.byref(self.model), C.byref(self.tables), _p(img), len(ci), _p(ci),
+                             int(n_sub), int(n_phi), len(bl), _p(bl), float(distance), _p(out))
         return out
 
     def conv_stat(self, state, T_prev, s2_prev, n_min: int = 100):

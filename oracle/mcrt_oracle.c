@@ -795,6 +795,28 @@ static int cmp_double(const void* a, const void* b) {
  * pi (b_hi^2 - b_lo^2) / n_phi.  The star adds its luminosity per bin (the
  * spectrum the packets are launched with) times e^(-tau) along the line of
  * sight from its centre.  out [n_inc][n_lambda]. */
+/* The star's luminosity per bin (the spectrum the packets are launched
+ * with) times e^(-tau) along the line of sight n from its centre; cr is
+ * scratch for the crossings. */
+static void star_dimmed(const ora_model* m, const ora_tables* t, const double n[3], double* cr,
+                        double* out) {
+  const double zero[3] = {0.0, 0.0, 0.0};
+  int nx = ray_crossings(m, zero, n, cr);
+  qsort(cr, nx, sizeof(double), cmp_double);
+  for (int k = 0; k < m->n_lambda; ++k) {
+    double tau = 0.0;
+    for (int g = 0; g + 1 < nx; ++g) {
+      const double len = cr[g + 1] - cr[g];
+      const double sm = 0.5 * (cr[g] + cr[g + 1]);
+      if (!(len > 0.0) || sm <= 0.0) continue;
+      const int64_t c = ora_locate(m, sm * n[0], sm * n[1], sm * n[2]);
+      if (c >= 0) tau += m->rho[c] * (m->kappa_abs[k] + m->kappa_sca[k]) * len;
+    }
+    const double share = t->star_cdf[k] - (k ? t->star_cdf[k - 1] : 0.0);
+    out[k] = t->L_star * share * exp(-tau);
+  }
+}
+
 static void raytrace(const ora_model* m, const ora_tables* t, const double* T, const double* J,
                      int n_inc, const double* cos_i, int n_sub, int n_phi, double* out,
                      double* img) {
@@ -857,21 +879,8 @@ static void raytrace(const ora_model* m, const ora_tables* t, const double* T, c
     }
     if (!L) continue;
     /* the star, through the cells along the line of sight from its centre */
-    const double zero[3] = {0.0, 0.0, 0.0};
-    int nx = ray_crossings(m, zero, n, cr);
-    qsort(cr, nx, sizeof(double), cmp_double);
-    for (int k = 0; k < nl; ++k) {
-      double tau = 0.0;
-      for (int g = 0; g + 1 < nx; ++g) {
-        const double len = cr[g + 1] - cr[g];
-        const double sm = 0.5 * (cr[g] + cr[g + 1]);
-        if (!(len > 0.0) || sm <= 0.0) continue;
-        const int64_t c = ora_locate(m, sm * n[0], sm * n[1], sm * n[2]);
-        if (c >= 0) tau += m->rho[c] * (m->kappa_abs[k] + m->kappa_sca[k]) * len;
-      }
-      const double share = t->star_cdf[k] - (k ? t->star_cdf[k - 1] : 0.0);
-      L[k] += t->L_star * share * exp(-tau);
-    }
+    star_dimmed(m, t, n, cr, I);
+    for (int k = 0; k < nl; ++k) L[k] += I[k];
   }
   free(S); free(Bb); free(dBb); free(I); free(cr);
 }
@@ -888,6 +897,65 @@ void ora_raytrace_image(const ora_model* m, const ora_tables* t, const double* T
                         const double* J, int n_inc, const double* cos_i, int n_sub, int n_phi,
                         double* img) {
   raytrace(m, t, T, J, n_inc, cos_i, n_sub, n_phi, NULL, img);
+}
+
+/* Visibility amplitudes of a ray-traced image (Sect. 3.4 shows visibility
+ * curves: the normalised Fourier transform of the image at the spatial
+ * frequency of a baseline), with the star as a point at the centre.  img is
+ * ora_raytrace_image's [n_inc][(n_r + 1) n_sub][n_phi][n_lambda]; ray
+ * (ring, p) sits at b (cos phi e1 + sin phi e2), e1 = (cos i, 0, -sin i),
+ * e2 = (0, 1, 0), phi = (p + 1/2) pi / n_phi, and stands also for its mirror
+ * image at -phi; each of the two carries half of pi (b_hi^2 - b_lo^2) / n_phi.
+ * Baseline j: length base[2 j] (cm), position angle base[2 j + 1] (radians
+ * from e1 towards e2).  At the distance D (cm), bin k is sampled at the
+ * spatial frequency s = B / (lambda_k D) cycles per cm of the image plane,
+ * lambda_k the bin's geometric centre:
+ *   V = |sum A I e^(-2 pi i s (x cos theta + y sin theta)) + L_star,k / (4 pi)|
+ *       / (sum A I + L_star,k / (4 pi)),
+ * L_star,k the star dimmed along the line of sight.  V [n_inc][n_base][n_lambda]. */
+void ora_visibility(const ora_model* m, const ora_tables* t, const double* img, int n_inc,
+                    const double* cos_i, int n_sub, int n_phi, int n_base, const double* base,
+                    double distance, double* V) {
+  const int nl = m->n_lambda, nr = m->n_r, nmu = m->n_mu;
+  const int n_rings = (nr + 1) * n_sub;
+  double* star = (double*)malloc(sizeof(double) * nl);
+  double* cr = (double*)malloc(sizeof(double) * (2 * (nr + 1) + 2 * nmu + 2));
+  for (int q = 0; q < n_inc; ++q) {
+    const double ci = cos_i[q], si = sqrt(fmax(0.0, 1.0 - ci * ci));
+    const double n[3] = {si, 0.0, ci};
+    star_dimmed(m, t, n, cr, star);
+    for (int j = 0; j < n_base; ++j) {
+      const double B = base[2 * j], th = base[2 * j + 1];
+      for (int k = 0; k < nl; ++k) {
+        const double lam = sqrt(m->lambda_edges[k] * m->lambda_edges[k + 1]);
+        const double sf = B / (lam * distance);
+        double re = star[k] / (4.0 * PI), im = 0.0, tot = star[k] / (4.0 * PI);
+        for (int ring = 0; ring < n_rings; ++ring) {
+          const int cell = ring / n_sub, part = ring % n_sub;
+          const double lo = cell == 0 ? 0.0 : m->r_edges[cell - 1];
+          const double hi = m->r_edges[cell];
+          const double b_lo = lo + (hi - lo) * part / n_sub;
+          const double b_hi = lo + (hi - lo) * (part + 1) / n_sub;
+          const double bm = 0.5 * (b_lo + b_hi);
+          const double half = 0.5 * PI * (b_hi * b_hi - b_lo * b_lo) / n_phi;
+          for (int p = 0; p < n_phi; ++p) {
+            const double phi = (p + 0.5) * PI / n_phi;
+            const double x = bm * cos(phi), y = bm * sin(phi);
+            const double Iv = img[(((size_t)q * n_rings + ring) * n_phi + p) * nl + k];
+            for (int mirror = 0; mirror < 2; ++mirror) {
+              const double yy = mirror ? -y : y;
+              const double arg = -2.0 * PI * sf * (x * cos(th) + yy * sin(th));
+              re += half * Iv * cos(arg);
+              im += half * Iv * sin(arg);
+              tot += half * Iv;
+            }
+          }
+        }
+        V[((size_t)q * n_base + j) * nl + k] = tot > 0.0 ? sqrt(re * re + im * im) / tot : 0.0;
+      }
+    }
+  }
+  free(star); free(cr);
 }
 
 void ora_update_T(const ora_model* m, const ora_tables* t, const double* E_abs, double* T) {

@@ -124,6 +124,13 @@ void ora_raytrace_image(const ora_model* m, const ora_tables* t, const double* T
                         const double* J, int n_inc, const double* cos_i, int n_sub, int n_phi,
                         double* img);
 
+/* Visibility amplitudes [n_inc][n_base][n_lambda] of such an image and the
+ * dimmed star, for baselines base [n_base][2] (length cm, position angle rad)
+ * at distance D (cm). */
+void ora_visibility(const ora_model* m, const ora_tables* t, const double* img, int n_inc,
+                    const double* cos_i, int n_sub, int n_phi, int n_base, const double* base,
+                    double distance, double* V);
+
 /* Convergence statistic of the vertical-structure loop from one pass's
  * tallies (E_half: the odd-numbered packets' share; visits: packets entering
  * each cell, >= n_min to take part) against the previous pass's T_prev and

@@ -14,6 +14,7 @@ import test_oracle_convergence as CV  # noqa: E402
 import test_oracle_raytrace as RT  # noqa: E402
 import test_oracle_pda_nl as NL  # noqa: E402
 import test_oracle_raytrace_image as IM  # noqa: E402
+import test_oracle_visibility as VI  # noqa: E402
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "mcrt_oracle.c")
 
@@ -68,6 +69,9 @@ MUTANTS = {
     # the image plane's first axis leaves out the tilt of the pole
     "image_axis_untilted": ("    const double e1[3] = {ci, 0.0, -si};    /* image plane */",
                             "    const double e1[3] = {0.0, 0.0, -1.0};    /* image plane */"),
+    # the visibility forgets the mirror images of the rays
+    "visibility_no_mirror": ("            for (int mirror = 0; mirror < 2; ++mirror) {",
+                             "            for (int mirror = 0; mirror < 1; ++mirror) {"),
 }
 
 PIN = {
@@ -89,6 +93,7 @@ PIN = {
         lambda o: NL.test_nonlinear_gradient_matches_finite_differences(o, "logrho", False),
     "image_layout_swapped": lambda o: IM.test_isothermal_shell_image_is_the_chord_law(o),
     "image_axis_untilted": lambda o: IM.test_pole_on_image_is_axisymmetric(o),
+    "visibility_no_mirror": lambda o: VI.test_ring_is_a_bessel_function(o),
 }
 
 
