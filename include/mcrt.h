@@ -480,16 +480,39 @@ int mcrt_raytrace_sed(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, i
  * (erg s^-1 cm^-2 sr^-1 integrated over the bin), without the star.  Same
  * arguments, source function and formal solution as mcrt_raytrace_sed.
  * I_dev [n_inc][(n_r + 1) n_sub][n_phi][n_lambda] double, overwritten: ray
- * (q, ring, p) looks along cos(inclination) cos_i[q] at impact parameter b =
- * the mid radius of ring `ring` (ring = c n_sub + part: c = 0 the hole
- * [0, r_0], c >= 1 the radial cell [r_(c-1), r_c], cut into n_sub equal
- * rings) and position angle phi = (p + 1/2) pi / n_phi from the projected
- * pole, towards +y; the mirror image (-phi) has the same intensity.  Sum of
+ * (q, ring, p) runs towards the observer along n = (sin i, 0, cos i),
+ * cos i = cos_i[q], through b (cos phi e1 + sin phi e2), e1 = (cos i, 0,
+ * -sin i), e2 = (0, 1, 0), with b the mid radius of ring `ring` (ring =
+ * c n_sub + part: c = 0 the hole [0, r_0], c >= 1 the radial cell
+ * [r_(c-1), r_c], cut into n_sub equal rings) and phi = (p + 1/2) pi / n_phi;
+ * the mirror image (-phi) has the same intensity.  Sum of
  * 4 pi I pi (b_hi^2 - b_lo^2) / n_phi over the rays, plus the dimmed star, is
  * mcrt_raytrace_sed.  Asynchronous.  Errors: as mcrt_raytrace_sed. */
 int mcrt_raytrace_image(mcrt_ctx* ctx, const double* T_dev, const double* J_dev, int32_t n_inc,
                         const double* cos_i_host, int32_t n_sub, int32_t n_phi, double* I_dev,
                         hipStream_t stream);
+
+/* Visibility amplitudes of a ray-traced image (Sect. 3.4 shows visibility
+ * curves of the disks: the Fourier transform of the image at a baseline's
+ * spatial frequency over the total flux).  I_dev: the image of
+ * mcrt_raytrace_image with the same n_inc, cos_i_host, n_sub and n_phi
+ * (device, not modified); the star joins as a point at the centre with its
+ * luminosity per bin dimmed along the line of sight.  Ray (ring, p) sits at
+ * x = b cos phi, y = b sin phi on the image-plane axes of mcrt_raytrace_image
+ * and stands also for its mirror image at -y, each carrying half of
+ * pi (b_hi^2 - b_lo^2) / n_phi.  baselines_host [n_base][2]: projected length
+ * (cm) and position angle (radians from the x axis towards y).  At the
+ * distance `distance` (cm), bin k is sampled at s = B / (lambda_k distance)
+ * cycles per cm, lambda_k the bin's geometric centre:
+ *   V = |sum A I e^(-2 pi i s (x cos theta + y sin theta)) + L_star,k / 4 pi|
+ *       / (sum A I + L_star,k / 4 pi).
+ * V_dev [n_inc][n_base][n_lambda] double, overwritten.  Asynchronous.
+ * Errors: MCRT_E_ARG for null pointers, n_inc, n_base outside [1, 64], n_sub
+ * or n_phi < 1, a cos_i outside [0, 1], a negative or non-finite baseline,
+ * distance <= 0, or more than 512 bins. */
+int mcrt_visibility(mcrt_ctx* ctx, const double* I_dev, int32_t n_inc, const double* cos_i_host,
+                    int32_t n_sub, int32_t n_phi, int32_t n_base, const double* baselines_host,
+                    double distance, double* V_dev, hipStream_t stream);
 
 /* Outcome of mcrt_batch_converge for one disk. */
 typedef struct {

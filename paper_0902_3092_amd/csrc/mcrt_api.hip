@@ -162,6 +162,9 @@ int launch_trace_fp64(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
 int launch_raytrace_image(mcrt_ctx* ctx, const double* T, const double* J, int n_inc,
                           const double* cos_i_host, int n_sub, int n_phi, double* img,
                           hipStream_t s);
+int launch_visibility(mcrt_ctx* ctx, const double* img, int n_inc, const double* cos_i_host,
+                      int n_sub, int n_phi, int n_base, const double* base_host, double distance,
+                      double* V, hipStream_t s);
 int launch_trace_fp32(mcrt_ctx* ctx, const TraceArgs& a, hipStream_t s);
 
 TraceArgs make_trace_args(mcrt_ctx* ctx, uint64_t n_packets, uint64_t n_total, uint64_t seed,
@@ -803,6 +806,27 @@ int mcrt_raytrace_image(mcrt_ctx* ctx, const double* T_dev, const double* J_dev,
   rc = mcrt::launch_raytrace_image(ctx, T_dev ? T_dev : ctx->d_T, J_dev, n_inc, cos_i_host,
                                    n_sub, n_phi, I_dev, stream);
   return rc ? fail(ctx, rc, "ray tracing launch failed") : MCRT_OK;
+}
+
+int mcrt_visibility(mcrt_ctx* ctx, const double* I_dev, int32_t n_inc, const double* cos_i_host,
+                    int32_t n_sub, int32_t n_phi, int32_t n_base, const double* baselines_host,
+                    double distance, double* V_dev, hipStream_t stream) {
+  if (!ctx || !I_dev || !V_dev || !cos_i_host || !baselines_host)
+    return fail(ctx, MCRT_E_ARG, "null argument");
+  if (n_inc < 1 || n_sub < 1 || n_phi < 1 || n_base < 1)
+    return fail(ctx, MCRT_E_ARG, "n_inc, n_sub, n_phi, n_base >= 1");
+  if (!(distance > 0.0) || !std::isfinite(distance))
+    return fail(ctx, MCRT_E_ARG, "distance must be positive");
+  for (int q = 0; q < n_inc; ++q)
+    if (!(cos_i_host[q] >= 0.0 && cos_i_host[q] <= 1.0))
+      return fail(ctx, MCRT_E_ARG, "cos_i must lie in [0, 1]");
+  for (int j = 0; j < n_base; ++j)
+    if (!(baselines_host[2 * j] >= 0.0) || !std::isfinite(baselines_host[2 * j]) ||
+        !std::isfinite(baselines_host[2 * j + 1]))
+      return fail(ctx, MCRT_E_ARG, "baseline lengths >= 0 and finite angles");
+  int rc = mcrt::launch_visibility(ctx, I_dev, n_inc, cos_i_host, n_sub, n_phi, n_base,
+                                   baselines_host, distance, V_dev, stream);
+  return rc ? fail(ctx, rc, rc == MCRT_E_ARG ? ctx->err : "visibility launch failed") : MCRT_OK;
 }
 
 int mcrt_set_T(mcrt_ctx* ctx, const double* T_dev, hipStream_t stream) {

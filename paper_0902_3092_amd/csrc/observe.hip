@@ -255,7 +255,119 @@ __global__ void star_kernel(DevModel M, RayGeom G, double* __restrict__ L) {
   }
 }
 
+// Visibility amplitudes of a ray-traced image (Sect. 3.4): one workgroup per
+// (inclination, baseline); its four wavefronts take every fourth ray, each
+// lane the bins lane, lane + 64, ...; the partial sums meet in LDS.
+constexpr int MAX_BASE = 64;
+constexpr int VIS_BS = 256;
+
+struct VisGeom {
+  int n_inc, n_rings, n_sub, n_phi, n_base;
+  double distance;
+  double cos_i[MAX_INC];
+  double B[MAX_BASE], theta[MAX_BASE];
+};
+
+__global__ void __launch_bounds__(VIS_BS) visibility_kernel(DevModel M, VisGeom G,
+                                                            const double* __restrict__ img,
+                                                            double* __restrict__ V) {
+  __shared__ double part[VIS_BS / 64][3][MAX_BINS];
+  const int q = blockIdx.x / G.n_base, jb = blockIdx.x % G.n_base;
+  const int lane = __lane_id(), w = threadIdx.x / 64;
+  const int nl = M.n_lambda, nq = (nl + 63) / 64;
+  const double ct = cos(G.theta[jb]), st = sin(G.theta[jb]);
+  double re[MAX_BINS / 64], im[MAX_BINS / 64], tot[MAX_BINS / 64], sf[MAX_BINS / 64];
+  for (int m = 0; m < nq; ++m) {
+    re[m] = im[m] = tot[m] = 0.0;
+    const int k = min(lane + 64 * m, nl - 1);
+    sf[m] = G.B[jb] / (sqrt(M.lam[k] * M.lam[k + 1]) * G.distance);
+  }
+  const long long rays = (long long)G.n_rings * G.n_phi;
+  for (long long r = w; r < rays; r += VIS_BS / 64) {
+    const int ring = (int)(r / G.n_phi), p = (int)(r % G.n_phi);
+    const int cell = ring / G.n_sub, sub = ring % G.n_sub;
+    const double lo = cell == 0 ? 0.0 : M.r_edges[cell - 1];
+    const double hi = M.r_edges[cell];
+    const double b_lo = lo + (hi - lo) * sub / G.n_sub;
+    const double b_hi = lo + (hi - lo) * (sub + 1) / G.n_sub;
+    const double bm = 0.5 * (b_lo + b_hi);
+    const double half = 0.5 * KPI * (b_hi * b_hi - b_lo * b_lo) / G.n_phi;
+    double sp, cp;
+    sincos((p + 0.5) * KPI / G.n_phi, &sp, &cp);
+    const double x = bm * cp, y = bm * sp;
+    const double* row = img + ((size_t)q * rays + r) * nl;
+    for (int m = 0; m < nq; ++m) {
+      const int k = lane + 64 * m;
+      if (k >= nl) continue;
+      const double a = half * row[k];
+      if (a == 0.0) continue;
+      // the ray and its mirror image at -y
+      double s1, c1, s2, c2;
+      sincos(-2.0 * KPI * sf[m] * (x * ct + y * st), &s1, &c1);
+      sincos(-2.0 * KPI * sf[m] * (x * ct - y * st), &s2, &c2);
+      re[m] += a * (c1 + c2);
+      im[m] += a * (s1 + s2);
+      tot[m] += 2.0 * a;
+    }
+  }
+  for (int m = 0; m < nq; ++m) {
+    const int k = lane + 64 * m;
+    if (k < nl) {
+      part[w][0][k] = re[m];
+      part[w][1][k] = im[m];
+      part[w][2][k] = tot[m];
+    }
+  }
+  __syncthreads();
+  if (w != 0) return;
+  // the star, a point at the centre, dimmed along the line of sight (which
+  // stays in the row of |mu| = cos i)
+  const double ci = G.cos_i[q];
+  const int jr = mu_row(M.mu2, M.n_mu, 1.0, ci * ci);
+  for (int m = 0; m < nq; ++m) {
+    const int k = lane + 64 * m;
+    if (k >= nl) continue;
+    double tau = 0.0;
+    for (int i = 0; i < M.n_r; ++i)
+      tau += M.rho[i * M.n_mu + jr] * M.chi[k] * (M.r_edges[i + 1] - M.r_edges[i]);
+    const double share = M.star_cdf[k] - (k ? M.star_cdf[k - 1] : 0.0);
+    const double fs = M.L_star * share * exp(-tau) / (4.0 * KPI);
+    double R = fs, I = 0.0, F = fs;
+    for (int u = 0; u < VIS_BS / 64; ++u) {
+      R += part[u][0][k];
+      I += part[u][1][k];
+      F += part[u][2][k];
+    }
+    V[((size_t)q * G.n_base + jb) * nl + k] = F > 0.0 ? sqrt(R * R + I * I) / F : 0.0;
+  }
+}
+
 }  // namespace
+
+int launch_visibility(mcrt_ctx* ctx, const double* img, int n_inc, const double* cos_i_host,
+                      int n_sub, int n_phi, int n_base, const double* base_host, double distance,
+                      double* V, hipStream_t s) {
+  const DevModel& M = ctx->m;
+  if (M.n_lambda > MAX_BINS || n_inc > MAX_INC || n_base > MAX_BASE) {
+    set_error(ctx, "visibilities: at most 512 bins, 64 inclinations and 64 baselines per call");
+    return MCRT_E_ARG;
+  }
+  VisGeom G{};
+  G.n_inc = n_inc;
+  G.n_rings = (M.n_r + 1) * n_sub;
+  G.n_sub = n_sub;
+  G.n_phi = n_phi;
+  G.n_base = n_base;
+  G.distance = distance;
+  for (int q = 0; q < n_inc; ++q) G.cos_i[q] = cos_i_host[q];
+  for (int j = 0; j < n_base; ++j) {
+    G.B[j] = base_host[2 * j];
+    G.theta[j] = base_host[2 * j + 1];
+  }
+  hipLaunchKernelGGL(visibility_kernel, dim3((unsigned)(n_inc * n_base)), dim3(VIS_BS), 0, s, M,
+                     G, img, V);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
 
 int launch_mean_intensity(mcrt_ctx* ctx, const double* T, double* J, hipStream_t s) {
   const int nc = ctx->n_cells;

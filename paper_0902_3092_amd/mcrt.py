@@ -31,7 +31,7 @@ EXPORTS = ["mcrt_default_options", "mcrt_setup", "mcrt_destroy", "mcrt_reset", "
            "mcrt_batch_run", "mcrt_pda_linear", "mcrt_pda_adjoint", "mcrt_pda_solve_noalloc",
            "mcrt_batch_pda", "mcrt_convergence", "mcrt_batch_converge", "mcrt_mean_intensity",
            "mcrt_raytrace_sed", "mcrt_region_mask", "mcrt_pda_nonlinear",
-           "mcrt_pda_nonlinear_adjoint", "mcrt_raytrace_image"]
+           "mcrt_pda_nonlinear_adjoint", "mcrt_raytrace_image", "mcrt_visibility"]
 
 
 class McrtError(RuntimeError):
@@ -130,6 +130,7 @@ def lib():
         L.mcrt_region_mask.argtypes = [vp, i32, C.c_double, vp, vp]
         L.mcrt_raytrace_sed.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
         L.mcrt_raytrace_image.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
+        L.mcrt_visibility.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, C.c_double, vp, vp]
         L.mcrt_batch_converge.argtypes = [vp, C.c_int, vp, vp, C.c_int, i32, C.c_double, C.c_int,
                                           vp, vp, vp, vp]
         _lib = L
@@ -364,6 +365,25 @@ class Context:
                                          int(n_sub), int(n_phi), _ptr(img), _stream(stream)),
                "mcrt_raytrace_image")
         return img
+
+    def visibility(self, image, cos_i, n_sub: int, n_phi: int, baselines, distance: float,
+                   stream=None):
+        """mcrt_visibility: amplitudes [n_inc, n_base, n_lambda] of an image
+        from raytrace_image (the same cos_i, n_sub, n_phi) with the dimmed
+        star; baselines [n_base, 2]: length (cm), position angle (rad)."""
+        import torch
+        shape = (len(cos_i), (self.n_r + 1) * int(n_sub), int(n_phi), self.n_lambda)
+        if tuple(image.shape) != shape or image.dtype != torch.float64 or \
+                not image.is_contiguous():
+            raise ValueError("image must be a contiguous float64 tensor of shape %s" % (shape,))
+        ci = (C.c_double * len(cos_i))(*[float(x) for x in cos_i])
+        bl = np.ascontiguousarray(baselines, dtype=np.float64).reshape(-1, 2)
+        bh = (C.c_double * bl.size)(*bl.reshape(-1).tolist())
+        V = torch.empty((len(cos_i), len(bl), self.n_lambda), dtype=torch.float64, device="cuda")
+        _check(lib().mcrt_visibility(self.handle, _ptr(image), len(cos_i), ci, int(n_sub),
+                                     int(n_phi), len(bl), bh, float(distance), _ptr(V),
+                                     _stream(stream)), "mcrt_visibility")
+        return V
 
     def set_T(self, T, stream=None):
         _check(lib().mcrt_set_T(self.handle, _ptr(T), _stream(stream)), "mcrt_set_T")

@@ -9,7 +9,10 @@
 * the optically thin isothermal shell against its closed form;
 * the ray-traced image (the intensity of every ray) of the same disk and of
   the 1e-2 Msun workload's grid, ray for ray against the oracle, and summed
-  with the rays' areas against the ray-traced SED.
+  with the rays' areas against the ray-traced SED;
+* visibility amplitudes of an image (the oracle's, on both sides) at several
+  baselines, position angles and inclinations against the oracle's, and the
+  argument checks of the entry point.
 """
 import math
 import os
@@ -240,4 +243,49 @@ def test_raytrace_image_full_grid(mcrt, oracle_mod, torch_cuda):
     assert big.mean() > 0.3
     assert np.allclose(Ig[big], Io[big], rtol=1e-8, atol=0), np.max(np.abs(Ig[big] / Io[big] - 1))
     assert np.all(np.abs(Ig[~big]) <= 1e-10 * scale)
+
+
+def test_visibility_matches_oracle(mcrt, oracle_mod, torch_cuda):
+    """The 30 x 20 disk's image at three inclinations (the oracle's, given to
+    both sides), 150 pc away, baselines of 0, 100 and 500 m at three position
+    angles: every amplitude against the oracle's."""
+    torch = torch_cuda
+    d = W.make_disk("ray", M_dust_msun=1e-3, n_r=30, n_mu=20, n_lambda=30)
+    ora = oracle_mod.Oracle(d)
+    ctx = mcrt.Context(d)
+    T, J = _ray_inputs(ora, d)
+    ci, n_sub, n_phi = [0.05, 0.5, 0.95], 2, 8
+    img = ora.raytrace_image(T, J=J, cos_i=ci, n_sub=n_sub, n_phi=n_phi)
+    base = [[0.0, 0.0], [1e4, 0.0], [1e4, 1.0], [5e4, 2.0]]
+    dist = 150 * 3.0857e18
+    Vo = ora.visibility(img, ci, n_sub, n_phi, base, dist)
+    Vg = ctx.visibility(torch.from_numpy(img).cuda(), ci, n_sub, n_phi, base, dist).cpu().numpy()
+    assert Vg.shape == Vo.shape == (3, 4, d.n_lambda)
+    assert np.allclose(Vg, Vo, rtol=1e-10, atol=1e-13), np.max(np.abs(Vg - Vo))
+    assert np.allclose(Vo[:, 0, :], 1.0, atol=1e-13)        # zero baseline
+    assert Vo[:, 3, :].min() < 0.9                           # resolved somewhere
+    with pytest.raises(mcrt.McrtError):
+        ctx.visibility(torch.from_numpy(img).cuda(), ci, n_sub, n_phi, [[-1.0, 0.0]], dist)
+    with pytest.raises(mcrt.McrtError):
+        ctx.visibility(torch.from_numpy(img).cuda(), ci, n_sub, n_phi, base, 0.0)
+
+
+def test_visibility_of_the_workload_image(mcrt, oracle_mod, torch_cuda):
+    """The 1e-2 Msun workload's grid seen at 45 degrees from 150 pc with a
+    100 m baseline (the setting of the paper's visibility curves): the image
+    traced on the device and its amplitudes against the oracle's, both from
+    the oracle's temperature field."""
+    torch = torch_cuda
+    d, _ = W.config("mrw_pda")
+    ora = oracle_mod.Oracle(d)
+    ctx = mcrt.Context(d)
+    T = _field(d)
+    ci, n_sub, n_phi = [0.7071067811865476], 2, 16
+    base, dist = [[1e4, 0.0], [1e4, 1.5707963267948966]], 150 * 3.0857e18
+    Ig = ctx.raytrace_image(torch.from_numpy(T).cuda(), cos_i=ci, n_sub=n_sub, n_phi=n_phi)
+    Vg = ctx.visibility(Ig, ci, n_sub, n_phi, base, dist).cpu().numpy()
+    Io = ora.raytrace_image(T, cos_i=ci, n_sub=n_sub, n_phi=n_phi)
+    Vo = ora.visibility(Io, ci, n_sub, n_phi, base, dist)
+    assert np.allclose(Vg, Vo, rtol=1e-8, atol=1e-12), np.max(np.abs(Vg - Vo))
+    assert np.all((Vo >= 0.0) & (Vo <= 1.0 + 1e-12))
 
