@@ -586,6 +586,23 @@ def sed_study(mcrt, W, torch, n_packets, cos_i=(0.7071067811865476, 0.2588190451
         seds[name] = L.cpu().numpy()
         out[name + "_trace_s"] = t1 - t0
         out[name + "_raytrace_ms"] = (t2 - t1) * 1e3
+        if name == "mrw":
+            # the image behind the same rays at 45 degrees and its visibility
+            # amplitudes for a 100 m baseline at 150 pc (two position angles)
+            img = ctx.raytrace_image(T, J, cos_i=[cos_i[0]], n_sub=4, n_phi=32)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            V = ctx.visibility(img, [cos_i[0]], 4, 32, [[1e4, 0.0], [1e4, 1.5707963267948966]],
+                               150 * 3.0857e18)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            lam = np.sqrt(d.lambda_edges[:-1] * d.lambda_edges[1:])
+            nband = (lam >= 8e-4) & (lam <= 13e-4)
+            Vn = V.cpu().numpy()[0][:, nband]
+            out["visibility_100m_150pc_nband"] = {
+                "position_angles_rad": [0.0, 1.5707963267948966],
+                "min": [float(v.min()) for v in Vn], "max": [float(v.max()) for v in Vn],
+                "visibility_ms": (t4 - t3) * 1e3, "bins": int(nband.sum())}
         log("sed study: %s done (%.1f s trace, %.1f ms ray tracing)" % (name, t1 - t0,
                                                                       (t2 - t1) * 1e3))
         del ctx
