@@ -506,10 +506,13 @@ int mcrt_raytrace_image(mcrt_ctx* ctx, const double* T_dev, const double* J_dev,
  * cycles per cm, lambda_k the bin's geometric centre:
  *   V = |sum A I e^(-2 pi i s (x cos theta + y sin theta)) + L_star,k / 4 pi|
  *       / (sum A I + L_star,k / 4 pi).
- * V_dev [n_inc][n_base][n_lambda] double, overwritten.  Asynchronous.
- * Errors: MCRT_E_ARG for null pointers, n_inc, n_base outside [1, 64], n_sub
- * or n_phi < 1, a cos_i outside [0, 1], a negative or non-finite baseline,
- * distance <= 0, or more than 512 bins. */
+ * V_dev [n_inc][n_base][n_lambda] double, overwritten.  The partial sums
+ * use the context's source-function buffer (8 n_cells n_lambda bytes,
+ * allocated on first use), so a visibility call and a ray tracing call on one
+ * context must not overlap.  Asynchronous.  Errors: MCRT_E_ARG for null
+ * pointers, n_inc, n_base outside [1, 64], n_sub or n_phi < 1, a cos_i
+ * outside [0, 1], a negative or non-finite baseline, distance <= 0, more than
+ * 512 bins, or n_inc n_base > n_cells / 3; MCRT_E_OOM. */
 int mcrt_visibility(mcrt_ctx* ctx, const double* I_dev, int32_t n_inc, const double* cos_i_host,
                     int32_t n_sub, int32_t n_phi, int32_t n_base, const double* baselines_host,
                     double distance, double* V_dev, hipStream_t stream);

@@ -824,6 +824,12 @@ int mcrt_visibility(mcrt_ctx* ctx, const double* I_dev, int32_t n_inc, const dou
     if (!(baselines_host[2 * j] >= 0.0) || !std::isfinite(baselines_host[2 * j]) ||
         !std::isfinite(baselines_host[2 * j + 1]))
       return fail(ctx, MCRT_E_ARG, "baseline lengths >= 0 and finite angles");
+  if (!ctx->d_src &&
+      hipMalloc((void**)&ctx->d_src, (size_t)ctx->n_cells * ctx->n_lambda * sizeof(double)) !=
+          hipSuccess) {
+    ctx->d_src = nullptr;
+    return fail(ctx, MCRT_E_OOM, "source-function buffer");
+  }
   int rc = mcrt::launch_visibility(ctx, I_dev, n_inc, cos_i_host, n_sub, n_phi, n_base,
                                    baselines_host, distance, V_dev, stream);
   return rc ? fail(ctx, rc, rc == MCRT_E_ARG ? ctx->err : "visibility launch failed") : MCRT_OK;

@@ -12,6 +12,8 @@
 // across the lanes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mcrt_internal.h"
 #include "trace_common.h"
 
@@ -255,24 +257,28 @@ __global__ void star_kernel(DevModel M, RayGeom G, double* __restrict__ L) {
   }
 }
 
-// Visibility amplitudes of a ray-traced image (Sect. 3.4): one workgroup per
-// (inclination, baseline); its four wavefronts take every fourth ray, each
-// lane the bins lane, lane + 64, ...; the partial sums meet in LDS.
+// Visibility amplitudes of a ray-traced image (Sect. 3.4), in two steps.
+// Partial sums: workgroup (pair, chunk) takes a contiguous range of the rays
+// of one (inclination, baseline) pair; its four wavefronts take every fourth
+// ray of it, each lane the bins lane, lane + 64, ...; the four meet in LDS
+// and the chunk's sums of A I cos, A I sin and A I per bin go to `part`.
+// Then one thread per (pair, bin) adds the chunks in order and the star.
 constexpr int MAX_BASE = 64;
 constexpr int VIS_BS = 256;
 
 struct VisGeom {
-  int n_inc, n_rings, n_sub, n_phi, n_base;
+  int n_inc, n_rings, n_sub, n_phi, n_base, n_chunk;
   double distance;
   double cos_i[MAX_INC];
   double B[MAX_BASE], theta[MAX_BASE];
 };
 
-__global__ void __launch_bounds__(VIS_BS) visibility_kernel(DevModel M, VisGeom G,
-                                                            const double* __restrict__ img,
-                                                            double* __restrict__ V) {
-  __shared__ double part[VIS_BS / 64][3][MAX_BINS];
-  const int q = blockIdx.x / G.n_base, jb = blockIdx.x % G.n_base;
+__global__ void __launch_bounds__(VIS_BS) vis_partial_kernel(DevModel M, VisGeom G,
+                                                             const double* __restrict__ img,
+                                                             double* __restrict__ part) {
+  __shared__ double red[VIS_BS / 64][3][MAX_BINS];
+  const int pair = blockIdx.x / G.n_chunk, chunk = blockIdx.x % G.n_chunk;
+  const int q = pair / G.n_base, jb = pair % G.n_base;
   const int lane = __lane_id(), w = threadIdx.x / 64;
   const int nl = M.n_lambda, nq = (nl + 63) / 64;
   const double ct = cos(G.theta[jb]), st = sin(G.theta[jb]);
@@ -283,7 +289,8 @@ __global__ void __launch_bounds__(VIS_BS) visibility_kernel(DevModel M, VisGeom 
     sf[m] = G.B[jb] / (sqrt(M.lam[k] * M.lam[k + 1]) * G.distance);
   }
   const long long rays = (long long)G.n_rings * G.n_phi;
-  for (long long r = w; r < rays; r += VIS_BS / 64) {
+  const long long r0 = rays * chunk / G.n_chunk, r1 = rays * (chunk + 1) / G.n_chunk;
+  for (long long r = r0 + w; r < r1; r += VIS_BS / 64) {
     const int ring = (int)(r / G.n_phi), p = (int)(r % G.n_phi);
     const int cell = ring / G.n_sub, sub = ring % G.n_sub;
     const double lo = cell == 0 ? 0.0 : M.r_edges[cell - 1];
@@ -313,33 +320,46 @@ __global__ void __launch_bounds__(VIS_BS) visibility_kernel(DevModel M, VisGeom 
   for (int m = 0; m < nq; ++m) {
     const int k = lane + 64 * m;
     if (k < nl) {
-      part[w][0][k] = re[m];
-      part[w][1][k] = im[m];
-      part[w][2][k] = tot[m];
+      red[w][0][k] = re[m];
+      red[w][1][k] = im[m];
+      red[w][2][k] = tot[m];
     }
   }
   __syncthreads();
-  if (w != 0) return;
-  // the star, a point at the centre, dimmed along the line of sight (which
-  // stays in the row of |mu| = cos i)
+  for (int k = threadIdx.x; k < nl; k += VIS_BS) {
+    double* dst = part + ((size_t)blockIdx.x * 3) * nl;
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+      for (int u = 0; u < VIS_BS / 64; ++u) v += red[u][c][k];
+      dst[(size_t)c * nl + k] = v;
+    }
+  }
+}
+
+// The star, a point at the centre dimmed along the line of sight (which
+// stays in the row of |mu| = cos i), and the amplitude.
+__global__ void vis_final_kernel(DevModel M, VisGeom G, const double* __restrict__ part,
+                                 double* __restrict__ V) {
+  const int nl = M.n_lambda;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)G.n_inc * G.n_base * nl) return;
+  const int pair = (int)(idx / nl), k = (int)(idx % nl);
+  const int q = pair / G.n_base;
   const double ci = G.cos_i[q];
   const int jr = mu_row(M.mu2, M.n_mu, 1.0, ci * ci);
-  for (int m = 0; m < nq; ++m) {
-    const int k = lane + 64 * m;
-    if (k >= nl) continue;
-    double tau = 0.0;
-    for (int i = 0; i < M.n_r; ++i)
-      tau += M.rho[i * M.n_mu + jr] * M.chi[k] * (M.r_edges[i + 1] - M.r_edges[i]);
-    const double share = M.star_cdf[k] - (k ? M.star_cdf[k - 1] : 0.0);
-    const double fs = M.L_star * share * exp(-tau) / (4.0 * KPI);
-    double R = fs, I = 0.0, F = fs;
-    for (int u = 0; u < VIS_BS / 64; ++u) {
-      R += part[u][0][k];
-      I += part[u][1][k];
-      F += part[u][2][k];
-    }
-    V[((size_t)q * G.n_base + jb) * nl + k] = F > 0.0 ? sqrt(R * R + I * I) / F : 0.0;
+  double tau = 0.0;
+  for (int i = 0; i < M.n_r; ++i)
+    tau += M.rho[i * M.n_mu + jr] * M.chi[k] * (M.r_edges[i + 1] - M.r_edges[i]);
+  const double share = M.star_cdf[k] - (k ? M.star_cdf[k - 1] : 0.0);
+  const double fs = M.L_star * share * exp(-tau) / (4.0 * KPI);
+  double R = fs, I = 0.0, F = fs;
+  for (int c = 0; c < G.n_chunk; ++c) {
+    const double* src = part + ((size_t)(pair * G.n_chunk + c) * 3) * nl;
+    R += src[k];
+    I += src[nl + k];
+    F += src[2 * nl + k];
   }
+  V[idx] = F > 0.0 ? sqrt(R * R + I * I) / F : 0.0;
 }
 
 }  // namespace
@@ -364,8 +384,23 @@ int launch_visibility(mcrt_ctx* ctx, const double* img, int n_inc, const double*
     G.B[j] = base_host[2 * j];
     G.theta[j] = base_host[2 * j + 1];
   }
-  hipLaunchKernelGGL(visibility_kernel, dim3((unsigned)(n_inc * n_base)), dim3(VIS_BS), 0, s, M,
-                     G, img, V);
+  // the partial sums live in the source-function buffer (n_cells x n_lambda
+  // doubles): chunks per pair as that holds, about 512 workgroups in all
+  const int pairs = n_inc * n_base;
+  const long long rays = (long long)G.n_rings * n_phi;
+  long long nch = ctx->n_cells / (3LL * pairs);
+  nch = std::min<long long>(nch, std::max<long long>(1, 512 / pairs));
+  nch = std::min<long long>(nch, rays);
+  if (nch < 1) {
+    set_error(ctx, "visibilities: too many inclinations x baselines for this grid's buffer");
+    return MCRT_E_ARG;
+  }
+  G.n_chunk = (int)nch;
+  hipLaunchKernelGGL(vis_partial_kernel, dim3((unsigned)(pairs * nch)), dim3(VIS_BS), 0, s, M, G,
+                     img, ctx->d_src);
+  const long long outs = (long long)pairs * M.n_lambda;
+  hipLaunchKernelGGL(vis_final_kernel, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, M,
+                     G, ctx->d_src, V);
   return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
 }
 
