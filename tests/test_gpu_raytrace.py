@@ -268,6 +268,14 @@ def test_visibility_matches_oracle(mcrt, oracle_mod, torch_cuda):
         ctx.visibility(torch.from_numpy(img).cuda(), ci, n_sub, n_phi, [[-1.0, 0.0]], dist)
     with pytest.raises(mcrt.McrtError):
         ctx.visibility(torch.from_numpy(img).cuda(), ci, n_sub, n_phi, base, 0.0)
+    # more (inclination, baseline) pairs than a third of the cells: the
+    # partial sums would not fit the context's buffer, so the call refuses
+    many = [0.5] * 64
+    big_img = torch.zeros((64, (d.n_r + 1) * n_sub, n_phi, d.n_lambda), dtype=torch.float64,
+                          device="cuda")
+    assert 64 * 4 > ctx.n_cells // 3
+    with pytest.raises(mcrt.McrtError):
+        ctx.visibility(big_img, many, n_sub, n_phi, base, dist)
 
 
 def test_visibility_of_the_workload_image(mcrt, oracle_mod, torch_cuda):
